@@ -1,0 +1,177 @@
+/*
+ * colden: tree-based column densities on a fully threaded octree, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Method: Valdivia & Hennebelle (2014), "A fast tree-based method for
+ * estimating column densities in Adaptive Mesh Refinement codes", A&A.
+ * For every leaf (target) cell and every direction sector the column
+ *   N(m,n) = sum_i n_i dx_i(m,n)                                 (Eq. 6)
+ * is split into the internal + local part (the target and its 7 siblings,
+ * rays from the target centre) and the external part, a sum over concentric
+ * cubic shells, one per coarser level, whose cells are weighted by
+ * precalculated geometric factors K (Sect. 3.2 and 3.3, Eqs. 7-9):
+ *   N_ext(m,n) = sum_l dx_l sum_{i in C_l} n_i K(r_i - r_target, m, n, dl).
+ * The attenuation factor is chi = (1/D) sum_d exp(-gamma A_V,d) with
+ * A_V = N av_per_nh (Eq. 5; gamma = 3.74 and av_per_nh = 1/1.87e21 cm^2
+ * reproduce the paper's sigma = 2e-21 cm^2).
+ *
+ * Conventions for every call:
+ *  - Status codes: CD_OK (0) or a negative CD_E* value; cd_last_error()
+ *    returns a thread-local message for the last failure.  Nothing aborts,
+ *    nothing throws across this boundary.
+ *  - Pointers named *_dev are device pointers (HIP global memory); every
+ *    other pointer is host memory.  The caller owns every buffer it passes;
+ *    the library owns the opaque handles and the device memory behind them.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
+ *    asynchronous on that stream; host arguments are consumed before return.
+ *  - Leaf order (input densities, output rows): base-level cells in row-major
+ *    order (x fastest) skipping refined ones, then for each finer level the
+ *    octs in the order given, each oct's children c = i + 2j + 4k (i, j, k
+ *    the x, y, z child bits) skipping refined ones.  A uniform 2^L grid
+ *    (base_level == max_level) is plain row-major order.
+ *  - Densities are in cm^-3, columns in cm^-2; densities must be finite and
+ *    >= 0 (not checked on the device).
+ *  - Boundary: non-periodic; no matter outside the box.
+ */
+#ifndef COLDEN_H
+#define COLDEN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    CD_OK = 0,
+    CD_EINVAL = -1,       /* invalid argument */
+    CD_ENOMEM = -2,       /* device or host allocation failed */
+    CD_EDEVICE = -3,      /* HIP runtime or kernel launch error */
+    CD_EUNSUPPORTED = -4  /* valid but not provided by this build */
+};
+
+/* direction families */
+enum {
+    CD_DIR_HEALPIX = 0,   /* HEALPix ring-scheme pixel centres, p1 = Nside: 12 Nside^2 sectors */
+    CD_DIR_PAPER_MN = 1,  /* the paper's M x N grid (Sect. 3.2, Eq. 3), p1 = M, p2 = N */
+    CD_DIR_AXES6 = 2      /* +x, -x, +y, -y, +z, -z (Sect. 4.4) */
+};
+
+/* reference-point modes */
+enum {
+    CD_PRECALC73 = 0,     /* two-level approximation, 73 configurations (Sect. 3.3) */
+    CD_INSITU = 1         /* reference at the oct centre for every shell (Sect. 4.4) */
+};
+
+/* contraction precision */
+enum {
+    CD_FP32 = 0,          /* FP32 densities and weights, FP32 accumulation */
+    CD_BF16X2 = 1,        /* densities and weights split hi+lo in bf16, MFMA, FP32 accumulation */
+    CD_FP16X2 = 2         /* same with fp16 and a per-tile power-of-two density scale */
+};
+
+#define CD_MAX_DIRS 128
+#define CD_MAX_LEVEL 12
+
+typedef struct cd_tree cd_tree;
+typedef struct cd_weights cd_weights;
+
+/* Thread-local message describing the last failed call ("" if none). */
+const char* cd_last_error(void);
+
+/* ABI version (incremented on incompatible changes). */
+int cd_version(void);
+
+/*
+ * Direction set of a family (Sect. 3.2).  Writes D unit vectors, row d =
+ * (ux, uy, uz), into out[capacity][3] and sets *D.  Components with
+ * |u_k| < 1e-14 are set to 0.
+ * Errors: CD_EINVAL for unknown scheme, p1/p2 < 1, or capacity < D.
+ */
+int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D);
+
+/*
+ * Build the tree of a fully threaded octree and its pyramid (Sect. 3: a
+ * coarse cell holds the mean of its 8 children).
+ *   box_cm           edge of the cubic box in cm; dx_l = 0.5^l box_cm.
+ *   base_level       B: level of the full base grid (2^B cells per axis).
+ *   max_level        Lmax >= B, at most CD_MAX_LEVEL.
+ *   n_octs           host [Lmax - B] oct counts of levels B+1 .. Lmax (NULL if Lmax == B).
+ *   oct_parents      host [Lmax - B] pointers; level l's array is int32
+ *                    [n_octs][3] (x, y, z) of the refined parent cells at
+ *                    level l-1; each parent must exist.
+ *   leaf_n_dev       device float [n_leaf] leaf densities in leaf order.
+ *                    Read during this call's device work only.
+ *   n_leaf           number of leaves implied by the structure.
+ * The structure is copied; the pyramid is built on `stream`.  Device
+ * memory for the pyramid and the index maps is owned by the handle.
+ * Errors: CD_EINVAL (malformed structure, wrong n_leaf), CD_ENOMEM,
+ * CD_EDEVICE.
+ */
+int cd_build_tree(double box_cm, int base_level, int max_level,
+                  const int64_t* n_octs, const int32_t* const* oct_parents,
+                  const float* leaf_n_dev, int64_t n_leaf, void* stream, cd_tree** out);
+
+/* New leaf densities for an existing structure (one hydro step later):
+ * rebuilds the pyramid on `stream`.  Same layout rules as cd_build_tree. */
+int cd_tree_update(cd_tree* tree, const float* leaf_n_dev, void* stream);
+
+/* Number of leaves of the tree. */
+int cd_tree_n_leaf(const cd_tree* tree, int64_t* n_leaf);
+
+/* Level (int8) and (x, y, z) coordinates (int32) of every leaf, host buffers
+ * [n_leaf] and [n_leaf][3]. */
+int cd_tree_leaf_coords(const cd_tree* tree, int8_t* level, int32_t* ijk);
+
+/* Release the handle and its device memory (after the stream's work that
+ * uses it has completed).  NULL is ignored. */
+void cd_tree_destroy(cd_tree* tree);
+
+/*
+ * Precalculated geometric weights (Sect. 3.3): for the 73 reference
+ * configurations and every cell of the 11^3 standard cube, the distance a
+ * ray along each direction crosses in that cell (in cell widths), restricted
+ * to the cells of each shell shape, computed once in double precision on the
+ * host and uploaded once.  Also the internal + local weights of a target's
+ * own oct.
+ *   dirs       host [D][3] unit vectors (|u| = 1 within 1e-9).
+ *   D          1 .. CD_MAX_DIRS.
+ *   mode       CD_PRECALC73 (CD_INSITU: CD_EUNSUPPORTED in this build).
+ *   precision  CD_FP32, CD_BF16X2 or CD_FP16X2 (which sweep kernels use it).
+ * Errors: CD_EINVAL, CD_EUNSUPPORTED, CD_ENOMEM, CD_EDEVICE.
+ */
+int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
+                          void* stream, cd_weights** out);
+
+/* Number of directions of a weights handle. */
+int cd_weights_n_dirs(const cd_weights* w, int* D);
+
+/* Release the handle (after the stream's work that uses it). */
+void cd_weights_destroy(cd_weights* w);
+
+/*
+ * Column densities of every leaf (Eqs. 6-9): writes N_dev[n_leaf][D]
+ * (float, cm^-2, row-major, direction fastest).  If chi_dev is not NULL the
+ * screening factor (Eq. 5) is fused and written to chi_dev[n_leaf]
+ * using av_per_nh and gamma (ignored otherwise).  The contraction runs in
+ * the precision of the weights handle.  Asynchronous on `stream`.
+ * Errors: CD_EINVAL (NULL handles or output), CD_ENOMEM, CD_EDEVICE.
+ */
+int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
+                        double av_per_nh, double gamma, void* stream);
+
+/*
+ * Screening factor (Eq. 5): A_V = N av_per_nh, chi = (1/D) sum_d
+ * exp(-gamma A_V,d).  N_dev [n_leaf][D]; writes chi_dev[n_leaf] and, if not
+ * NULL, av_dev[n_leaf][D].  Asynchronous on `stream`.
+ * Errors: CD_EINVAL (n_leaf < 0, D outside 1..CD_MAX_DIRS, NULL buffers).
+ */
+int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per_nh,
+                        double gamma, float* chi_dev, float* av_dev, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* COLDEN_H */

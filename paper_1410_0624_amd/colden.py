@@ -1,0 +1,171 @@
+"""Python binding of the colden C ABI (include/colden.h): argument marshalling
+only.  Every step of the column-density path runs in the HIP library; torch
+tensors provide device memory and streams.  Missing library = hard error."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcolden.so")
+
+CD_OK, CD_EINVAL, CD_ENOMEM, CD_EDEVICE, CD_EUNSUPPORTED = 0, -1, -2, -3, -4
+CD_DIR_HEALPIX, CD_DIR_PAPER_MN, CD_DIR_AXES6 = 0, 1, 2
+CD_PRECALC73, CD_INSITU = 0, 1
+CD_FP32, CD_BF16X2, CD_FP16X2 = 0, 1, 2
+AV_PER_NH = 1.0 / 1.87e21
+GAMMA = 3.74
+
+EXPORTS = [
+    "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
+    "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
+    "cd_weights_n_dirs", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
+]
+
+
+class ColdenError(RuntimeError):
+    def __init__(self, rc: int, msg: str):
+        super().__init__(f"colden error {rc}: {msg}")
+        self.rc = rc
+
+
+_lib = None
+
+
+def lib():
+    """Load libcolden.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        P, I, I64, D = C.c_void_p, C.c_int, C.c_int64, C.c_double
+        L.cd_last_error.restype = C.c_char_p
+        L.cd_version.restype = I
+        L.cd_directions.argtypes = [I, I, I, P, I, P]
+        L.cd_build_tree.argtypes = [D, I, I, P, P, P, I64, P, P]
+        L.cd_tree_update.argtypes = [P, P, P]
+        L.cd_tree_n_leaf.argtypes = [P, P]
+        L.cd_tree_leaf_coords.argtypes = [P, P, P]
+        L.cd_tree_destroy.argtypes = [P]
+        L.cd_tree_destroy.restype = None
+        L.cd_precompute_weights.argtypes = [P, I, I, I, P, P]
+        L.cd_weights_n_dirs.argtypes = [P, P]
+        L.cd_weights_destroy.argtypes = [P]
+        L.cd_weights_destroy.restype = None
+        L.cd_column_densities.argtypes = [P, P, P, P, D, D, P]
+        L.cd_screening_factor.argtypes = [P, I64, I, D, D, P, P, P]
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != CD_OK:
+        raise ColdenError(rc, lib().cd_last_error().decode())
+
+
+def _np(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def directions(scheme: int, p1: int, p2: int = 0) -> np.ndarray:
+    cap = 4096
+    out = np.zeros((cap, 3))
+    D = C.c_int(0)
+    _check(lib().cd_directions(scheme, p1, p2, _np(out), cap, C.byref(D)))
+    return out[:D.value].copy()
+
+
+def _dev_f32(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Tree:
+    """cd_tree handle.  `leaf_n` is a float32 CUDA tensor in leaf order; for
+    uniform grids the tree keeps reading it until the next update (keep it
+    alive and unchanged)."""
+
+    def __init__(self, tin, leaf_n, stream=None):
+        self._keep_leaf = leaf_n
+        self._par = [np.ascontiguousarray(p, dtype=np.int32) for p in tin.oct_parents]
+        n_octs = np.array([p.shape[0] for p in self._par] + [0], dtype=np.int64)
+        ptrs = (C.c_void_p * (len(self._par) + 1))(*[p.ctypes.data for p in self._par], None)
+        h = C.c_void_p()
+        _check(lib().cd_build_tree(float(tin.box_cm), int(tin.base_level), int(tin.max_level),
+                                   _np(n_octs) if self._par else None, C.cast(ptrs, C.c_void_p),
+                                   _dev_f32(leaf_n), int(leaf_n.numel()), _stream(stream), C.byref(h)))
+        self.h = h
+        self.n_leaf = int(leaf_n.numel())
+
+    def update(self, leaf_n, stream=None):
+        self._keep_leaf = leaf_n
+        _check(lib().cd_tree_update(self.h, _dev_f32(leaf_n), _stream(stream)))
+
+    def leaf_coords(self):
+        lv = np.zeros(self.n_leaf, np.int8)
+        ijk = np.zeros((self.n_leaf, 3), np.int32)
+        _check(lib().cd_tree_leaf_coords(self.h, _np(lv), _np(ijk)))
+        return lv, ijk
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().cd_tree_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Weights:
+    """cd_weights handle (precalculated geometric factors, uploaded once)."""
+
+    def __init__(self, dirs: np.ndarray, mode: int = CD_PRECALC73, precision: int = CD_FP32,
+                 stream=None):
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        h = C.c_void_p()
+        _check(lib().cd_precompute_weights(_np(dirs), dirs.shape[0], mode, precision,
+                                           _stream(stream), C.byref(h)))
+        self.h = h
+        self.D = dirs.shape[0]
+        self.precision = precision
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            lib().cd_weights_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def column_densities(tree: Tree, w: Weights, N, chi=None, av_per_nh: float = AV_PER_NH,
+                     gamma: float = GAMMA, stream=None):
+    """N: float32 CUDA tensor [n_leaf, D]; chi: optional float32 [n_leaf]."""
+    assert tuple(N.shape) == (tree.n_leaf, w.D)
+    chip = _dev_f32(chi) if chi is not None else None
+    _check(lib().cd_column_densities(tree.h, w.h, _dev_f32(N), chip, av_per_nh, gamma, _stream(stream)))
+    return N
+
+
+def screening_factor(N, chi, av=None, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):
+    n, D = N.shape
+    _check(lib().cd_screening_factor(_dev_f32(N), n, D, av_per_nh, gamma, _dev_f32(chi),
+                                     _dev_f32(av) if av is not None else None, _stream(stream)))
+    return chi

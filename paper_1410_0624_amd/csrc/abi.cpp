@@ -1,0 +1,159 @@
+// Error reporting, directions and weight upload of the colden C ABI.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "cd_internal.h"
+
+namespace cd {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+void clear_error() { g_err[0] = 0; }
+
+}  // namespace cd
+
+extern "C" const char* cd_last_error(void) { return cd::g_err; }
+
+extern "C" int cd_version(void) { return 1; }
+
+extern "C" int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D) {
+    cd::clear_error();
+    if (!D || (!out && capacity > 0)) {
+        cd::set_error("cd_directions: NULL output");
+        return CD_EINVAL;
+    }
+    std::vector<std::array<double, 3>> v;
+    int rc = cd::make_directions(scheme, p1, p2, v);
+    if (rc != CD_OK) {
+        cd::set_error("cd_directions: bad scheme %d or parameters (%d, %d)", scheme, p1, p2);
+        return rc;
+    }
+    if ((int)v.size() > capacity) {
+        cd::set_error("cd_directions: capacity %d < %zu directions", capacity, v.size());
+        *D = (int)v.size();
+        return CD_EINVAL;
+    }
+    for (size_t d = 0; d < v.size(); ++d)
+        for (int k = 0; k < 3; ++k) out[3 * d + k] = v[d][k];
+    *D = (int)v.size();
+    return CD_OK;
+}
+
+template <class T>
+static int upload(const std::vector<T>& h, T** dptr, hipStream_t s) {
+    size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+    if (hipMalloc((void**)dptr, bytes) != hipSuccess) {
+        cd::set_error("hipMalloc of %zu bytes failed", bytes);
+        return CD_ENOMEM;
+    }
+    if (!h.empty()) CD_HIP(hipMemcpyAsync(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return CD_OK;
+}
+
+namespace cd {
+int upload_split_banks(cd_weights* w, hipStream_t s);  // split.hip
+void free_split_banks(cd_weights* w);
+}
+
+extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int precision, void* stream,
+                                     cd_weights** out) {
+    cd::clear_error();
+    if (!dirs || !out) {
+        cd::set_error("cd_precompute_weights: NULL argument");
+        return CD_EINVAL;
+    }
+    *out = nullptr;
+    if (D < 1 || D > CD_MAX_DIRS) {
+        cd::set_error("cd_precompute_weights: D = %d outside 1..%d", D, CD_MAX_DIRS);
+        return CD_EINVAL;
+    }
+    if (mode != CD_PRECALC73 && mode != CD_INSITU) {
+        cd::set_error("cd_precompute_weights: unknown mode %d", mode);
+        return CD_EINVAL;
+    }
+    if (mode == CD_INSITU) {
+        cd::set_error("cd_precompute_weights: in-situ reference points are not provided by this build");
+        return CD_EUNSUPPORTED;
+    }
+    if (precision != CD_FP32 && precision != CD_BF16X2 && precision != CD_FP16X2) {
+        cd::set_error("cd_precompute_weights: unknown precision %d", precision);
+        return CD_EINVAL;
+    }
+    std::vector<std::array<double, 3>> u(D);
+    for (int d = 0; d < D; ++d) {
+        double n2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            u[d][k] = dirs[3 * d + k];
+            if (!std::isfinite(u[d][k])) {
+                cd::set_error("cd_precompute_weights: direction %d is not finite", d);
+                return CD_EINVAL;
+            }
+            n2 += u[d][k] * u[d][k];
+        }
+        if (std::fabs(std::sqrt(n2) - 1.0) > 1e-9) {
+            cd::set_error("cd_precompute_weights: direction %d is not a unit vector", d);
+            return CD_EINVAL;
+        }
+    }
+    cd_weights* w = new cd_weights();
+    w->D = D;
+    w->mode = mode;
+    w->precision = precision;
+    cd::build_tables(u, w->host);
+    hipStream_t s = (hipStream_t)stream;
+    int rc = CD_OK;
+    for (int k = 1; k < cd::kKinds && rc == CD_OK; ++k) {
+        w->ncombo[k] = w->host.ncombo[k];
+        w->len[k] = w->host.len[k];
+        std::vector<float> wf(w->host.w[k].begin(), w->host.w[k].end());
+        rc = upload(w->host.off[k], &w->off[k], s);
+        if (rc == CD_OK) rc = upload(wf, &w->w[k], s);
+        if (rc == CD_OK) rc = upload(w->host.cnt[k], &w->cnt[k], s);
+    }
+    if (rc == CD_OK) {
+        std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
+        rc = upload(kf, &w->kloc, s);
+    }
+    if (rc == CD_OK && precision != CD_FP32) rc = cd::upload_split_banks(w, s);
+    // host vectors must stay alive until the copies are done
+    if (rc == CD_OK && hipStreamSynchronize(s) != hipSuccess) {
+        cd::set_error("cd_precompute_weights: upload failed");
+        rc = CD_EDEVICE;
+    }
+    if (rc != CD_OK) {
+        cd_weights_destroy(w);
+        return rc;
+    }
+    *out = w;
+    return CD_OK;
+}
+
+extern "C" int cd_weights_n_dirs(const cd_weights* w, int* D) {
+    if (!w || !D) {
+        cd::set_error("cd_weights_n_dirs: NULL argument");
+        return CD_EINVAL;
+    }
+    *D = w->D;
+    return CD_OK;
+}
+
+extern "C" void cd_weights_destroy(cd_weights* w) {
+    if (!w) return;
+    for (int k = 0; k < cd::kKinds; ++k) {
+        if (w->off[k]) (void)hipFree(w->off[k]);
+        if (w->w[k]) (void)hipFree(w->w[k]);
+        if (w->cnt[k]) (void)hipFree(w->cnt[k]);
+    }
+    if (w->kloc) (void)hipFree(w->kloc);
+    cd::free_split_banks(w);
+    delete w;
+}

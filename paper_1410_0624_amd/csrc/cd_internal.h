@@ -1,0 +1,125 @@
+// Internal declarations of the colden library (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "colden.h"
+
+namespace cd {
+
+// ----------------------------------------------------------------- errors --
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define CD_HIP(expr)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::cd::set_error("%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                            __FILE__, __LINE__);                                  \
+            return CD_EDEVICE;                                                    \
+        }                                                                         \
+    } while (0)
+
+// Zero halo around every padded pyramid level: shells reach at most 5 cells
+// beyond the level-l ancestor (the 11^3 standard cube of Sect. 3.3).
+constexpr int kHalo = 5;
+
+// Shell kinds by dl = l0 - l (Sect. 3.2-3.3):
+//   1: dl = 1, reference at the centre of the level-l ancestor A_l
+//   2: dl = 2, reference at the centre of A_{l+1} (8 positions)
+//   3: dl = 3, reference at the centre of A_{l+2} (64 positions)
+//   4: dl >= 4, reference at the centre of A_{l+2}, inner limit in one of
+//      three per-axis states
+constexpr int kKinds = 5;  // index 1..4 used
+
+// Per-axis shape of a shell relative to the level-l ancestor (in level-l
+// cells): inner [ilo, ihi], outer [olo, ohi], and the reference coordinate.
+struct AxisShape {
+    int ilo, ihi, olo, ohi;
+    double ref;
+};
+
+// Per-axis shapes of each kind, in the order of the per-axis codes:
+//   kind 1: code = p                         (p = parity of A_l)
+//   kind 2: code = 2 p + b1                  (b1 = parity of A_{l+1})
+//   kind 3: code = 4 p + 2 b1 + b2           (b2 = parity of A_{l+2})
+//   kind 4: code = 6 p + s                   (s = inner-state code, below)
+// Inner-state codes of kind 4 (state, b1, b2):
+//   0 ([-2,1],0,0) 1 ([-1,2],1,1) 2 ([-2,2],0,0) 3 ([-2,2],0,1)
+//   4 ([-2,2],1,0) 5 ([-2,2],1,1)
+std::vector<AxisShape> axis_shapes(int kind);
+int axis_codes(int kind);  // 2, 4, 8, 12
+// Next inner-state code one level coarser, given the parity p of A_l.
+int next_state_code(int s, int p);
+// Inner-state code at dl = 4 from (b1, b2).
+int state_code_dl4(int b1, int b2);
+
+// Direction families.
+int make_directions(int scheme, int p1, int p2, std::vector<std::array<double, 3>>& out);
+
+// Chord of the half-line o + t u (t >= 0) through the box [lo, hi].
+double chord(const double lo[3], const double hi[3], const double o[3], const double u[3]);
+
+// Host weight tables for one direction set.
+struct HostTables {
+    int D = 0;
+    int ncombo[kKinds] = {0};
+    int len[kKinds] = {0};                 // padded entries per (combo, d)
+    std::vector<int32_t> off[kKinds];      // [ncombo][D][len] packed (ox,oy,oz) int8x3
+    std::vector<double> w[kKinds];         // [ncombo][D][len] chord in cell widths
+    std::vector<int32_t> cnt[kKinds];      // [ncombo][D] true entry counts
+    std::vector<double> kloc;              // [8 target octant][8 oct cell][D]
+};
+int build_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
+
+inline int32_t pack_off(int ox, int oy, int oz) {
+    return (int32_t)((uint32_t)(ox & 0xff) | ((uint32_t)(oy & 0xff) << 8) |
+                     ((uint32_t)(oz & 0xff) << 16));
+}
+
+}  // namespace cd
+
+// ----------------------------------------------------------------- handles --
+struct cd_weights {
+    int D = 0;
+    int mode = CD_PRECALC73;
+    int precision = CD_FP32;
+    int ncombo[cd::kKinds] = {0};
+    int len[cd::kKinds] = {0};
+    int32_t* off[cd::kKinds] = {nullptr};   // device
+    float* w[cd::kKinds] = {nullptr};       // device, FP32 weights
+    int32_t* cnt[cd::kKinds] = {nullptr};   // device
+    float* kloc = nullptr;                  // device [8][8][D]
+    // split-precision banks (hi/lo) for the MFMA sweep
+    void* split = nullptr;
+    cd::HostTables host;
+};
+
+struct cd_tree {
+    double box_cm = 0;
+    int base = 0, lmax = 0;
+    int64_t n_leaf = 0;
+    bool uniform = true;
+    // dense padded pyramid levels 0..min(base, lmax-1); side 2^l + 2*kHalo
+    float* lev[CD_MAX_LEVEL + 1] = {nullptr};
+    const float* leaf = nullptr;  // uniform grids: the caller's leaf array (row-major)
+    // AMR part (levels base+1 .. lmax)
+    int64_t n_octs[CD_MAX_LEVEL + 1] = {0};
+    int32_t* d_octidx[CD_MAX_LEVEL + 1] = {nullptr};  // [l] over the level-(l-1) grid
+    int32_t* d_octpar[CD_MAX_LEVEL + 1] = {nullptr};  // [l] n_octs * 3
+    float* d_octden[CD_MAX_LEVEL + 1] = {nullptr};    // [l] n_octs * 8
+    int64_t* d_octleaf[CD_MAX_LEVEL + 1] = {nullptr}; // [l] n_octs * 8 leaf index or -1
+    int64_t* d_baseleaf = nullptr;                    // base cells: leaf index or -1
+    std::vector<std::vector<int32_t>> h_octpar;        // host copy of the structure
+    // coarse accumulated external columns (per level, per inner-state code)
+    float* q[CD_MAX_LEVEL + 1] = {nullptr};
+    size_t q_bytes[CD_MAX_LEVEL + 1] = {0};
+    int q_D = 0;
+    std::vector<void*> scratch;  // other device allocations to free
+};

@@ -1,0 +1,321 @@
+// FP32 column-density sweep on a uniform grid (Sect. 3.2-3.3, Eqs. 6-9) and
+// the screening epilogue (Eq. 5).
+//
+// For a target at level L in the oct whose parent cell is A (level L-1):
+//   N = internal+local(target) + sum_{l < L} E_l(oct),
+//   E_l = dx_l sum_{i in shell C_l} n_l(i) K(i - A_l, d; configuration).
+// The shells at dl = 1, 2, 3 are unique to each oct and are summed in the
+// per-oct kernel.  From dl = 4 on a shell depends only on the ancestor A_l,
+// the per-axis inner-limit state and the two octant bits of the reference
+// point, so the sum over all levels l <= L-4 is accumulated top-down once per
+// (level-(L-4) cell, state code) by the coarse kernels and read by each oct.
+#include <cmath>
+
+#include "cd_internal.h"
+#include "tree_amr.h"
+
+namespace cd {
+
+struct KindTable {
+    const int32_t* off;
+    const float* w;
+    int len;
+};
+
+struct FineArgs {
+    const float* leaf;
+    int L;
+    const float* lev[4];  // padded levels L-1, L-2, L-3 at index 1..3 (nullptr if absent)
+    float dx[4];          // their cell size (cm)
+    float dxL;            // leaf cell size (cm)
+    const float* q4;      // [8^(L-4)][64][D] or nullptr
+    KindTable kt[4];      // kinds 1..3
+    const float* kloc;    // [8][8][D]
+    int D;
+    float* N;
+    float* chi;
+    float chi_scale;      // gamma * av_per_nh
+};
+
+__device__ __forceinline__ int sext8(int v) { return (int)(int8_t)(v & 0xff); }
+
+// Sum of one shell for DC directions starting at d0.
+template <int DC>
+__device__ __forceinline__ void shell_sum(float (&acc)[DC], const float* __restrict__ lev, int l, int cx,
+                                          int cy, int cz, int combo, const KindTable& kt, int D, int d0,
+                                          float dx) {
+    const int S = (1 << l) + 2 * kHalo;
+    const float* base = lev + ((int64_t)(cz + kHalo) * S + (cy + kHalo)) * S + (cx + kHalo);
+#pragma unroll
+    for (int j = 0; j < DC; ++j) {
+        const int d = d0 + j;
+        if (d < D) {
+            const int64_t row = ((int64_t)combo * D + d) * kt.len;
+            float s = 0.f;
+            for (int e = 0; e < kt.len; ++e) {
+                const int pk = kt.off[row + e];
+                const int ox = sext8(pk), oy = sext8(pk >> 8), oz = sext8(pk >> 16);
+                s = fmaf(kt.w[row + e], base[((int64_t)oz * S + oy) * S + ox], s);
+            }
+            acc[j] = fmaf(dx, s, acc[j]);
+        }
+    }
+}
+
+template <int DC>
+__global__ __launch_bounds__(256) void k_fine_uniform(const FineArgs a) {
+    const int L1 = a.L - 1;
+    const int64_t n1 = (int64_t)1 << L1;
+    const int64_t oct = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (oct >= n1 * n1 * n1) return;
+    const int ax = (int)(oct & (n1 - 1)), ay = (int)((oct >> L1) & (n1 - 1)), az = (int)(oct >> (2 * L1));
+    const int64_t n = 2 * n1;
+    float ln[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        ln[s] = a.leaf[((int64_t)(2 * az + (s >> 2)) * n + (2 * ay + ((s >> 1) & 1))) * n + 2 * ax + (s & 1)];
+    float chis[8];
+#pragma unroll
+    for (int o = 0; o < 8; ++o) chis[o] = 0.f;
+
+    // configuration codes of the three per-oct shells (see axis_shapes)
+    const int c1 = (ax & 1) + 2 * (ay & 1) + 4 * (az & 1);
+    const int c2 = (ax & 3) + 4 * (ay & 3) + 16 * (az & 3);
+    const int c3 = (ax & 7) + 8 * (ay & 7) + 64 * (az & 7);
+    const int c4 = ((ax >> 1) & 3) + 4 * ((ay >> 1) & 3) + 16 * ((az >> 1) & 3);
+    const int64_t q4cell = a.q4 ? ((((int64_t)(az >> 3) << (L1 - 3)) + (ay >> 3)) << (L1 - 3)) + (ax >> 3) : 0;
+
+    for (int d0 = 0; d0 < a.D; d0 += DC) {
+        float acc[DC];
+#pragma unroll
+        for (int j = 0; j < DC; ++j) acc[j] = 0.f;
+        if (a.lev[1]) shell_sum<DC>(acc, a.lev[1], a.L - 1, ax, ay, az, c1, a.kt[1], a.D, d0, a.dx[1]);
+        if (a.lev[2]) shell_sum<DC>(acc, a.lev[2], a.L - 2, ax >> 1, ay >> 1, az >> 1, c2, a.kt[2], a.D, d0, a.dx[2]);
+        if (a.lev[3]) shell_sum<DC>(acc, a.lev[3], a.L - 3, ax >> 2, ay >> 2, az >> 2, c3, a.kt[3], a.D, d0, a.dx[3]);
+        if (a.q4) {
+            const float* q = a.q4 + (q4cell * 64 + c4) * a.D;
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+                if (d0 + j < a.D) acc[j] += q[d0 + j];
+        }
+        // internal + local for the 8 targets of the oct
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int64_t T = ((int64_t)(2 * az + (o >> 2)) * n + (2 * ay + ((o >> 1) & 1))) * n + 2 * ax + (o & 1);
+            float* out = a.N + T * a.D;
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                const int d = d0 + j;
+                if (d < a.D) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(o * 8 + sb) * a.D + d], s);
+                    const float v = fmaf(a.dxL, s, acc[j]);
+                    out[d] = v;
+                    chis[o] += expf(-a.chi_scale * v);
+                }
+            }
+        }
+    }
+    if (a.chi) {
+        const float invD = 1.f / (float)a.D;
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            const int64_t T = ((int64_t)(2 * az + (o >> 2)) * n + (2 * ay + ((o >> 1) & 1))) * n + 2 * ax + (o & 1);
+            a.chi[T] = chis[o] * invD;
+        }
+    }
+}
+
+// ----------------------------------------------------------- coarse levels --
+struct CoarseArgs {
+    const float* lev;   // padded level l
+    int l;
+    float dx;
+    const float* qprev; // [8^(l-1)][216][D] or nullptr
+    float* q;           // [8^l][ncodes][D]
+    int compact;        // 1: level L-4, codes = 4 per axis (bits of the dl = 3, 2 ancestors)
+    KindTable kt;       // kind 4
+    int D;
+    int8_t next[6][2];
+    int8_t dl4[4];
+};
+
+__global__ __launch_bounds__(256) void k_coarse_q(const CoarseArgs a) {
+    const int ncodes = a.compact ? 64 : 216;
+    const int64_t n = (int64_t)1 << a.l;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n * n * ncodes) return;
+    const int64_t cell = idx / ncodes;
+    const int code = (int)(idx - cell * ncodes);
+    const int c[3] = {(int)(cell & (n - 1)), (int)((cell >> a.l) & (n - 1)), (int)(cell >> (2 * a.l))};
+    int st[3];
+    if (a.compact) {
+        st[0] = a.dl4[code & 3];
+        st[1] = a.dl4[(code >> 2) & 3];
+        st[2] = a.dl4[(code >> 4) & 3];
+    } else {
+        st[0] = code % 6;
+        st[1] = (code / 6) % 6;
+        st[2] = code / 36;
+    }
+    int combo = 0, pcode = 0, mul = 1, pmul = 1;
+    for (int k = 0; k < 3; ++k) {
+        const int p = c[k] & 1;
+        combo += (6 * p + st[k]) * mul;
+        pcode += a.next[st[k]][p] * pmul;
+        mul *= 12;
+        pmul *= 6;
+    }
+    const int S = (int)n + 2 * kHalo;
+    const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
+    const float* prev = nullptr;
+    if (a.qprev) {
+        const int64_t np = n >> 1;
+        const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
+        prev = a.qprev + (pcell * 216 + pcode) * a.D;
+    }
+    float* out = a.q + (cell * ncodes + code) * a.D;
+    for (int d = 0; d < a.D; ++d) {
+        const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
+        float s = 0.f;
+        for (int e = 0; e < a.kt.len; ++e) {
+            const int pk = a.kt.off[row + e];
+            s = fmaf(a.kt.w[row + e], base[((int64_t)sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk)], s);
+        }
+        out[d] = fmaf(a.dx, s, prev ? prev[d] : 0.f);
+    }
+}
+
+// -------------------------------------------------------------- screening --
+__global__ __launch_bounds__(256) void k_screening(const float* __restrict__ N, int64_t n, int D, float scale,
+                                                   float avs, float* __restrict__ chi, float* __restrict__ av) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float* row = N + i * D;
+    float s = 0.f;
+    for (int d = 0; d < D; ++d) {
+        const float v = row[d];
+        s += expf(-scale * v);
+        if (av) av[i * D + d] = v * avs;
+    }
+    chi[i] = s / (float)D;
+}
+
+// --------------------------------------------------------------- drivers --
+static int ensure_q(cd_tree* t, int D) {
+    const int L = t->lmax;
+    if (t->q_D == D) return CD_OK;
+    for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
+        if (t->q[l]) (void)hipFree(t->q[l]);
+        t->q[l] = nullptr;
+        t->q_bytes[l] = 0;
+    }
+    t->q_D = 0;
+    for (int l = 2; l <= L - 4; ++l) {
+        const int ncodes = (l == L - 4) ? 64 : 216;
+        const size_t bytes = ((size_t)1 << (3 * l)) * ncodes * D * sizeof(float);
+        if (hipMalloc((void**)&t->q[l], bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes (coarse columns, level %d) failed", bytes, l);
+            return CD_ENOMEM;
+        }
+        t->q_bytes[l] = bytes;
+    }
+    t->q_D = D;
+    return CD_OK;
+}
+
+template <int DC>
+static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
+    k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
+}
+
+int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+    const int L = t->lmax;
+    const int D = w->D;
+    int rc = ensure_q(t, D);
+    if (rc != CD_OK) return rc;
+    // coarse levels, top-down
+    for (int l = 2; l <= L - 4; ++l) {
+        CoarseArgs c{};
+        c.lev = t->lev[l];
+        c.l = l;
+        c.dx = (float)(t->box_cm * std::ldexp(1.0, -l));
+        c.qprev = (l > 2) ? t->q[l - 1] : nullptr;
+        c.q = t->q[l];
+        c.compact = (l == L - 4);
+        c.kt = {w->off[4], w->w[4], w->len[4]};
+        c.D = D;
+        for (int sc = 0; sc < 6; ++sc)
+            for (int p = 0; p < 2; ++p) c.next[sc][p] = (int8_t)next_state_code(sc, p);
+        for (int q = 0; q < 4; ++q) c.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
+        const int64_t nthreads = ((int64_t)1 << (3 * l)) * (c.compact ? 64 : 216);
+        k_coarse_q<<<(unsigned)((nthreads + 255) / 256), 256, 0, s>>>(c);
+    }
+    if (L >= 1) {
+        FineArgs a{};
+        a.leaf = t->leaf;
+        a.L = L;
+        for (int k = 1; k <= 3; ++k) {
+            const int l = L - k;
+            a.lev[k] = (l >= 0) ? t->lev[l] : nullptr;
+            a.dx[k] = (l >= 0) ? (float)(t->box_cm * std::ldexp(1.0, -l)) : 0.f;
+            a.kt[k] = {w->off[k], w->w[k], w->len[k]};
+        }
+        a.dxL = (float)(t->box_cm * std::ldexp(1.0, -L));
+        a.q4 = (L - 4 >= 2) ? t->q[L - 4] : nullptr;
+        a.kloc = w->kloc;
+        a.D = D;
+        a.N = N;
+        a.chi = chi;
+        a.chi_scale = chi_scale;
+        const int64_t n_oct = (int64_t)1 << (3 * (L - 1));
+        if (D <= 12) launch_fine<12>(a, n_oct, s);
+        else if (D <= 16) launch_fine<16>(a, n_oct, s);
+        else if (D <= 24) launch_fine<24>(a, n_oct, s);
+        else launch_fine<48>(a, n_oct, s);
+    } else {
+        set_error("cd_column_densities: a single-cell tree has no oct");
+        return CD_EINVAL;
+    }
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+}  // namespace cd
+
+extern "C" int cd_column_densities(cd_tree* t, const cd_weights* w, float* N_dev, float* chi_dev,
+                                   double av_per_nh, double gamma, void* stream) {
+    cd::clear_error();
+    if (!t || !w || !N_dev) {
+        cd::set_error("cd_column_densities: NULL argument");
+        return CD_EINVAL;
+    }
+    if (chi_dev && !(std::isfinite(av_per_nh) && std::isfinite(gamma))) {
+        cd::set_error("cd_column_densities: non-finite screening parameters");
+        return CD_EINVAL;
+    }
+    const float scale = (float)(gamma * av_per_nh);
+    hipStream_t s = (hipStream_t)stream;
+    if (w->precision != CD_FP32) {
+        cd::set_error("cd_column_densities: split-precision sweep not provided by this build");
+        return CD_EUNSUPPORTED;
+    }
+    if (t->uniform) return cd::uniform_columns(t, w, N_dev, chi_dev, scale, s);
+    return cd::amr_columns(t, w, N_dev, chi_dev, scale, s);
+}
+
+extern "C" int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per_nh, double gamma,
+                                   float* chi_dev, float* av_dev, void* stream) {
+    cd::clear_error();
+    if (n_leaf < 0 || D < 1 || D > CD_MAX_DIRS || (n_leaf > 0 && (!N_dev || !chi_dev))) {
+        cd::set_error("cd_screening_factor: bad arguments (n_leaf %lld, D %d)", (long long)n_leaf, D);
+        return CD_EINVAL;
+    }
+    if (n_leaf == 0) return CD_OK;
+    hipStream_t s = (hipStream_t)stream;
+    cd::k_screening<<<(unsigned)((n_leaf + 255) / 256), 256, 0, s>>>(N_dev, n_leaf, D, (float)(gamma * av_per_nh),
+                                                                    (float)av_per_nh, chi_dev, av_dev);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}

@@ -1,0 +1,178 @@
+// Tree construction: the pyramid of coarse densities (Sect. 3: a refined cell
+// holds the mean of its 8 children) stored as zero-padded dense levels.
+#include <cstring>
+
+#include "cd_internal.h"
+#include "tree_amr.h"
+
+namespace cd {
+
+static inline int64_t padded_side(int l) { return ((int64_t)1 << l) + 2 * kHalo; }
+static inline int64_t padded_cells(int l) {
+    int64_t s = padded_side(l);
+    return s * s * s;
+}
+
+// Level L-1 from the leaves of a uniform 2^L grid (row-major, x fastest).
+__global__ void k_pyramid_from_leaves(const float* __restrict__ leaf, int L, float* __restrict__ out) {
+    const int64_t n1 = (int64_t)1 << (L - 1);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n1 * n1 * n1) return;
+    const int64_t i = idx & (n1 - 1), j = (idx >> (L - 1)) & (n1 - 1), k = idx >> (2 * (L - 1));
+    const int64_t n = 2 * n1;
+    const float* p = leaf + ((2 * k) * n + 2 * j) * n + 2 * i;
+    float2 a = *reinterpret_cast<const float2*>(p);
+    float2 b = *reinterpret_cast<const float2*>(p + n);
+    float2 c = *reinterpret_cast<const float2*>(p + n * n);
+    float2 d = *reinterpret_cast<const float2*>(p + n * n + n);
+    const float s = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
+    const int64_t S = n1 + 2 * kHalo;
+    out[((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)] = 0.125f * s;
+}
+
+// Level l from padded level l+1.
+__global__ void k_pyramid_level(const float* __restrict__ in, int l, float* __restrict__ out) {
+    const int64_t n = (int64_t)1 << l;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n * n) return;
+    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
+    const int64_t Si = 2 * n + 2 * kHalo, So = n + 2 * kHalo;
+    const float* p = in + ((2 * k + kHalo) * Si + (2 * j + kHalo)) * Si + (2 * i + kHalo);
+    const float s = ((p[0] + p[1]) + (p[Si] + p[Si + 1])) +
+                    ((p[Si * Si] + p[Si * Si + 1]) + (p[Si * Si + Si] + p[Si * Si + Si + 1]));
+    out[((k + kHalo) * So + (j + kHalo)) * So + (i + kHalo)] = 0.125f * s;
+}
+
+static int launch_blocks(int64_t n) { return (int)((n + 255) / 256); }
+
+// Rebuild the dense padded levels below `top` (the finest dense level
+// already filled, or the leaves for a uniform grid).
+int build_uniform_pyramid(cd_tree* t, hipStream_t s) {
+    const int L = t->lmax;
+    if (L >= 1) {
+        const int64_t n1 = (int64_t)1 << (L - 1);
+        k_pyramid_from_leaves<<<launch_blocks(n1 * n1 * n1), 256, 0, s>>>(t->leaf, L, t->lev[L - 1]);
+        for (int l = L - 2; l >= 0; --l) {
+            const int64_t n = (int64_t)1 << l;
+            k_pyramid_level<<<launch_blocks(n * n * n), 256, 0, s>>>(t->lev[l + 1], l, t->lev[l]);
+        }
+    }
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+int alloc_dense_levels(cd_tree* t, int top, hipStream_t s) {
+    for (int l = 0; l <= top; ++l) {
+        const size_t bytes = (size_t)padded_cells(l) * sizeof(float);
+        if (hipMalloc((void**)&t->lev[l], bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes (pyramid level %d) failed", bytes, l);
+            return CD_ENOMEM;
+        }
+        CD_HIP(hipMemsetAsync(t->lev[l], 0, bytes, s));
+    }
+    return CD_OK;
+}
+
+}  // namespace cd
+
+extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const int64_t* n_octs,
+                             const int32_t* const* oct_parents, const float* leaf_n_dev, int64_t n_leaf,
+                             void* stream, cd_tree** out) {
+    cd::clear_error();
+    if (!out || !leaf_n_dev) {
+        cd::set_error("cd_build_tree: NULL argument");
+        return CD_EINVAL;
+    }
+    *out = nullptr;
+    if (!(box_cm > 0) || base_level < 0 || max_level < base_level || max_level > CD_MAX_LEVEL) {
+        cd::set_error("cd_build_tree: bad box or levels (box %g, base %d, max %d)", box_cm, base_level,
+                      max_level);
+        return CD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    cd_tree* t = new cd_tree();
+    t->box_cm = box_cm;
+    t->base = base_level;
+    t->lmax = max_level;
+    int rc;
+    if (base_level == max_level) {
+        const int L = max_level;
+        if (n_leaf != ((int64_t)1 << (3 * L))) {
+            cd::set_error("cd_build_tree: uniform 2^%d grid needs %lld leaves, got %lld", L,
+                          (long long)((int64_t)1 << (3 * L)), (long long)n_leaf);
+            delete t;
+            return CD_EINVAL;
+        }
+        t->uniform = true;
+        t->n_leaf = n_leaf;
+        t->leaf = leaf_n_dev;
+        rc = cd::alloc_dense_levels(t, L - 1, s);
+        if (rc == CD_OK) rc = cd::build_uniform_pyramid(t, s);
+    } else {
+        t->uniform = false;
+        rc = cd::amr_build(t, n_octs, oct_parents, leaf_n_dev, n_leaf, s);
+    }
+    if (rc != CD_OK) {
+        cd_tree_destroy(t);
+        return rc;
+    }
+    *out = t;
+    return CD_OK;
+}
+
+extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, void* stream) {
+    cd::clear_error();
+    if (!t || !leaf_n_dev) {
+        cd::set_error("cd_tree_update: NULL argument");
+        return CD_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (t->uniform) {
+        t->leaf = leaf_n_dev;
+        return cd::build_uniform_pyramid(t, s);
+    }
+    return cd::amr_update(t, leaf_n_dev, s);
+}
+
+extern "C" int cd_tree_n_leaf(const cd_tree* t, int64_t* n_leaf) {
+    if (!t || !n_leaf) {
+        cd::set_error("cd_tree_n_leaf: NULL argument");
+        return CD_EINVAL;
+    }
+    *n_leaf = t->n_leaf;
+    return CD_OK;
+}
+
+extern "C" int cd_tree_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
+    if (!t || !level || !ijk) {
+        cd::set_error("cd_tree_leaf_coords: NULL argument");
+        return CD_EINVAL;
+    }
+    if (t->uniform) {
+        const int L = t->lmax;
+        const int64_t n = (int64_t)1 << L;
+        for (int64_t q = 0; q < t->n_leaf; ++q) {
+            level[q] = (int8_t)L;
+            ijk[3 * q] = (int32_t)(q & (n - 1));
+            ijk[3 * q + 1] = (int32_t)((q >> L) & (n - 1));
+            ijk[3 * q + 2] = (int32_t)(q >> (2 * L));
+        }
+        return CD_OK;
+    }
+    return cd::amr_leaf_coords(t, level, ijk);
+}
+
+extern "C" void cd_tree_destroy(cd_tree* t) {
+    if (!t) return;
+    for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
+        if (t->lev[l]) (void)hipFree(t->lev[l]);
+        if (t->d_octidx[l]) (void)hipFree(t->d_octidx[l]);
+        if (t->d_octpar[l]) (void)hipFree(t->d_octpar[l]);
+        if (t->d_octden[l]) (void)hipFree(t->d_octden[l]);
+        if (t->d_octleaf[l]) (void)hipFree(t->d_octleaf[l]);
+        if (t->q[l]) (void)hipFree(t->q[l]);
+    }
+    if (t->d_baseleaf) (void)hipFree(t->d_baseleaf);
+    for (void* p : t->scratch) (void)hipFree(p);
+    delete t;
+}

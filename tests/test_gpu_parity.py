@@ -1,0 +1,163 @@
+"""Parity of the HIP path with the FP64 CPU oracle (MI355X).  Every call goes
+through the C ABI; the oracle is the FP64 plain implementation in oracle/.
+Gate for the FP32 sweep: <= 1e-5 relative per output N_H(t, d)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_0624_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+REL_FP32 = 1e-5
+
+
+@pytest.fixture(scope="module")
+def colden():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0624_amd import colden as c
+    c.lib()
+    return c
+
+
+def _run(colden, tin, dirs, chi=True, precision=0):
+    dev = torch.device("cuda:0")
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    tree = colden.Tree(tin, leaf)
+    w = colden.Weights(dirs, precision=precision)
+    N = torch.full((tin.n_leaf, dirs.shape[0]), float("nan"), dtype=torch.float32, device=dev)
+    c = torch.full((tin.n_leaf,), float("nan"), dtype=torch.float32, device=dev) if chi else None
+    colden.column_densities(tree, w, N, c)
+    torch.cuda.synchronize()
+    return N.cpu().numpy().astype(np.float64), (c.cpu().numpy().astype(np.float64) if chi else None)
+
+
+def _rel(a, b):
+    return np.abs(a - b) / np.maximum(np.abs(b), 1e-300)
+
+
+def test_library_directions_match_oracle(colden):
+    for args, ref in [((0, 1, 0), oracle.dirs_healpix(1)), ((0, 2, 0), oracle.dirs_healpix(2)),
+                      ((1, 3, 4), oracle.dirs_mn(3, 4)), ((1, 5, 8), oracle.dirs_mn(5, 8)),
+                      ((1, 7, 12), oracle.dirs_mn(7, 12)), ((2, 0, 0), oracle.dirs_axes6())]:
+        np.testing.assert_allclose(colden.directions(*args), ref, atol=1e-15)
+
+
+@pytest.mark.parametrize("L", [1, 2, 3, 4, 5, 6, 7])
+def test_uniform_parity_all_leaves(colden, L):
+    """Every output of grids from one oct (2^3) to 128^3, D = 12: spans the
+    per-oct shells (dl = 1..3), the first coarse table (L = 6) and the
+    216-code coarse recursion (L = 7)."""
+    tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=10 + L)
+    dirs = oracle.dirs_healpix(1)
+    N, chi = _run(colden, tin, dirs)
+    tr = oracle.Tree(tin)
+    if tin.n_leaf <= 300000:
+        tg = np.arange(tin.n_leaf)
+    else:
+        tg = np.random.default_rng(L).choice(tin.n_leaf, 60000, replace=False)
+    ref = tr.columns(dirs, tg)
+    rel = _rel(N[tg], ref)
+    print(f"L={L}: max rel {rel.max():.3e} mean {rel.mean():.3e}")
+    assert np.isfinite(N).all()
+    assert rel.max() <= REL_FP32
+    chi_ref = oracle.screening(ref)
+    assert np.abs(chi[tg] - chi_ref).max() <= 2e-6
+
+
+@pytest.mark.parametrize("name,dirs", [
+    ("healpix2", oracle.dirs_healpix(2)), ("axes6", oracle.dirs_axes6()),
+    ("mn3x4", oracle.dirs_mn(3, 4)), ("mn5x8", oracle.dirs_mn(5, 8)), ("mn7x12", oracle.dirs_mn(7, 12))])
+def test_direction_families_parity(colden, name, dirs):
+    tin = synth.workload_uniform(6, sigma=1.5, mean=10.0, seed=3)
+    N, chi = _run(colden, tin, dirs)
+    ref = oracle.Tree(tin).columns(dirs)
+    rel = _rel(N, ref)
+    print(f"{name} D={dirs.shape[0]}: max rel {rel.max():.3e}")
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
+
+
+def test_c2_256_sampled_parity(colden):
+    """The 256^3 workload (16.8M leaves, 9-level pyramid, D = 12), in the
+    launch configuration the benchmark times: 40k sampled leaves against the
+    oracle, and every output finite and positive."""
+    tin = synth.workload_uniform(8, sigma=1.5, mean=10.0, seed=2)
+    dirs = oracle.dirs_healpix(1)
+    N, chi = _run(colden, tin, dirs)
+    assert np.isfinite(N).all() and (N > 0).all()
+    assert np.isfinite(chi).all() and (chi > 0).all() and (chi <= 1).all()
+    tg = np.random.default_rng(0).choice(tin.n_leaf, 40000, replace=False)
+    tg = np.concatenate([tg, [0, tin.n_leaf - 1, 255, 256 * 255]])
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    rel = _rel(N[tg], ref)
+    print(f"C2 sampled: max rel {rel.max():.3e} mean {rel.mean():.3e}")
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
+
+
+def test_uniform_density_closed_form_on_gpu(colden):
+    n0 = 4.0
+    L = 5
+    n = 1 << L
+    tin = synth.uniform_tree(np.full((n, n, n), n0), box_cm=synth.PC_CM * 10)
+    dirs = oracle.dirs_healpix(2)
+    N, _ = _run(colden, tin, dirs, chi=False)
+    ref = oracle.Tree(tin).columns(dirs)
+    assert _rel(N, ref).max() <= REL_FP32
+
+
+def test_tree_update_recomputes_pyramid(colden):
+    dev = torch.device("cuda:0")
+    t1 = synth.workload_uniform(6, seed=31)
+    t2 = synth.workload_uniform(6, seed=32)
+    dirs = oracle.dirs_healpix(1)
+    l1 = torch.from_numpy(t1.leaf_n).to(dev)
+    l2 = torch.from_numpy(t2.leaf_n).to(dev)
+    tree = colden.Tree(t1, l1)
+    w = colden.Weights(dirs)
+    N = torch.empty((t1.n_leaf, 12), dtype=torch.float32, device=dev)
+    colden.column_densities(tree, w, N)
+    tree.update(l2)
+    colden.column_densities(tree, w, N)
+    torch.cuda.synchronize()
+    ref = oracle.Tree(t2).columns(dirs)
+    assert _rel(N.cpu().numpy().astype(np.float64), ref).max() <= REL_FP32
+
+
+def test_screening_factor_kernel(colden):
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4)
+    N = (10 ** rng.uniform(18, 23, size=(5000, 12))).astype(np.float32)
+    Nt = torch.from_numpy(N).to(dev)
+    chi = torch.empty(5000, dtype=torch.float32, device=dev)
+    av = torch.empty((5000, 12), dtype=torch.float32, device=dev)
+    colden.screening_factor(Nt, chi, av)
+    torch.cuda.synchronize()
+    ref = oracle.screening(N.astype(np.float64))
+    assert np.abs(chi.cpu().numpy() - ref).max() <= 2e-6
+    np.testing.assert_allclose(av.cpu().numpy(), N.astype(np.float64) / 1.87e21, rtol=1e-6)
+    # empty input is a no-op
+    colden.screening_factor(Nt[:0], chi[:0])
+
+
+def test_error_paths(colden):
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Weights(np.zeros((0, 3)))
+    assert e.value.rc == colden.CD_EINVAL
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Weights(np.array([[1.0, 1.0, 0.0]]))
+    assert e.value.rc == colden.CD_EINVAL
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Weights(oracle.dirs_healpix(1), mode=colden.CD_INSITU)
+    assert e.value.rc == colden.CD_EUNSUPPORTED
+    with pytest.raises(colden.ColdenError):
+        colden.directions(7, 1, 1)
+    dev = torch.device("cuda:0")
+    tin = synth.workload_uniform(3, seed=1)
+    leaf = torch.from_numpy(tin.leaf_n[:-1].copy()).to(dev)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Tree(tin, leaf)
+    assert e.value.rc == colden.CD_EINVAL
