@@ -53,7 +53,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--level", type=int, default=8, help="uniform grid of 2^level cells per axis")
     ap.add_argument("--nside", type=int, default=1, help="HEALPix Nside (D = 12 Nside^2)")
-    ap.add_argument("--cpu-sample-octs", type=int, default=150000,
+    ap.add_argument("--cpu-sample-octs", type=int, default=2097152,
                     help="octs timed with the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()

@@ -108,23 +108,31 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     w->D = D;
     w->mode = mode;
     w->precision = precision;
-    cd::build_tables(u, w->host);
+    int brc = cd::build_tables(u, w->host);
+    if (brc == CD_OK) brc = cd::build_tile_tables(u, w->host);
+    if (brc != CD_OK) {
+        delete w;
+        return brc;
+    }
     hipStream_t s = (hipStream_t)stream;
     int rc = CD_OK;
+    // host staging buffers live until the stream is synchronised below
+    std::vector<std::vector<float>> wf(cd::kKinds);
     for (int k = 1; k < cd::kKinds && rc == CD_OK; ++k) {
         w->ncombo[k] = w->host.ncombo[k];
         w->len[k] = w->host.len[k];
-        std::vector<float> wf(w->host.w[k].begin(), w->host.w[k].end());
+        wf[k].assign(w->host.w[k].begin(), w->host.w[k].end());
         rc = upload(w->host.off[k], &w->off[k], s);
-        if (rc == CD_OK) rc = upload(wf, &w->w[k], s);
+        if (rc == CD_OK) rc = upload(wf[k], &w->w[k], s);
         if (rc == CD_OK) rc = upload(w->host.cnt[k], &w->cnt[k], s);
     }
-    if (rc == CD_OK) {
-        std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
-        rc = upload(kf, &w->kloc, s);
-    }
+    std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
+    std::vector<float> gf(w->host.gloc.begin(), w->host.gloc.end());
+    if (rc == CD_OK) rc = upload(kf, &w->kloc, s);
+    if (rc == CD_OK) rc = upload(w->host.blob, &w->blob, s);
+    if (rc == CD_OK) rc = upload(gf, &w->gloc, s);
+    if (rc == CD_OK) rc = upload(w->host.sgn, &w->sgn, s);
     if (rc == CD_OK && precision != CD_FP32) rc = cd::upload_split_banks(w, s);
-    // host vectors must stay alive until the copies are done
     if (rc == CD_OK && hipStreamSynchronize(s) != hipSuccess) {
         cd::set_error("cd_precompute_weights: upload failed");
         rc = CD_EDEVICE;
@@ -154,6 +162,9 @@ extern "C" void cd_weights_destroy(cd_weights* w) {
         if (w->cnt[k]) (void)hipFree(w->cnt[k]);
     }
     if (w->kloc) (void)hipFree(w->kloc);
+    if (w->blob) (void)hipFree(w->blob);
+    if (w->gloc) (void)hipFree(w->gloc);
+    if (w->sgn) (void)hipFree(w->sgn);
     cd::free_split_banks(w);
     delete w;
 }

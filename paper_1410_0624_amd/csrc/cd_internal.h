@@ -75,8 +75,16 @@ struct HostTables {
     std::vector<double> w[kKinds];         // [ncombo][D][len] chord in cell widths
     std::vector<int32_t> cnt[kKinds];      // [ncombo][D] true entry counts
     std::vector<double> kloc;              // [8 target octant][8 oct cell][D]
+    // tiled-sweep tables (see sweep_layout.h): one blob per (round, direction chunk)
+    int tile_dc = 0;                       // directions per chunk (0: no tiled sweep)
+    int blob_words = 0;                    // int32 words per blob
+    std::vector<int32_t> blob;             // [rounds][D / tile_dc][blob_words]
+    std::vector<double> gloc;              // [D][8] internal+local chords by crossed-axis set m
+    std::vector<int32_t> sgn;              // [D] sign bits of u (1 = negative component)
 };
 int build_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
+int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
+int tile_chunk(int D);
 
 inline int32_t pack_off(int ox, int oy, int oz) {
     return (int32_t)((uint32_t)(ox & 0xff) | ((uint32_t)(oy & 0xff) << 8) |
@@ -96,6 +104,9 @@ struct cd_weights {
     float* w[cd::kKinds] = {nullptr};       // device, FP32 weights
     int32_t* cnt[cd::kKinds] = {nullptr};   // device
     float* kloc = nullptr;                  // device [8][8][D]
+    int32_t* blob = nullptr;                // device tiled-sweep tables
+    float* gloc = nullptr;                  // device [D][8]
+    int32_t* sgn = nullptr;                 // device [D]
     // split-precision banks (hi/lo) for the MFMA sweep
     void* split = nullptr;
     cd::HostTables host;
@@ -121,5 +132,7 @@ struct cd_tree {
     float* q[CD_MAX_LEVEL + 1] = {nullptr};
     size_t q_bytes[CD_MAX_LEVEL + 1] = {0};
     int q_D = 0;
+    float* ext = nullptr;  // per-oct external columns [n_oct][D]
+    size_t ext_bytes = 0;
     std::vector<void*> scratch;  // other device allocations to free
 };

@@ -141,14 +141,24 @@ struct CoarseArgs {
     int8_t dl4[4];
 };
 
-__global__ __launch_bounds__(256) void k_coarse_q(const CoarseArgs a) {
+#define CD_CONST __attribute__((address_space(4)))
+constexpr int kCoarseLen = 12;
+
+// One wave per (state code, parity class, group of 16 directions, 4 cells of
+// that parity): the shell shape and reference point are the same for the
+// whole wave; lanes are (cell, direction) with the direction fastest, so each
+// cell's row of the table is written contiguously.
+__global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
     const int ncodes = a.compact ? 64 : 216;
-    const int64_t n = (int64_t)1 << a.l;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n * n * ncodes) return;
-    const int64_t cell = idx / ncodes;
-    const int code = (int)(idx - cell * ncodes);
-    const int c[3] = {(int)(cell & (n - 1)), (int)((cell >> a.l) & (n - 1)), (int)(cell >> (2 * a.l))};
+    const int dgroups = (a.D + 15) >> 4;
+    const int code = blockIdx.x / (8 * dgroups);
+    const int par = (blockIdx.x / dgroups) & 7;
+    const int d = (blockIdx.x % dgroups) * 16 + (threadIdx.x & 15);
+    const int64_t h = (int64_t)1 << (a.l - 1);  // cells of one parity per axis
+    const int64_t q = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 4);
+    if (q >= h * h * h || d >= a.D) return;
+    const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
+                      (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
     int st[3];
     if (a.compact) {
         st[0] = a.dl4[code & 3];
@@ -161,30 +171,31 @@ __global__ __launch_bounds__(256) void k_coarse_q(const CoarseArgs a) {
     }
     int combo = 0, pcode = 0, mul = 1, pmul = 1;
     for (int k = 0; k < 3; ++k) {
-        const int p = c[k] & 1;
+        const int p = (par >> k) & 1;
         combo += (6 * p + st[k]) * mul;
         pcode += a.next[st[k]][p] * pmul;
         mul *= 12;
         pmul *= 6;
     }
+    const int64_t n = (int64_t)1 << a.l;
     const int S = (int)n + 2 * kHalo;
     const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
-    const float* prev = nullptr;
+    float prev = 0.f;
     if (a.qprev) {
         const int64_t np = n >> 1;
         const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
-        prev = a.qprev + (pcell * 216 + pcode) * a.D;
+        prev = a.qprev[(pcell * 216 + pcode) * a.D + d];
     }
-    float* out = a.q + (cell * ncodes + code) * a.D;
-    for (int d = 0; d < a.D; ++d) {
-        const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
-        float s = 0.f;
-        for (int e = 0; e < a.kt.len; ++e) {
-            const int pk = a.kt.off[row + e];
-            s = fmaf(a.kt.w[row + e], base[((int64_t)sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk)], s);
-        }
-        out[d] = fmaf(a.dx, s, prev ? prev[d] : 0.f);
+    const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
+    float s = 0.f;
+    // kind-4 lists hold at most kCoarseLen entries (zero-weight padded)
+#pragma unroll
+    for (int e = 0; e < kCoarseLen; ++e) {
+        const int pk = a.kt.off[row + e];
+        s = fmaf(a.kt.w[row + e], base[((int64_t)sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk)], s);
     }
+    const int64_t cell = ((int64_t)c[2] * n + c[1]) * n + c[0];
+    a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
 }
 
 // -------------------------------------------------------------- screening --
@@ -225,6 +236,26 @@ static int ensure_q(cd_tree* t, int D) {
     return CD_OK;
 }
 
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
+bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
+                        float chi_scale, hipStream_t s);
+bool tiled_supported(const cd_tree* t, const cd_weights* w);
+
+// Per-oct external columns E[n_oct][D] owned by the tree.
+static int ensure_ext(cd_tree* t, int D) {
+    const size_t bytes = ((size_t)1 << (3 * (t->lmax - 1))) * D * sizeof(float);
+    if (t->ext_bytes >= bytes) return CD_OK;
+    if (t->ext) (void)hipFree(t->ext);
+    t->ext = nullptr;
+    t->ext_bytes = 0;
+    if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
+        set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
+        return CD_ENOMEM;
+    }
+    t->ext_bytes = bytes;
+    return CD_OK;
+}
+
 template <int DC>
 static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
     k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
@@ -233,6 +264,10 @@ static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
 int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
     const int L = t->lmax;
     const int D = w->D;
+    if (w->len[4] != kCoarseLen) {
+        set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
+        return CD_EINVAL;
+    }
     int rc = ensure_q(t, D);
     if (rc != CD_OK) return rc;
     // coarse levels, top-down
@@ -249,8 +284,17 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         for (int sc = 0; sc < 6; ++sc)
             for (int p = 0; p < 2; ++p) c.next[sc][p] = (int8_t)next_state_code(sc, p);
         for (int q = 0; q < 4; ++q) c.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
-        const int64_t nthreads = ((int64_t)1 << (3 * l)) * (c.compact ? 64 : 216);
-        k_coarse_q<<<(unsigned)((nthreads + 255) / 256), 256, 0, s>>>(c);
+        const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
+        dim3 grid((c.compact ? 64 : 216) * 8 * ((D + 15) / 16), (unsigned)((per_parity + 3) / 4));
+        k_coarse_q<<<grid, 64, 0, s>>>(c);
+    }
+    if (L >= 1 && tiled_supported(t, w)) {
+        rc = ensure_ext(t, D);
+        if (rc != CD_OK) return rc;
+        launch_external_tiled(t, w, t->ext, s);
+        launch_target_rows(t, w, t->ext, N, chi, chi_scale, s);
+        CD_HIP(hipGetLastError());
+        return CD_OK;
     }
     if (L >= 1) {
         FineArgs a{};

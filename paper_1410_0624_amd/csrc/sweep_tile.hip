@@ -1,0 +1,244 @@
+// Tiled FP32 column-density sweep on a uniform grid (Sect. 3.2-3.3).
+//
+// One workgroup per tile of 16^3 octs.  The tile's neighbourhoods at levels
+// L-1, L-2 and L-3 (the dl = 1, 2, 3 shells reach 3, 4 and 5 cells beyond the
+// ancestor) are staged once in LDS.  Waves are grouped by configuration class
+// (A mod 4 per axis), so the shell weight lists of dl = 1 and 2 and the
+// reference point of dl = 3 are the same for all 64 lanes: the lists are read
+// with scalar loads and only the densities are per lane.  The dl = 3 outer
+// box still depends on the parity of A >> 2 (one bit per axis, per lane): its
+// list is the union over those 8 parities with a per-entry mask.  The coarse
+// part (dl >= 4) comes from the top-down table of the coarse kernels.
+//
+// The internal + local part (Sect. 3.2: target and its siblings, rays from the
+// target centre) uses mirror symmetry: with u mirrored into the positive
+// octant, a target reaches the siblings across its "low-side" axes only, and
+// the chord through the sibling across axis set m is one number G[d][m] for
+// every target.  For each direction the sign pattern selects (uniformly) a
+// specialisation with the zero terms removed at compile time.
+#include <cmath>
+
+#include "cd_internal.h"
+#include "sweep_layout.h"
+
+namespace cd {
+
+struct TileArgs {
+    const float* leaf;
+    int L;
+    const float* lev1;  // padded level L-1
+    const float* lev2;  // padded level L-2
+    const float* lev3;  // padded level L-3
+    float dx1, dx2, dx3, dxL;
+    const float* q4;    // [8^(L-4)][64][D] or nullptr
+    const int32_t* blob;  // [rounds][D / DC][blob_words]
+    int blob_words;
+    const float* gloc;  // [D][8]
+    const int32_t* sgn; // [D]
+    float* E;           // [n_oct][D] external columns (output)
+    int tiles_per_axis;
+};
+
+__device__ __forceinline__ float as_float(int32_t b) { return __int_as_float(b); }
+
+// Read-only tables are read through the constant address space: with a
+// wave-uniform address the loads become scalar (s_load) loads.
+#define CD_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const CD_CONST T* cptr(const void* p) {
+    return (const CD_CONST T*)(p);
+}
+
+template <int D, int DC>
+__global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArgs a) {
+    using namespace tile;
+    __shared__ float s1[k1Size];
+    __shared__ float s2[k2Size];
+    __shared__ float s3[k3Size];
+    __shared__ int4 tab[kTabWords / 4];
+
+    const int tpa = a.tiles_per_axis;
+    const int tile_id = blockIdx.x;
+    const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = tile_id / (tpa * tpa);
+    const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;  // tile origin, level L-1 cells
+    const int L1 = a.L - 1;
+    const int64_t S1 = ((int64_t)1 << L1) + 2 * kHalo;
+    const int64_t S2 = ((int64_t)1 << (L1 - 1)) + 2 * kHalo;
+    const int64_t S3 = ((int64_t)1 << (L1 - 2)) + 2 * kHalo;
+
+    // stage the three neighbourhoods (coalesced global reads, scattered LDS writes)
+    for (int i = threadIdx.x; i < k1Side * k1Side * k1Side; i += kThreads) {
+        const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
+        // level L-1 coordinate X1 + xx - 4, padded index + kHalo
+        const float v = a.lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
+        s1[slot1(xx) + k1Py * slot1(yy) + k1Pz * slot1(zz)] = v;
+    }
+    for (int i = threadIdx.x; i < k2Side * k2Side * k2Side; i += kThreads) {
+        const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
+        const float v = a.lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
+        s2[slot2(xx) + k2Py * slot2(yy) + k2Pz * slot2(zz)] = v;
+    }
+    for (int i = threadIdx.x; i < k3Side * k3Side * k3Side; i += kThreads) {
+        const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
+        const float v = a.lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
+        s3[xx + k3Py * yy + k3Pz * zz] = v;
+    }
+
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int pbit = 16 + ((lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2));  // parity mask bit of dl = 3
+    const int b1 = lane1(lx, ly, lz), b2 = lane2(lx, ly, lz), b3 = lane3(lx, ly, lz);
+    const int64_t n = (int64_t)1 << a.L;
+    const int n4 = 1 << (L1 - 3);  // level L-4 cells per axis
+    constexpr int kChunks = D / DC;
+    const int4* hdr = tab + wave * DC;   // this wave's headers
+    const int4* ent0 = tab + 16 * DC;    // entry pairs
+
+    for (int r = 0; r < kRounds; ++r) {
+        const int ci = r * 16 + wave;  // configuration class, wave-uniform
+        const int cx = ci & 3, cy = (ci >> 2) & 3, cz = ci >> 4;
+        const int Ax = X1 + 4 * lx + cx, Ay = Y1 + 4 * ly + cy, Az = Z1 + 4 * lz + cz;
+
+        const int64_t oct = ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
+        const float* q = nullptr;
+        if (a.q4) {
+            const int64_t cell = ((int64_t)(Az >> 3) * n4 + (Ay >> 3)) * n4 + (Ax >> 3);
+            const int code = ((Ax >> 1) & 3) + 4 * ((Ay >> 1) & 3) + 16 * ((Az >> 1) & 3);
+            q = a.q4 + (cell * 64 + code) * D;
+        }
+
+#pragma unroll 1
+        for (int k = 0; k < kChunks; ++k) {
+            const int d0 = k * DC;
+            // weight lists of this round and chunk into LDS
+            __syncthreads();
+            {
+                const int4* src = reinterpret_cast<const int4*>(a.blob + (int64_t)(r * kChunks + k) * a.blob_words);
+                for (int i = threadIdx.x; i < a.blob_words / 4; i += kThreads) tab[i] = src[i];
+            }
+            __syncthreads();
+
+            float acc[DC];
+            if (q) {
+                if constexpr (DC % 4 == 0) {
+#pragma unroll
+                    for (int j = 0; j < DC; j += 4) {
+                        const float4 v = *reinterpret_cast<const float4*>(q + d0 + j);
+                        acc[j] = v.x;
+                        acc[j + 1] = v.y;
+                        acc[j + 2] = v.z;
+                        acc[j + 3] = v.w;
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < DC; ++j) acc[j] = q[d0 + j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < DC; ++j) acc[j] = 0.f;
+            }
+
+            // external shells dl = 1, 2, 3 (pairs of (LDS offset, weight))
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                const int4 h = hdr[j];
+                const int first = __builtin_amdgcn_readfirstlane(h.x);
+                const int n1p = __builtin_amdgcn_readfirstlane(h.y);
+                const int n2p = __builtin_amdgcn_readfirstlane(h.z);
+                const int n3 = __builtin_amdgcn_readfirstlane(h.w);
+                const int n3c = n3 & 0xffff, n3v = n3 >> 16;
+                const int4* e = ent0 + (first >> 1);
+                float s = 0.f, t = 0.f, u = 0.f;
+                for (int i = 0; i < n1p; ++i) {
+                    const int4 p = e[i];
+                    const float v0 = s1[b1 + p.x], v1 = s1[b1 + p.z];
+                    s = fmaf(as_float(p.y), v0, s);
+                    s = fmaf(as_float(p.w), v1, s);
+                }
+                e += n1p;
+                for (int i = 0; i < n2p; ++i) {
+                    const int4 p = e[i];
+                    const float v0 = s2[b2 + p.x], v1 = s2[b2 + p.z];
+                    t = fmaf(as_float(p.y), v0, t);
+                    t = fmaf(as_float(p.w), v1, t);
+                }
+                e += n2p;
+                for (int i = 0; i < n3c; ++i) {
+                    const int4 p = e[i];
+                    const float v0 = s3[b3 + p.x], v1 = s3[b3 + p.z];
+                    u = fmaf(as_float(p.y), v0, u);
+                    u = fmaf(as_float(p.w), v1, u);
+                }
+                e += n3c;
+                for (int i = 0; i < n3v; ++i) {
+                    const int4 p = e[i];
+                    const float v0 = s3[b3 + (p.x & 0xffff)], v1 = s3[b3 + (p.z & 0xffff)];
+                    u = fmaf(as_float(p.y), ((p.x >> pbit) & 1) ? v0 : 0.f, u);
+                    u = fmaf(as_float(p.w), ((p.z >> pbit) & 1) ? v1 : 0.f, u);
+                }
+                acc[j] = fmaf(a.dx1, s, fmaf(a.dx2, t, fmaf(a.dx3, u, acc[j])));
+            }
+
+            // the oct's row piece of external columns, back-to-back stores
+            float* row = a.E + oct * D + d0;
+            if constexpr (DC % 4 == 0) {
+#pragma unroll
+                for (int j = 0; j < DC; j += 4)
+                    *reinterpret_cast<float4*>(row + j) = make_float4(acc[j], acc[j + 1], acc[j + 2], acc[j + 3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < DC; ++j) row[j] = acc[j];
+            }
+        }
+    }
+}
+
+template <int D, int DC>
+static void launch(const TileArgs& a, hipStream_t s) {
+    static_assert(D % DC == 0, "direction chunks must tile D");
+    const int ntiles = a.tiles_per_axis * a.tiles_per_axis * a.tiles_per_axis;
+    k_external_tiled<D, DC><<<ntiles, tile::kThreads, 0, s>>>(a);
+}
+
+// The tiled external kernel and the target-row kernel handle this tree and
+// direction set.
+bool tiled_supported(const cd_tree* t, const cd_weights* w) {
+    const int L = t->lmax;
+    const int D = w->D;
+    if (!t->uniform || L < 5) return false;
+    if (!(D == 6 || D == 12 || D == 24 || D == 40 || D == 48)) return false;
+    return w->host.tile_dc == tile_chunk(D) && w->host.blob_words <= tile::kTabWords;
+}
+
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s) {
+    const int L = t->lmax;
+    const int D = w->D;
+    TileArgs a{};
+    a.leaf = t->leaf;
+    a.L = L;
+    a.lev1 = t->lev[L - 1];
+    a.lev2 = t->lev[L - 2];
+    a.lev3 = t->lev[L - 3];
+    a.dx1 = (float)(t->box_cm * std::ldexp(1.0, -(L - 1)));
+    a.dx2 = (float)(t->box_cm * std::ldexp(1.0, -(L - 2)));
+    a.dx3 = (float)(t->box_cm * std::ldexp(1.0, -(L - 3)));
+    a.dxL = (float)(t->box_cm * std::ldexp(1.0, -L));
+    a.q4 = (L - 4 >= 2) ? t->q[L - 4] : nullptr;
+    a.blob = w->blob;
+    a.blob_words = w->host.blob_words;
+    a.gloc = w->gloc;
+    a.sgn = w->sgn;
+    a.E = E;
+    a.tiles_per_axis = 1 << (L - 1 - 4);
+    switch (D) {
+        case 6: launch<6, 6>(a, s); break;
+        case 12: launch<12, 12>(a, s); break;
+        case 24: launch<24, 12>(a, s); break;
+        case 40: launch<40, 8>(a, s); break;
+        default: launch<48, 16>(a, s); break;  // tile_chunk(48) = 16
+    }
+    return true;
+}
+
+}  // namespace cd

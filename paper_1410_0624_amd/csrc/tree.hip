@@ -173,6 +173,7 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
         if (t->q[l]) (void)hipFree(t->q[l]);
     }
     if (t->d_baseleaf) (void)hipFree(t->d_baseleaf);
+    if (t->ext) (void)hipFree(t->ext);
     for (void* p : t->scratch) (void)hipFree(p);
     delete t;
 }
