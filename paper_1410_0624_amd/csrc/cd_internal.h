@@ -37,6 +37,7 @@ constexpr int kHalo = 5;
 //   4: dl >= 4, reference at the centre of A_{l+2}, inner limit in one of
 //      three per-axis states
 constexpr int kKinds = 5;  // index 1..4 used
+constexpr int kMaxSlabs = 4;  // z-slabs overlapping the two sweep stages
 
 // Per-axis shape of a shell relative to the level-l ancestor (in level-l
 // cells): inner [ilo, ihi], outer [olo, ohi], and the reference coordinate.
@@ -134,5 +135,7 @@ struct cd_tree {
     int q_D = 0;
     float* ext = nullptr;  // per-oct external columns [n_oct][D]
     size_t ext_bytes = 0;
+    hipStream_t aux = nullptr;               // second stream of the sweep
+    hipEvent_t ev[cd::kMaxSlabs + 1] = {};  // slab hand-over and join events
     std::vector<void*> scratch;  // other device allocations to free
 };

@@ -141,13 +141,15 @@ struct CoarseArgs {
     int8_t dl4[4];
 };
 
-#define CD_CONST __attribute__((address_space(4)))
 constexpr int kCoarseLen = 12;
 
-// One wave per (state code, parity class, group of 16 directions, 4 cells of
-// that parity): the shell shape and reference point are the same for the
-// whole wave; lanes are (cell, direction) with the direction fastest, so each
-// cell's row of the table is written contiguously.
+// One wave per (state code, parity class, group of 16 directions, 4 groups
+// of kCoarseCells cells of that parity): the shell shape and reference point
+// are the same for the whole wave; lanes are (cell group, direction) with the
+// direction fastest, so each cell's row of the table is written contiguously,
+// and each lane reuses its weight list for the cells of its group.
+constexpr int kCoarseCells = 8;
+
 __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
     const int ncodes = a.compact ? 64 : 216;
     const int dgroups = (a.D + 15) >> 4;
@@ -155,10 +157,9 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
     const int par = (blockIdx.x / dgroups) & 7;
     const int d = (blockIdx.x % dgroups) * 16 + (threadIdx.x & 15);
     const int64_t h = (int64_t)1 << (a.l - 1);  // cells of one parity per axis
-    const int64_t q = (int64_t)blockIdx.y * 4 + (threadIdx.x >> 4);
-    if (q >= h * h * h || d >= a.D) return;
-    const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
-                      (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
+    const int64_t ncell = h * h * h;
+    const int64_t q0 = ((int64_t)blockIdx.y * 4 + (threadIdx.x >> 4)) * kCoarseCells;
+    if (q0 >= ncell || d >= a.D) return;
     int st[3];
     if (a.compact) {
         st[0] = a.dl4[code & 3];
@@ -179,23 +180,34 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
     }
     const int64_t n = (int64_t)1 << a.l;
     const int S = (int)n + 2 * kHalo;
-    const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
-    float prev = 0.f;
-    if (a.qprev) {
-        const int64_t np = n >> 1;
-        const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
-        prev = a.qprev[(pcell * 216 + pcode) * a.D + d];
-    }
+    // weight list of (configuration, direction): kCoarseLen entries, zero padded
     const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
-    float s = 0.f;
-    // kind-4 lists hold at most kCoarseLen entries (zero-weight padded)
+    int off[kCoarseLen];
+    float wt[kCoarseLen];
 #pragma unroll
     for (int e = 0; e < kCoarseLen; ++e) {
         const int pk = a.kt.off[row + e];
-        s = fmaf(a.kt.w[row + e], base[((int64_t)sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk)], s);
+        off[e] = (sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk);
+        wt[e] = a.kt.w[row + e];
     }
-    const int64_t cell = ((int64_t)c[2] * n + c[1]) * n + c[0];
-    a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
+    const int64_t np = n >> 1;
+    for (int k = 0; k < kCoarseCells; ++k) {
+        const int64_t q = q0 + k;
+        if (q >= ncell) break;
+        const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
+                          (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
+        const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
+        float prev = 0.f;
+        if (a.qprev) {
+            const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
+            prev = a.qprev[(pcell * 216 + pcode) * a.D + d];
+        }
+        float s = 0.f;
+#pragma unroll
+        for (int e = 0; e < kCoarseLen; ++e) s = fmaf(wt[e], base[off[e]], s);
+        const int64_t cell = ((int64_t)c[2] * n + c[1]) * n + c[0];
+        a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
+    }
 }
 
 // -------------------------------------------------------------- screening --
@@ -236,9 +248,19 @@ static int ensure_q(cd_tree* t, int D) {
     return CD_OK;
 }
 
-bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
-                        float chi_scale, hipStream_t s);
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);
+
+// Second stream and events of a tree: the target-row kernel of z-slab j runs
+// there while the external-column kernel of slab j+1 runs on the caller's
+// stream (both at the default priority).
+static int ensure_aux(cd_tree* t) {
+    if (t->aux) return CD_OK;
+    CD_HIP(hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking));
+    for (int j = 0; j < kMaxSlabs + 1; ++j) CD_HIP(hipEventCreateWithFlags(&t->ev[j], hipEventDisableTiming));
+    return CD_OK;
+}
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
 
 // Per-oct external columns E[n_oct][D] owned by the tree.
@@ -285,14 +307,25 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
             for (int p = 0; p < 2; ++p) c.next[sc][p] = (int8_t)next_state_code(sc, p);
         for (int q = 0; q < 4; ++q) c.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
-        dim3 grid((c.compact ? 64 : 216) * 8 * ((D + 15) / 16), (unsigned)((per_parity + 3) / 4));
+        dim3 grid((c.compact ? 64 : 216) * 8 * ((D + 15) / 16),
+                  (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
         k_coarse_q<<<grid, 64, 0, s>>>(c);
     }
     if (L >= 1 && tiled_supported(t, w)) {
         rc = ensure_ext(t, D);
+        if (rc == CD_OK) rc = ensure_aux(t);
         if (rc != CD_OK) return rc;
-        launch_external_tiled(t, w, t->ext, s);
-        launch_target_rows(t, w, t->ext, N, chi, chi_scale, s);
+        const int tpa = 1 << (L - 5);             // tiles per axis (16 octs each)
+        const int nslab = 1;  // z-slabs of whole tile layers (overlap measured slower)
+        const int per = tpa / nslab;
+        for (int j = 0; j < nslab; ++j) {
+            launch_external_tiled(t, w, t->ext, j * per, per, s);
+            CD_HIP(hipEventRecord(t->ev[j], s));
+            CD_HIP(hipStreamWaitEvent(t->aux, t->ev[j], 0));
+            launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, t->aux);
+        }
+        CD_HIP(hipEventRecord(t->ev[kMaxSlabs], t->aux));
+        CD_HIP(hipStreamWaitEvent(s, t->ev[kMaxSlabs], 0));
         CD_HIP(hipGetLastError());
         return CD_OK;
     }

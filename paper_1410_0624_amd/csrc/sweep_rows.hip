@@ -1,17 +1,19 @@
 // Target rows of a uniform grid: internal + local part (Sect. 3.2) added to
 // the oct's external columns, and the screening factor (Eq. 5).
 //
-// A wave owns up to 64 consecutive targets along x of one row (y, z), so the
-// octant bits oy, oz are wave-uniform and only ox varies between lanes.  Each
-// lane reads its oct's densities as "own" (same x column as the target) and
-// "other" (the x sibling column), indexed by the y, z offsets j relative to
-// the target.  With u mirrored into the positive octant the ray from the
-// target centre can enter the sibling across axis k only when the target
-// sits on the low side of k (target bit == sign bit of u_k), and the chord
-// through the sibling across the axis set m is G[d][m] for every target:
+// A lane owns the x pair of targets of one oct in one row (y, z): the octant
+// bits oy, oz are wave-uniform, and so is, for each direction, whether the
+// ray of the low-x and of the high-x target runs into the x sibling.  The
+// lane reads its oct's densities as the low and high x columns, indexed by
+// the y, z offsets j relative to the targets' row and plane.  With u mirrored
+// into the positive octant a ray can enter the sibling across axis k only if
+// the target sits on the low side of k (target bit == sign bit of u_k), and
+// the chord through the sibling across the axis set m is G[d][m] for every
+// target:
 //   IL = sum_{j in Fyz} own[j] G[2j] + [x forward] sum_{j in Fyz} other[j] G[2j+1].
-// Rows of N are written by back-to-back stores of consecutive lanes (whole
-// cache lines), chi by one coalesced store per wave.
+// A wave's 128 targets are contiguous in N: their rows go through a small LDS
+// buffer, 32 targets at a time, and leave as fully coalesced 16-byte stores
+// (consecutive lanes, consecutive addresses); chi is written per lane pair.
 #include <cmath>
 
 #include "cd_internal.h"
@@ -28,68 +30,80 @@ struct RowArgs {
     float* N;
     float* chi;
     float chi_scale;
+    int64_t z0;         // first target plane of this launch
+    int64_t nz;         // number of target planes of this launch
 };
 
 #define CD_CONST __attribute__((address_space(4)))
 
+// Internal + local sums of the low-x (c0) and high-x (c1) targets.
 template <int FYZ>
-__device__ __forceinline__ float il_sum(const float (&own)[4], const float (&oth)[4], const float (&G)[8], bool fx) {
-    float a = 0.f, b = 0.f;
+__device__ __forceinline__ void il_pair(const float (&c0)[4], const float (&c1)[4], const float (&G)[8], bool fx0,
+                                        float& r0, float& r1) {
+    float a0 = 0.f, b0 = 0.f, a1 = 0.f, b1 = 0.f;
 #pragma unroll
     for (int j = 0; j < 4; ++j)
         if ((j & FYZ) == j) {
-            a = fmaf(own[j], G[2 * j], a);
-            b = fmaf(oth[j], G[2 * j + 1], b);
+            a0 = fmaf(c0[j], G[2 * j], a0);      // low target, own column
+            b0 = fmaf(c1[j], G[2 * j + 1], b0);  // low target, x sibling
+            a1 = fmaf(c1[j], G[2 * j], a1);      // high target, own column
+            b1 = fmaf(c0[j], G[2 * j + 1], b1);  // high target, x sibling
         }
-    return fx ? a + b : a;
+    r0 = fx0 ? a0 + b0 : a0;
+    r1 = fx0 ? a1 : a1 + b1;
 }
 
 template <int D>
 __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
     const int L = a.L;
     const int64_t n = (int64_t)1 << L;
-    const int seg = n >= 64 ? 64 : (int)n;  // targets per wave
-    const int64_t wave_g = ((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const int64_t n1 = n >> 1;                   // octs per row
+    const int seg = n1 >= 64 ? 64 : (int)n1;     // octs per wave
+    const int64_t segs = n1 / seg;
+    // A workgroup's 4 waves are the rows (y, y^1) x (z, z^1) of one oct row
+    // segment: they read the same external columns and leaf rows, which
+    // then come through one L2 (workgroups are spread over the XCDs).
     const int lane = threadIdx.x & 63;
-    const int64_t segs = n / seg;
-    const int64_t row = wave_g / segs;
-    if (row >= n * n || lane >= seg) return;
-    const int64_t x = (wave_g - row * segs) * seg + lane;
-    const int64_t y = row & (n - 1), z = row >> L;
-    const int ox = (int)(x & 1), oy = (int)(y & 1), oz = (int)(z & 1);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
+    const int64_t blk = blockIdx.x;
+    const int64_t seg_i = blk % segs;
+    const int64_t orow = blk / segs;                 // oct row (Y, Z) within this launch
+    if (orow >= (a.nz >> 1) * n1) return;  // whole workgroup: uniform
+    const bool live = lane < seg;
+    const int64_t Y = orow & (n1 - 1), Zl = orow >> (L - 1);
+    const int64_t y = 2 * Y + (w & 1), z = a.z0 + 2 * Zl + (w >> 1);
+    const int64_t ax = live ? seg_i * seg + lane : n1 - 1;  // oct x index (dead lanes: any valid oct)
+    const int oy = (int)(y & 1), oz = (int)(z & 1);
     const int L1 = L - 1;
-    const int64_t oct = ((z >> 1) << (2 * L1)) + ((y >> 1) << L1) + (x >> 1);
+    const int64_t oct = ((z >> 1) << (2 * L1)) + ((y >> 1) << L1) + ax;
 
-    // own / other x column, j = (other y row) + 2 (other z plane)
-    float own[4], oth[4];
-    {
-        const int64_t x0 = x & ~(int64_t)1;
+    // low / high x column of the oct, j = (other y row) + 2 (other z plane)
+    float c0[4], c1[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t yy = y ^ (j & 1), zz = z ^ (j >> 1);
-            const float2 p = *reinterpret_cast<const float2*>(a.leaf + (zz * n + yy) * n + x0);
-            own[j] = ox ? p.y : p.x;
-            oth[j] = ox ? p.x : p.y;
-        }
+    for (int j = 0; j < 4; ++j) {
+        const int64_t yy = y ^ (j & 1), zz = z ^ (j >> 1);
+        const float2 p = *reinterpret_cast<const float2*>(a.leaf + (zz * n + yy) * n + 2 * ax);
+        c0[j] = p.x;
+        c1[j] = p.y;
     }
-    float e[D];
+    float e0[D], e1[D];
     {
         const float* er = a.E + oct * D;
         if constexpr (D % 4 == 0) {
 #pragma unroll
             for (int d = 0; d < D; d += 4) {
                 const float4 v = *reinterpret_cast<const float4*>(er + d);
-                e[d] = v.x;
-                e[d + 1] = v.y;
-                e[d + 2] = v.z;
-                e[d + 3] = v.w;
+                e0[d] = v.x;
+                e0[d + 1] = v.y;
+                e0[d + 2] = v.z;
+                e0[d + 3] = v.w;
             }
         } else {
 #pragma unroll
-            for (int d = 0; d < D; ++d) e[d] = er[d];
+            for (int d = 0; d < D; ++d) e0[d] = er[d];
         }
     }
-    float chis = 0.f;
+    float chi0 = 0.f, chi1 = 0.f;
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         const int sg = ((const CD_CONST int32_t*)a.sgn)[d];
@@ -97,40 +111,68 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
         float G[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) G[m] = gl[m];
-        const bool fx = ox == (sg & 1);
+        const bool fx0 = (sg & 1) == 0;  // the low-x target runs into the x sibling
         const int fyz = (oy == ((sg >> 1) & 1) ? 1 : 0) | (oz == ((sg >> 2) & 1) ? 2 : 0);  // wave-uniform
-        float il;
+        float r0, r1;
         switch (fyz) {
-            case 0: il = il_sum<0>(own, oth, G, fx); break;
-            case 1: il = il_sum<1>(own, oth, G, fx); break;
-            case 2: il = il_sum<2>(own, oth, G, fx); break;
-            default: il = il_sum<3>(own, oth, G, fx); break;
+            case 0: il_pair<0>(c0, c1, G, fx0, r0, r1); break;
+            case 1: il_pair<1>(c0, c1, G, fx0, r0, r1); break;
+            case 2: il_pair<2>(c0, c1, G, fx0, r0, r1); break;
+            default: il_pair<3>(c0, c1, G, fx0, r0, r1); break;
         }
-        e[d] = fmaf(a.dxL, il, e[d]);
-        if (a.chi) chis += __expf(-a.chi_scale * e[d]);
+        e1[d] = fmaf(a.dxL, r1, e0[d]);
+        e0[d] = fmaf(a.dxL, r0, e0[d]);
+        if (a.chi) {
+            chi0 += __expf(-a.chi_scale * e0[d]);
+            chi1 += __expf(-a.chi_scale * e1[d]);
+        }
     }
-    const int64_t T = (z * n + y) * n + x;
-    float* out = a.N + T * D;
-    if constexpr (D % 4 == 0) {
+    const int64_t T = (z * n + y) * n + 2 * ax;
+    if (a.chi && live)
+        *reinterpret_cast<float2*>(a.chi + T) = make_float2(chi0 * (1.f / (float)D), chi1 * (1.f / (float)D));
+
+    // rows of the wave's targets through LDS, 16 lanes (32 targets) at a time
+    __shared__ float stage[4][32 * D];
+    float* st = stage[w];
+    const int64_t T0 = (z * n + y) * n + 2 * seg_i * seg;  // first target of the wave
+    const int nl = seg < 64 ? seg : 64;
+    for (int p = 0; p * 16 < nl; ++p) {
+        if ((lane >> 4) == p) {
+            float* r = st + (lane & 15) * 2 * D;
 #pragma unroll
-        for (int d = 0; d < D; d += 4) *reinterpret_cast<float4*>(out + d) = make_float4(e[d], e[d + 1], e[d + 2], e[d + 3]);
-    } else {
-#pragma unroll
-        for (int d = 0; d < D; ++d) out[d] = e[d];
+            for (int d = 0; d < D; ++d) {
+                r[d] = e0[d];
+                r[D + d] = e1[d];
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+        const int ntg = (nl - 16 * p) >= 16 ? 32 : 2 * (nl - 16 * p);  // targets in this piece
+        float* dst = a.N + (T0 + 32 * p) * D;
+        if constexpr (D % 4 == 0) {
+            const int nf4 = ntg * D / 4;
+            for (int i = lane; i < nf4; i += 64)
+                *reinterpret_cast<float4*>(dst + 4 * i) = *reinterpret_cast<const float4*>(st + 4 * i);
+        } else {
+            const int nf = ntg * D;
+            for (int i = lane; i < nf; i += 64) dst[i] = st[i];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
     }
-    if (a.chi) a.chi[T] = chis * (1.f / (float)D);
 }
 
 template <int D>
-static void launch_rows(const RowArgs& a, hipStream_t s) {
-    const int64_t n = (int64_t)1 << a.L;
-    const int64_t seg = n >= 64 ? 64 : n;
-    const int64_t waves = n * n * (n / seg);
-    k_target_rows<D><<<(unsigned)((waves + 3) / 4), 256, 0, s>>>(a);
+static void launch_rows(const RowArgs& a, int64_t nz, hipStream_t s) {
+    const int64_t n1 = (int64_t)1 << (a.L - 1);
+    const int64_t seg = n1 >= 64 ? 64 : n1;
+    const int64_t blocks = (nz / 2) * n1 * (n1 / seg);  // (oct row, segment) pairs
+    k_target_rows<D><<<(unsigned)blocks, 256, 0, s>>>(a);
 }
 
+// Target planes [z0, z0 + nz).
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
-                        float chi_scale, hipStream_t s) {
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s) {
     const int D = w->D;
     RowArgs a{};
     a.leaf = t->leaf;
@@ -142,12 +184,14 @@ bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, f
     a.N = N;
     a.chi = chi;
     a.chi_scale = chi_scale;
+    a.z0 = z0;
+    a.nz = nz;
     switch (D) {
-        case 6: launch_rows<6>(a, s); return true;
-        case 12: launch_rows<12>(a, s); return true;
-        case 24: launch_rows<24>(a, s); return true;
-        case 40: launch_rows<40>(a, s); return true;
-        case 48: launch_rows<48>(a, s); return true;
+        case 6: launch_rows<6>(a, nz, s); return true;
+        case 12: launch_rows<12>(a, nz, s); return true;
+        case 24: launch_rows<24>(a, nz, s); return true;
+        case 40: launch_rows<40>(a, nz, s); return true;
+        case 48: launch_rows<48>(a, nz, s); return true;
         default: return false;
     }
 }

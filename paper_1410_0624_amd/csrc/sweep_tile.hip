@@ -37,6 +37,7 @@ struct TileArgs {
     const int32_t* sgn; // [D]
     float* E;           // [n_oct][D] external columns (output)
     int tiles_per_axis;
+    int tz0;            // first tile layer along z of this launch
 };
 
 __device__ __forceinline__ float as_float(int32_t b) { return __int_as_float(b); }
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
 
     const int tpa = a.tiles_per_axis;
     const int tile_id = blockIdx.x;
-    const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = tile_id / (tpa * tpa);
+    const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = a.tz0 + tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;  // tile origin, level L-1 cells
     const int L1 = a.L - 1;
     const int64_t S1 = ((int64_t)1 << L1) + 2 * kHalo;
@@ -195,9 +196,9 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
 }
 
 template <int D, int DC>
-static void launch(const TileArgs& a, hipStream_t s) {
+static void launch(const TileArgs& a, int nz, hipStream_t s) {
     static_assert(D % DC == 0, "direction chunks must tile D");
-    const int ntiles = a.tiles_per_axis * a.tiles_per_axis * a.tiles_per_axis;
+    const int ntiles = a.tiles_per_axis * a.tiles_per_axis * nz;
     k_external_tiled<D, DC><<<ntiles, tile::kThreads, 0, s>>>(a);
 }
 
@@ -211,7 +212,8 @@ bool tiled_supported(const cd_tree* t, const cd_weights* w) {
     return w->host.tile_dc == tile_chunk(D) && w->host.blob_words <= tile::kTabWords;
 }
 
-bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s) {
+// Tile layers [tz0, tz0 + nz) along z.
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s) {
     const int L = t->lmax;
     const int D = w->D;
     TileArgs a{};
@@ -231,12 +233,13 @@ bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, hipS
     a.sgn = w->sgn;
     a.E = E;
     a.tiles_per_axis = 1 << (L - 1 - 4);
+    a.tz0 = tz0;
     switch (D) {
-        case 6: launch<6, 6>(a, s); break;
-        case 12: launch<12, 12>(a, s); break;
-        case 24: launch<24, 12>(a, s); break;
-        case 40: launch<40, 8>(a, s); break;
-        default: launch<48, 16>(a, s); break;  // tile_chunk(48) = 16
+        case 6: launch<6, 6>(a, nz, s); break;
+        case 12: launch<12, 12>(a, nz, s); break;
+        case 24: launch<24, 12>(a, nz, s); break;
+        case 40: launch<40, 8>(a, nz, s); break;
+        default: launch<48, 16>(a, nz, s); break;  // tile_chunk(48) = 16
     }
     return true;
 }

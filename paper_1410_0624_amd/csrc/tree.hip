@@ -174,6 +174,12 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
     }
     if (t->d_baseleaf) (void)hipFree(t->d_baseleaf);
     if (t->ext) (void)hipFree(t->ext);
+    if (t->aux) {
+        (void)hipStreamSynchronize(t->aux);
+        for (auto& e : t->ev)
+            if (e) (void)hipEventDestroy(e);
+        (void)hipStreamDestroy(t->aux);
+    }
     for (void* p : t->scratch) (void)hipFree(p);
     delete t;
 }
