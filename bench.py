@@ -13,6 +13,7 @@ sectors, FP32.  Prints one JSON line.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -38,12 +39,30 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def alg_bytes(n_leaf: int, D: int, L: int) -> float:
+def alg_bytes_sweep(n_leaf: int, D: int, L: int) -> float:
     """Algorithmic HBM bytes of one column sweep: read every leaf density
     once (4 B) and the coarse pyramid once (4 B x n_leaf/7 for all levels
     below L), write N (4 B x D) and chi (4 B) per leaf."""
     pyr_cells = sum(8 ** l for l in range(L))
     return n_leaf * (4.0 + 4.0 * D + 4.0) + 4.0 * pyr_cells
+
+
+def alg_bytes_rows(n_leaf: int, D: int) -> float:
+    """Algorithmic HBM bytes of the target-row stage (the dominant kernel):
+    read the leaf density (4 B) and the oct's external columns (4 D B per 8
+    leaves), write the row of N (4 D B) and chi (4 B)."""
+    return n_leaf * (4.0 + 4.0 * D / 8.0 + 4.0 * D + 4.0)
+
+
+def measured_traffic(key: str):
+    """HBM bytes per launch from the committed rocprofv3 counter runs
+    (profiles/traffic.json), or None if the kernel source changed since."""
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))[key]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes"] if hashlib.sha256(src).hexdigest() == rec["sha256"] else None
 
 
 def main():
@@ -99,16 +118,19 @@ def main():
     torch.cuda.synchronize()
     ms_step = ev0.elapsed_time(ev1) / args.steps
 
-    # dominant kernel(s): the column sweep alone, bracketed on its stream
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
-    for a, b in evs:
-        a.record(stream)
-        colden.column_densities(tree, w, N, chi)
-        b.record(stream)
-    torch.cuda.synchronize()
-    sweep_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
-    bytes_alg = alg_bytes(tin.n_leaf, D, L)
-    achieved = bytes_alg / (sweep_ms * 1e-3) / 1e9
+    # stage durations from the library's HIP events (recorded on the stream
+    # each stage runs on), averaged over the same number of steps
+    tree.profile(True)
+    stages = {k: [] for k in colden.STAGES}
+    for _ in range(args.steps):
+        step()
+        for k, v in tree.stage_ms().items():
+            stages[k].append(v)
+    tree.profile(False)
+    stage_ms = {k: float(np.mean(v)) for k, v in stages.items()}
+    rows_bytes = alg_bytes_rows(tin.n_leaf, D)
+    achieved = rows_bytes / (stage_ms["rows"] * 1e-3) / 1e9
+    sweep_bytes = alg_bytes_sweep(tin.n_leaf, D, L)
 
     cell_dirs = tin.n_leaf * D
     value = cell_dirs / (ms_step * 1e-3)
@@ -158,9 +180,13 @@ def main():
                                f"box 10 pc, seed 2), {D} HEALPix sectors, FP32 sweep + fused screening",
                    "n_leaf": tin.n_leaf, "n_dirs": D, "levels": L + 1, "step": "pyramid rebuild + column sweep"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "cd_column_densities (k_coarse_q + k_fine_uniform)",
-                     "kernel_ms": sweep_ms, "alg_bytes_per_launch": bytes_alg},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}"),
+                     "kernel": f"k_target_rows<{D}> (internal+local, N and chi rows)",
+                     "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
+        "stages_ms": stage_ms,
+        "sweep": {"alg_bytes": sweep_bytes, "ms": stage_ms["sweep"],
+                  "GB_per_s": sweep_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle_sample": relerr,
     }

@@ -102,7 +102,10 @@ int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D)
  *                    [n_octs][3] (x, y, z) of the refined parent cells at
  *                    level l-1; each parent must exist.
  *   leaf_n_dev       device float [n_leaf] leaf densities in leaf order.
- *                    Read during this call's device work only.
+ *                    A uniform grid keeps reading this buffer in every
+ *                    later cd_column_densities until the next
+ *                    cd_tree_update: keep it alive and unchanged.  An AMR
+ *                    tree copies the leaves.
  *   n_leaf           number of leaves implied by the structure.
  * The structure is copied; the pyramid is built on `stream`.  Device
  * memory for the pyramid and the index maps is owned by the handle.
@@ -114,7 +117,8 @@ int cd_build_tree(double box_cm, int base_level, int max_level,
                   const float* leaf_n_dev, int64_t n_leaf, void* stream, cd_tree** out);
 
 /* New leaf densities for an existing structure (one hydro step later):
- * rebuilds the pyramid on `stream`.  Same layout rules as cd_build_tree. */
+ * rebuilds the pyramid on `stream`.  Same layout and lifetime rules as
+ * cd_build_tree. */
 int cd_tree_update(cd_tree* tree, const float* leaf_n_dev, void* stream);
 
 /* Number of leaves of the tree. */
@@ -169,6 +173,21 @@ int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float*
  */
 int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per_nh,
                         double gamma, float* chi_dev, float* av_dev, void* stream);
+
+/*
+ * Stage timing.  When enabled on a tree, cd_column_densities and
+ * cd_tree_update record HIP events around each of their stages on the
+ * streams the stages run on; cd_profile_read waits for the last call's events
+ * and returns the stage durations in milliseconds (0 for a stage that did not
+ * run).  Stages: CD_STAGE_PYRAMID (cd_tree_update), CD_STAGE_COARSE (shells
+ * dl >= 4), CD_STAGE_EXTERNAL (shells dl = 1..3), CD_STAGE_ROWS (internal +
+ * local, N and chi), CD_STAGE_SWEEP (the whole cd_column_densities call).
+ * Errors: CD_EINVAL (NULL tree or output), CD_EDEVICE.
+ */
+enum { CD_STAGE_PYRAMID = 0, CD_STAGE_COARSE = 1, CD_STAGE_EXTERNAL = 2, CD_STAGE_ROWS = 3, CD_STAGE_SWEEP = 4,
+       CD_NUM_STAGES = 5 };
+int cd_profile_enable(cd_tree* tree, int on);
+int cd_profile_read(cd_tree* tree, float* ms /* [CD_NUM_STAGES] */);
 
 #ifdef __cplusplus
 }

@@ -22,7 +22,9 @@ EXPORTS = [
     "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
     "cd_weights_n_dirs", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
+    "cd_profile_enable", "cd_profile_read",
 ]
+STAGES = ["pyramid", "coarse", "external", "rows", "sweep"]
 
 
 class ColdenError(RuntimeError):
@@ -57,6 +59,8 @@ def lib():
         L.cd_weights_destroy.restype = None
         L.cd_column_densities.argtypes = [P, P, P, P, D, D, P]
         L.cd_screening_factor.argtypes = [P, I64, I, D, D, P, P, P]
+        L.cd_profile_enable.argtypes = [P, I]
+        L.cd_profile_read.argtypes = [P, P]
         _lib = L
     return _lib
 
@@ -111,6 +115,16 @@ class Tree:
     def update(self, leaf_n, stream=None):
         self._keep_leaf = leaf_n
         _check(lib().cd_tree_update(self.h, _dev_f32(leaf_n), _stream(stream)))
+
+    def profile(self, on: bool = True):
+        """Record HIP events around each stage of later calls on this tree."""
+        _check(lib().cd_profile_enable(self.h, 1 if on else 0))
+
+    def stage_ms(self) -> dict:
+        """Stage durations (ms) of the last profiled calls."""
+        ms = np.zeros(len(STAGES), np.float32)
+        _check(lib().cd_profile_read(self.h, _np(ms)))
+        return dict(zip(STAGES, ms.tolist()))
 
     def leaf_coords(self):
         lv = np.zeros(self.n_leaf, np.int8)

@@ -136,6 +136,9 @@ struct cd_tree {
     float* ext = nullptr;  // per-oct external columns [n_oct][D]
     size_t ext_bytes = 0;
     hipStream_t aux = nullptr;               // second stream of the sweep
+    bool prof = false;                       // stage timing enabled
+    hipEvent_t pev[CD_NUM_STAGES][2] = {};   // start/stop events per stage
+    bool pran[CD_NUM_STAGES] = {};           // stage ran in the last call
     hipEvent_t ev[cd::kMaxSlabs + 1] = {};  // slab hand-over and join events
     std::vector<void*> scratch;  // other device allocations to free
 };

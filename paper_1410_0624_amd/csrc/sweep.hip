@@ -283,16 +283,9 @@ static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
     k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
 }
 
-int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+static void launch_coarse(cd_tree* t, const cd_weights* w, hipStream_t s) {
     const int L = t->lmax;
     const int D = w->D;
-    if (w->len[4] != kCoarseLen) {
-        set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
-        return CD_EINVAL;
-    }
-    int rc = ensure_q(t, D);
-    if (rc != CD_OK) return rc;
-    // coarse levels, top-down
     for (int l = 2; l <= L - 4; ++l) {
         CoarseArgs c{};
         c.lev = t->lev[l];
@@ -311,24 +304,59 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
                   (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
         k_coarse_q<<<grid, 64, 0, s>>>(c);
     }
+}
+
+int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+    const int L = t->lmax;
+    const int D = w->D;
+    if (w->len[4] != kCoarseLen) {
+        set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
+        return CD_EINVAL;
+    }
+    int rc = ensure_q(t, D);
+    if (rc != CD_OK) return rc;
     if (L >= 1 && tiled_supported(t, w)) {
+        // coarse tables (dl >= 4) on the second stream, concurrently with the
+        // tiled external kernel (dl = 1..3); the target rows need both
         rc = ensure_ext(t, D);
         if (rc == CD_OK) rc = ensure_aux(t);
         if (rc != CD_OK) return rc;
-        const int tpa = 1 << (L - 5);             // tiles per axis (16 octs each)
-        const int nslab = 1;  // z-slabs of whole tile layers (overlap measured slower)
+        // stream s: the tiled kernel slab by slab (whole tile layers along z);
+        // stream aux: the coarse tables, then the target rows of each slab
+        // once its external columns are done, overlapping the next slab
+        const int tpa = 1 << (L - 5);  // tiles per axis (16 octs each)
+        const int nslab = 1;  // slab overlap measured slower: one tiled launch
         const int per = tpa / nslab;
+        auto mark = [t](int stage, int edge, hipStream_t st) -> hipError_t {
+            if (!t->prof) return hipSuccess;
+            t->pran[stage] = true;
+            return hipEventRecord(t->pev[stage][edge], st);
+        };
+        CD_HIP(mark(CD_STAGE_SWEEP, 0, s));
+        CD_HIP(hipEventRecord(t->ev[kMaxSlabs], s));
+        CD_HIP(hipStreamWaitEvent(t->aux, t->ev[kMaxSlabs], 0));
+        CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
+        launch_coarse(t, w, t->aux);
+        CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
+        CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         for (int j = 0; j < nslab; ++j) {
             launch_external_tiled(t, w, t->ext, j * per, per, s);
             CD_HIP(hipEventRecord(t->ev[j], s));
+        }
+        CD_HIP(mark(CD_STAGE_EXTERNAL, 1, s));
+        for (int j = 0; j < nslab; ++j) {
             CD_HIP(hipStreamWaitEvent(t->aux, t->ev[j], 0));
+            if (j == 0) CD_HIP(mark(CD_STAGE_ROWS, 0, t->aux));
             launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, t->aux);
         }
+        CD_HIP(mark(CD_STAGE_ROWS, 1, t->aux));
         CD_HIP(hipEventRecord(t->ev[kMaxSlabs], t->aux));
         CD_HIP(hipStreamWaitEvent(s, t->ev[kMaxSlabs], 0));
+        CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
         CD_HIP(hipGetLastError());
         return CD_OK;
     }
+    launch_coarse(t, w, s);
     if (L >= 1) {
         FineArgs a{};
         a.leaf = t->leaf;

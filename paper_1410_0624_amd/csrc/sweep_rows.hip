@@ -23,7 +23,8 @@ namespace cd {
 struct RowArgs {
     const float* leaf;  // [n^3] row-major
     int L;
-    const float* E;     // [n_oct][D] external columns
+    const float* E;     // [n_oct][D] external columns of the shells dl = 1..3
+    const float* q4;    // [8^(L-4)][64][D] shells dl >= 4, or nullptr
     const float* gloc;  // [D][8]
     const int32_t* sgn; // [D]
     float dxL;
@@ -102,6 +103,28 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
 #pragma unroll
             for (int d = 0; d < D; ++d) e0[d] = er[d];
         }
+        if (a.q4) {
+            // shells dl >= 4: the level L-4 ancestor and the inner-limit state
+            // fixed by bits 1 and 2 of the oct's coordinates
+            const int64_t Ay = y >> 1, Az = z >> 1;
+            const int64_t n4 = n1 >> 3;
+            const int64_t cell = ((Az >> 3) * n4 + (Ay >> 3)) * n4 + (ax >> 3);
+            const int code = (int)(((ax >> 1) & 3) + 4 * ((Ay >> 1) & 3) + 16 * ((Az >> 1) & 3));
+            const float* qr = a.q4 + (cell * 64 + code) * D;
+            if constexpr (D % 4 == 0) {
+#pragma unroll
+                for (int d = 0; d < D; d += 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(qr + d);
+                    e0[d] += v.x;
+                    e0[d + 1] += v.y;
+                    e0[d + 2] += v.z;
+                    e0[d + 3] += v.w;
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < D; ++d) e0[d] += qr[d];
+            }
+        }
     }
     float chi0 = 0.f, chi1 = 0.f;
 #pragma unroll
@@ -178,6 +201,7 @@ bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, f
     a.leaf = t->leaf;
     a.L = t->lmax;
     a.E = E;
+    a.q4 = (t->lmax - 4 >= 2) ? t->q[t->lmax - 4] : nullptr;
     a.gloc = w->gloc;
     a.sgn = w->sgn;
     a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));

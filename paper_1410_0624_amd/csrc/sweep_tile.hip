@@ -8,7 +8,7 @@
 // with scalar loads and only the densities are per lane.  The dl = 3 outer
 // box still depends on the parity of A >> 2 (one bit per axis, per lane): its
 // list is the union over those 8 parities with a per-entry mask.  The coarse
-// part (dl >= 4) comes from the top-down table of the coarse kernels.
+// part (dl >= 4) is added by the target-row kernel.
 //
 // The internal + local part (Sect. 3.2: target and its siblings, rays from the
 // target centre) uses mirror symmetry: with u mirrored into the positive
@@ -30,7 +30,6 @@ struct TileArgs {
     const float* lev2;  // padded level L-2
     const float* lev3;  // padded level L-3
     float dx1, dx2, dx3, dxL;
-    const float* q4;    // [8^(L-4)][64][D] or nullptr
     const int32_t* blob;  // [rounds][D / DC][blob_words]
     int blob_words;
     const float* gloc;  // [D][8]
@@ -67,22 +66,62 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     const int64_t S2 = ((int64_t)1 << (L1 - 1)) + 2 * kHalo;
     const int64_t S3 = ((int64_t)1 << (L1 - 2)) + 2 * kHalo;
 
-    // stage the three neighbourhoods (coalesced global reads, scattered LDS writes)
-    for (int i = threadIdx.x; i < k1Side * k1Side * k1Side; i += kThreads) {
-        const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
-        // level L-1 coordinate X1 + xx - 4, padded index + kHalo
-        const float v = a.lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
-        s1[slot1(xx) + k1Py * slot1(yy) + k1Pz * slot1(zz)] = v;
-    }
-    for (int i = threadIdx.x; i < k2Side * k2Side * k2Side; i += kThreads) {
-        const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
-        const float v = a.lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
-        s2[slot2(xx) + k2Py * slot2(yy) + k2Pz * slot2(zz)] = v;
-    }
-    for (int i = threadIdx.x; i < k3Side * k3Side * k3Side; i += kThreads) {
-        const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
-        const float v = a.lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
-        s3[xx + k3Py * yy + k3Pz * zz] = v;
+    // stage the three neighbourhoods: all global loads of a thread are issued
+    // before its (scattered) LDS writes
+    {
+        constexpr int n1 = k1Side * k1Side * k1Side, n2 = k2Side * k2Side * k2Side, n3 = k3Side * k3Side * k3Side;
+        constexpr int r1 = (n1 + kThreads - 1) / kThreads, r2 = (n2 + kThreads - 1) / kThreads,
+                      r3 = (n3 + kThreads - 1) / kThreads;
+        float v1[r1], v2[r2], v3[r3];
+#pragma unroll
+        for (int q = 0; q < r1; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n1) {
+                const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
+                // level L-1 coordinate X1 + xx - 4, padded index + kHalo
+                v1[q] = a.lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < r2; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n2) {
+                const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
+                v2[q] = a.lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < r3; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n3) {
+                const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
+                v3[q] = a.lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < r1; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n1) {
+                const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
+                s1[slot1(xx) + k1Py * slot1(yy) + k1Pz * slot1(zz)] = v1[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < r2; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n2) {
+                const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
+                s2[slot2(xx) + k2Py * slot2(yy) + k2Pz * slot2(zz)] = v2[q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < r3; ++q) {
+            const int i = threadIdx.x + q * kThreads;
+            if (i < n3) {
+                const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
+                s3[xx + k3Py * yy + k3Pz * zz] = v3[q];
+            }
+        }
     }
 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -91,10 +130,23 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     const int pbit = 16 + ((lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2));  // parity mask bit of dl = 3
     const int b1 = lane1(lx, ly, lz), b2 = lane2(lx, ly, lz), b3 = lane3(lx, ly, lz);
     const int64_t n = (int64_t)1 << a.L;
-    const int n4 = 1 << (L1 - 3);  // level L-4 cells per axis
     constexpr int kChunks = D / DC;
     const int4* hdr = tab + wave * DC;   // this wave's headers
     const int4* ent0 = tab + 16 * DC;    // entry pairs
+    constexpr int kTabRegs = (kTabWords / 4 + kThreads - 1) / kThreads;  // int4 per thread
+    const int nblob4 = a.blob_words / 4;
+    static_assert(kTabRegs <= 4, "prefetch registers are unrolled by hand");
+    int4 pre0 = make_int4(0, 0, 0, 0), pre1 = pre0, pre2 = pre0, pre3 = pre0;
+#define CD_FETCH_BLOB(rr, kk)                                                                                  \
+    do {                                                                                                       \
+        const int4* src_ = reinterpret_cast<const int4*>(a.blob + (int64_t)((rr) * kChunks + (kk)) * a.blob_words); \
+        const int i0_ = threadIdx.x;                                                                           \
+        if (i0_ < nblob4) pre0 = src_[i0_];                                                                    \
+        if (i0_ + kThreads < nblob4) pre1 = src_[i0_ + kThreads];                                              \
+        if (i0_ + 2 * kThreads < nblob4) pre2 = src_[i0_ + 2 * kThreads];                                      \
+        if (i0_ + 3 * kThreads < nblob4) pre3 = src_[i0_ + 3 * kThreads];                                      \
+    } while (0)
+    CD_FETCH_BLOB(0, 0);
 
     for (int r = 0; r < kRounds; ++r) {
         const int ci = r * 16 + wave;  // configuration class, wave-uniform
@@ -102,43 +154,29 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
         const int Ax = X1 + 4 * lx + cx, Ay = Y1 + 4 * ly + cy, Az = Z1 + 4 * lz + cz;
 
         const int64_t oct = ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
-        const float* q = nullptr;
-        if (a.q4) {
-            const int64_t cell = ((int64_t)(Az >> 3) * n4 + (Ay >> 3)) * n4 + (Ax >> 3);
-            const int code = ((Ax >> 1) & 3) + 4 * ((Ay >> 1) & 3) + 16 * ((Az >> 1) & 3);
-            q = a.q4 + (cell * 64 + code) * D;
-        }
-
 #pragma unroll 1
         for (int k = 0; k < kChunks; ++k) {
             const int d0 = k * DC;
-            // weight lists of this round and chunk into LDS
+            // weight lists of this round and chunk into LDS (fetched during the
+            // previous chunk), then fetch the next ones
             __syncthreads();
             {
-                const int4* src = reinterpret_cast<const int4*>(a.blob + (int64_t)(r * kChunks + k) * a.blob_words);
-                for (int i = threadIdx.x; i < a.blob_words / 4; i += kThreads) tab[i] = src[i];
+                const int i0 = threadIdx.x;
+                if (i0 < nblob4) tab[i0] = pre0;
+                if (i0 + kThreads < nblob4) tab[i0 + kThreads] = pre1;
+                if (i0 + 2 * kThreads < nblob4) tab[i0 + 2 * kThreads] = pre2;
+                if (i0 + 3 * kThreads < nblob4) tab[i0 + 3 * kThreads] = pre3;
             }
             __syncthreads();
+            {
+                const int nk = (k + 1 < kChunks) ? k + 1 : 0;
+                const int nr = (k + 1 < kChunks) ? r : r + 1;
+                if (nr < kRounds) CD_FETCH_BLOB(nr, nk);
+            }
 
             float acc[DC];
-            if (q) {
-                if constexpr (DC % 4 == 0) {
 #pragma unroll
-                    for (int j = 0; j < DC; j += 4) {
-                        const float4 v = *reinterpret_cast<const float4*>(q + d0 + j);
-                        acc[j] = v.x;
-                        acc[j + 1] = v.y;
-                        acc[j + 2] = v.z;
-                        acc[j + 3] = v.w;
-                    }
-                } else {
-#pragma unroll
-                    for (int j = 0; j < DC; ++j) acc[j] = q[d0 + j];
-                }
-            } else {
-#pragma unroll
-                for (int j = 0; j < DC; ++j) acc[j] = 0.f;
-            }
+            for (int j = 0; j < DC; ++j) acc[j] = 0.f;
 
             // external shells dl = 1, 2, 3 (pairs of (LDS offset, weight))
 #pragma unroll
@@ -193,6 +231,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
             }
         }
     }
+#undef CD_FETCH_BLOB
 }
 
 template <int D, int DC>
@@ -209,7 +248,7 @@ bool tiled_supported(const cd_tree* t, const cd_weights* w) {
     const int D = w->D;
     if (!t->uniform || L < 5) return false;
     if (!(D == 6 || D == 12 || D == 24 || D == 40 || D == 48)) return false;
-    return w->host.tile_dc == tile_chunk(D) && w->host.blob_words <= tile::kTabWords;
+    return w->host.tile_dc == tile_chunk(D) && w->host.blob_words > 0 && w->host.blob_words <= tile::kTabWords;
 }
 
 // Tile layers [tz0, tz0 + nz) along z.
@@ -226,7 +265,6 @@ bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int 
     a.dx2 = (float)(t->box_cm * std::ldexp(1.0, -(L - 2)));
     a.dx3 = (float)(t->box_cm * std::ldexp(1.0, -(L - 3)));
     a.dxL = (float)(t->box_cm * std::ldexp(1.0, -L));
-    a.q4 = (L - 4 >= 2) ? t->q[L - 4] : nullptr;
     a.blob = w->blob;
     a.blob_words = w->host.blob_words;
     a.gloc = w->gloc;

@@ -43,19 +43,51 @@ __global__ void k_pyramid_level(const float* __restrict__ in, int l, float* __re
     out[((k + kHalo) * So + (j + kHalo)) * So + (i + kHalo)] = 0.125f * s;
 }
 
+// Levels l+1 and l from level l+2 (the leaves of a uniform grid when
+// l + 2 == L, else a padded level): each thread averages a 4^3 block into its
+// 8 level-(l+1) means and their level-l mean (same order of operations as
+// one level at a time).
+__global__ void k_pyramid_two(const float* __restrict__ in, bool in_is_leaf, int l, float* __restrict__ out1,
+                              float* __restrict__ out0) {
+    const int64_t n = (int64_t)1 << l;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n * n) return;
+    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
+    const int64_t n2 = 4 * n;                                  // cells per axis at level l+2
+    const int64_t Si = in_is_leaf ? n2 : n2 + 2 * kHalo;       // row pitch of the input
+    const int64_t h = in_is_leaf ? 0 : kHalo;
+    const int64_t S1 = 2 * n + 2 * kHalo, S0 = n + 2 * kHalo;
+    float m1[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+        const float* p = in + ((4 * k + 2 * cz + h) * Si + (4 * j + 2 * cy + h)) * Si + (4 * i + 2 * cx + h);
+        const float sum = ((p[0] + p[1]) + (p[Si] + p[Si + 1])) +
+                          ((p[Si * Si] + p[Si * Si + 1]) + (p[Si * Si + Si] + p[Si * Si + Si + 1]));
+        m1[c] = 0.125f * sum;
+        out1[((2 * k + cz + kHalo) * S1 + (2 * j + cy + kHalo)) * S1 + (2 * i + cx + kHalo)] = m1[c];
+    }
+    const float s0 = ((m1[0] + m1[1]) + (m1[2] + m1[3])) + ((m1[4] + m1[5]) + (m1[6] + m1[7]));
+    out0[((k + kHalo) * S0 + (j + kHalo)) * S0 + (i + kHalo)] = 0.125f * s0;
+}
+
 static int launch_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 // Rebuild the dense padded levels below `top` (the finest dense level
 // already filled, or the leaves for a uniform grid).
 int build_uniform_pyramid(cd_tree* t, hipStream_t s) {
     const int L = t->lmax;
-    if (L >= 1) {
-        const int64_t n1 = (int64_t)1 << (L - 1);
-        k_pyramid_from_leaves<<<launch_blocks(n1 * n1 * n1), 256, 0, s>>>(t->leaf, L, t->lev[L - 1]);
-        for (int l = L - 2; l >= 0; --l) {
-            const int64_t n = (int64_t)1 << l;
-            k_pyramid_level<<<launch_blocks(n * n * n), 256, 0, s>>>(t->lev[l + 1], l, t->lev[l]);
-        }
+    int top = L;  // finest level already available
+    while (top >= 2) {
+        const int l = top - 2;
+        const int64_t n = (int64_t)1 << l;
+        const float* in = (top == L) ? t->leaf : t->lev[top];
+        k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, top == L, l, t->lev[l + 1], t->lev[l]);
+        top = l;
+    }
+    if (top == 1) {
+        if (L == 1) k_pyramid_from_leaves<<<1, 256, 0, s>>>(t->leaf, 1, t->lev[0]);
+        else k_pyramid_level<<<1, 256, 0, s>>>(t->lev[1], 0, t->lev[0]);
     }
     CD_HIP(hipGetLastError());
     return CD_OK;
@@ -127,11 +159,49 @@ extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, void* stream)
         return CD_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_PYRAMID][0], s));
+    int rc;
     if (t->uniform) {
         t->leaf = leaf_n_dev;
-        return cd::build_uniform_pyramid(t, s);
+        rc = cd::build_uniform_pyramid(t, s);
+    } else {
+        rc = cd::amr_update(t, leaf_n_dev, s);
     }
-    return cd::amr_update(t, leaf_n_dev, s);
+    if (t->prof && rc == CD_OK) {
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_PYRAMID][1], s));
+        t->pran[CD_STAGE_PYRAMID] = true;
+    }
+    return rc;
+}
+
+extern "C" int cd_profile_enable(cd_tree* t, int on) {
+    cd::clear_error();
+    if (!t) {
+        cd::set_error("cd_profile_enable: NULL tree");
+        return CD_EINVAL;
+    }
+    if (on && !t->pev[0][0]) {
+        for (auto& st : t->pev)
+            for (auto& e : st) CD_HIP(hipEventCreate(&e));
+    }
+    t->prof = on != 0;
+    for (auto& r : t->pran) r = false;
+    return CD_OK;
+}
+
+extern "C" int cd_profile_read(cd_tree* t, float* ms) {
+    cd::clear_error();
+    if (!t || !ms) {
+        cd::set_error("cd_profile_read: NULL argument");
+        return CD_EINVAL;
+    }
+    for (int k = 0; k < CD_NUM_STAGES; ++k) {
+        ms[k] = 0.f;
+        if (!t->pran[k]) continue;
+        CD_HIP(hipEventSynchronize(t->pev[k][1]));
+        CD_HIP(hipEventElapsedTime(&ms[k], t->pev[k][0], t->pev[k][1]));
+    }
+    return CD_OK;
 }
 
 extern "C" int cd_tree_n_leaf(const cd_tree* t, int64_t* n_leaf) {
@@ -174,6 +244,9 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
     }
     if (t->d_baseleaf) (void)hipFree(t->d_baseleaf);
     if (t->ext) (void)hipFree(t->ext);
+    for (auto& st : t->pev)
+        for (auto& e : st)
+            if (e) (void)hipEventDestroy(e);
     if (t->aux) {
         (void)hipStreamSynchronize(t->aux);
         for (auto& e : t->ev)
