@@ -1,15 +1,530 @@
-// AMR trees: not yet provided.
+// Adaptive trees: a full base grid (level B) plus refined octs up to Lmax
+// (the fully threaded tree of Sect. 3).
+//
+// Storage: the dense padded pyramid levels 0..B (as for uniform grids) and,
+// for each level l > B, the densities of its octs' 8 cells (oct order) and a
+// dense map from the level-(l-1) cells to their oct (or -1).  A level-l
+// position with no cell reads the covering coarser leaf, so every cell
+// reaches the coarser levels (Sect. 3).  A refined cell holds the mean of its
+// children.
+//
+// Sweep: one thread per target oct (an oct, or a 2x2x2 block of base cells,
+// holding at least one leaf).  Shells dl = 1, 2, 3 come from the generic
+// weight lists; shells dl >= 4 at levels above the dense base grid follow the
+// per-axis inner-limit automaton with the dl >= 4 lists; the rest is one read
+// of the dense coarse table Q_l (all 216 state codes, since targets sit at
+// several levels; the table at Lmax - 4 is read only from level Lmax and keeps
+// the 64 codes of dl = 4).  Then the internal + local part of the oct's leaf
+// children, their rows of N and chi.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
 #include "tree_amr.h"
 
 namespace cd {
-int amr_build(cd_tree*, const int64_t*, const int32_t* const*, const float*, int64_t, hipStream_t) {
-    set_error("cd_build_tree: AMR trees are not provided by this build");
-    return CD_EUNSUPPORTED;
+
+struct AmrHost {
+    std::vector<int64_t> base_dst;   // per base leaf: padded index in level B
+    std::vector<int64_t> oct_dst;    // per oct leaf: index into the oct densities
+    std::vector<int64_t> den_off;    // [l]: offset of level l's oct densities (l > B)
+    std::vector<int64_t> oct_first;  // [l]: first oct of level l in the concatenation
+    std::vector<int64_t> par_dst;    // per oct: parent slot, -(1 + padded base index) or oct-density index
+    std::vector<int32_t> tg_info;    // [n_tg][4]: level of the children, oct coordinates (x, y, z)
+    std::vector<int64_t> tg_src;     // [n_tg][8]: child density slot (as par_dst)
+    std::vector<int64_t> tg_leaf;    // [n_tg][8]: leaf index of the child or -1
+    std::vector<int8_t> leaf_level;
+    std::vector<int32_t> leaf_ijk;
+};
+
+struct AmrDev {
+    float* octden = nullptr;  // every oct's 8 densities, levels B+1 .. Lmax
+    int64_t* base_dst = nullptr;
+    int64_t* oct_dst = nullptr;
+    int64_t* par_dst = nullptr;
+    int32_t* tg_info = nullptr;
+    int64_t* tg_src = nullptr;
+    int64_t* tg_leaf = nullptr;
+    int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0;
+    std::vector<void*> mem;
+    AmrHost h;
+};
+
+static inline int64_t padded_index(int l, int64_t i, int64_t j, int64_t k) {
+    const int64_t S = ((int64_t)1 << l) + 2 * kHalo;
+    return ((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo);
 }
-int amr_update(cd_tree*, const float*, hipStream_t) {
-    set_error("cd_tree_update: AMR trees are not provided by this build");
-    return CD_EUNSUPPORTED;
+
+// ------------------------------------------------------------------ kernels --
+__global__ void k_scatter(const float* __restrict__ src, const int64_t* __restrict__ dst, int64_t n,
+                          float* __restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < n) out[dst[q]] = src[q];
 }
-int amr_leaf_coords(const cd_tree*, int8_t*, int32_t*) { return CD_EUNSUPPORTED; }
-int amr_columns(cd_tree*, const cd_weights*, float*, float*, float, hipStream_t) { return CD_EUNSUPPORTED; }
+
+// Mean of each oct of one level, written to its parent's slot.
+__global__ void k_oct_mean(int64_t first, int64_t n, const int64_t* __restrict__ pdst, float* __restrict__ octden,
+                           float* __restrict__ base) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= n) return;
+    const float* c = octden + (first + o) * 8;
+    const float m = 0.125f * (((c[0] + c[1]) + (c[2] + c[3])) + ((c[4] + c[5]) + (c[6] + c[7])));
+    const int64_t d = pdst[first + o];
+    if (d < 0) base[-(d + 1)] = m;
+    else octden[d] = m;
+}
+
+struct AmrLookup {
+    const float* lev[CD_MAX_LEVEL + 1];       // padded dense levels 0..B
+    const int32_t* octidx[CD_MAX_LEVEL + 1];  // [l > B] over the level-(l-1) grid
+    const float* den[CD_MAX_LEVEL + 1];       // [l > B] oct densities of level l
+    int B;
+};
+
+// Density of the level-l cell (i, j, k): zero outside the box; a position
+// without a level-l cell reads the covering coarser leaf.
+__device__ __forceinline__ float amr_density(const AmrLookup& t, int l, int64_t i, int64_t j, int64_t k) {
+    int64_t n = (int64_t)1 << l;
+    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0.f;
+    while (l > t.B) {
+        const int64_t pi = i >> 1, pj = j >> 1, pk = k >> 1;
+        const int64_t np = n >> 1;
+        const int32_t o = t.octidx[l][(pk * np + pj) * np + pi];
+        if (o >= 0) return t.den[l][(int64_t)o * 8 + ((i & 1) | ((j & 1) << 1) | ((k & 1) << 2))];
+        i = pi;
+        j = pj;
+        k = pk;
+        n = np;
+        --l;
+    }
+    const int64_t S = n + 2 * kHalo;
+    return t.lev[l][((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)];
+}
+
+struct AmrSweepArgs {
+    AmrLookup lk;
+    const int32_t* tg_info;
+    const int64_t* tg_src;
+    const int64_t* tg_leaf;
+    int64_t n_tg;
+    const float* octden;
+    const float* base;  // padded level B
+    const int32_t* off[5];
+    const float* w[5];
+    int len[5];
+    const float* kloc;
+    const float* q[CD_MAX_LEVEL + 1];  // coarse tables of levels 2 .. qtop, 216 codes
+    int qtop;
+    int qcompact;  // Q_qtop holds only the 64 codes of dl = 4 (qtop == Lmax - 4)
+    int8_t next[6][2];
+    int8_t dl4[4];
+    double box;
+    int D;
+    float* N;
+    float* chi;
+    float chi_scale;
+};
+
+__device__ __forceinline__ int sx8(int v) { return (int)(int8_t)(v & 0xff); }
+
+// Sum over one shell's weight list of (configuration, direction).
+__device__ __forceinline__ float list_sum(const AmrLookup& lk, const int32_t* off, const float* w, int len,
+                                          int64_t row, int l, const int64_t (&C)[3]) {
+    float s = 0.f;
+    for (int e = 0; e < len; ++e) {
+        const float wt = w[row + e];
+        if (wt == 0.f) continue;  // padding
+        const int pk = off[row + e];
+        s = fmaf(wt, amr_density(lk, l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16)), s);
+    }
+    return s;
+}
+
+template <int DC>
+__global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.n_tg) return;
+    const int l0 = a.tg_info[4 * g];  // level of the targets; the oct's cell is at l0 - 1
+    const int64_t A[3] = {a.tg_info[4 * g + 1], a.tg_info[4 * g + 2], a.tg_info[4 * g + 3]};
+    float ln[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int64_t s = a.tg_src[8 * g + c];
+        ln[c] = s >= 0 ? a.octden[s] : a.base[-(s + 1)];
+    }
+    const float dxL = (float)(a.box * ldexp(1.0, -l0));
+    // configuration codes of the shells dl = 1, 2, 3 (bits of A, A >> 1, A >> 2)
+    int combo[4] = {0, 0, 0, 0};
+    int st0[3];
+    for (int k = 2; k >= 0; --k) {
+        combo[1] = combo[1] * 2 + (int)(A[k] & 1);
+        combo[2] = combo[2] * 4 + (int)(A[k] & 3);
+        combo[3] = combo[3] * 8 + (int)(A[k] & 7);
+        st0[k] = a.dl4[(A[k] >> 1) & 3];  // inner-limit state at dl = 4
+    }
+    float chis[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) chis[c] = 0.f;
+    for (int d0 = 0; d0 < a.D; d0 += DC) {
+        float acc[DC];
+#pragma unroll
+        for (int j = 0; j < DC; ++j) acc[j] = 0.f;
+        // dl = 1, 2, 3
+#pragma unroll
+        for (int kind = 1; kind <= 3; ++kind) {
+            const int l = l0 - kind;
+            if (l < 0) break;
+            const float dx = (float)(a.box * ldexp(1.0, -l));
+            const int64_t C[3] = {A[0] >> (kind - 1), A[1] >> (kind - 1), A[2] >> (kind - 1)};
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                const int d = d0 + j;
+                if (d < a.D) {
+                    const int64_t row = ((int64_t)combo[kind] * a.D + d) * a.len[kind];
+                    acc[j] = fmaf(dx, list_sum(a.lk, a.off[kind], a.w[kind], a.len[kind], row, l, C), acc[j]);
+                }
+            }
+        }
+        // dl >= 4 above the coarse tables: walk the inner-limit automaton
+        int st[3] = {st0[0], st0[1], st0[2]};
+        int l = l0 - 4;
+        for (; l >= 2 && l > a.qtop; --l) {
+            const int sh = l0 - 1 - l;
+            const int64_t C[3] = {A[0] >> sh, A[1] >> sh, A[2] >> sh};
+            int cb = 0;
+            for (int k = 2; k >= 0; --k) cb = cb * 12 + 6 * (int)(C[k] & 1) + st[k];
+            const float dx = (float)(a.box * ldexp(1.0, -l));
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                const int d = d0 + j;
+                if (d < a.D) {
+                    const int64_t row = ((int64_t)cb * a.D + d) * a.len[4];
+                    acc[j] = fmaf(dx, list_sum(a.lk, a.off[4], a.w[4], a.len[4], row, l, C), acc[j]);
+                }
+            }
+            for (int k = 0; k < 3; ++k) st[k] = a.next[st[k]][C[k] & 1];
+        }
+        if (l >= 2) {
+            // every remaining level at once: Q_l of the level-l ancestor
+            const int sh = l0 - 1 - l;
+            const int64_t nq = (int64_t)1 << l;
+            const int64_t cell = ((A[2] >> sh) * nq + (A[1] >> sh)) * nq + (A[0] >> sh);
+            // at qtop == Lmax - 4 only targets at Lmax arrive, with st == st0
+            const int64_t code = (a.qcompact && l == a.qtop)
+                                     ? cell * 64 + ((A[0] >> 1) & 3) + 4 * ((A[1] >> 1) & 3) + 16 * ((A[2] >> 1) & 3)
+                                     : cell * 216 + st[0] + 6 * st[1] + 36 * st[2];
+            const float* qr = a.q[l] + code * a.D;
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+                if (d0 + j < a.D) acc[j] += qr[d0 + j];
+        }
+        // internal + local of the oct's leaf children
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t leaf = a.tg_leaf[8 * g + c];
+            if (leaf < 0) continue;
+            float* out = a.N + leaf * a.D;
+#pragma unroll
+            for (int j = 0; j < DC; ++j) {
+                const int d = d0 + j;
+                if (d < a.D) {
+                    float s = 0.f;
+#pragma unroll
+                    for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(c * 8 + sb) * a.D + d], s);
+                    const float v = fmaf(dxL, s, acc[j]);
+                    out[d] = v;
+                    chis[c] += expf(-a.chi_scale * v);
+                }
+            }
+        }
+    }
+    if (a.chi) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            const int64_t leaf = a.tg_leaf[8 * g + c];
+            if (leaf >= 0) a.chi[leaf] = chis[c] / (float)a.D;
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host --
+template <class T>
+static int dev_copy(const std::vector<T>& h, T** d, hipStream_t s, std::vector<void*>& own) {
+    const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+    if (hipMalloc((void**)d, bytes) != hipSuccess) {
+        set_error("hipMalloc of %zu bytes (adaptive tree) failed", bytes);
+        return CD_ENOMEM;
+    }
+    own.push_back(*d);
+    if (!h.empty()) CD_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return CD_OK;
+}
+
+constexpr int kAmrMaxLevel = 10;  // dense oct maps: 4 * 8^(Lmax-1) bytes at the finest level
+
+int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, const float* leaf_n_dev,
+              int64_t n_leaf, hipStream_t s) {
+    const int B = t->base, L = t->lmax;
+    if (B < 1 || L > kAmrMaxLevel || !n_octs || !oct_parents) {
+        set_error("cd_build_tree: adaptive trees need base level >= 1, max level <= %d and oct lists",
+                  kAmrMaxLevel);
+        return CD_EINVAL;
+    }
+    AmrDev* A = new AmrDev();
+    t->amr = A;
+    AmrHost& h = A->h;
+    // structure and dense oct maps
+    std::vector<std::vector<int32_t>> octidx(L + 1);
+    t->h_octpar.assign(L + 1, {});
+    h.oct_first.assign(L + 1, 0);
+    h.den_off.assign(L + 1, 0);
+    int64_t total_octs = 0;
+    for (int l = B + 1; l <= L; ++l) {
+        const int64_t no = n_octs[l - B - 1];
+        const int64_t np = (int64_t)1 << (l - 1);
+        if (no < 0 || no > np * np * np || (no > 0 && !oct_parents[l - B - 1])) {
+            set_error("cd_build_tree: bad oct list at level %d", l);
+            return CD_EINVAL;
+        }
+        t->n_octs[l] = no;
+        if (no > 0) t->h_octpar[l].assign(oct_parents[l - B - 1], oct_parents[l - B - 1] + 3 * no);
+        octidx[l].assign((size_t)(np * np * np), -1);
+        for (int64_t o = 0; o < no; ++o) {
+            const int32_t* p = &t->h_octpar[l][3 * o];
+            if (p[0] < 0 || p[1] < 0 || p[2] < 0 || p[0] >= np || p[1] >= np || p[2] >= np) {
+                set_error("cd_build_tree: oct parent outside the level-%d grid", l - 1);
+                return CD_EINVAL;
+            }
+            int32_t& slot = octidx[l][(size_t)((p[2] * np + p[1]) * np + p[0])];
+            if (slot >= 0) {
+                set_error("cd_build_tree: cell refined twice at level %d", l - 1);
+                return CD_EINVAL;
+            }
+            slot = (int32_t)o;
+            if (l - 1 > B) {
+                const int64_t npp = np >> 1;
+                if (octidx[l - 1][(size_t)(((p[2] >> 1) * npp + (p[1] >> 1)) * npp + (p[0] >> 1))] < 0) {
+                    set_error("cd_build_tree: oct at level %d has no parent cell", l);
+                    return CD_EINVAL;
+                }
+            }
+        }
+        h.oct_first[l] = total_octs;
+        h.den_off[l] = total_octs * 8;
+        total_octs += no;
+    }
+    auto refined = [&](int l, int64_t i, int64_t j, int64_t k) -> bool {
+        if (l >= L) return false;
+        const int64_t n = (int64_t)1 << l;
+        return octidx[l + 1][(size_t)((k * n + j) * n + i)] >= 0;
+    };
+    // leaves in the documented order
+    const int64_t nb = (int64_t)1 << B;
+    std::vector<int64_t> base_leaf((size_t)(nb * nb * nb), -1);
+    for (int64_t k = 0; k < nb; ++k)
+        for (int64_t j = 0; j < nb; ++j)
+            for (int64_t i = 0; i < nb; ++i)
+                if (!refined(B, i, j, k)) {
+                    base_leaf[(size_t)((k * nb + j) * nb + i)] = (int64_t)h.base_dst.size();
+                    h.base_dst.push_back(padded_index(B, i, j, k));
+                    h.leaf_level.push_back((int8_t)B);
+                    h.leaf_ijk.insert(h.leaf_ijk.end(), {(int32_t)i, (int32_t)j, (int32_t)k});
+                }
+    A->n_base_leaf = (int64_t)h.base_dst.size();
+    std::vector<std::vector<int64_t>> child_leaf(L + 1);
+    for (int l = B + 1; l <= L; ++l) {
+        child_leaf[l].assign((size_t)t->n_octs[l] * 8, -1);
+        for (int64_t o = 0; o < t->n_octs[l]; ++o)
+            for (int c = 0; c < 8; ++c) {
+                const int32_t* p = &t->h_octpar[l][3 * o];
+                const int64_t i = 2 * p[0] + (c & 1), j = 2 * p[1] + ((c >> 1) & 1), k = 2 * p[2] + (c >> 2);
+                if (!refined(l, i, j, k)) {
+                    child_leaf[l][o * 8 + c] = A->n_base_leaf + (int64_t)h.oct_dst.size();
+                    h.oct_dst.push_back(h.den_off[l] + o * 8 + c);
+                    h.leaf_level.push_back((int8_t)l);
+                    h.leaf_ijk.insert(h.leaf_ijk.end(), {(int32_t)i, (int32_t)j, (int32_t)k});
+                }
+            }
+    }
+    A->n_oct_leaf = (int64_t)h.oct_dst.size();
+    if (A->n_base_leaf + A->n_oct_leaf != n_leaf) {
+        set_error("cd_build_tree: the structure has %lld leaves, got %lld",
+                  (long long)(A->n_base_leaf + A->n_oct_leaf), (long long)n_leaf);
+        return CD_EINVAL;
+    }
+    t->n_leaf = n_leaf;
+    // parent slot of every oct
+    h.par_dst.assign((size_t)std::max<int64_t>(total_octs, 1), 0);
+    for (int l = B + 1; l <= L; ++l)
+        for (int64_t o = 0; o < t->n_octs[l]; ++o) {
+            const int32_t* p = &t->h_octpar[l][3 * o];
+            int64_t d;
+            if (l - 1 == B) {
+                d = -(1 + padded_index(B, p[0], p[1], p[2]));
+            } else {
+                const int64_t npp = (int64_t)1 << (l - 2);
+                const int32_t po = octidx[l - 1][(size_t)(((p[2] >> 1) * npp + (p[1] >> 1)) * npp + (p[0] >> 1))];
+                const int c = (p[0] & 1) | ((p[1] & 1) << 1) | ((p[2] & 1) << 2);
+                d = h.den_off[l - 1] + (int64_t)po * 8 + c;
+            }
+            h.par_dst[(size_t)(h.oct_first[l] + o)] = d;
+        }
+    // target octs: 2x2x2 base blocks holding a base leaf, then octs holding a leaf
+    const int64_t nb1 = nb >> 1;
+    for (int64_t k = 0; k < nb1; ++k)
+        for (int64_t j = 0; j < nb1; ++j)
+            for (int64_t i = 0; i < nb1; ++i) {
+                int64_t src[8], lf[8];
+                bool any = false;
+                for (int c = 0; c < 8; ++c) {
+                    const int64_t ci = 2 * i + (c & 1), cj = 2 * j + ((c >> 1) & 1), ck = 2 * k + (c >> 2);
+                    src[c] = -(1 + padded_index(B, ci, cj, ck));
+                    lf[c] = base_leaf[(size_t)((ck * nb + cj) * nb + ci)];
+                    any |= lf[c] >= 0;
+                }
+                if (!any) continue;
+                h.tg_info.insert(h.tg_info.end(), {B, (int32_t)i, (int32_t)j, (int32_t)k});
+                h.tg_src.insert(h.tg_src.end(), src, src + 8);
+                h.tg_leaf.insert(h.tg_leaf.end(), lf, lf + 8);
+            }
+    for (int l = B + 1; l <= L; ++l)
+        for (int64_t o = 0; o < t->n_octs[l]; ++o) {
+            bool any = false;
+            for (int c = 0; c < 8; ++c) any |= child_leaf[l][o * 8 + c] >= 0;
+            if (!any) continue;
+            const int32_t* p = &t->h_octpar[l][3 * o];
+            h.tg_info.insert(h.tg_info.end(), {l, p[0], p[1], p[2]});
+            for (int c = 0; c < 8; ++c) {
+                h.tg_src.push_back(h.den_off[l] + o * 8 + c);
+                h.tg_leaf.push_back(child_leaf[l][o * 8 + c]);
+            }
+        }
+    A->n_tg = (int64_t)(h.tg_info.size() / 4);
+    // device memory
+    int rc = alloc_dense_levels(t, B, s);
+    if (rc != CD_OK) return rc;
+    {
+        const size_t bytes = (size_t)std::max<int64_t>(total_octs * 8, 1) * sizeof(float);
+        if (hipMalloc((void**)&A->octden, bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes (oct densities) failed", bytes);
+            return CD_ENOMEM;
+        }
+        A->mem.push_back(A->octden);
+    }
+    std::vector<void*> maps;  // owned through t->d_octidx
+    for (int l = B + 1; l <= L; ++l) {
+        rc = dev_copy(octidx[l], &t->d_octidx[l], s, maps);
+        if (rc != CD_OK) return rc;
+    }
+    if ((rc = dev_copy(h.base_dst, &A->base_dst, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.oct_dst, &A->oct_dst, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.par_dst, &A->par_dst, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.tg_info, &A->tg_info, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.tg_src, &A->tg_src, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.tg_leaf, &A->tg_leaf, s, A->mem)) != CD_OK) return rc;
+    CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
+    return amr_update(t, leaf_n_dev, s);
+}
+
+int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s) {
+    AmrDev* A = t->amr;
+    const int B = t->base, L = t->lmax;
+    if (A->n_base_leaf > 0)
+        k_scatter<<<(unsigned)((A->n_base_leaf + 255) / 256), 256, 0, s>>>(leaf_n_dev, A->base_dst, A->n_base_leaf,
+                                                                         t->lev[B]);
+    if (A->n_oct_leaf > 0)
+        k_scatter<<<(unsigned)((A->n_oct_leaf + 255) / 256), 256, 0, s>>>(leaf_n_dev + A->n_base_leaf, A->oct_dst,
+                                                                        A->n_oct_leaf, A->octden);
+    for (int l = L; l > B; --l) {  // finest first: a refined cell's mean is ready before its own oct's
+        const int64_t no = t->n_octs[l];
+        if (no > 0)
+            k_oct_mean<<<(unsigned)((no + 255) / 256), 256, 0, s>>>(A->h.oct_first[l], no, A->par_dst, A->octden,
+                                                                   t->lev[B]);
+    }
+    CD_HIP(hipGetLastError());
+    return build_dense_below(t, B, s);
+}
+
+int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
+    const AmrHost& h = t->amr->h;
+    std::memcpy(level, h.leaf_level.data(), h.leaf_level.size());
+    std::memcpy(ijk, h.leaf_ijk.data(), h.leaf_ijk.size() * sizeof(int32_t));
+    return CD_OK;
+}
+
+int ensure_q(cd_tree* t, int D, int top, bool compact);                                     // sweep.hip
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s);  // sweep.hip
+
+int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+    AmrDev* A = t->amr;
+    const int B = t->base, L = t->lmax;
+    const int qtop = std::min(B, L - 4);  // coarse tables only on dense levels
+    if (w->len[4] != 12) {
+        set_error("internal: coarse weight lists of length %d, expected 12", w->len[4]);
+        return CD_EINVAL;
+    }
+    const bool compact = qtop == L - 4;
+    int rc = ensure_q(t, w->D, qtop, compact);
+    if (rc != CD_OK) return rc;
+    if (t->prof) {
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], s));
+    }
+    launch_coarse(t, w, qtop, compact, s);
+    if (t->prof) {
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], s));
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_ROWS][0], s));
+    }
+    AmrSweepArgs a{};
+    for (int l = 0; l <= B; ++l) a.lk.lev[l] = t->lev[l];
+    for (int l = B + 1; l <= L; ++l) {
+        a.lk.octidx[l] = t->d_octidx[l];
+        a.lk.den[l] = A->octden + A->h.den_off[l];
+    }
+    a.lk.B = B;
+    a.tg_info = A->tg_info;
+    a.tg_src = A->tg_src;
+    a.tg_leaf = A->tg_leaf;
+    a.n_tg = A->n_tg;
+    a.octden = A->octden;
+    a.base = t->lev[B];
+    for (int k = 1; k <= 4; ++k) {
+        a.off[k] = w->off[k];
+        a.w[k] = w->w[k];
+        a.len[k] = w->len[k];
+    }
+    a.kloc = w->kloc;
+    for (int l = 2; l <= qtop; ++l) a.q[l] = t->q[l];
+    a.qtop = qtop;
+    a.qcompact = compact ? 1 : 0;
+    for (int sc = 0; sc < 6; ++sc)
+        for (int p = 0; p < 2; ++p) a.next[sc][p] = (int8_t)next_state_code(sc, p);
+    for (int q = 0; q < 4; ++q) a.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
+    a.box = t->box_cm;
+    a.D = w->D;
+    a.N = N;
+    a.chi = chi;
+    a.chi_scale = chi_scale;
+    if (A->n_tg > 0) {
+        const unsigned blocks = (unsigned)((A->n_tg + 255) / 256);
+        if (w->D <= 12) k_amr_octs<12><<<blocks, 256, 0, s>>>(a);
+        else k_amr_octs<16><<<blocks, 256, 0, s>>>(a);
+    }
+    CD_HIP(hipGetLastError());
+    if (t->prof) {
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_ROWS][1], s));
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][1], s));
+        t->pran[CD_STAGE_SWEEP] = t->pran[CD_STAGE_COARSE] = t->pran[CD_STAGE_ROWS] = true;
+    }
+    return CD_OK;
+}
+
+void amr_free(cd_tree* t) {
+    if (!t->amr) return;
+    for (void* p : t->amr->mem) (void)hipFree(p);
+    delete t->amr;
+    t->amr = nullptr;
+}
+
 }  // namespace cd

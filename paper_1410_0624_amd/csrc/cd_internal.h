@@ -12,6 +12,8 @@
 
 namespace cd {
 
+struct AmrDev;
+
 // ----------------------------------------------------------------- errors --
 void set_error(const char* fmt, ...);
 void clear_error();
@@ -123,12 +125,9 @@ struct cd_tree {
     const float* leaf = nullptr;  // uniform grids: the caller's leaf array (row-major)
     // AMR part (levels base+1 .. lmax)
     int64_t n_octs[CD_MAX_LEVEL + 1] = {0};
-    int32_t* d_octidx[CD_MAX_LEVEL + 1] = {nullptr};  // [l] over the level-(l-1) grid
-    int32_t* d_octpar[CD_MAX_LEVEL + 1] = {nullptr};  // [l] n_octs * 3
-    float* d_octden[CD_MAX_LEVEL + 1] = {nullptr};    // [l] n_octs * 8
-    int64_t* d_octleaf[CD_MAX_LEVEL + 1] = {nullptr}; // [l] n_octs * 8 leaf index or -1
-    int64_t* d_baseleaf = nullptr;                    // base cells: leaf index or -1
+    int32_t* d_octidx[CD_MAX_LEVEL + 1] = {nullptr};  // [l] over the level-(l-1) grid: oct or -1
     std::vector<std::vector<int32_t>> h_octpar;        // host copy of the structure
+    cd::AmrDev* amr = nullptr;                         // index maps and targets (amr.hip)
     // coarse accumulated external columns (per level, per inner-state code)
     float* q[CD_MAX_LEVEL + 1] = {nullptr};
     size_t q_bytes[CD_MAX_LEVEL + 1] = {0};

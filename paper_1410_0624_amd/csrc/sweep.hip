@@ -226,8 +226,9 @@ __global__ __launch_bounds__(256) void k_screening(const float* __restrict__ N, 
 }
 
 // --------------------------------------------------------------- drivers --
-static int ensure_q(cd_tree* t, int D) {
-    const int L = t->lmax;
+// Coarse tables Q_l for levels 2 .. top; the last one holds only the 64
+// codes reachable at dl = 4 when `compact` (targets all at level top + 4).
+int ensure_q(cd_tree* t, int D, int top, bool compact) {
     if (t->q_D == D) return CD_OK;
     for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
         if (t->q[l]) (void)hipFree(t->q[l]);
@@ -235,8 +236,8 @@ static int ensure_q(cd_tree* t, int D) {
         t->q_bytes[l] = 0;
     }
     t->q_D = 0;
-    for (int l = 2; l <= L - 4; ++l) {
-        const int ncodes = (l == L - 4) ? 64 : 216;
+    for (int l = 2; l <= top; ++l) {
+        const int ncodes = (compact && l == top) ? 64 : 216;
         const size_t bytes = ((size_t)1 << (3 * l)) * ncodes * D * sizeof(float);
         if (hipMalloc((void**)&t->q[l], bytes) != hipSuccess) {
             set_error("hipMalloc of %zu bytes (coarse columns, level %d) failed", bytes, l);
@@ -283,17 +284,16 @@ static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
     k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
 }
 
-static void launch_coarse(cd_tree* t, const cd_weights* w, hipStream_t s) {
-    const int L = t->lmax;
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s) {
     const int D = w->D;
-    for (int l = 2; l <= L - 4; ++l) {
+    for (int l = 2; l <= top; ++l) {
         CoarseArgs c{};
         c.lev = t->lev[l];
         c.l = l;
         c.dx = (float)(t->box_cm * std::ldexp(1.0, -l));
         c.qprev = (l > 2) ? t->q[l - 1] : nullptr;
         c.q = t->q[l];
-        c.compact = (l == L - 4);
+        c.compact = compact && l == top;
         c.kt = {w->off[4], w->w[4], w->len[4]};
         c.D = D;
         for (int sc = 0; sc < 6; ++sc)
@@ -313,7 +313,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
         return CD_EINVAL;
     }
-    int rc = ensure_q(t, D);
+    int rc = ensure_q(t, D, L - 4, true);
     if (rc != CD_OK) return rc;
     if (L >= 1 && tiled_supported(t, w)) {
         // coarse tables (dl >= 4) on the second stream, concurrently with the
@@ -336,7 +336,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipEventRecord(t->ev[kMaxSlabs], s));
         CD_HIP(hipStreamWaitEvent(t->aux, t->ev[kMaxSlabs], 0));
         CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
-        launch_coarse(t, w, t->aux);
+        launch_coarse(t, w, L - 4, true, t->aux);
         CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         for (int j = 0; j < nslab; ++j) {
@@ -356,7 +356,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipGetLastError());
         return CD_OK;
     }
-    launch_coarse(t, w, s);
+    launch_coarse(t, w, L - 4, true, s);
     if (L >= 1) {
         FineArgs a{};
         a.leaf = t->leaf;

@@ -73,25 +73,29 @@ __global__ void k_pyramid_two(const float* __restrict__ in, bool in_is_leaf, int
 
 static int launch_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
-// Rebuild the dense padded levels below `top` (the finest dense level
-// already filled, or the leaves for a uniform grid).
-int build_uniform_pyramid(cd_tree* t, hipStream_t s) {
-    const int L = t->lmax;
-    int top = L;  // finest level already available
-    while (top >= 2) {
-        const int l = top - 2;
+// Rebuild the dense padded levels below `top`, the finest level already
+// available: the leaves of a uniform grid (top == L), or the padded base
+// level of an adaptive tree.
+int build_dense_below(cd_tree* t, int top, hipStream_t s) {
+    const bool from_leaf = t->uniform;
+    int cur = top;
+    while (cur >= 2) {
+        const int l = cur - 2;
         const int64_t n = (int64_t)1 << l;
-        const float* in = (top == L) ? t->leaf : t->lev[top];
-        k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, top == L, l, t->lev[l + 1], t->lev[l]);
-        top = l;
+        const bool leaf_in = from_leaf && cur == top;
+        const float* in = leaf_in ? t->leaf : t->lev[cur];
+        k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1], t->lev[l]);
+        cur = l;
     }
-    if (top == 1) {
-        if (L == 1) k_pyramid_from_leaves<<<1, 256, 0, s>>>(t->leaf, 1, t->lev[0]);
+    if (cur == 1) {
+        if (from_leaf && top == 1) k_pyramid_from_leaves<<<1, 256, 0, s>>>(t->leaf, 1, t->lev[0]);
         else k_pyramid_level<<<1, 256, 0, s>>>(t->lev[1], 0, t->lev[0]);
     }
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
+
+int build_uniform_pyramid(cd_tree* t, hipStream_t s) { return build_dense_below(t, t->lmax, s); }
 
 int alloc_dense_levels(cd_tree* t, int top, hipStream_t s) {
     for (int l = 0; l <= top; ++l) {
@@ -237,12 +241,9 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
     for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
         if (t->lev[l]) (void)hipFree(t->lev[l]);
         if (t->d_octidx[l]) (void)hipFree(t->d_octidx[l]);
-        if (t->d_octpar[l]) (void)hipFree(t->d_octpar[l]);
-        if (t->d_octden[l]) (void)hipFree(t->d_octden[l]);
-        if (t->d_octleaf[l]) (void)hipFree(t->d_octleaf[l]);
         if (t->q[l]) (void)hipFree(t->q[l]);
     }
-    if (t->d_baseleaf) (void)hipFree(t->d_baseleaf);
+    cd::amr_free(t);
     if (t->ext) (void)hipFree(t->ext);
     for (auto& st : t->pev)
         for (auto& e : st)
