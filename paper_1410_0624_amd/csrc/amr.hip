@@ -36,6 +36,8 @@ struct AmrHost {
     std::vector<int64_t> tg_leaf;    // [n_tg][8]: leaf index of the child or -1
     std::vector<int8_t> leaf_level;
     std::vector<int32_t> leaf_ijk;
+    std::vector<int32_t> grp;       // [ngroups][64]: target octs of one level and class (-1: none)
+    std::vector<int32_t> grp_info;  // [ngroups][2]: level, class (A mod 4 per axis)
 };
 
 struct AmrDev {
@@ -46,7 +48,9 @@ struct AmrDev {
     int32_t* tg_info = nullptr;
     int64_t* tg_src = nullptr;
     int64_t* tg_leaf = nullptr;
-    int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0;
+    int32_t* grp = nullptr;
+    int32_t* grp_info = nullptr;
+    int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0;
     std::vector<void*> mem;
     AmrHost h;
 };
@@ -75,35 +79,8 @@ __global__ void k_oct_mean(int64_t first, int64_t n, const int64_t* __restrict__
     else octden[d] = m;
 }
 
-struct AmrLookup {
-    const float* lev[CD_MAX_LEVEL + 1];       // padded dense levels 0..B
-    const int32_t* octidx[CD_MAX_LEVEL + 1];  // [l > B] over the level-(l-1) grid
-    const float* den[CD_MAX_LEVEL + 1];       // [l > B] oct densities of level l
-    int B;
-};
-
-// Density of the level-l cell (i, j, k): zero outside the box; a position
-// without a level-l cell reads the covering coarser leaf.
-__device__ __forceinline__ float amr_density(const AmrLookup& t, int l, int64_t i, int64_t j, int64_t k) {
-    int64_t n = (int64_t)1 << l;
-    if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0.f;
-    while (l > t.B) {
-        const int64_t pi = i >> 1, pj = j >> 1, pk = k >> 1;
-        const int64_t np = n >> 1;
-        const int32_t o = t.octidx[l][(pk * np + pj) * np + pi];
-        if (o >= 0) return t.den[l][(int64_t)o * 8 + ((i & 1) | ((j & 1) << 1) | ((k & 1) << 2))];
-        i = pi;
-        j = pj;
-        k = pk;
-        n = np;
-        --l;
-    }
-    const int64_t S = n + 2 * kHalo;
-    return t.lev[l][((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)];
-}
-
 struct AmrSweepArgs {
-    AmrLookup lk;
+    AmrLookupView lk;
     const int32_t* tg_info;
     const int64_t* tg_src;
     const int64_t* tg_leaf;
@@ -121,6 +98,7 @@ struct AmrSweepArgs {
     int8_t dl4[4];
     double box;
     int D;
+    const float* E;  // [n_tg][D] shells dl = 1..3 computed by the split kernel, or nullptr
     float* N;
     float* chi;
     float chi_scale;
@@ -129,14 +107,14 @@ struct AmrSweepArgs {
 __device__ __forceinline__ int sx8(int v) { return (int)(int8_t)(v & 0xff); }
 
 // Sum over one shell's weight list of (configuration, direction).
-__device__ __forceinline__ float list_sum(const AmrLookup& lk, const int32_t* off, const float* w, int len,
+__device__ __forceinline__ float list_sum(const AmrLookupView& lk, const int32_t* off, const float* w, int len,
                                           int64_t row, int l, const int64_t (&C)[3]) {
     float s = 0.f;
     for (int e = 0; e < len; ++e) {
         const float wt = w[row + e];
         if (wt == 0.f) continue;  // padding
         const int pk = off[row + e];
-        s = fmaf(wt, amr_density(lk, l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16)), s);
+        s = fmaf(wt, lk.density(l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16)), s);
     }
     return s;
 }
@@ -169,10 +147,10 @@ __global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
     for (int d0 = 0; d0 < a.D; d0 += DC) {
         float acc[DC];
 #pragma unroll
-        for (int j = 0; j < DC; ++j) acc[j] = 0.f;
+        for (int j = 0; j < DC; ++j) acc[j] = (a.E && d0 + j < a.D) ? a.E[g * a.D + d0 + j] : 0.f;
         // dl = 1, 2, 3
 #pragma unroll
-        for (int kind = 1; kind <= 3; ++kind) {
+        for (int kind = 1; kind <= 3 && !a.E; ++kind) {
             const int l = l0 - kind;
             if (l < 0) break;
             const float dx = (float)(a.box * ldexp(1.0, -l));
@@ -401,6 +379,22 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
             }
         }
     A->n_tg = (int64_t)(h.tg_info.size() / 4);
+    // groups of the split-precision kernel: up to 64 targets of one level and class
+    {
+        std::vector<std::vector<int32_t>> bykey((size_t)(L + 1) * 64);
+        for (int64_t q = 0; q < A->n_tg; ++q) {
+            const int32_t* ti = &h.tg_info[4 * q];
+            bykey[(size_t)ti[0] * 64 + (ti[1] & 3) + 4 * (ti[2] & 3) + 16 * (ti[3] & 3)].push_back((int32_t)q);
+        }
+        for (size_t key = 0; key < bykey.size(); ++key)
+            for (size_t f = 0; f < bykey[key].size(); f += 64) {
+                for (size_t e = 0; e < 64; ++e)
+                    h.grp.push_back(f + e < bykey[key].size() ? bykey[key][f + e] : -1);
+                h.grp_info.push_back((int32_t)(key / 64));
+                h.grp_info.push_back((int32_t)(key % 64));
+            }
+        A->n_grp = (int64_t)(h.grp_info.size() / 2);
+    }
     // device memory
     int rc = alloc_dense_levels(t, B, s);
     if (rc != CD_OK) return rc;
@@ -423,6 +417,8 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     if ((rc = dev_copy(h.tg_info, &A->tg_info, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.tg_src, &A->tg_src, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.tg_leaf, &A->tg_leaf, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.grp, &A->grp, s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.grp_info, &A->grp_info, s, A->mem)) != CD_OK) return rc;
     CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
     return amr_update(t, leaf_n_dev, s);
 }
@@ -460,6 +456,11 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     AmrDev* A = t->amr;
     const int B = t->base, L = t->lmax;
     const int qtop = std::min(B, L - 4);  // coarse tables only on dense levels
+    if (w->precision == CD_FP16X2) {
+        set_error("cd_column_densities: adaptive trees take CD_FP32 or CD_BF16X2 weights "
+                  "(binary16 needs the per-tile scale of the uniform-grid kernel)");
+        return CD_EUNSUPPORTED;
+    }
     if (w->len[4] != 12) {
         set_error("internal: coarse weight lists of length %d, expected 12", w->len[4]);
         return CD_EINVAL;
@@ -472,17 +473,42 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], s));
     }
     launch_coarse(t, w, qtop, compact, s);
+    AmrLookupView lk{};
+    for (int l = 0; l <= B; ++l) lk.lev[l] = t->lev[l];
+    for (int l = B + 1; l <= L; ++l) {
+        lk.octidx[l] = t->d_octidx[l];
+        lk.den[l] = A->octden + A->h.den_off[l];
+    }
+    lk.B = B;
     if (t->prof) {
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], s));
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
+    }
+    const float* E = nullptr;
+    if (w->precision == CD_BF16X2) {
+        // shells dl = 1..3 on the matrix cores into E[n_tg][D]
+        const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
+        if (t->ext_bytes < bytes) {
+            if (t->ext) (void)hipFree(t->ext);
+            t->ext = nullptr;
+            t->ext_bytes = 0;
+            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
+                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
+                return CD_ENOMEM;
+            }
+            t->ext_bytes = bytes;
+        }
+        launch_amr_external_mfma(lk, A->tg_info, A->grp, A->grp_info, A->n_grp, w, t->box_cm, t->ext, s);
+        E = t->ext;
+    }
+    if (t->prof) {
+        CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][1], s));
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_ROWS][0], s));
+        t->pran[CD_STAGE_EXTERNAL] = E != nullptr;
     }
     AmrSweepArgs a{};
-    for (int l = 0; l <= B; ++l) a.lk.lev[l] = t->lev[l];
-    for (int l = B + 1; l <= L; ++l) {
-        a.lk.octidx[l] = t->d_octidx[l];
-        a.lk.den[l] = A->octden + A->h.den_off[l];
-    }
-    a.lk.B = B;
+    a.lk = lk;
+    a.E = E;
     a.tg_info = A->tg_info;
     a.tg_src = A->tg_src;
     a.tg_leaf = A->tg_leaf;

@@ -89,6 +89,26 @@ int build_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
 int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
 int tile_chunk(int D);
 
+// Split-precision banks of the MFMA sweep (shells dl = 1, 2, 3).  For each
+// configuration class c (A mod 4 per axis), kind and tile of 16 directions:
+// the union of the shell offsets with a non-zero weight for one of the
+// tile's directions (for dl = 3 also over the 8 parities of the level-(L-3)
+// ancestor, with a parity mask), in steps of 32 offsets.  Per step:
+//   ent[32]   LDS offset of the tiled sweep (bits 0..15) | parity mask << 16
+//   eoff[32]  (ox, oy, oz) as int8 | parity mask << 24
+//   bank[64]  the MFMA B operand of lane L = 16 g + j (direction j of the
+//             tile, offsets 8 g .. 8 g + 7 of the step): 8 hi halves then
+//             8 lo halves, K = hi + 2^-p lo (bf16: p = 0, fp16: p = 11).
+struct SplitHost {
+    int precision = 0;
+    int ntiles = 0;                  // ceil(D / 16)
+    std::vector<int32_t> hdr;        // [64][3][ntiles][2]: first step, steps
+    std::vector<int32_t> ent, eoff;  // [steps][32]
+    std::vector<uint16_t> bank;      // [steps][64][16]
+};
+int build_split_tables(const HostTables& t, int precision, SplitHost& out);
+constexpr int kSplitLoExp[3] = {0, 0, 11};  // p by precision: bf16 residuals need no rescaling
+
 inline int32_t pack_off(int ox, int oy, int oz) {
     return (int32_t)((uint32_t)(ox & 0xff) | ((uint32_t)(oy & 0xff) << 8) |
                      ((uint32_t)(oz & 0xff) << 16));
@@ -111,8 +131,13 @@ struct cd_weights {
     float* gloc = nullptr;                  // device [D][8]
     int32_t* sgn = nullptr;                 // device [D]
     // split-precision banks (hi/lo) for the MFMA sweep
-    void* split = nullptr;
+    int split_ntiles = 0;
+    int32_t* split_hdr = nullptr;    // device, see cd::SplitHost
+    int32_t* split_ent = nullptr;
+    int32_t* split_eoff = nullptr;
+    uint16_t* split_bank = nullptr;
     cd::HostTables host;
+    cd::SplitHost split_host;
 };
 
 struct cd_tree {

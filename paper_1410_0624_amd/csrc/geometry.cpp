@@ -406,3 +406,138 @@ int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables
 }
 
 }  // namespace cd
+
+namespace cd {
+
+// Round to bfloat16 / binary16 (nearest, ties to even), as 16-bit patterns.
+static uint16_t to_half_bits(double v, int precision) {
+    const float f = (float)v;
+    if (precision == CD_BF16X2) {
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+    const _Float16 h = (_Float16)f;
+    uint16_t b;
+    std::memcpy(&b, &h, 2);
+    return b;
+}
+
+static double from_half_bits(uint16_t b, int precision) {
+    if (precision == CD_BF16X2) {
+        const uint32_t u = (uint32_t)b << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    }
+    _Float16 h;
+    std::memcpy(&h, &b, 2);
+    return (double)(float)h;
+}
+
+int build_split_tables(const HostTables& t, int precision, SplitHost& out) {
+    using namespace tile;
+    const int D = t.D;
+    const int nt = (D + 15) / 16;
+    const double lo_scale = std::ldexp(1.0, kSplitLoExp[precision]);
+    out = SplitHost();
+    out.precision = precision;
+    out.ntiles = nt;
+    out.hdr.assign((size_t)64 * 3 * nt * 2, 0);
+    for (int ci = 0; ci < 64; ++ci) {
+        const int c[3] = {ci & 3, (ci >> 2) & 3, ci >> 4};
+        for (int kind = 1; kind <= 3; ++kind) {
+            for (int tl = 0; tl < nt; ++tl) {
+                // offset -> (weights of the tile's directions, parity mask)
+                std::map<int32_t, std::pair<std::array<double, 16>, int>> uni;
+                auto add = [&](int combo, int mask) -> int {
+                    for (int j = 0; j < 16 && 16 * tl + j < D; ++j) {
+                        const size_t row = (size_t)combo * D + 16 * tl + j;
+                        for (int e = 0; e < t.cnt[kind][row]; ++e) {
+                            const int32_t pk = t.off[kind][row * t.len[kind] + e];
+                            const double wv = t.w[kind][row * t.len[kind] + e];
+                            auto it = uni.find(pk);
+                            if (it == uni.end()) {
+                                std::array<double, 16> z{};
+                                it = uni.emplace(pk, std::make_pair(z, 0)).first;
+                            }
+                            double& slot = it->second.first[j];
+                            if (slot != 0.0 && std::fabs(slot - wv) > 1e-12) {
+                                set_error("internal: dl=3 weights differ across parities");
+                                return CD_EINVAL;
+                            }
+                            slot = wv;
+                            it->second.second |= mask;
+                        }
+                    }
+                    return CD_OK;
+                };
+                int rc = CD_OK;
+                if (kind == 1) rc = add((c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1), 0xff);
+                else if (kind == 2) rc = add(c[0] + 4 * c[1] + 16 * c[2], 0xff);
+                else
+                    for (int p3 = 0; p3 < 8 && rc == CD_OK; ++p3) {
+                        int combo = 0, mul = 1;
+                        for (int a = 0; a < 3; ++a) {
+                            combo += (4 * ((p3 >> a) & 1) + c[a]) * mul;
+                            mul *= 8;
+                        }
+                        rc = add(combo, 1 << p3);
+                    }
+                if (rc != CD_OK) return rc;
+                const int n = (int)uni.size();
+                const int steps = (n + 31) / 32;
+                int32_t* h = &out.hdr[(((size_t)ci * 3 + (kind - 1)) * nt + tl) * 2];
+                h[0] = (int32_t)(out.ent.size() / 32);
+                h[1] = steps;
+                std::vector<int32_t> ent((size_t)steps * 32, 0), eoff((size_t)steps * 32, 0);
+                std::vector<std::array<double, 16>> wk((size_t)steps * 32);
+                int q = 0;
+                for (auto& kv : uni) {
+                    const int32_t pk = kv.first;
+                    const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
+                    int u[3];
+                    for (int a = 0; a < 3; ++a) {
+                        if (kind == 1) {
+                            const int v = c[a] + 4 + o[a];
+                            u[a] = (v & 3) * 6 + (v >> 2);
+                        } else if (kind == 2) {
+                            const int v = (c[a] >> 1) + 4 + o[a];
+                            u[a] = (v & 1) * 8 + (v >> 1);
+                        } else {
+                            u[a] = 5 + o[a];
+                        }
+                    }
+                    const int32_t lds = kind == 1   ? u[0] + k1Py * u[1] + k1Pz * u[2]
+                                        : kind == 2 ? u[0] + k2Py * u[1] + k2Pz * u[2]
+                                                    : u[0] + k3Py * u[1] + k3Pz * u[2];
+                    const int mask = kv.second.second;
+                    ent[q] = lds | (mask << 16);
+                    eoff[q] = (pk & 0xffffff) | (mask << 24);
+                    wk[q] = kv.second.first;
+                    ++q;
+                }
+                // padding entries: LDS offset 0, mask 0, weight 0
+                out.ent.insert(out.ent.end(), ent.begin(), ent.end());
+                out.eoff.insert(out.eoff.end(), eoff.begin(), eoff.end());
+                for (int st = 0; st < steps; ++st)
+                    for (int L = 0; L < 64; ++L) {
+                        const int g = L >> 4, j = L & 15;
+                        uint16_t hi8[8], lo8[8];
+                        for (int e = 0; e < 8; ++e) {
+                            const double K = wk[(size_t)st * 32 + 8 * g + e][j];
+                            const uint16_t hb = to_half_bits(K, precision);
+                            hi8[e] = hb;
+                            lo8[e] = to_half_bits((K - from_half_bits(hb, precision)) * lo_scale, precision);
+                        }
+                        out.bank.insert(out.bank.end(), hi8, hi8 + 8);
+                        out.bank.insert(out.bank.end(), lo8, lo8 + 8);
+                    }
+            }
+        }
+    }
+    return CD_OK;
+}
+
+}  // namespace cd

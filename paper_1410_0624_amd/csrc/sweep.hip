@@ -263,6 +263,7 @@ static int ensure_aux(cd_tree* t) {
     return CD_OK;
 }
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
+bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
 
 // Per-oct external columns E[n_oct][D] owned by the tree.
 static int ensure_ext(cd_tree* t, int D) {
@@ -313,6 +314,12 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
         return CD_EINVAL;
     }
+    const bool split = w->precision != CD_FP32;
+    if (split && !tiled_supported(t, w)) {
+        set_error("cd_column_densities: split precision on uniform grids needs 2^L >= 32 cells per axis "
+                  "and D in {6, 12, 24, 40, 48}");
+        return CD_EUNSUPPORTED;
+    }
     int rc = ensure_q(t, D, L - 4, true);
     if (rc != CD_OK) return rc;
     if (L >= 1 && tiled_supported(t, w)) {
@@ -340,7 +347,8 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         for (int j = 0; j < nslab; ++j) {
-            launch_external_tiled(t, w, t->ext, j * per, per, s);
+            if (split) launch_external_mfma(t, w, t->ext, s);  // whole grid (nslab == 1)
+            else launch_external_tiled(t, w, t->ext, j * per, per, s);
             CD_HIP(hipEventRecord(t->ev[j], s));
         }
         CD_HIP(mark(CD_STAGE_EXTERNAL, 1, s));
@@ -402,10 +410,6 @@ extern "C" int cd_column_densities(cd_tree* t, const cd_weights* w, float* N_dev
     }
     const float scale = (float)(gamma * av_per_nh);
     hipStream_t s = (hipStream_t)stream;
-    if (w->precision != CD_FP32) {
-        cd::set_error("cd_column_densities: split-precision sweep not provided by this build");
-        return CD_EUNSUPPORTED;
-    }
     if (t->uniform) return cd::uniform_columns(t, w, N_dev, chi_dev, scale, s);
     return cd::amr_columns(t, w, N_dev, chi_dev, scale, s);
 }

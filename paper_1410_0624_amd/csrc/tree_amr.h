@@ -4,6 +4,41 @@
 #include "cd_internal.h"
 
 namespace cd {
+
+// Device view of an adaptive tree's densities: dense padded levels 0..B and,
+// above B, per-level oct densities behind dense maps from the level-(l-1)
+// cells to their oct (or -1).
+struct AmrLookupView {
+    const float* lev[CD_MAX_LEVEL + 1];       // padded dense levels 0..B
+    const int32_t* octidx[CD_MAX_LEVEL + 1];  // [l > B] over the level-(l-1) grid
+    const float* den[CD_MAX_LEVEL + 1];       // [l > B] oct densities of level l
+    int B;
+
+    // Density of the level-l cell (i, j, k): zero outside the box; a
+    // position without a level-l cell reads the covering coarser leaf.
+    __device__ __forceinline__ float density(int l, int64_t i, int64_t j, int64_t k) const {
+        int64_t n = (int64_t)1 << l;
+        if (i < 0 || j < 0 || k < 0 || i >= n || j >= n || k >= n) return 0.f;
+        while (l > B) {
+            const int64_t pi = i >> 1, pj = j >> 1, pk = k >> 1;
+            const int64_t np = n >> 1;
+            const int32_t o = octidx[l][(pk * np + pj) * np + pi];
+            if (o >= 0) return den[l][(int64_t)o * 8 + ((i & 1) | ((j & 1) << 1) | ((k & 1) << 2))];
+            i = pi;
+            j = pj;
+            k = pk;
+            n = np;
+            --l;
+        }
+        const int64_t S = n + 2 * kHalo;
+        return lev[l][((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)];
+    }
+};
+
+void launch_amr_external_mfma(const AmrLookupView& lk, const int32_t* tg_info, const int32_t* grp,
+                              const int32_t* grp_info, int64_t ngroups, const cd_weights* w, double box, float* E,
+                              hipStream_t s);
+
 int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, const float* leaf_n_dev,
               int64_t n_leaf, hipStream_t s);
 int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s);

@@ -1,0 +1,120 @@
+"""Split-precision (bf16 / fp16 hi + lo on the matrix cores) sweeps against
+the FP64 oracle, through the C ABI.  Gate: max |ln N_gpu - ln N_oracle| <= 1e-3
+over every checked output; the measured error is printed per case, next to
+the FP32 sweep's."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1410_0624_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+LN_GATE = 1e-3
+
+
+@pytest.fixture(scope="module")
+def colden():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0624_amd import colden as c
+    c.lib()
+    return c
+
+
+def _run(colden, tin, dirs, precision, chi=True):
+    dev = torch.device("cuda:0")
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    tree = colden.Tree(tin, leaf)
+    w = colden.Weights(dirs, precision=precision)
+    N = torch.full((tin.n_leaf, dirs.shape[0]), float("nan"), dtype=torch.float32, device=dev)
+    c = torch.full((tin.n_leaf,), float("nan"), dtype=torch.float32, device=dev) if chi else None
+    colden.column_densities(tree, w, N, c)
+    torch.cuda.synchronize()
+    return N.cpu().numpy().astype(np.float64), (c.cpu().numpy().astype(np.float64) if chi else None)
+
+
+def _lnerr(a, b):
+    return np.abs(np.log(a) - np.log(b))
+
+
+PREC = {"bf16x2": 1, "fp16x2": 2}
+
+
+@pytest.mark.parametrize("pname", ["bf16x2", "fp16x2"])
+@pytest.mark.parametrize("L,dname", [(5, "healpix1"), (6, "healpix2"), (6, "axes6"), (7, "healpix1")])
+def test_split_uniform_all_leaves(colden, pname, L, dname):
+    tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=40 + L)
+    dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2),
+            "axes6": oracle.dirs_axes6()}[dname]
+    N, chi = _run(colden, tin, dirs, PREC[pname])
+    Nf, _ = _run(colden, tin, dirs, 0, chi=False)
+    ref = oracle.Tree(tin).columns(dirs)
+    assert np.isfinite(N).all() and (N > 0).all()
+    err = _lnerr(N, ref)
+    print(f"{pname} L={L} {dname}: max |d ln N| {err.max():.3e} mean {err.mean():.3e} "
+          f"(FP32 {_lnerr(Nf, ref).max():.3e})")
+    assert err.max() <= LN_GATE
+    assert np.abs(chi - oracle.screening(ref)).max() <= 1e-3
+
+
+@pytest.mark.parametrize("pname", ["bf16x2", "fp16x2"])
+def test_split_c2_256_sampled(colden, pname):
+    tin = synth.workload_uniform(8, sigma=1.5, mean=10.0, seed=2)
+    dirs = oracle.dirs_healpix(1)
+    N, _ = _run(colden, tin, dirs, PREC[pname], chi=False)
+    assert np.isfinite(N).all() and (N > 0).all()
+    tg = np.random.default_rng(5).choice(tin.n_leaf, 30000, replace=False)
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    err = _lnerr(N[tg], ref)
+    print(f"{pname} 256^3 sampled: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    assert err.max() <= LN_GATE
+
+
+@pytest.mark.parametrize("Lf,B,th,seed,dname", [(6, 3, 14.0, 5, "healpix1"), (7, 4, 30.0, 5, "healpix2"),
+                                                (7, 2, 30.0, 6, "healpix1")])
+def test_split_amr_all_leaves(colden, Lf, B, th, seed, dname):
+    tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, seed), B, th, 10 * synth.PC_CM)
+    dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2)}[dname]
+    N, chi = _run(colden, tin, dirs, 1)
+    ref = oracle.Tree(tin).columns(dirs)
+    err = _lnerr(N, ref)
+    print(f"bf16x2 AMR {Lf}/{B}/{th} {dname}: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    assert err.max() <= LN_GATE
+    assert np.abs(chi - oracle.screening(ref)).max() <= 1e-3
+
+
+def test_split_c3_amr_sampled(colden):
+    """The AMR workload (128^3 base + 2 levels, D = 48) in bf16 x 2."""
+    tin = synth.workload_amr()
+    dirs = oracle.dirs_healpix(2)
+    N, _ = _run(colden, tin, dirs, 1, chi=False)
+    assert np.isfinite(N).all() and (N > 0).all()
+    rng = np.random.default_rng(2)
+    tg = np.concatenate([rng.choice(np.nonzero(tin.leaf_level == l)[0], 8000, replace=False)
+                         for l in range(tin.base_level, tin.max_level + 1)])
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    err = _lnerr(N[tg], ref)
+    print(f"bf16x2 C3 sampled: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    assert err.max() <= LN_GATE
+
+
+def test_split_unsupported_cases(colden):
+    dev = torch.device("cuda:0")
+    # binary16 on an adaptive tree (no LDS tile to scale)
+    tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    w = colden.Weights(oracle.dirs_healpix(1), precision=2)
+    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.column_densities(tree, w, N)
+    assert e.value.rc == colden.CD_EUNSUPPORTED
+    # uniform grids below 32^3 have no tiled split kernel
+    tin = synth.workload_uniform(4, seed=1)
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    w = colden.Weights(oracle.dirs_healpix(1), precision=1)
+    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.column_densities(tree, w, N)
+    assert e.value.rc == colden.CD_EUNSUPPORTED
