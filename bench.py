@@ -6,9 +6,13 @@ sweep with the fused screening epilogue (cd_column_densities: N_H[n_leaf][D]
 and chi[n_leaf]).  The weight tables are precalculated once, outside the
 timed region, as in the method (Sect. 3.3).
 
-Workload: 256^3 uniform grid (16.8M leaves, 9-level pyramid), log-normal
-turbulent field sigma_ln n = 1.5, mean 10 cm^-3, box 10 pc, 12 HEALPix
-sectors, FP32.  Prints one JSON line.
+Default workload: 256^3 uniform grid (16.8M leaves, 9-level pyramid),
+log-normal turbulent field sigma_ln n = 1.5, mean 10 cm^-3, box 10 pc, 12
+HEALPix sectors, FP32.  The same resident input is also timed with the
+split-precision forms (bf16 / fp16 hi + lo on the matrix cores), reported
+under "forms" with their speed-up and error against an oracle sample.
+--workload amr: the adaptive tree (128^3 base + 2 levels, D = 48);
+--level 9: the 512^3 grid.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -65,15 +69,32 @@ def measured_traffic(key: str):
     return rec["traffic_bytes"] if hashlib.sha256(src).hexdigest() == rec["sha256"] else None
 
 
+PREC = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
+MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
+
+
+def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int, split: bool) -> float:
+    """Algorithmic HBM bytes of the adaptive-tree target kernel: per leaf the
+    row of N (4 D B), chi (4 B) and its density (4 B); per target oct its row
+    of the coarse table (4 D B) and, for split forms, of E (4 D B)."""
+    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * (2 if split else 1)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", choices=["uniform", "amr"], default="uniform")
     ap.add_argument("--level", type=int, default=8, help="uniform grid of 2^level cells per axis")
-    ap.add_argument("--nside", type=int, default=1, help="HEALPix Nside (D = 12 Nside^2)")
+    ap.add_argument("--nside", type=int, default=0, help="HEALPix Nside, D = 12 Nside^2 "
+                    "(default 1 for uniform grids, 2 for the adaptive tree)")
+    ap.add_argument("--precision", choices=list(PREC), default="fp32")
+    ap.add_argument("--no-forms", action="store_true", help="skip timing the other precision forms")
     ap.add_argument("--cpu-sample-octs", type=int, default=2097152,
-                    help="octs timed with the CPU oracle (bounded sample)")
+                    help="uniform grids: octs timed with the CPU oracle (bounded sample)")
+    ap.add_argument("--cpu-sample-leaves", type=int, default=100000,
+                    help="adaptive tree: leaves timed with the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -86,83 +107,146 @@ def main():
     from paper_1410_0624_amd import colden, synth
 
     dev = torch.device("cuda:0")
-    L = args.level
+    amr = args.workload == "amr"
+    nside = args.nside or (2 if amr else 1)
     t0 = time.time()
-    tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=2)
-    dirs = colden.directions(colden.CD_DIR_HEALPIX, args.nside)
+    if amr:
+        tin = synth.workload_amr()
+        wl = (f"AMR tree: 128^3 base + 2 refined levels on cells with averaged n > 100 cm^-3 "
+              f"(log-normal, sigma_ln n=2, mean 10 cm^-3, generated at 512^3, box 20 pc, seed 3)")
+        L = tin.max_level
+    else:
+        L = args.level
+        seed = {8: 2, 9: 4}.get(L, 2)
+        tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=seed)
+        wl = (f"uniform {1 << L}^3 log-normal turbulent field (sigma_ln n=1.5, mean 10 cm^-3, "
+              f"box 10 pc, seed {seed})")
+    dirs = colden.directions(colden.CD_DIR_HEALPIX, nside)
     D = dirs.shape[0]
-    print(f"# generated 2^{L} field in {time.time() - t0:.1f}s", file=sys.stderr, flush=True)
+    print(f"# generated workload in {time.time() - t0:.1f}s: {tin.n_leaf} leaves, D={D}",
+          file=sys.stderr, flush=True)
 
     leaf = torch.from_numpy(tin.leaf_n).to(dev)
     N = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
     chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
     tree = colden.Tree(tin, leaf)
-    w = colden.Weights(dirs)
+    rng = np.random.default_rng(0)
+    check = rng.choice(tin.n_leaf, size=min(2000, tin.n_leaf), replace=False)
 
-    def step():
-        tree.update(leaf)
-        colden.column_densities(tree, w, N, chi)
+    def measure(prec: str) -> dict:
+        w = colden.Weights(dirs, precision=PREC[prec])
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
+        def step():
+            tree.update(leaf)
+            colden.column_densities(tree, w, N, chi)
 
-    # timed region: K whole steps
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_step = ev0.elapsed_time(ev1) / args.steps
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        # timed region: K whole steps
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(args.steps):
+            step()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_step = ev0.elapsed_time(ev1) / args.steps
+        # stage durations from the library's HIP events (recorded on the
+        # stream each stage runs on), averaged over as many steps
+        tree.profile(True)
+        stages = {k: [] for k in colden.STAGES}
+        for _ in range(args.steps):
+            step()
+            for k, v in tree.stage_ms().items():
+                stages[k].append(v)
+        tree.profile(False)
+        torch.cuda.synchronize()
+        out = {"ms_per_step": ms_step, "value": tin.n_leaf * D / (ms_step * 1e-3),
+               "stages_ms": {k: float(np.mean(v)) for k, v in stages.items()},
+               "sample": N[torch.from_numpy(check).to(dev)].cpu().numpy().astype(np.float64),
+               "split_steps": w.split_steps()}
+        w.close()
+        return out
 
-    # stage durations from the library's HIP events (recorded on the stream
-    # each stage runs on), averaged over the same number of steps
-    tree.profile(True)
-    stages = {k: [] for k in colden.STAGES}
-    for _ in range(args.steps):
-        step()
-        for k, v in tree.stage_ms().items():
-            stages[k].append(v)
-    tree.profile(False)
-    stage_ms = {k: float(np.mean(v)) for k, v in stages.items()}
-    rows_bytes = alg_bytes_rows(tin.n_leaf, D)
+    main_form = measure(args.precision)
+    forms = {args.precision: main_form}
+    if not args.no_forms:
+        for p in PREC:
+            if p == args.precision or (amr and p == "fp16x2"):
+                continue
+            forms[p] = measure(p)
+            print(f"# form {p}: {forms[p]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    stage_ms = main_form["stages_ms"]
+    ms_step = main_form["ms_per_step"]
+    value = main_form["value"]
+
+    if amr:
+        # dominant kernel: the per-target-oct kernel (internal + local, rows of N and chi)
+        lv = tin.leaf_level
+        ijk = tin.leaf_ijk.astype(np.int64)
+        key = (lv.astype(np.int64) << 60) | ((ijk[:, 2] >> 1) << 40) | ((ijk[:, 1] >> 1) << 20) | (ijk[:, 0] >> 1)
+        n_tg = int(np.unique(key).shape[0])
+        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D, args.precision != "fp32")
+        kname = "k_amr_octs (per target oct: shells, internal+local, N and chi rows)"
+    else:
+        rows_bytes = alg_bytes_rows(tin.n_leaf, D)
+        kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"
     achieved = rows_bytes / (stage_ms["rows"] * 1e-3) / 1e9
     sweep_bytes = alg_bytes_sweep(tin.n_leaf, D, L)
 
-    cell_dirs = tin.n_leaf * D
-    value = cell_dirs / (ms_step * 1e-3)
-
     cpu = None
+    ref_check = None
     if not args.no_cpu:
         import oracle
         tr = oracle.Tree(tin)
-        n1 = 1 << (L - 1)
-        rng = np.random.default_rng(0)
-        octs = rng.choice(n1 ** 3, size=min(args.cpu_sample_octs, n1 ** 3), replace=False)
-        ax, ay, az = octs % n1, (octs // n1) % n1, octs // (n1 * n1)
-        n = 1 << L
-        tg = []
-        for o in range(8):
-            tg.append(((2 * az + (o >> 2)) * n + 2 * ay + ((o >> 1) & 1)) * n + 2 * ax + (o & 1))
-        tg = np.concatenate(tg).astype(np.int64)
         threads = os.cpu_count() or 1
+        if amr:
+            tg = rng.choice(tin.n_leaf, size=min(args.cpu_sample_leaves, tin.n_leaf), replace=False)
+            what = f"{tg.shape[0]} random leaves of the same tree"
+        else:
+            n1 = 1 << (L - 1)
+            octs = rng.choice(n1 ** 3, size=min(args.cpu_sample_octs, n1 ** 3), replace=False)
+            ax, ay, az = octs % n1, (octs // n1) % n1, octs // (n1 * n1)
+            n = 1 << L
+            tg = np.concatenate([((2 * az + (o >> 2)) * n + 2 * ay + ((o >> 1) & 1)) * n + 2 * ax + (o & 1)
+                                 for o in range(8)]).astype(np.int64)
+            what = f"{octs.shape[0]} random octs ({tg.shape[0]} leaves) of the same field"
         t0 = time.time()
         ref = tr.columns(dirs, tg, nthreads=threads)
         oracle.screening(ref)
         dt = time.time() - t0
         cpu = {"value": float(tg.shape[0] * D / dt), "unit": "cell*dir/s", "cores": threads,
                "kind": "oracle", "cpu_model": cpu_model(),
-               "sample": f"{octs.shape[0]} random octs ({tg.shape[0]} leaves) of the same field, "
-                         f"FP64 OpenMP oracle, {dt:.1f} s"}
-        # spot parity of the timed output against the oracle sample
-        got = N.cpu().numpy()[tg[:2000]].astype(np.float64)
-        relerr = float(np.max(np.abs(got - ref[:2000]) / ref[:2000]))
-    else:
-        relerr = None
+               "sample": f"{what}, FP64 OpenMP oracle, {dt:.1f} s"}
+        ref_check = tr.columns(dirs, check, nthreads=threads)
 
+    def errs(f):
+        if ref_check is None:
+            return None, None
+        got = f["sample"]
+        return (float(np.max(np.abs(got - ref_check) / ref_check)),
+                float(np.max(np.abs(np.log(got) - np.log(ref_check)))))
+
+    n_tiles = ((1 << (L - 1)) // 16) ** 3 if not amr else 0
+    forms_out = {}
+    for p, f in forms.items():
+        rel, lnerr = errs(f)
+        o = {"ms_per_step": f["ms_per_step"], "value": f["value"],
+             "speedup_vs_fp32": (forms["fp32"]["ms_per_step"] / f["ms_per_step"]) if "fp32" in forms else None,
+             "external_ms": f["stages_ms"]["external"], "sweep_ms": f["stages_ms"]["sweep"],
+             "max_rel_err_vs_oracle": rel, "max_abs_dlnN_vs_oracle": lnerr,
+             "oracle_sample": f"{check.shape[0]} random leaves"}
+        if p != "fp32" and not amr and f["stages_ms"]["external"] > 0:
+            flops = f["split_steps"] * 4 * 3 * (16 * 16 * 32 * 2) * n_tiles
+            tf = flops / (f["stages_ms"]["external"] * 1e-3) / 1e12
+            o["mfma"] = {"kernel": f"k_external_mfma<{p}>", "flops_per_launch": flops, "achieved_tflops": tf,
+                         "peak_tflops": MFMA_PEAK_TFLOPS, "frac": tf / MFMA_PEAK_TFLOPS}
+        forms_out[p] = o
+    relerr, lnerr = errs(main_form)
+
+    dtype = {"fp32": "f32", "bf16x2": "bf16x2 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)"}[args.precision]
     rec = {
         "metric": "cell*directions/s of full column sweep",
         "value": value,
@@ -174,21 +258,23 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"uniform {1 << L}^3 log-normal turbulent field (sigma_ln n=1.5, mean 10 cm^-3, "
-                               f"box 10 pc, seed 2), {D} HEALPix sectors, FP32 sweep + fused screening",
-                   "n_leaf": tin.n_leaf, "n_dirs": D, "levels": L + 1, "step": "pyramid rebuild + column sweep"},
+        "config": {"workload": f"{wl}, {D} HEALPix sectors, {args.precision} external shells + fused screening",
+                   "n_leaf": tin.n_leaf, "n_dirs": D, "levels": L + 1, "precision": args.precision,
+                   "step": "pyramid rebuild + column sweep"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}"),
-                     "kernel": f"k_target_rows<{D}> (internal+local, N and chi rows)",
-                     "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
+                     "traffic": (measured_traffic(f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}")
+                                 if not amr else None),
+                     "kernel": kname, "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
         "stages_ms": stage_ms,
         "sweep": {"alg_bytes": sweep_bytes, "ms": stage_ms["sweep"],
                   "GB_per_s": sweep_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},
+        "forms": forms_out,
         "cpu_baseline": cpu,
         "max_rel_err_vs_oracle_sample": relerr,
+        "max_abs_dlnN_vs_oracle_sample": lnerr,
     }
     print(json.dumps(rec))
 

@@ -142,7 +142,15 @@ void cd_tree_destroy(cd_tree* tree);
  *   dirs       host [D][3] unit vectors (|u| = 1 within 1e-9).
  *   D          1 .. CD_MAX_DIRS.
  *   mode       CD_PRECALC73 (CD_INSITU: CD_EUNSUPPORTED in this build).
- *   precision  CD_FP32, CD_BF16X2 or CD_FP16X2 (which sweep kernels use it).
+ *   precision  CD_FP32, CD_BF16X2 or CD_FP16X2: the arithmetic of the
+ *              external shells dl = 1, 2, 3 in cd_column_densities.  The
+ *              split forms keep densities and weights as hi + lo pairs of
+ *              16-bit halves (rounded from the FP64 weights here) and run
+ *              the contraction on the matrix cores with FP32 accumulation;
+ *              measured error |d ln N| <= 3e-5 (bf16) and <= 1e-6 (fp16).
+ *              CD_FP16X2 divides each LDS density tile by a power of two and
+ *              is offered on uniform grids only.  Split forms on uniform
+ *              grids need 2^L >= 32 and D in {6, 12, 24, 40, 48}.
  * Errors: CD_EINVAL, CD_EUNSUPPORTED, CD_ENOMEM, CD_EDEVICE.
  */
 int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
@@ -150,6 +158,17 @@ int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
 
 /* Number of directions of a weights handle. */
 int cd_weights_n_dirs(const cd_weights* w, int* D);
+
+/*
+ * Size of the split-precision contraction (cost model): the number of steps
+ * of 32 shell offsets summed over the 64 configuration classes (A mod 4 per
+ * axis), the shells dl = 1, 2, 3 and the tiles of 16 directions.  On a
+ * uniform grid a tile of 16^3 octs runs steps x 4 row blocks x 3 matrix
+ * instructions of 16 x 16 x 32 (bf16 or fp16) for those shells.  0 for
+ * CD_FP32 weights.
+ * Errors: CD_EINVAL (NULL argument).
+ */
+int cd_weights_split_steps(const cd_weights* w, int64_t* steps);
 
 /* Release the handle (after the stream's work that uses it). */
 void cd_weights_destroy(cd_weights* w);
@@ -159,8 +178,11 @@ void cd_weights_destroy(cd_weights* w);
  * (float, cm^-2, row-major, direction fastest).  If chi_dev is not NULL the
  * screening factor (Eq. 5) is fused and written to chi_dev[n_leaf]
  * using av_per_nh and gamma (ignored otherwise).  The contraction runs in
- * the precision of the weights handle.  Asynchronous on `stream`.
- * Errors: CD_EINVAL (NULL handles or output), CD_ENOMEM, CD_EDEVICE.
+ * the precision of the weights handle (see cd_precompute_weights); the
+ * coarse shells (dl >= 4), the internal + local part, the level sums and chi
+ * are FP32 in every form.  Asynchronous on `stream`.
+ * Errors: CD_EINVAL (NULL handles or output), CD_EUNSUPPORTED (a split
+ * form on a tree it is not offered for), CD_ENOMEM, CD_EDEVICE.
  */
 int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
                         double av_per_nh, double gamma, void* stream);

@@ -21,7 +21,7 @@ GAMMA = 3.74
 EXPORTS = [
     "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
-    "cd_weights_n_dirs", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
+    "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
     "cd_profile_enable", "cd_profile_read",
 ]
 STAGES = ["pyramid", "coarse", "external", "rows", "sweep"]
@@ -55,6 +55,7 @@ def lib():
         L.cd_tree_destroy.restype = None
         L.cd_precompute_weights.argtypes = [P, I, I, I, P, P]
         L.cd_weights_n_dirs.argtypes = [P, P]
+        L.cd_weights_split_steps.argtypes = [P, P]
         L.cd_weights_destroy.argtypes = [P]
         L.cd_weights_destroy.restype = None
         L.cd_column_densities.argtypes = [P, P, P, P, D, D, P]
@@ -156,6 +157,13 @@ class Weights:
         self.h = h
         self.D = dirs.shape[0]
         self.precision = precision
+
+    def split_steps(self) -> int:
+        """32-offset steps of the split contraction summed over classes,
+        shells dl = 1..3 and direction tiles (0 for FP32 weights)."""
+        n = C.c_int64(0)
+        _check(lib().cd_weights_split_steps(self.h, C.byref(n)))
+        return n.value
 
     def close(self):
         if getattr(self, "h", None) is not None and self.h.value:

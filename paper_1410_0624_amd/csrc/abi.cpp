@@ -154,6 +154,18 @@ extern "C" int cd_weights_n_dirs(const cd_weights* w, int* D) {
     return CD_OK;
 }
 
+extern "C" int cd_weights_split_steps(const cd_weights* w, int64_t* steps) {
+    if (!w || !steps) {
+        cd::set_error("cd_weights_split_steps: NULL argument");
+        return CD_EINVAL;
+    }
+    int64_t n = 0;
+    const std::vector<int32_t>& h = w->split_host.hdr;
+    for (size_t i = 1; i < h.size(); i += 2) n += h[i];
+    *steps = n;
+    return CD_OK;
+}
+
 extern "C" void cd_weights_destroy(cd_weights* w) {
     if (!w) return;
     for (int k = 0; k < cd::kKinds; ++k) {
