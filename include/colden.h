@@ -211,6 +211,107 @@ enum { CD_STAGE_PYRAMID = 0, CD_STAGE_COARSE = 1, CD_STAGE_EXTERNAL = 2, CD_STAG
 int cd_profile_enable(cd_tree* tree, int on);
 int cd_profile_read(cd_tree* tree, float* ms /* [CD_NUM_STAGES] */);
 
+
+/*
+ * Learned surrogate of the column sweep.  Not part of the paper's method: a
+ * network trained on the columns the method computes, with the method as
+ * fallback.  Uniform grids of 2^L >= 256 cells per axis.
+ *
+ * Features of a leaf (576): for each absolute level l = 0 .. 8 of the
+ * pyramid (Sect. 3: a coarse cell holds the mean of its children), the 4^3
+ * level-l cells centred on the centre of the leaf's level-(l-1) ancestor A
+ * (indices 2A-1 .. 2A+2 per axis; A = 0 at l = 0), feature
+ * l*64 + sx + 4 sy + 16 sz = (ln max(n, 1e-10) - in_shift) / in_scale, with
+ * n = 0 outside the box.  The features are those of the leaf's oct, shared
+ * by its 8 leaves, and so is what the network predicts: the external part
+ * of the column (shells dl >= 1), y = (ln(N - N_il + 1e17) - out_shift) /
+ * out_scale per direction, N_il the leaf's internal + local part (Sect.
+ * 3.2), which is added back exactly: N = N_il + max(exp(y out_scale +
+ * out_shift) - 1e17, 0).  Network: 576 -> width -> width -> D, ReLU.  Loss:
+ * mean squared error over all outputs.  Optimiser: Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8).
+ * Parameters in the order W1 [576][width], b1, W2 [width][width], b2,
+ * W3 [width][D], b3 (row-major, y = x W + b), FP32 master copies.
+ *
+ * CD_SURR_BF16: weights and activations rounded to bfloat16 for the matrix
+ * cores, FP32 accumulation.  CD_SURR_FP32: every product in FP32 (a checking
+ * path).  A handle holds scratch for its largest batch; calls on one handle
+ * must not overlap.
+ */
+enum { CD_SURR_FP32 = 0, CD_SURR_BF16 = 1 };
+typedef struct cd_surrogate cd_surrogate;
+
+/* New network for D directions, hidden width (multiple of 16, 16 .. 1024),
+ * precision CD_SURR_*, He-uniform weights from `seed`, zero biases.
+ * norm = {in_shift, in_scale, out_shift, out_scale} (scales > 0).
+ * Errors: CD_EINVAL, CD_ENOMEM. */
+int cd_surrogate_create(int D, int width, int precision, uint64_t seed, const float* norm, cd_surrogate** out);
+
+/* Release the handle (after the stream's work that uses it).  NULL is ignored. */
+void cd_surrogate_destroy(cd_surrogate* s);
+
+/* Number of parameters; copies of the FP32 parameters to / from host memory
+ * (set_params also clears the Adam moments and step count). */
+int cd_surrogate_n_params(const cd_surrogate* s, int64_t* n);
+int cd_surrogate_get_params(const cd_surrogate* s, float* params);
+int cd_surrogate_set_params(cd_surrogate* s, const float* params);
+
+/* Scaled features of n leaves (row-major leaf indices cells_dev[n], device
+ * int64) into X_dev[n][576] (device float).  An index outside [0, n_leaf)
+ * gives NaN features (here and in cd_surrogate_train_step).
+ * Errors: CD_EINVAL (tree not uniform or 2^L < 256, NULL buffers). */
+int cd_surrogate_features(const cd_surrogate* s, const cd_tree* tree, const int64_t* cells_dev, int64_t n,
+                          float* X_dev, void* stream);
+
+/* Training targets of n leaves (cells_dev[n]): T_dev[n][D] = scaled
+ * ln(N - N_il + 1e17) from the method's columns N_dev[n_leaf][D] and the
+ * internal + local parts (weights w).  An index outside [0, n_leaf) gives
+ * NaN.  Errors: CD_EINVAL. */
+int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const float* N_dev,
+                         const int64_t* cells_dev, int64_t n, float* T_dev, void* stream);
+
+/* Network outputs Y_dev[n][D] (scaled log columns) of inputs X_dev[n][576]. */
+int cd_surrogate_forward(cd_surrogate* s, const float* X_dev, int64_t n, float* Y_dev, void* stream);
+
+/* Loss and gradient of the loss for inputs X_dev[n][576] and targets
+ * T_dev[n][D] (scaled log columns), without an update: grad[n_params] and
+ * *loss in host memory (synchronises the stream). */
+int cd_surrogate_gradients(cd_surrogate* s, const float* X_dev, const float* T_dev, int64_t n, float* grad,
+                           float* loss, void* stream);
+
+/* One Adam step of learning rate lr on a batch of leaves cells_dev[batch] of
+ * a uniform tree, with targets from the method's columns N_dev[n_leaf][D]
+ * (cm^-2, from cd_column_densities on the same tree) minus the internal +
+ * local parts (weights w of the same D supply them).  If loss is not NULL
+ * the batch loss before the step is written there (synchronises the stream).
+ * Errors: CD_EINVAL. */
+int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const float* N_dev,
+                            const int64_t* cells_dev, int64_t batch, float lr, float* loss, void* stream);
+
+/* Columns of every leaf of a uniform tree from the network plus the exact
+ * internal + local parts (weights w): N_dev[n_leaf][D] (cm^-2) and, if
+ * chi_dev is not NULL, chi (Eq. 5) with av_per_nh, gamma.
+ * Errors: CD_EINVAL, CD_ENOMEM. */
+int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
+                       double av_per_nh, double gamma, void* stream);
+
+/* Sampled check and fallback after cd_surrogate_infer: the grid is cut into
+ * tiles of 8^3 leaves; in each, ceil(frac * 512) leaves drawn from `seed`
+ * are computed with the method (FP32 weights w); a tile where a sample's chi
+ * differs from the network's by more than tol_chi (relative) is recomputed
+ * entirely with the method (N and chi).  Writes the number of such tiles and
+ * of all tiles, and the largest sampled relative chi error (may be NULL).
+ * Synchronises the stream (the host picks the tiles).
+ * Errors: CD_EINVAL (frac outside (0, 1], tree not uniform, w not FP32),
+ * CD_ENOMEM, CD_EDEVICE. */
+int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* tree, const cd_weights* w, double frac, double tol_chi,
+                                uint64_t seed, float* N_dev, float* chi_dev, double av_per_nh, double gamma,
+                                int64_t* n_fallback_tiles, int64_t* n_tiles, float* max_sample_err, void* stream);
+
+/* Parameters, Adam state and settings to / from a file. */
+int cd_surrogate_save(const cd_surrogate* s, const char* path);
+int cd_surrogate_load(const char* path, cd_surrogate** out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -488,6 +488,20 @@ int orc_columns(const orc_tree* t, const double* dirs, int D, int mode,
     return 0;
 }
 
+/* Internal + local part alone (Sect. 3.2: the target and its 7 siblings,
+ * rays from the target centre) of the listed leaves, N[n][D] in cm^-2. */
+int orc_internal_local(const orc_tree* t, const double* dirs, int D, const int64_t* targets, int64_t n,
+                       double* out) {
+    if (D < 1 || n < 0) return -1;
+    for (int64_t q = 0; q < n; ++q) {
+        if (targets[q] < 0 || targets[q] >= t->n_leaf) return -1;
+        int64_t li = targets[q];
+        int64_t T[3] = {t->leaf_ijk[3 * li], t->leaf_ijk[3 * li + 1], t->leaf_ijk[3 * li + 2]};
+        orc_target_column(t, t->leaf_level[li], T, dirs, D, ORC_PRECALC73, out + q * D, NULL);
+    }
+    return 0;
+}
+
 /* Shell description seen from leaf `target` (for tests): per shell 16
  * int64: level, olo[3], ohi[3], ilo[3], ihi[3], unused x3; and 3 doubles of
  * the reference point (box units) in ref_out.  Returns the shell count. */

@@ -57,6 +57,7 @@ def lib():
         L.orc_density.restype = C.c_double
         L.orc_columns.argtypes = [P, P, C.c_int, C.c_int, P, C.c_int64, P, C.c_int]
         L.orc_shells.argtypes = [P, C.c_int64, C.c_int, P, P]
+        L.orc_internal_local.argtypes = [P, P, C.c_int, P, C.c_int64, P]
         L.orc_screening.argtypes = [P, C.c_int64, C.c_int, C.c_double, C.c_double, P]
         L.orc_raymarch.argtypes = [P, P, C.c_int, P, C.c_int64, P, C.c_int]
         _lib = L
@@ -147,6 +148,15 @@ class Tree:
         rc = lib().orc_columns(self.h, _p(dirs), D, mode, _p(targets), targets.shape[0],
                                _p(out), nthreads)
         if rc != 0:
+            raise ValueError("oracle: bad arguments")
+        return out
+
+    def internal_local(self, dirs: np.ndarray, targets) -> np.ndarray:
+        """Internal + local part alone (Sect. 3.2), [n_targets, D] cm^-2."""
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.zeros((targets.shape[0], dirs.shape[0]))
+        if lib().orc_internal_local(self.h, _p(dirs), dirs.shape[0], _p(targets), targets.shape[0], _p(out)) != 0:
             raise ValueError("oracle: bad arguments")
         return out
 

@@ -15,7 +15,11 @@ coarse data to the columns the method computes.  What it is built from:
   ln max(n, 1e-10) at offset (sx, sy, sz), zero density outside the box;
   features are then shifted and scaled, f' = (f - in_shift) / in_scale;
 * a multilayer perceptron 576 -> W -> W -> D with ReLU activations, outputs
-  the scaled log columns y = (ln N - out_shift) / out_scale;
+  the scaled log external columns y = (ln(N - N_il + EXT_FLOOR) - out_shift)
+  / out_scale, N_il the target's internal + local part (Sect. 3.2).  The
+  features are those of the target's oct (its 8 leaves share them), and so
+  is the external part (the shells are per oct); N_il is added back exactly:
+  N = N_il + max(exp(y out_scale + out_shift) - EXT_FLOOR, 0);
 * mean squared error over all outputs and Adam (Kingma & Ba 2015,
   Algorithm 1: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected).
 
@@ -32,6 +36,7 @@ N_LEVELS = 9
 STENCIL = 4
 N_FEAT = N_LEVELS * STENCIL ** 3  # 576
 FLOOR = 1e-10
+EXT_FLOOR = 1e17  # cm^-2 added to the external column before the logarithm
 ADAM_B1, ADAM_B2, ADAM_EPS = 0.9, 0.999, 1e-8
 
 
@@ -133,9 +138,15 @@ def adam_step(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int
     return p - lr * mhat / (np.sqrt(vhat) + ADAM_EPS), m, v
 
 
-def columns_from_output(Y: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
-    """N (cm^-2) from the scaled log columns."""
-    return np.exp(Y * out_scale + out_shift)
+def targets(N: np.ndarray, N_il: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
+    """Scaled log external columns from the method's columns and the
+    internal + local parts."""
+    return (np.log(np.maximum(N - N_il, 0.0) + EXT_FLOOR) - out_shift) / out_scale
+
+
+def columns_from_output(Y: np.ndarray, N_il: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
+    """N (cm^-2) from the network outputs and the internal + local parts."""
+    return N_il + np.maximum(np.exp(Y * out_scale + out_shift) - EXT_FLOOR, 0.0)
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:
@@ -156,3 +167,25 @@ def forward_bf16(params: list, X: np.ndarray):
     A1 = bf16_round(np.maximum(Xb @ bf16_round(W1) + b1, 0.0))
     A2 = bf16_round(np.maximum(A1 @ bf16_round(W2) + b2, 0.0))
     return A2 @ bf16_round(W3) + b3
+
+
+def backward_bf16(params: list, X: np.ndarray, T: np.ndarray) -> list:
+    """Gradients of the bfloat16 network (the forward of forward_bf16):
+    the loss gradient, the hidden-layer gradients, inputs and weights are
+    rounded to bfloat16 where the matrix-core path stores them, bias
+    gradients are summed from the unrounded gradients; sums in float64."""
+    W1, b1, W2, b2, W3, b3 = params
+    W1b, W2b, W3b = bf16_round(W1), bf16_round(W2), bf16_round(W3)
+    Xb = bf16_round(X)
+    Z1 = Xb @ W1b + b1
+    A1 = bf16_round(np.maximum(Z1, 0.0))
+    Z2 = A1 @ W2b + b2
+    A2 = bf16_round(np.maximum(Z2, 0.0))
+    Y = A2 @ W3b + b3
+    dY = 2.0 * (Y - T) / Y.size
+    dYb = bf16_round(dY)
+    dZ2 = (dYb @ W3b.T) * (Z2 > 0)
+    dZ2b = bf16_round(dZ2)
+    dZ1 = (dZ2b @ W2b.T) * (Z1 > 0)
+    dZ1b = bf16_round(dZ1)
+    return [Xb.T @ dZ1b, dZ1.sum(axis=0), A1.T @ dZ2b, dZ2.sum(axis=0), A2.T @ dYb, dY.sum(axis=0)]

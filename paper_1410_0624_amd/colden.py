@@ -191,3 +191,142 @@ def screening_factor(N, chi, av=None, av_per_nh: float = AV_PER_NH, gamma: float
     _check(lib().cd_screening_factor(_dev_f32(N), n, D, av_per_nh, gamma, _dev_f32(chi),
                                      _dev_f32(av) if av is not None else None, _stream(stream)))
     return chi
+
+
+# ------------------------------------------------------------- surrogate --
+CD_SURR_FP32, CD_SURR_BF16 = 0, 1
+SURROGATE_EXPORTS = [
+    "cd_surrogate_create", "cd_surrogate_destroy", "cd_surrogate_n_params", "cd_surrogate_get_params",
+    "cd_surrogate_set_params", "cd_surrogate_features", "cd_surrogate_targets", "cd_surrogate_forward", "cd_surrogate_gradients",
+    "cd_surrogate_train_step", "cd_surrogate_infer", "cd_surrogate_check_fallback", "cd_surrogate_save",
+    "cd_surrogate_load",
+]
+EXPORTS += SURROGATE_EXPORTS
+N_FEAT = 576
+
+
+def _surr_types():
+    L = lib()
+    if getattr(L, "_surr_typed", False):
+        return L
+    P, I, I64, D, F = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_float
+    L.cd_surrogate_create.argtypes = [I, I, I, C.c_uint64, P, P]
+    L.cd_surrogate_destroy.argtypes = [P]
+    L.cd_surrogate_destroy.restype = None
+    L.cd_surrogate_n_params.argtypes = [P, P]
+    L.cd_surrogate_get_params.argtypes = [P, P]
+    L.cd_surrogate_set_params.argtypes = [P, P]
+    L.cd_surrogate_features.argtypes = [P, P, P, I64, P, P]
+    L.cd_surrogate_targets.argtypes = [P, P, P, P, P, I64, P, P]
+    L.cd_surrogate_forward.argtypes = [P, P, I64, P, P]
+    L.cd_surrogate_gradients.argtypes = [P, P, P, I64, P, P, P]
+    L.cd_surrogate_train_step.argtypes = [P, P, P, P, P, I64, F, P, P]
+    L.cd_surrogate_infer.argtypes = [P, P, P, P, P, D, D, P]
+    L.cd_surrogate_check_fallback.argtypes = [P, P, P, D, D, C.c_uint64, P, P, D, D, P, P, P, P]
+    L.cd_surrogate_save.argtypes = [P, C.c_char_p]
+    L.cd_surrogate_load.argtypes = [C.c_char_p, P]
+    L._surr_typed = True
+    return L
+
+
+def _dev_i64(t):
+    import torch
+    assert isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.int64 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Surrogate:
+    """cd_surrogate handle: ReLU MLP 576 -> width -> width -> D on the
+    pyramid features, trained and run by the library's kernels."""
+
+    def __init__(self, D: int = 12, width: int = 256, precision: int = CD_SURR_BF16, seed: int = 0,
+                 norm=(0.0, 1.0, 0.0, 1.0), _handle=None):
+        L = _surr_types()
+        if _handle is None:
+            nrm = np.asarray(norm, dtype=np.float32)
+            h = C.c_void_p()
+            _check(L.cd_surrogate_create(D, width, precision, seed, _np(nrm), C.byref(h)))
+            _handle = h
+        self.h = _handle
+        self.D, self.width, self.precision = D, width, precision
+
+    @classmethod
+    def load(cls, path: str) -> "Surrogate":
+        L = _surr_types()
+        h = C.c_void_p()
+        _check(L.cd_surrogate_load(path.encode(), C.byref(h)))
+        s = cls(_handle=h)
+        s.D = s.width = None  # as stored in the file
+        return s
+
+    def save(self, path: str):
+        _check(_surr_types().cd_surrogate_save(self.h, path.encode()))
+
+    def n_params(self) -> int:
+        n = C.c_int64(0)
+        _check(_surr_types().cd_surrogate_n_params(self.h, C.byref(n)))
+        return n.value
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params(), np.float32)
+        _check(_surr_types().cd_surrogate_get_params(self.h, _np(p)))
+        return p
+
+    def set_params(self, p):
+        p = np.ascontiguousarray(p, dtype=np.float32)
+        _check(_surr_types().cd_surrogate_set_params(self.h, _np(p)))
+
+    def features(self, tree: Tree, cells, X, stream=None):
+        _check(_surr_types().cd_surrogate_features(self.h, tree.h, _dev_i64(cells), int(cells.numel()),
+                                                   _dev_f32(X), _stream(stream)))
+        return X
+
+    def targets(self, tree: Tree, w: Weights, N, cells, T, stream=None):
+        _check(_surr_types().cd_surrogate_targets(self.h, tree.h, w.h, _dev_f32(N), _dev_i64(cells),
+                                                  int(cells.numel()), _dev_f32(T), _stream(stream)))
+        return T
+
+    def forward(self, X, Y, stream=None):
+        _check(_surr_types().cd_surrogate_forward(self.h, _dev_f32(X), int(X.shape[0]), _dev_f32(Y),
+                                                  _stream(stream)))
+        return Y
+
+    def gradients(self, X, T, stream=None):
+        g = np.zeros(self.n_params(), np.float32)
+        loss = C.c_float(0)
+        _check(_surr_types().cd_surrogate_gradients(self.h, _dev_f32(X), _dev_f32(T), int(X.shape[0]), _np(g),
+                                                    C.byref(loss), _stream(stream)))
+        return g, loss.value
+
+    def train_step(self, tree: Tree, w: Weights, N, cells, lr: float, want_loss: bool = False, stream=None):
+        loss = C.c_float(0)
+        _check(_surr_types().cd_surrogate_train_step(self.h, tree.h, w.h, _dev_f32(N), _dev_i64(cells),
+                                                     int(cells.numel()), float(lr),
+                                                     C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def infer(self, tree: Tree, w: Weights, N, chi=None, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA,
+              stream=None):
+        _check(_surr_types().cd_surrogate_infer(self.h, tree.h, w.h, _dev_f32(N),
+                                                _dev_f32(chi) if chi is not None else None, av_per_nh, gamma,
+                                                _stream(stream)))
+        return N
+
+    def check_fallback(self, tree: Tree, w: Weights, N, chi, frac: float = 0.01, tol_chi: float = 0.03,
+                       seed: int = 0, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):
+        nf, nt, emax = C.c_int64(0), C.c_int64(0), C.c_float(0)
+        _check(_surr_types().cd_surrogate_check_fallback(self.h, tree.h, w.h, frac, tol_chi, seed, _dev_f32(N),
+                                                         _dev_f32(chi), av_per_nh, gamma, C.byref(nf),
+                                                         C.byref(nt), C.byref(emax), _stream(stream)))
+        return nf.value, nt.value, emax.value
+
+    def close(self):
+        if getattr(self, "h", None) is not None and self.h.value:
+            _surr_types().cd_surrogate_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

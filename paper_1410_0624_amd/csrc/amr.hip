@@ -79,31 +79,6 @@ __global__ void k_oct_mean(int64_t first, int64_t n, const int64_t* __restrict__
     else octden[d] = m;
 }
 
-struct AmrSweepArgs {
-    AmrLookupView lk;
-    const int32_t* tg_info;
-    const int64_t* tg_src;
-    const int64_t* tg_leaf;
-    int64_t n_tg;
-    const float* octden;
-    const float* base;  // padded level B
-    const int32_t* off[5];
-    const float* w[5];
-    int len[5];
-    const float* kloc;
-    const float* q[CD_MAX_LEVEL + 1];  // coarse tables of levels 2 .. qtop, 216 codes
-    int qtop;
-    int qcompact;  // Q_qtop holds only the 64 codes of dl = 4 (qtop == Lmax - 4)
-    int8_t next[6][2];
-    int8_t dl4[4];
-    double box;
-    int D;
-    const float* E;  // [n_tg][D] shells dl = 1..3 computed by the split kernel, or nullptr
-    float* N;
-    float* chi;
-    float chi_scale;
-};
-
 __device__ __forceinline__ int sx8(int v) { return (int)(int8_t)(v & 0xff); }
 
 // Sum over one shell's weight list of (configuration, direction).
@@ -532,11 +507,7 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     a.N = N;
     a.chi = chi;
     a.chi_scale = chi_scale;
-    if (A->n_tg > 0) {
-        const unsigned blocks = (unsigned)((A->n_tg + 255) / 256);
-        if (w->D <= 12) k_amr_octs<12><<<blocks, 256, 0, s>>>(a);
-        else k_amr_octs<16><<<blocks, 256, 0, s>>>(a);
-    }
+    launch_target_octs(a, s);
     CD_HIP(hipGetLastError());
     if (t->prof) {
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_ROWS][1], s));
@@ -544,6 +515,13 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         t->pran[CD_STAGE_SWEEP] = t->pran[CD_STAGE_COARSE] = t->pran[CD_STAGE_ROWS] = true;
     }
     return CD_OK;
+}
+
+void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
+    if (a.n_tg <= 0) return;
+    const unsigned blocks = (unsigned)((a.n_tg + 255) / 256);
+    if (a.D <= 12) k_amr_octs<12><<<blocks, 256, 0, s>>>(a);
+    else k_amr_octs<16><<<blocks, 256, 0, s>>>(a);
 }
 
 void amr_free(cd_tree* t) {

@@ -1,0 +1,1057 @@
+// Learned surrogate of the column sweep: features from the pyramid, a ReLU
+// MLP 576 -> W -> W -> D trained with Adam, batched inference, and a sampled
+// check with the method itself as fallback.  Every step runs in the kernels
+// below: feature gather, a strided GEMM (bfloat16 on the matrix cores or
+// FP32 on the vector units) with bias / ReLU / mask epilogues, the loss and
+// its gradient, column sums, the Adam update and the output transform.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "cd_internal.h"
+#include "tree_amr.h"
+
+namespace cd {
+
+constexpr int kFeatLevels = 9;
+constexpr int kFeat = kFeatLevels * 64;  // 576
+constexpr float kFloor = 1e-10f;
+constexpr float kExtFloor = 1e17f;  // cm^-2 added to the external column before the logarithm
+
+// The network predicts the external part of the column (shells dl >= 1,
+// shared by the 8 leaves of an oct, like the features); the internal + local
+// part (Sect. 3.2) is computed exactly from the oct's densities.
+struct IlArgs {
+    const float* leaf;  // [n^3] row-major
+    const float* kloc;  // [8 target octant][8 oct cell][D]
+    int L, D;
+    float dxL;
+};
+
+// the oct densities of leaf q and its octant in the oct
+struct OctCells {
+    float n[8];
+    int o;
+};
+__device__ __forceinline__ OctCells oct_cells(const IlArgs& a, int64_t q) {
+    const int64_t n = (int64_t)1 << a.L;
+    const int64_t x = q & (n - 1), y = (q >> a.L) & (n - 1), z = q >> (2 * a.L);
+    OctCells c;
+    c.o = (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+        c.n[s] = a.leaf[(((z & ~1LL) + (s >> 2)) * n + (y & ~1LL) + ((s >> 1) & 1)) * n + (x & ~1LL) + (s & 1)];
+    return c;
+}
+// internal + local part of that leaf for direction d
+__device__ __forceinline__ float internal_local(const IlArgs& a, const OctCells& c, int d) {
+    float acc = 0.f;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) acc = fmaf(c.n[s], a.kloc[(c.o * 8 + s) * a.D + d], acc);
+    return a.dxL * acc;
+}
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ uint16_t f2bf(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+template <typename T>
+__device__ __forceinline__ T from_f(float x);
+template <>
+__device__ __forceinline__ float from_f<float>(float x) { return x; }
+template <>
+__device__ __forceinline__ uint16_t from_f<uint16_t>(float x) { return f2bf(x); }
+
+// ---------------------------------------------------------------- features --
+struct FeatArgs {
+    const float* lev[kFeatLevels];  // level l < L: padded pyramid level; l == L: the leaves
+    int L;
+    const int64_t* cells;  // leaf indices, or nullptr: c0 + i
+    int64_t c0, n;
+    float shift, inv_scale;
+};
+
+// One thread per (leaf, level): the 64 stencil values of that level.
+template <typename T>
+__global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restrict__ X) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= a.n * kFeatLevels) return;
+    const int64_t i = idx / kFeatLevels;
+    const int l = (int)(idx % kFeatLevels);
+    const int L = a.L;
+    const int64_t q = a.cells ? a.cells[i] : a.c0 + i;
+    const int64_t nL = (int64_t)1 << L;
+    T* out = X + i * kFeat + l * 64;
+    if (q < 0 || q >= nL * nL * nL) {  // not a leaf: NaN features, no access
+        for (int s = 0; s < 64; ++s) out[s] = from_f<T>(__builtin_nanf(""));
+        return;
+    }
+    const int64_t x = q & (nL - 1), y = (q >> L) & (nL - 1), z = q >> (2 * L);
+    const int sh = L - l + 1;  // ancestor at level l - 1
+    const int64_t Ax = x >> sh, Ay = y >> sh, Az = z >> sh;
+    const int64_t nl = (int64_t)1 << l;
+    const float* lev = a.lev[l];
+    for (int s = 0; s < 64; ++s) {
+        const int64_t px = 2 * Ax - 1 + (s & 3), py = 2 * Ay - 1 + ((s >> 2) & 3), pz = 2 * Az - 1 + (s >> 4);
+        float v = 0.f;
+        if (l < L) {  // padded level: the zero halo covers -1 and 2^l
+            const int64_t S = nl + 2 * kHalo;
+            v = lev[((pz + kHalo) * S + (py + kHalo)) * S + (px + kHalo)];
+        } else if (px >= 0 && py >= 0 && pz >= 0 && px < nl && py < nl && pz < nl) {
+            v = lev[(pz * nl + py) * nl + px];
+        }
+        out[s] = from_f<T>((logf(fmaxf(v, kFloor)) - a.shift) * a.inv_scale);
+    }
+}
+
+template <typename T>
+__global__ void k_convert(const float* __restrict__ in, int64_t n, T* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = from_f<T>(in[i]);
+}
+
+// targets: scaled ln of the external part of the method's columns for the
+// listed leaves (one thread per leaf)
+__global__ void k_targets(const IlArgs il, const float* __restrict__ N, const int64_t* __restrict__ cells,
+                          int64_t n, int64_t n_leaf, float shift, float inv_scale, float* __restrict__ T) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int D = il.D;
+    const int64_t q = cells[r];
+    if (q < 0 || q >= n_leaf) {
+        for (int d = 0; d < D; ++d) T[r * D + d] = __builtin_nanf("");
+        return;
+    }
+    const OctCells oc = oct_cells(il, q);
+    for (int d = 0; d < D; ++d)
+        T[r * D + d] = (logf(fmaxf(N[q * D + d] - internal_local(il, oc, d), 0.f) + kExtFloor) - shift) * inv_scale;
+}
+
+// -------------------------------------------------------------------- GEMM --
+// C(m, n) = epilogue(sum_k A(m, k) B(k, n)) with A(m, k) = A[m sam + k sak],
+// B(k, n) = B[k sbk + n sbn]; epilogue: + bias[n], ReLU, times (mask > 0);
+// C in FP32 (optional) and in the storage type (optional), leading dim ldc.
+template <typename T>
+struct GemmArgs {
+    const T* A;
+    int64_t sam, sak;
+    const T* B;
+    int64_t sbk, sbn;
+    int64_t M, N, K;
+    float* C;
+    T* Cl;
+    int64_t ldc;
+    const float* bias;
+    const float* mask;
+    int relu;
+};
+
+constexpr int kGT = 64;   // block tile (M and N)
+constexpr int kGK = 32;   // k step
+constexpr int kGP = 40;   // LDS row pitch (elements)
+
+template <typename T>
+__device__ __forceinline__ void gemm_stage(const GemmArgs<T>& g, int64_t m0, int64_t n0, int64_t k0, T (*As)[kGP],
+                                           T (*Bs)[kGP]) {
+    const int tid = threadIdx.x;
+    const bool a_kfast = g.sak == 1;
+    const bool b_nfast = g.sbn == 1;
+#pragma unroll
+    for (int r = 0; r < (kGT * kGK) / 256; ++r) {
+        const int e = tid + 256 * r;
+        int m, k;
+        if (a_kfast) {
+            m = e / kGK;
+            k = e % kGK;
+        } else {
+            m = e % kGT;
+            k = e / kGT;
+        }
+        const int64_t gm = m0 + m, gk = k0 + k;
+        As[m][k] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (T)0;
+        int n, kb;
+        if (b_nfast) {
+            n = e % kGT;
+            kb = e / kGT;
+        } else {
+            n = e / kGK;
+            kb = e % kGK;
+        }
+        const int64_t gn = n0 + n, gkb = k0 + kb;
+        Bs[n][kb] = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : (T)0;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void gemm_store(const GemmArgs<T>& g, int64_t row, int64_t col, float v) {
+    if (row >= g.M || col >= g.N) return;
+    if (g.bias) v += g.bias[col];
+    if (g.relu) v = fmaxf(v, 0.f);
+    if (g.mask && !(g.mask[row * g.ldc + col] > 0.f)) v = 0.f;
+    if (g.C) g.C[row * g.ldc + col] = v;
+    if (g.Cl) g.Cl[row * g.ldc + col] = from_f<T>(v);
+}
+
+// bfloat16 operands on the matrix cores: 4 waves, each a 32 x 32 quarter of
+// the 64 x 64 tile as 2 x 2 blocks of 16 x 16 x 32.
+__global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs<uint16_t> g) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[kGT][kGP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[kGT][kGP];
+    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int r = lane & 15, grp = lane >> 4;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+        __syncthreads();
+        gemm_stage<uint16_t>(g, m0, n0, k0, As, Bs);
+        __syncthreads();
+        bf16x8 af[2], bfr[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            af[i] = *reinterpret_cast<const bf16x8*>(&As[wm + 16 * i + r][8 * grp]);
+            bfr[i] = *reinterpret_cast<const bf16x8*>(&Bs[wn + 16 * i + r][8 * grp]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
+    }
+    // C layout of 16 x 16: lane holds column (lane & 15) of rows 4 (lane >> 4) + e
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                gemm_store<uint16_t>(g, m0 + wm + 16 * i + 4 * grp + e, n0 + wn + 16 * j + r, acc[i][j][e]);
+}
+
+// FP32 on the vector units: each thread a 4 x 4 block of the 64 x 64 tile.
+__global__ __launch_bounds__(256) void k_gemm_f32(const GemmArgs<float> g) {
+    __shared__ float As[kGT][kGP];
+    __shared__ float Bs[kGT][kGP];
+    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+    const int tm = threadIdx.x >> 4, tn = threadIdx.x & 15;
+    float acc[4][4] = {};
+    for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+        __syncthreads();
+        gemm_stage<float>(g, m0, n0, k0, As, Bs);
+        __syncthreads();
+        for (int k = 0; k < kGK; ++k) {
+            float a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = As[4 * tm + i][k];
+                b[i] = Bs[4 * tn + i][k];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) gemm_store<float>(g, m0 + 4 * tm + i, n0 + 4 * tn + j, acc[i][j]);
+}
+
+template <typename T>
+static void gemm(const GemmArgs<T>& g, hipStream_t s) {
+    dim3 grid((unsigned)((g.M + kGT - 1) / kGT), (unsigned)((g.N + kGT - 1) / kGT));
+    if constexpr (sizeof(T) == 2) k_gemm_bf16<<<grid, 256, 0, s>>>(g);
+    else k_gemm_f32<<<grid, 256, 0, s>>>(g);
+}
+
+// ------------------------------------------------------- loss and updates --
+// dY = 2 (Y - T) / (n D); per-block partial sums of (Y - T)^2
+template <typename T>
+__global__ __launch_bounds__(256) void k_mse(const float* __restrict__ Y, const float* __restrict__ Tg, int64_t n,
+                                             float* __restrict__ dY, T* __restrict__ dYl, float* __restrict__ part) {
+    __shared__ float red[256];
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    float e2 = 0.f;
+    if (i < n) {
+        const float e = Y[i] - Tg[i];
+        const float gr = 2.f * e / (float)n;
+        dY[i] = gr;
+        dYl[i] = from_f<T>(gr);
+        e2 = e * e;
+    }
+    red[threadIdx.x] = e2;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int64_t n, float scale,
+                                             float* __restrict__ out) {
+    __shared__ float red[256];
+    float s = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 256) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+// column sums of a [rows][cols] FP32 matrix (bias gradients)
+__global__ void k_colsum(const float* __restrict__ a, int64_t rows, int cols, float* __restrict__ out) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cols) return;
+    float s = 0.f;
+    for (int64_t r = 0; r < rows; ++r) s += a[r * cols + c];
+    out[c] = s;
+}
+
+__global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float* __restrict__ M,
+                       float* __restrict__ V, uint16_t* __restrict__ Pb, int64_t n, float lr, float bc1, float bc2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = G[i];
+    const float m = 0.9f * M[i] + 0.1f * g;
+    const float v = 0.999f * V[i] + 0.001f * g * g;
+    M[i] = m;
+    V[i] = v;
+    const float p = P[i] - lr * (m / bc1) / (sqrtf(v / bc2) + 1e-8f);
+    P[i] = p;
+    Pb[i] = f2bf(p);
+}
+
+__global__ void k_to_bf16(const float* __restrict__ P, int64_t n, uint16_t* __restrict__ Pb) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) Pb[i] = f2bf(P[i]);
+}
+
+// N = internal + local + max(exp(y out_scale + out_shift) - floor, 0) and
+// chi (Eq. 5) for the rows c0 .. c0 + n - 1
+__global__ void k_output(const IlArgs il, const float* __restrict__ Y, int64_t c0, int64_t n, float out_shift,
+                         float out_scale, float chi_scale, float* __restrict__ N, float* __restrict__ chi) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int D = il.D;
+    const OctCells oc = oct_cells(il, c0 + i);
+    float c = 0.f;
+    for (int d = 0; d < D; ++d) {
+        const float v = internal_local(il, oc, d) + fmaxf(expf(fmaf(Y[i * D + d], out_scale, out_shift)) - kExtFloor, 0.f);
+        N[(c0 + i) * D + d] = v;
+        c += expf(-chi_scale * v);
+    }
+    if (chi) chi[c0 + i] = c / (float)D;
+}
+
+// relative chi error of each sampled leaf
+__global__ void k_sample_err(const float* __restrict__ chi_net, const int64_t* __restrict__ cells, int64_t n,
+                             const float* __restrict__ chi_ref, float* __restrict__ err) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) err[i] = fabsf(chi_net[cells[i]] - chi_ref[i]) / chi_ref[i];
+}
+
+static unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace cd
+
+// ------------------------------------------------------------------ handle --
+struct cd_surrogate {
+    int D = 0, W = 0, prec = CD_SURR_BF16;
+    float norm[4] = {0.f, 1.f, 0.f, 1.f};  // in_shift, in_scale, out_shift, out_scale
+    int64_t off[7] = {0};                  // W1 b1 W2 b2 W3 b3 end
+    int64_t n_params = 0;
+    float *P = nullptr, *G = nullptr, *M = nullptr, *V = nullptr;
+    uint16_t* Pb = nullptr;
+    int64_t t = 0;
+    // batch scratch
+    int64_t cap = 0;
+    void* X = nullptr;     // [cap][576] storage type
+    float* A1 = nullptr;   // [cap][W] FP32 activations (masks)
+    float* A2 = nullptr;
+    void* A1l = nullptr;   // storage-type copies
+    void* A2l = nullptr;
+    float* Y = nullptr;    // [cap][D]
+    float* Tg = nullptr;
+    float* dY = nullptr;
+    void* dYl = nullptr;
+    float* dZ2 = nullptr;
+    void* dZ2l = nullptr;
+    float* dZ1 = nullptr;
+    void* dZ1l = nullptr;
+    float* part = nullptr;
+    float* loss = nullptr;
+    int64_t* cells = nullptr;  // [cap] scratch index list
+};
+
+namespace cd {
+
+static size_t esize(const cd_surrogate* s) { return s->prec == CD_SURR_BF16 ? 2 : 4; }
+
+static void free_scratch(cd_surrogate* s) {
+    void* bufs[] = {s->X, s->A1, s->A2, s->A1l, s->A2l, s->Y, s->Tg, s->dY, s->dYl, s->dZ2, s->dZ2l, s->dZ1,
+                    s->dZ1l, s->part, s->loss, s->cells};
+    for (void* b : bufs)
+        if (b) (void)hipFree(b);
+    s->X = s->A1l = s->A2l = s->dYl = s->dZ2l = s->dZ1l = nullptr;
+    s->A1 = s->A2 = s->Y = s->Tg = s->dY = s->dZ2 = s->dZ1 = s->part = s->loss = nullptr;
+    s->cells = nullptr;
+    s->cap = 0;
+}
+
+static int ensure_cap(cd_surrogate* s, int64_t n) {
+    if (n <= s->cap) return CD_OK;
+    free_scratch(s);
+    const size_t es = esize(s), W = s->W, D = s->D, nr = (size_t)n;
+    struct {
+        void** p;
+        size_t bytes;
+    } req[] = {
+        {&s->X, nr * kFeat * es},       {(void**)&s->A1, nr * W * 4}, {(void**)&s->A2, nr * W * 4},
+        {&s->A1l, nr * W * es},         {&s->A2l, nr * W * es},       {(void**)&s->Y, nr * D * 4},
+        {(void**)&s->Tg, nr * D * 4},   {(void**)&s->dY, nr * D * 4}, {&s->dYl, nr * D * es},
+        {(void**)&s->dZ2, nr * W * 4},  {&s->dZ2l, nr * W * es},      {(void**)&s->dZ1, nr * W * 4},
+        {&s->dZ1l, nr * W * es},        {(void**)&s->part, (nr * std::max<size_t>(W, D) / 256 + 2) * 4},
+        {(void**)&s->loss, 16},        {(void**)&s->cells, nr * 8},
+    };
+    for (auto& r : req) {
+        if (hipMalloc(r.p, r.bytes) != hipSuccess) {
+            set_error("hipMalloc of %zu bytes (surrogate batch of %lld) failed", r.bytes, (long long)n);
+            free_scratch(s);
+            return CD_ENOMEM;
+        }
+    }
+    s->cap = n;
+    return CD_OK;
+}
+
+static bool surrogate_tree_ok(const cd_tree* t) { return t && t->uniform && t->lmax >= 8 && t->lmax <= CD_MAX_LEVEL; }
+
+static IlArgs il_args(const cd_tree* t, const cd_weights* w) {
+    IlArgs a{};
+    a.leaf = t->leaf;
+    a.kloc = w->kloc;
+    a.L = t->lmax;
+    a.D = w->D;
+    a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));
+    return a;
+}
+
+static FeatArgs feat_args(const cd_surrogate* s, const cd_tree* t) {
+    FeatArgs a{};
+    for (int l = 0; l < kFeatLevels; ++l) a.lev[l] = (l < t->lmax) ? t->lev[l] : t->leaf;
+    a.L = t->lmax;
+    a.shift = s->norm[0];
+    a.inv_scale = 1.f / s->norm[1];
+    return a;
+}
+
+template <typename T>
+static void launch_features(const FeatArgs& a, T* X, hipStream_t st) {
+    k_features<T><<<nblk(a.n * kFeatLevels), 256, 0, st>>>(a, X);
+}
+
+// Forward pass of n rows already in s->X; Y in FP32.  keep: FP32 activations
+// for the backward pass.
+template <typename T>
+static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st) {
+    const int W = s->W, D = s->D;
+    const T* Wt = s->prec == CD_SURR_BF16 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    GemmArgs<T> g{};
+    // layer 1: X [n][576] W1 [576][W]
+    g.A = (const T*)s->X; g.sam = kFeat; g.sak = 1;
+    g.B = Wt + s->off[0]; g.sbk = W; g.sbn = 1;
+    g.M = n; g.N = W; g.K = kFeat;
+    g.C = keep ? s->A1 : nullptr; g.Cl = (T*)s->A1l; g.ldc = W;
+    g.bias = s->P + s->off[1]; g.mask = nullptr; g.relu = 1;
+    gemm<T>(g, st);
+    // layer 2
+    g.A = (const T*)s->A1l; g.sam = W;
+    g.B = Wt + s->off[2];
+    g.K = W;
+    g.C = keep ? s->A2 : nullptr; g.Cl = (T*)s->A2l;
+    g.bias = s->P + s->off[3];
+    gemm<T>(g, st);
+    // layer 3
+    g.A = (const T*)s->A2l;
+    g.B = Wt + s->off[4]; g.sbk = D;
+    g.N = D;
+    g.C = s->Y; g.Cl = nullptr; g.ldc = D;
+    g.bias = s->P + s->off[5]; g.relu = 0;
+    gemm<T>(g, st);
+}
+
+// Loss, gradient into s->G (targets in s->Tg, activations kept).
+template <typename T>
+static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
+    const int W = s->W, D = s->D;
+    const T* Wt = s->prec == CD_SURR_BF16 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    const int64_t nd = n * D;
+    const unsigned nb = nblk(nd);
+    k_mse<T><<<nb, 256, 0, st>>>(s->Y, s->Tg, nd, s->dY, (T*)s->dYl, s->part);
+    k_sum<<<1, 256, 0, st>>>(s->part, nb, 1.f / (float)nd, s->loss);
+    GemmArgs<T> g{};
+    // dW3 = A2^T dY: [W][D]
+    g.A = (const T*)s->A2l; g.sam = 1; g.sak = W;
+    g.B = (const T*)s->dYl; g.sbk = D; g.sbn = 1;
+    g.M = W; g.N = D; g.K = n;
+    g.C = s->G + s->off[4]; g.Cl = nullptr; g.ldc = D;
+    gemm<T>(g, st);
+    k_colsum<<<nblk(D), 256, 0, st>>>(s->dY, n, D, s->G + s->off[5]);
+    // dZ2 = (dY W3^T) * (A2 > 0): [n][W]
+    g.A = (const T*)s->dYl; g.sam = D; g.sak = 1;
+    g.B = Wt + s->off[4]; g.sbk = 1; g.sbn = D;
+    g.M = n; g.N = W; g.K = D;
+    g.C = s->dZ2; g.Cl = (T*)s->dZ2l; g.ldc = W; g.mask = s->A2;
+    gemm<T>(g, st);
+    // dW2 = A1^T dZ2
+    g.A = (const T*)s->A1l; g.sam = 1; g.sak = W;
+    g.B = (const T*)s->dZ2l; g.sbk = W; g.sbn = 1;
+    g.M = W; g.N = W; g.K = n;
+    g.C = s->G + s->off[2]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
+    gemm<T>(g, st);
+    k_colsum<<<nblk(W), 256, 0, st>>>(s->dZ2, n, W, s->G + s->off[3]);
+    // dZ1 = (dZ2 W2^T) * (A1 > 0)
+    g.A = (const T*)s->dZ2l; g.sam = W; g.sak = 1;
+    g.B = Wt + s->off[2]; g.sbk = 1; g.sbn = W;
+    g.M = n; g.N = W; g.K = W;
+    g.C = s->dZ1; g.Cl = (T*)s->dZ1l; g.ldc = W; g.mask = s->A1;
+    gemm<T>(g, st);
+    // dW1 = X^T dZ1: [576][W]
+    g.A = (const T*)s->X; g.sam = 1; g.sak = kFeat;
+    g.B = (const T*)s->dZ1l; g.sbk = W; g.sbn = 1;
+    g.M = kFeat; g.N = W; g.K = n;
+    g.C = s->G + s->off[0]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
+    gemm<T>(g, st);
+    k_colsum<<<nblk(W), 256, 0, st>>>(s->dZ1, n, W, s->G + s->off[1]);
+}
+
+static void adam(cd_surrogate* s, float lr, hipStream_t st) {
+    s->t += 1;
+    const float bc1 = (float)(1.0 - std::pow(0.9, (double)s->t));
+    const float bc2 = (float)(1.0 - std::pow(0.999, (double)s->t));
+    k_adam<<<nblk(s->n_params), 256, 0, st>>>(s->P, s->G, s->M, s->V, s->Pb, s->n_params, lr, bc1, bc2);
+}
+
+static uint64_t splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+}  // namespace cd
+
+using namespace cd;
+
+#define SURR_CHECK(cond, ...)         \
+    do {                              \
+        if (!(cond)) {                \
+            set_error(__VA_ARGS__);   \
+            return CD_EINVAL;         \
+        }                             \
+    } while (0)
+
+extern "C" int cd_surrogate_create(int D, int width, int precision, uint64_t seed, const float* norm,
+                                   cd_surrogate** out) {
+    clear_error();
+    SURR_CHECK(out, "cd_surrogate_create: NULL output");
+    *out = nullptr;
+    SURR_CHECK(D >= 1 && D <= CD_MAX_DIRS, "cd_surrogate_create: D = %d outside 1..%d", D, CD_MAX_DIRS);
+    SURR_CHECK(width >= 16 && width <= 1024 && width % 16 == 0, "cd_surrogate_create: width %d", width);
+    SURR_CHECK(precision == CD_SURR_FP32 || precision == CD_SURR_BF16, "cd_surrogate_create: precision %d",
+               precision);
+    SURR_CHECK(!norm || (norm[1] > 0 && norm[3] > 0 && std::isfinite(norm[0]) && std::isfinite(norm[2])),
+               "cd_surrogate_create: bad normalisation");
+    cd_surrogate* s = new cd_surrogate();
+    s->D = D;
+    s->W = width;
+    s->prec = precision;
+    if (norm) std::memcpy(s->norm, norm, sizeof(s->norm));
+    const int64_t sizes[6] = {(int64_t)kFeat * width, width, (int64_t)width * width, width, (int64_t)width * D, D};
+    for (int i = 0; i < 6; ++i) s->off[i + 1] = s->off[i] + sizes[i];
+    s->n_params = s->off[6];
+    // He-uniform weights (ReLU fan-in), Glorot-uniform output layer, zero biases
+    std::vector<float> h((size_t)s->n_params, 0.f);
+    uint64_t c = seed;
+    auto uni = [&c]() { return (double)(splitmix64(c++) >> 11) * 0x1.0p-53; };
+    const double lim[3] = {std::sqrt(6.0 / kFeat), std::sqrt(6.0 / width), std::sqrt(6.0 / (width + D))};
+    for (int layer = 0; layer < 3; ++layer)
+        for (int64_t i = s->off[2 * layer]; i < s->off[2 * layer + 1]; ++i)
+            h[(size_t)i] = (float)((2.0 * uni() - 1.0) * lim[layer]);
+    const size_t pb = (size_t)s->n_params * 4;
+    if (hipMalloc((void**)&s->P, pb) != hipSuccess || hipMalloc((void**)&s->G, pb) != hipSuccess ||
+        hipMalloc((void**)&s->M, pb) != hipSuccess || hipMalloc((void**)&s->V, pb) != hipSuccess ||
+        hipMalloc((void**)&s->Pb, pb / 2) != hipSuccess) {
+        set_error("hipMalloc of the surrogate parameters failed");
+        cd_surrogate_destroy(s);
+        return CD_ENOMEM;
+    }
+    int rc = cd_surrogate_set_params(s, h.data());
+    if (rc != CD_OK) {
+        cd_surrogate_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CD_OK;
+}
+
+extern "C" void cd_surrogate_destroy(cd_surrogate* s) {
+    if (!s) return;
+    (void)hipDeviceSynchronize();
+    free_scratch(s);
+    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb})
+        if (p) (void)hipFree(p);
+    delete s;
+}
+
+extern "C" int cd_surrogate_n_params(const cd_surrogate* s, int64_t* n) {
+    clear_error();
+    SURR_CHECK(s && n, "cd_surrogate_n_params: NULL argument");
+    *n = s->n_params;
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_get_params(const cd_surrogate* s, float* params) {
+    clear_error();
+    SURR_CHECK(s && params, "cd_surrogate_get_params: NULL argument");
+    CD_HIP(hipDeviceSynchronize());
+    CD_HIP(hipMemcpy(params, s->P, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_set_params(cd_surrogate* s, const float* params) {
+    clear_error();
+    SURR_CHECK(s && params, "cd_surrogate_set_params: NULL argument");
+    const size_t pb = (size_t)s->n_params * 4;
+    CD_HIP(hipDeviceSynchronize());
+    CD_HIP(hipMemcpy(s->P, params, pb, hipMemcpyHostToDevice));
+    CD_HIP(hipMemset(s->M, 0, pb));
+    CD_HIP(hipMemset(s->V, 0, pb));
+    CD_HIP(hipMemset(s->G, 0, pb));
+    k_to_bf16<<<nblk(s->n_params), 256>>>(s->P, s->n_params, s->Pb);
+    CD_HIP(hipGetLastError());
+    CD_HIP(hipDeviceSynchronize());
+    s->t = 0;
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_features(const cd_surrogate* s, const cd_tree* t, const int64_t* cells_dev, int64_t n,
+                                     float* X_dev, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && X_dev && (cells_dev || n == 0) && n >= 0, "cd_surrogate_features: bad arguments");
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_features: the surrogate needs a uniform grid with 2^L >= 256");
+    if (n == 0) return CD_OK;
+    FeatArgs a = feat_args(s, t);
+    a.cells = cells_dev;
+    a.n = n;
+    launch_features<float>(a, X_dev, (hipStream_t)stream);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+template <typename T>
+static int forward_impl(cd_surrogate* s, const float* X, int64_t n, float* Y, hipStream_t st) {
+    int rc = ensure_cap(s, n);
+    if (rc != CD_OK) return rc;
+    k_convert<T><<<nblk(n * kFeat), 256, 0, st>>>(X, n * kFeat, (T*)s->X);
+    forward_rows<T>(s, n, false, st);
+    CD_HIP(hipMemcpyAsync(Y, s->Y, (size_t)n * s->D * 4, hipMemcpyDeviceToDevice, st));
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_forward(cd_surrogate* s, const float* X_dev, int64_t n, float* Y_dev, void* stream) {
+    clear_error();
+    SURR_CHECK(s && X_dev && Y_dev && n >= 0, "cd_surrogate_forward: bad arguments");
+    if (n == 0) return CD_OK;
+    hipStream_t st = (hipStream_t)stream;
+    return s->prec == CD_SURR_BF16 ? forward_impl<uint16_t>(s, X_dev, n, Y_dev, st)
+                                   : forward_impl<float>(s, X_dev, n, Y_dev, st);
+}
+
+template <typename T>
+static int grad_impl(cd_surrogate* s, const float* X, const float* Tg, int64_t n, hipStream_t st) {
+    int rc = ensure_cap(s, n);
+    if (rc != CD_OK) return rc;
+    k_convert<T><<<nblk(n * kFeat), 256, 0, st>>>(X, n * kFeat, (T*)s->X);
+    CD_HIP(hipMemcpyAsync(s->Tg, Tg, (size_t)n * s->D * 4, hipMemcpyDeviceToDevice, st));
+    forward_rows<T>(s, n, true, st);
+    backward_rows<T>(s, n, st);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_gradients(cd_surrogate* s, const float* X_dev, const float* T_dev, int64_t n,
+                                      float* grad, float* loss, void* stream) {
+    clear_error();
+    SURR_CHECK(s && X_dev && T_dev && grad && n > 0, "cd_surrogate_gradients: bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = s->prec == CD_SURR_BF16 ? grad_impl<uint16_t>(s, X_dev, T_dev, n, st)
+                                     : grad_impl<float>(s, X_dev, T_dev, n, st);
+    if (rc != CD_OK) return rc;
+    CD_HIP(hipStreamSynchronize(st));
+    CD_HIP(hipMemcpy(grad, s->G, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
+    if (loss) CD_HIP(hipMemcpy(loss, s->loss, 4, hipMemcpyDeviceToHost));
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N_dev,
+                                    const int64_t* cells_dev, int64_t n, float* T_dev, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && N_dev && T_dev && (cells_dev || n == 0) && n >= 0, "cd_surrogate_targets: bad arguments");
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_targets: the surrogate needs a uniform grid with 2^L >= 256");
+    SURR_CHECK(w->D == s->D, "cd_surrogate_targets: weights of D = %d for a network of D = %d", w->D, s->D);
+    if (n == 0) return CD_OK;
+    k_targets<<<nblk(n), 256, 0, (hipStream_t)stream>>>(il_args(t, w), N_dev, cells_dev, n, t->n_leaf, s->norm[2],
+                                                        1.f / s->norm[3], T_dev);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+template <typename T>
+static int train_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N, const int64_t* cells,
+                      int64_t n, float lr, hipStream_t st) {
+    int rc = ensure_cap(s, n);
+    if (rc != CD_OK) return rc;
+    FeatArgs a = feat_args(s, t);
+    a.cells = cells;
+    a.n = n;
+    launch_features<T>(a, (T*)s->X, st);
+    k_targets<<<nblk(n), 256, 0, st>>>(il_args(t, w), N, cells, n, t->n_leaf, s->norm[2], 1.f / s->norm[3], s->Tg);
+    forward_rows<T>(s, n, true, st);
+    backward_rows<T>(s, n, st);
+    adam(s, lr, st);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N_dev,
+                                       const int64_t* cells_dev, int64_t batch, float lr, float* loss, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && N_dev && cells_dev && batch > 0 && lr > 0, "cd_surrogate_train_step: bad arguments");
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_train_step: the surrogate needs a uniform grid with 2^L >= 256");
+    SURR_CHECK(w->D == s->D, "cd_surrogate_train_step: weights of D = %d for a network of D = %d", w->D, s->D);
+    hipStream_t st = (hipStream_t)stream;
+    int rc = s->prec == CD_SURR_BF16 ? train_impl<uint16_t>(s, t, w, N_dev, cells_dev, batch, lr, st)
+                                     : train_impl<float>(s, t, w, N_dev, cells_dev, batch, lr, st);
+    if (rc != CD_OK) return rc;
+    if (loss) {
+        CD_HIP(hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToHost, st));
+        CD_HIP(hipStreamSynchronize(st));
+    }
+    return CD_OK;
+}
+
+template <typename T>
+static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
+                      hipStream_t st) {
+    const int64_t total = t->n_leaf;
+    const int64_t batch = std::min<int64_t>(total, (int64_t)1 << 20);
+    int rc = ensure_cap(s, batch);
+    if (rc != CD_OK) return rc;
+    FeatArgs a = feat_args(s, t);
+    for (int64_t c0 = 0; c0 < total; c0 += batch) {
+        const int64_t nb = std::min(batch, total - c0);
+        a.cells = nullptr;
+        a.c0 = c0;
+        a.n = nb;
+        launch_features<T>(a, (T*)s->X, st);
+        forward_rows<T>(s, nb, false, st);
+        k_output<<<nblk(nb), 256, 0, st>>>(il_args(t, w), s->Y, c0, nb, s->norm[2], s->norm[3], chi_scale, N, chi);
+    }
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N_dev,
+                                  float* chi_dev, double av_per_nh, double gamma, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && N_dev, "cd_surrogate_infer: NULL argument");
+    SURR_CHECK(w->D == s->D, "cd_surrogate_infer: weights of D = %d for a network of D = %d", w->D, s->D);
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_infer: the surrogate needs a uniform grid with 2^L >= 256");
+    SURR_CHECK(!chi_dev || (std::isfinite(av_per_nh) && std::isfinite(gamma)), "cd_surrogate_infer: bad chi parameters");
+    hipStream_t st = (hipStream_t)stream;
+    const float cs = (float)(gamma * av_per_nh);
+    return s->prec == CD_SURR_BF16 ? infer_impl<uint16_t>(s, t, w, N_dev, chi_dev, cs, st)
+                                   : infer_impl<float>(s, t, w, N_dev, chi_dev, cs, st);
+}
+
+namespace cd {
+int ensure_q(cd_tree* t, int D, int top, bool compact);
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s);
+}
+
+// Generic per-oct arguments for target octs of a uniform tree (children at
+// level L read from the leaf array, shells from the dense levels).
+static AmrSweepArgs uniform_oct_args(const cd_tree* t, const cd_weights* w, float chi_scale) {
+    const int L = t->lmax;
+    AmrSweepArgs a{};
+    for (int l = 0; l < L; ++l) a.lk.lev[l] = t->lev[l];
+    a.lk.B = L - 1;
+    a.octden = t->leaf;
+    a.base = nullptr;
+    for (int k = 1; k <= 4; ++k) {
+        a.off[k] = w->off[k];
+        a.w[k] = w->w[k];
+        a.len[k] = w->len[k];
+    }
+    a.kloc = w->kloc;
+    a.qtop = L - 4;
+    a.qcompact = 1;
+    for (int l = 2; l <= L - 4; ++l) a.q[l] = t->q[l];
+    for (int sc = 0; sc < 6; ++sc)
+        for (int p = 0; p < 2; ++p) a.next[sc][p] = (int8_t)next_state_code(sc, p);
+    for (int q = 0; q < 4; ++q) a.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
+    a.box = t->box_cm;
+    a.D = w->D;
+    a.chi_scale = chi_scale;
+    return a;
+}
+
+// Device lists of target octs for the generic per-oct kernel: info (L, oct
+// x, y, z), the 8 child leaf indices (row-major) and each child's output row
+// (-1: not wanted).
+struct OctLists {
+    int32_t* info = nullptr;
+    int64_t* src = nullptr;
+    int64_t* out = nullptr;
+    int64_t n = 0;
+    int alloc(int64_t count) {
+        n = count;
+        if (count == 0) return CD_OK;
+        if (hipMalloc((void**)&info, count * 16) != hipSuccess || hipMalloc((void**)&src, count * 64) != hipSuccess ||
+            hipMalloc((void**)&out, count * 64) != hipSuccess) {
+            set_error("hipMalloc of %lld target octs failed", (long long)count);
+            return CD_ENOMEM;
+        }
+        return CD_OK;
+    }
+    ~OctLists() {
+        for (void* p : {(void*)info, (void*)src, (void*)out})
+            if (p) (void)hipFree(p);
+    }
+};
+
+__device__ __forceinline__ uint64_t d_splitmix64(uint64_t x) {
+    x += 0x9e3779b97f4a7c15ull;
+    x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+    x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+    return x ^ (x >> 31);
+}
+
+__device__ __forceinline__ void put_oct(int32_t* info, int64_t* src, int64_t* out, int64_t k, int L, int64_t ox,
+                                        int64_t oy, int64_t oz, int want /* child octant, or 8: all */, int64_t row) {
+    const int64_t n = (int64_t)1 << L;
+    info[4 * k] = L;
+    info[4 * k + 1] = (int32_t)ox;
+    info[4 * k + 2] = (int32_t)oy;
+    info[4 * k + 3] = (int32_t)oz;
+    for (int c = 0; c < 8; ++c) {
+        const int64_t q = ((2 * oz + (c >> 2)) * n + 2 * oy + ((c >> 1) & 1)) * n + 2 * ox + (c & 1);
+        src[8 * k + c] = q;
+        out[8 * k + c] = want == 8 ? q : (c == want ? row : -1);
+    }
+}
+
+// sample j of tile tl (tiles of 8^3 leaves, tpa per axis): a leaf drawn from
+// the seed, its oct as a target writing row tl * per + j
+__global__ void k_make_samples(int L, int64_t tpa, int per, uint64_t seed, int64_t ns, int32_t* info, int64_t* src,
+                               int64_t* out, int64_t* cells) {
+    const int64_t si = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= ns) return;
+    const int64_t tl = si / per, j = si % per;
+    const int64_t tx = tl % tpa, ty = (tl / tpa) % tpa, tz = tl / (tpa * tpa);
+    const uint64_t r = d_splitmix64(seed ^ d_splitmix64((uint64_t)tl * 1024 + (uint64_t)j));
+    const int64_t x = 8 * tx + (int64_t)(r & 7), y = 8 * ty + (int64_t)((r >> 3) & 7), z = 8 * tz + (int64_t)((r >> 6) & 7);
+    const int64_t n = (int64_t)1 << L;
+    cells[si] = (z * n + y) * n + x;
+    put_oct(info, src, out, si, L, x >> 1, y >> 1, z >> 1, (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)), si);
+}
+
+// every oct (64 per tile) of the listed tiles, all 8 leaves written in place
+__global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__ tiles, int64_t nfail, int32_t* info,
+                                 int64_t* src, int64_t* out) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nfail * 64) return;
+    const int64_t tl = tiles[k >> 6];
+    const int o = (int)(k & 63);
+    const int64_t tx = tl % tpa, ty = (tl / tpa) % tpa, tz = tl / (tpa * tpa);
+    put_oct(info, src, out, k, L, 4 * tx + (o & 3), 4 * ty + ((o >> 2) & 3), 4 * tz + (o >> 4), 8, 0);
+}
+
+static void run_octs(const cd_tree* t, const cd_weights* w, float chi_scale, const OctLists& ol, float* N, float* chi,
+                     hipStream_t st) {
+    AmrSweepArgs a = uniform_oct_args(t, w, chi_scale);
+    a.tg_info = ol.info;
+    a.tg_src = ol.src;
+    a.tg_leaf = ol.out;
+    a.n_tg = ol.n;
+    a.N = N;
+    a.chi = chi;
+    launch_target_octs(a, st);
+}
+
+extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd_weights* w, double frac,
+                                           double tol_chi, uint64_t seed, float* N_dev, float* chi_dev,
+                                           double av_per_nh, double gamma, int64_t* n_fallback_tiles,
+                                           int64_t* n_tiles, float* max_sample_err, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && N_dev && chi_dev && n_fallback_tiles && n_tiles, "cd_surrogate_check_fallback: NULL argument");
+    SURR_CHECK(frac > 0 && frac <= 1 && tol_chi >= 0, "cd_surrogate_check_fallback: frac %g, tol %g", frac, tol_chi);
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_check_fallback: the surrogate needs a uniform grid with 2^L >= 256");
+    SURR_CHECK(w->precision == CD_FP32 && w->D == s->D, "cd_surrogate_check_fallback: needs FP32 weights of D = %d",
+               s->D);
+    hipStream_t st = (hipStream_t)stream;
+    const float cs = (float)(gamma * av_per_nh);
+    const int L = t->lmax;
+    // coarse tables of the method (shells dl >= 4)
+    int rc = ensure_q(t, w->D, L - 4, true);
+    if (rc != CD_OK) return rc;
+    launch_coarse(t, w, L - 4, true, st);
+    // samples: ceil(frac * 512) leaves per tile of 8^3
+    const int64_t tpa = ((int64_t)1 << L) / 8, nt = tpa * tpa * tpa;
+    const int per = (int)std::ceil(frac * 512.0 - 1e-9);
+    const int64_t ns = nt * per;
+    OctLists sl;
+    if ((rc = sl.alloc(ns)) != CD_OK) return rc;
+    float *sN = nullptr, *sChi = nullptr, *err = nullptr;
+    int64_t* cells = nullptr;
+    struct Free {
+        std::vector<void*> p;
+        ~Free() {
+            for (void* q : p) (void)hipFree(q);
+        }
+    } guard;
+    auto dmalloc = [&guard](void** p, size_t bytes) {
+        if (hipMalloc(p, bytes) != hipSuccess) return false;
+        guard.p.push_back(*p);
+        return true;
+    };
+    if (!dmalloc((void**)&sN, (size_t)ns * w->D * 4) || !dmalloc((void**)&sChi, ns * 4) ||
+        !dmalloc((void**)&err, ns * 4) || !dmalloc((void**)&cells, ns * 8)) {
+        set_error("hipMalloc of the check samples failed");
+        return CD_ENOMEM;
+    }
+    k_make_samples<<<nblk(ns), 256, 0, st>>>(L, tpa, per, seed, ns, sl.info, sl.src, sl.out, cells);
+    run_octs(t, w, cs, sl, sN, sChi, st);
+    k_sample_err<<<nblk(ns), 256, 0, st>>>(chi_dev, cells, ns, sChi, err);
+    std::vector<float> e((size_t)ns);
+    CD_HIP(hipMemcpyAsync(e.data(), err, ns * 4, hipMemcpyDeviceToHost, st));
+    CD_HIP(hipStreamSynchronize(st));
+    // tiles with a failing sample: every oct recomputed by the method
+    std::vector<int64_t> fail;
+    float emax = 0.f;
+    for (int64_t tl = 0; tl < nt; ++tl) {
+        bool bad = false;
+        for (int j = 0; j < per; ++j) {
+            const float ej = e[(size_t)(tl * per + j)];
+            emax = std::max(emax, std::isfinite(ej) ? ej : INFINITY);
+            bad |= !(ej <= (float)tol_chi);
+        }
+        if (bad) fail.push_back(tl);
+    }
+    const int64_t nfail = (int64_t)fail.size();
+    if (nfail > 0) {
+        int64_t* dfail = nullptr;
+        if (!dmalloc((void**)&dfail, nfail * 8)) {
+            set_error("hipMalloc of the fallback tile list failed");
+            return CD_ENOMEM;
+        }
+        OctLists fl;
+        if ((rc = fl.alloc(nfail * 64)) != CD_OK) return rc;
+        CD_HIP(hipMemcpyAsync(dfail, fail.data(), nfail * 8, hipMemcpyHostToDevice, st));
+        k_make_tile_octs<<<nblk(nfail * 64), 256, 0, st>>>(L, tpa, dfail, nfail, fl.info, fl.src, fl.out);
+        run_octs(t, w, cs, fl, N_dev, chi_dev, st);
+        CD_HIP(hipGetLastError());
+        CD_HIP(hipStreamSynchronize(st));  // lists are freed on return
+    }
+    CD_HIP(hipGetLastError());
+    *n_fallback_tiles = nfail;
+    *n_tiles = nt;
+    if (max_sample_err) *max_sample_err = emax;
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_save(const cd_surrogate* s, const char* path) {
+    clear_error();
+    SURR_CHECK(s && path, "cd_surrogate_save: NULL argument");
+    std::vector<float> buf((size_t)s->n_params * 3);
+    CD_HIP(hipDeviceSynchronize());
+    CD_HIP(hipMemcpy(buf.data(), s->P, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
+    CD_HIP(hipMemcpy(buf.data() + s->n_params, s->M, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
+    CD_HIP(hipMemcpy(buf.data() + 2 * s->n_params, s->V, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
+    FILE* f = std::fopen(path, "wb");
+    SURR_CHECK(f, "cd_surrogate_save: cannot open %s", path);
+    const char magic[8] = {'C', 'D', 'S', 'U', 'R', 'R', '0', '1'};
+    const int32_t hdr[4] = {s->D, s->W, s->prec, 0};
+    const int64_t nt[2] = {s->n_params, s->t};
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 &&
+              std::fwrite(s->norm, 4, 4, f) == 4 && std::fwrite(nt, 8, 2, f) == 2 &&
+              std::fwrite(buf.data(), 4, buf.size(), f) == buf.size();
+    ok &= std::fclose(f) == 0;
+    SURR_CHECK(ok, "cd_surrogate_save: write to %s failed", path);
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_load(const char* path, cd_surrogate** out) {
+    clear_error();
+    SURR_CHECK(path && out, "cd_surrogate_load: NULL argument");
+    *out = nullptr;
+    FILE* f = std::fopen(path, "rb");
+    SURR_CHECK(f, "cd_surrogate_load: cannot open %s", path);
+    char magic[8];
+    int32_t hdr[4];
+    float norm[4];
+    int64_t nt[2];
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CDSURR01", 8) == 0 &&
+              std::fread(hdr, 4, 4, f) == 4 && std::fread(norm, 4, 4, f) == 4 && std::fread(nt, 8, 2, f) == 2;
+    if (!ok) {
+        std::fclose(f);
+        set_error("cd_surrogate_load: %s is not a surrogate file", path);
+        return CD_EINVAL;
+    }
+    cd_surrogate* s = nullptr;
+    int rc = cd_surrogate_create(hdr[0], hdr[1], hdr[2], 0, norm, &s);
+    if (rc != CD_OK) {
+        std::fclose(f);
+        return rc;
+    }
+    std::vector<float> buf((size_t)s->n_params * 3);
+    ok = nt[0] == s->n_params && std::fread(buf.data(), 4, buf.size(), f) == buf.size();
+    std::fclose(f);
+    if (!ok) {
+        cd_surrogate_destroy(s);
+        set_error("cd_surrogate_load: %s is truncated or does not match its header", path);
+        return CD_EINVAL;
+    }
+    rc = cd_surrogate_set_params(s, buf.data());
+    if (rc == CD_OK) {
+        if (hipMemcpy(s->M, buf.data() + s->n_params, (size_t)s->n_params * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipMemcpy(s->V, buf.data() + 2 * s->n_params, (size_t)s->n_params * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            set_error("cd_surrogate_load: upload failed");
+            rc = CD_EDEVICE;
+        }
+        s->t = nt[1];
+    }
+    if (rc != CD_OK) {
+        cd_surrogate_destroy(s);
+        return rc;
+    }
+    *out = s;
+    return CD_OK;
+}

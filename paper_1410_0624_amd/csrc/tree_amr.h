@@ -35,6 +35,38 @@ struct AmrLookupView {
     }
 };
 
+// Arguments of the generic per-target-oct FP32 kernel: for each target oct
+// (level of its children, oct coordinates), the child densities through
+// tg_src (>= 0: index into octden, < 0: -(1 + index into base)), the output
+// row of each child through tg_leaf (-1: not a target), shells dl = 1..3
+// from the weight lists (or E), dl >= 4 from the automaton and Q tables.
+struct AmrSweepArgs {
+    AmrLookupView lk;
+    const int32_t* tg_info;
+    const int64_t* tg_src;
+    const int64_t* tg_leaf;
+    int64_t n_tg;
+    const float* octden;
+    const float* base;  // padded level B
+    const int32_t* off[5];
+    const float* w[5];
+    int len[5];
+    const float* kloc;
+    const float* q[CD_MAX_LEVEL + 1];  // coarse tables of levels 2 .. qtop, 216 codes
+    int qtop;
+    int qcompact;  // Q_qtop holds only the 64 codes of dl = 4 (qtop == Lmax - 4)
+    int8_t next[6][2];
+    int8_t dl4[4];
+    double box;
+    int D;
+    const float* E;  // [n_tg][D] shells dl = 1..3 computed by the split kernel, or nullptr
+    float* N;
+    float* chi;
+    float chi_scale;
+};
+
+void launch_target_octs(const AmrSweepArgs& a, hipStream_t s);
+
 void launch_amr_external_mfma(const AmrLookupView& lk, const int32_t* tg_info, const int32_t* grp,
                               const int32_t* grp_info, int64_t ngroups, const cd_weights* w, double box, float* E,
                               hipStream_t s);

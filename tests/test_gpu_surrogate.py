@@ -1,0 +1,260 @@
+"""The learned surrogate on the GPU, through the C ABI, against the FP64
+reference in oracle/surrogate.py and against the method itself.
+
+Gates: features and targets to 2e-5 (ln units); forward and gradients of
+the FP32 checking path to 1e-5 against the FP64 reference, of the bfloat16
+path to 1e-2 against the reference rounded where the bfloat16 path rounds
+(relative, per parameter block); after the sampled check and fallback, the
+99th percentile of the relative chi error <= 3 %."""
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import surrogate as S
+from paper_1410_0624_amd import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def colden():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1410_0624_amd import colden as c
+    c.lib()
+    return c
+
+
+DEV = "cuda:0"
+
+
+def _field(seed, L=8):
+    return synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=seed)
+
+
+def _plain(colden, tin, w):
+    leaf = torch.from_numpy(tin.leaf_n).to(DEV)
+    tree = colden.Tree(tin, leaf)
+    N = torch.empty((tin.n_leaf, w.D), dtype=torch.float32, device=DEV)
+    chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=DEV)
+    colden.column_densities(tree, w, N, chi)
+    torch.cuda.synchronize()
+    return tree, leaf, N, chi
+
+
+def _blocks(flat, W, D):
+    return S.unflatten(np.asarray(flat, np.float64), W, D)
+
+
+def test_features_match_reference(colden):
+    tin = _field(100)
+    w = colden.Weights(oracle.dirs_healpix(1))
+    tree, leaf, _, _ = _plain(colden, tin, w)
+    n = 256
+    rng = np.random.default_rng(1)
+    cells = np.concatenate([[0, n ** 3 - 1, 255, n * n * 255], rng.choice(n ** 3, 600, replace=False)])
+    s = colden.Surrogate(12, 64, colden.CD_SURR_FP32, 0, norm=(1.0, 2.0, 0.0, 1.0))
+    X = torch.empty((cells.size, 576), dtype=torch.float32, device=DEV)
+    s.features(tree, torch.from_numpy(cells).to(DEV), X)
+    torch.cuda.synchronize()
+    lv = S.pyramid(tin.leaf_n.reshape(n, n, n).astype(np.float64))
+    ref = S.features(lv, cells, 1.0, 2.0)
+    err = np.abs(X.cpu().numpy() - ref).max()
+    print(f"features: max abs diff {err:.2e}")
+    assert err <= 2e-5
+    # an index that is not a leaf gives NaN, not an access
+    bad = torch.tensor([-1, n ** 3], dtype=torch.int64, device=DEV)
+    Xb = torch.zeros((2, 576), dtype=torch.float32, device=DEV)
+    s.features(tree, bad, Xb)
+    assert torch.isnan(Xb).all()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-2)])
+def test_forward_and_gradients_match_reference(colden, prec, tol):
+    W, D, n = 64, 12, 300
+    s = colden.Surrogate(D, W, prec, 7)
+    p = _blocks(s.get_params(), W, D)
+    rng = np.random.default_rng(2)
+    X = rng.normal(0, 1, (n, 576))
+    T = rng.normal(0, 1, (n, D))
+    Xd = torch.from_numpy(X.astype(np.float32)).to(DEV)
+    Td = torch.from_numpy(T.astype(np.float32)).to(DEV)
+    Y = torch.empty((n, D), dtype=torch.float32, device=DEV)
+    s.forward(Xd, Y)
+    torch.cuda.synchronize()
+    Xr = X.astype(np.float32).astype(np.float64)
+    Yref, cache = S.forward(p, Xr)
+    if prec == 1:
+        yerr = np.abs(Y.cpu().numpy() - S.forward_bf16(p, Xr)).max() / np.abs(Yref).max()
+    else:
+        yerr = np.abs(Y.cpu().numpy() - Yref).max() / np.abs(Yref).max()
+    g, loss = s.gradients(Xd, Td)
+    Tr = T.astype(np.float32).astype(np.float64)
+    gexact = S.backward(p, cache, Yref, Tr)
+    gref = S.backward_bf16(p, Xr, Tr) if prec == 1 else gexact
+    lref = S.mse(Yref, Tr)
+    rel = lambda gs, rs: [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(gs, rs)]
+    gerr = rel(_blocks(g, W, D), gref)
+    print(f"prec {prec}: forward {yerr:.2e}, loss {loss:.6f} vs {lref:.6f}, gradient blocks {np.round(gerr, 6)}; "
+          f"vs the exact FP64 gradient {np.round(rel(_blocks(g, W, D), gexact), 4)}")
+    assert yerr <= tol
+    assert abs(loss - lref) <= (tol if prec == 0 else 2e-2) * lref
+    assert max(gerr) <= tol
+
+
+def test_adam_step_matches_reference(colden):
+    """One training step of the FP32 path: features, targets from the
+    method's columns, gradient and the Adam update against the reference."""
+    tin = _field(101)
+    w = colden.Weights(oracle.dirs_healpix(1))
+    tree, leaf, N, _ = _plain(colden, tin, w)
+    W, D, lr = 32, 12, 1e-3
+    norm = (1.2, 1.5, 46.0, 1.0)
+    s = colden.Surrogate(D, W, colden.CD_SURR_FP32, 3, norm=norm)
+    p0 = s.get_params().astype(np.float64)
+    cells = np.random.default_rng(3).choice(tin.n_leaf, 512, replace=False)
+    dcells = torch.from_numpy(cells).to(DEV)
+    Tg = torch.empty((cells.size, D), dtype=torch.float32, device=DEV)
+    s.targets(tree, w, N, dcells, Tg)
+    s.train_step(tree, w, N, dcells, lr)
+    p1 = s.get_params().astype(np.float64)
+    n = 256
+    lv = S.pyramid(tin.leaf_n.reshape(n, n, n).astype(np.float64))
+    X = S.features(lv, cells, norm[0], norm[1])
+    nil = oracle.Tree(tin).internal_local(oracle.dirs_healpix(1), cells)
+    T = S.targets(N.cpu().numpy()[cells].astype(np.float64), nil, norm[2], norm[3])
+    terr = np.abs(Tg.cpu().numpy() - T).max()
+    print(f"targets: max abs diff {terr:.2e}")
+    assert terr <= 2e-5
+    params = S.unflatten(p0, W, D)
+    Y, cache = S.forward(params, X)
+    g = S.flatten(S.backward(params, cache, Y, T))
+    pref, _, _ = S.adam_step(p0, g, np.zeros_like(g), np.zeros_like(g), 1, lr)
+    d = np.abs(p1 - pref)
+    # first Adam step is -lr sign(g) (up to eps): only gradients within
+    # rounding of zero may differ, by at most 2 lr
+    close = d <= 1e-6 * np.abs(p0) + 1e-3 * lr
+    print(f"Adam step: {np.mean(~close):.2e} of parameters differ, max diff {d.max():.2e}")
+    assert np.mean(~close) <= 1e-3 and d.max() <= 2.001 * lr
+
+
+@pytest.fixture(scope="module")
+def trained(colden):
+    """A bfloat16 network trained on two seeded 256^3 fields."""
+    from paper_1410_0624_amd import surrogate_train
+    w = colden.Weights(oracle.dirs_healpix(1))
+    runs = [_plain(colden, _field(sd), w) for sd in (110, 111)]
+    trees = [r[0] for r in runs]
+    Ns = [r[2] for r in runs]
+    nrm = surrogate_train.norms(trees, w, Ns)
+    s = colden.Surrogate(12, 256, colden.CD_SURR_BF16, 11, norm=nrm)
+    untrained = s.get_params()
+    log = surrogate_train.fit(s, trees, w, Ns, steps=2000, batch=4096, lr=2e-3, lr_final=1e-4, seed=5,
+                              log_every=250)
+    print("training log:", [(k, round(l, 4)) for k, l in log])
+    return s, w, nrm, untrained, log, runs
+
+
+def _chi_err(a, b):
+    return np.abs(a - b) / b
+
+
+def test_training_lowers_the_loss_and_beats_baselines(colden, trained):
+    """What the network gains: on an unseen field its chi error is far below
+    that of the same network untrained and of the best constant column."""
+    s, w, nrm, untrained, log, _ = trained
+    assert log[-1][1] < 0.2 * log[0][1]
+    tin = _field(120)
+    tree, leaf, N, chi = _plain(colden, tin, w)
+    Ns = torch.empty_like(N)
+    chis = torch.empty_like(chi)
+    s.infer(tree, w, Ns, chis)
+    torch.cuda.synchronize()
+    ref = chi.cpu().numpy()
+    e_tr = _chi_err(chis.cpu().numpy(), ref)
+    trained_params = s.get_params()
+    s.set_params(untrained)
+    s.infer(tree, w, Ns, chis)
+    torch.cuda.synchronize()
+    e_un = _chi_err(chis.cpu().numpy(), ref)
+    # best constant external column: every direction at exp(out_shift), plus
+    # the exact internal + local part (the same split as the network's)
+    s.set_params(np.concatenate([np.zeros(s.n_params() - 12, np.float32), np.zeros(12, np.float32)]))
+    s.infer(tree, w, Ns, chis)
+    torch.cuda.synchronize()
+    e_cst = _chi_err(chis.cpu().numpy(), ref)
+    s.set_params(trained_params)
+    q = lambda e: (float(np.mean(e)), float(np.percentile(e, 99)))
+    print(f"chi error mean/p99: trained {q(e_tr)}, untrained {q(e_un)}, constant {q(e_cst)}")
+    assert np.percentile(e_tr, 99) < 0.5 * np.percentile(e_un, 99)
+    assert np.percentile(e_tr, 99) < 0.5 * np.percentile(e_cst, 99)
+
+
+def test_check_and_fallback_meet_the_chi_gate(colden, trained):
+    s, w, nrm, _, _, _ = trained
+    tin = _field(121)
+    tree, leaf, N, chi = _plain(colden, tin, w)
+    Ns = torch.empty_like(N)
+    chis = torch.empty_like(chi)
+    s.infer(tree, w, Ns, chis)
+    nf, nt, emax = s.check_fallback(tree, w, Ns, chis, frac=0.01, tol_chi=0.03, seed=9)
+    torch.cuda.synchronize()
+    e = _chi_err(chis.cpu().numpy(), chi.cpu().numpy())
+    print(f"fallback {nf}/{nt} tiles, max sampled err {emax:.3e}; chi error mean {e.mean():.3e} "
+          f"p99 {np.percentile(e, 99):.3e} max {e.max():.3e}")
+    assert np.percentile(e, 99) <= 0.03
+    # against the oracle on a sample
+    tg = np.random.default_rng(4).choice(tin.n_leaf, 2000, replace=False)
+    ref = oracle.screening(oracle.Tree(tin).columns(oracle.dirs_healpix(1), tg))
+    eo = _chi_err(chis.cpu().numpy()[tg], ref)
+    print(f"vs oracle: p99 {np.percentile(eo, 99):.3e}")
+    assert np.percentile(eo, 99) <= 0.03
+
+
+def test_zero_tolerance_falls_back_everywhere(colden, trained):
+    """tol = 0: every tile is recomputed by the method, so N equals the
+    tiled sweep's to FP32 parity."""
+    s, w, _, _, _, runs = trained
+    tree, leaf, N, chi = runs[0]
+    Ns = torch.empty_like(N)
+    chis = torch.empty_like(chi)
+    s.infer(tree, w, Ns, chis)
+    nf, nt, _ = s.check_fallback(tree, w, Ns, chis, frac=0.01, tol_chi=0.0, seed=1)
+    torch.cuda.synchronize()
+    assert nf == nt
+    rel = (torch.abs(Ns - N) / N).max().item()
+    assert rel <= 1e-5
+
+
+def test_save_load_round_trip(colden, trained):
+    s = trained[0]
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "net.bin")
+        s.save(path)
+        s2 = colden.Surrogate.load(path)
+        assert np.array_equal(s2.get_params(), s.get_params())
+        X = torch.randn((100, 576), device=DEV)
+        Y1 = torch.empty((100, 12), device=DEV)
+        Y2 = torch.empty((100, 12), device=DEV)
+        s.forward(X, Y1)
+        s2.forward(X, Y2)
+        torch.cuda.synchronize()
+        assert torch.equal(Y1, Y2)
+
+
+def test_surrogate_errors(colden):
+    with pytest.raises(colden.ColdenError):
+        colden.Surrogate(12, 100)  # width not a multiple of 16
+    tin = synth.workload_uniform(5, seed=1)
+    leaf = torch.from_numpy(tin.leaf_n).to(DEV)
+    tree = colden.Tree(tin, leaf)
+    s = colden.Surrogate(12, 32)
+    w = colden.Weights(oracle.dirs_healpix(1))
+    N = torch.empty((tin.n_leaf, 12), device=DEV)
+    with pytest.raises(colden.ColdenError) as e:
+        s.infer(tree, w, N)
+    assert e.value.rc == colden.CD_EINVAL

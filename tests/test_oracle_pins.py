@@ -495,3 +495,27 @@ def test_raymarch_uniform_is_distance_to_edge():
         c = (T + 0.5) / n
         for r, u in enumerate(rays):
             assert abs(R[q, r] - 2.0 * exit_distance(np.zeros(3), np.ones(3), c, u)) < 1e-12
+
+
+def test_internal_local_of_uniform_density_is_the_exit_distance_from_the_oct():
+    """Sect. 3.2: the internal + local part of a target is the sum over its
+    oct's 8 cells of n x chord from the target centre; for uniform n0 that is
+    n0 times the distance from the target centre to the oct's boundary along
+    u (written out here per axis, no chord routine)."""
+    L, n0, box = 4, 3.0, 2.0
+    n = 1 << L
+    tin = synth.uniform_tree(np.full((n, n, n), n0), box_cm=box)
+    tr = oracle.Tree(tin)
+    dirs = oracle.dirs_healpix(2)
+    rng = np.random.default_rng(8)
+    tg = rng.choice(tin.n_leaf, 50, replace=False)
+    got = tr.internal_local(dirs, tg)
+    dx = 1.0 / n
+    for q, t in enumerate(tg):
+        T = np.array([t % n, (t // n) % n, t // (n * n)])
+        c = (T + 0.5) * dx
+        lo, hi = (T // 2) * 2 * dx, (T // 2) * 2 * dx + 2 * dx
+        for d, u in enumerate(dirs):
+            dist = min(((hi[k] - c[k]) / u[k]) if u[k] > 0 else ((lo[k] - c[k]) / u[k])
+                       for k in range(3) if u[k] != 0)
+            assert abs(got[q, d] - n0 * box * dist) <= 1e-12 * n0 * box
