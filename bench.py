@@ -370,7 +370,9 @@ def bench_surrogate(args):
     e_net = np.abs(chi_net - ref) / ref
     e_fin = np.abs(chis.cpu().numpy().astype(np.float64) - ref) / ref
     q = lambda e: {"mean": float(e.mean()), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
-    flops = 2.0 * tin.n_leaf * (576 * 256 + 256 * 256 + 256 * D)
+    # the network runs once per level-7 cell (its leaves share the features)
+    net_rows = 1 << 21
+    flops = 2.0 * net_rows * (576 * 256 + 256 * 256 + 256 * D)
     achieved = flops / (ms_infer * 1e-3) / 1e12
 
     cpu = None
@@ -417,8 +419,8 @@ def bench_surrogate(args):
                    "n_leaf": tin.n_leaf, "n_dirs": D},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": achieved / 2500.0, "traffic": None,
-                     "kernel": "inference (features + 3 GEMMs on k_gemm_bf16 + output)",
-                     "kernel_ms": ms_infer, "flops_per_launch": flops},
+                     "kernel": "inference (features + network on 2^21 level-7 rows + per-leaf output)",
+                     "kernel_ms": ms_infer, "flops_per_launch": flops, "network_rows": net_rows},
         "forms": {"plain_fp32": {"ms_per_step": ms_plain, "value": tin.n_leaf * D / (ms_plain * 1e-3)},
                   "surrogate_infer_only": {"ms": ms_infer, "chi_rel_err_vs_plain": q(e_net)},
                   "surrogate_with_fallback": {"ms": ms_surr, "speedup_vs_plain": ms_plain / ms_surr,

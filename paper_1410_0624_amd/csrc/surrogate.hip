@@ -74,8 +74,14 @@ struct FeatArgs {
     int L;
     const int64_t* cells;  // leaf indices, or nullptr: c0 + i
     int64_t c0, n;
+    int l7rows;            // rows are level-7 cells c0 + i (x fastest), read through their first leaf
     float shift, inv_scale;
 };
+
+// The features of a leaf depend only on its level-7 ancestor (the finest
+// stencil, level 8, is centred on it), so the network runs once per level-7
+// cell and its leaves share the row.
+constexpr int kRowLevel = 7;
 
 // One thread per (leaf, level): the 64 stencil values of that level.
 template <typename T>
@@ -85,8 +91,14 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
     const int64_t i = idx / kFeatLevels;
     const int l = (int)(idx % kFeatLevels);
     const int L = a.L;
-    const int64_t q = a.cells ? a.cells[i] : a.c0 + i;
     const int64_t nL = (int64_t)1 << L;
+    int64_t q;
+    if (a.l7rows) {
+        const int64_t r = a.c0 + i, sh7 = L - kRowLevel, m = (int64_t)1 << kRowLevel;
+        q = (((r >> (2 * kRowLevel)) << sh7) * nL + (((r >> kRowLevel) & (m - 1)) << sh7)) * nL + ((r & (m - 1)) << sh7);
+    } else {
+        q = a.cells ? a.cells[i] : a.c0 + i;
+    }
     T* out = X + i * kFeat + l * 64;
     if (q < 0 || q >= nL * nL * nL) {  // not a leaf: NaN features, no access
         for (int s = 0; s < 64; ++s) out[s] = from_f<T>(__builtin_nanf(""));
@@ -342,20 +354,117 @@ __global__ void k_to_bf16(const float* __restrict__ P, int64_t n, uint16_t* __re
 }
 
 // N = internal + local + max(exp(y out_scale + out_shift) - floor, 0) and
-// chi (Eq. 5) for the rows c0 .. c0 + n - 1
-__global__ void k_output(const IlArgs il, const float* __restrict__ Y, int64_t c0, int64_t n, float out_shift,
+// chi (Eq. 5) for every leaf, y the row of its level-7 ancestor
+__global__ void k_output(const IlArgs il, const float* __restrict__ Y7, int64_t n_leaf, float out_shift,
                          float out_scale, float chi_scale, float* __restrict__ N, float* __restrict__ chi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int D = il.D;
-    const OctCells oc = oct_cells(il, c0 + i);
+    if (i >= n_leaf) return;
+    const int D = il.D, L = il.L, sh = L - kRowLevel;
+    const int64_t n = (int64_t)1 << L;
+    const int64_t x = i & (n - 1), y = (i >> L) & (n - 1), z = i >> (2 * L);
+    const int64_t r = (((z >> sh) << kRowLevel) + (y >> sh)) * ((int64_t)1 << kRowLevel) + (x >> sh);
+    const float* yr = Y7 + r * D;
+    const OctCells oc = oct_cells(il, i);
     float c = 0.f;
     for (int d = 0; d < D; ++d) {
-        const float v = internal_local(il, oc, d) + fmaxf(expf(fmaf(Y[i * D + d], out_scale, out_shift)) - kExtFloor, 0.f);
-        N[(c0 + i) * D + d] = v;
+        const float v = internal_local(il, oc, d) + fmaxf(expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
+        N[i * D + d] = v;
         c += expf(-chi_scale * v);
     }
-    if (chi) chi[c0 + i] = c / (float)D;
+    if (chi) chi[i] = c / (float)D;
+}
+
+// ------------------------------------------------------- inference GEMM --
+// C = act(A Bt^T + bias) for bfloat16 A [M][K] and Bt [Npad][K] (k
+// contiguous), M % 128 == 0, Npad % 128 == 0, K % 32 == 0: a workgroup per
+// 128 x 128 tile, 4 waves of 64 x 64 (4 x 4 blocks of 16 x 16 x 32), k tiles
+// of 32 double-buffered in LDS and loaded as 16-byte vectors.  Output columns
+// below n_valid: bfloat16 C16 (row pitch ldc) and / or FP32 C32 (pitch ldc).
+constexpr int kFT = 128, kFK = 32, kFP = 40;
+
+__global__ __launch_bounds__(256) void k_gemm_bf16_nt(const uint16_t* __restrict__ A, const uint16_t* __restrict__ Bt,
+                                                      const float* __restrict__ bias, int relu, uint16_t* __restrict__ C16,
+                                                      float* __restrict__ C32, int64_t ldc, int n_valid, int K) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[2][kFT][kFP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kFT][kFP];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * kFT;
+    const int n0 = blockIdx.y * kFT;
+    const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
+    const int r = lane & 15, g = lane >> 4;
+    // this thread's two 16-byte pieces of each operand tile
+    const int row0 = tid >> 2, row1 = row0 + 64, c8 = (tid & 3) * 8;
+    const uint16_t* pa0 = A + (m0 + row0) * K + c8;
+    const uint16_t* pa1 = A + (m0 + row1) * K + c8;
+    const uint16_t* pb0 = Bt + (int64_t)(n0 + row0) * K + c8;
+    const uint16_t* pb1 = Bt + (int64_t)(n0 + row1) * K + c8;
+    uint4 ra0, ra1, rb0, rb1;
+#define CD_GLOAD(k0)                                               \
+    do {                                                           \
+        ra0 = *reinterpret_cast<const uint4*>(pa0 + (k0));         \
+        ra1 = *reinterpret_cast<const uint4*>(pa1 + (k0));         \
+        rb0 = *reinterpret_cast<const uint4*>(pb0 + (k0));         \
+        rb1 = *reinterpret_cast<const uint4*>(pb1 + (k0));         \
+    } while (0)
+#define CD_SSTORE(buf)                                             \
+    do {                                                           \
+        *reinterpret_cast<uint4*>(&As[buf][row0][c8]) = ra0;       \
+        *reinterpret_cast<uint4*>(&As[buf][row1][c8]) = ra1;       \
+        *reinterpret_cast<uint4*>(&Bs[buf][row0][c8]) = rb0;       \
+        *reinterpret_cast<uint4*>(&Bs[buf][row1][c8]) = rb1;       \
+    } while (0)
+    f32x4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    CD_GLOAD(0);
+    CD_SSTORE(0);
+    __syncthreads();
+    const int nk = K / kFK;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int buf = kt & 1;
+        if (kt + 1 < nk) CD_GLOAD((kt + 1) * kFK);
+        bf16x8 af[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            af[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm + 16 * i + r][8 * g]);
+            bv[i] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn + 16 * i + r][8 * g]);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bv[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) CD_SSTORE(buf ^ 1);  // the other buffer: last read before the previous barrier
+        __syncthreads();
+    }
+#undef CD_GLOAD
+#undef CD_SSTORE
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int col = n0 + wn + 16 * j + r;
+        if (col >= n_valid) continue;
+        const float b = bias ? bias[col] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = m0 + wm + 16 * i + 4 * g + e;
+                float v = acc[i][j][e] + b;
+                if (relu) v = fmaxf(v, 0.f);
+                if (C16) C16[row * ldc + col] = f2bf(v);
+                if (C32) C32[row * ldc + col] = v;
+            }
+    }
+}
+
+// dst [npad][K] = src [K][N]^T, rows n >= N zero (bfloat16 weights)
+__global__ void k_transpose_pad(const uint16_t* __restrict__ src, int K, int N, int npad, uint16_t* __restrict__ dst) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)npad * K) return;
+    const int n = (int)(idx / K), k = (int)(idx % K);
+    dst[idx] = n < N ? src[(int64_t)k * N + n] : (uint16_t)0;
 }
 
 // relative chi error of each sampled leaf
@@ -396,6 +505,8 @@ struct cd_surrogate {
     float* part = nullptr;
     float* loss = nullptr;
     int64_t* cells = nullptr;  // [cap] scratch index list
+    float* Y7 = nullptr;       // [2^21][D] network rows of the level-7 cells (inference)
+    uint16_t* Wt = nullptr;    // transposed bfloat16 weights for the inference GEMM
 };
 
 namespace cd {
@@ -468,7 +579,7 @@ static void launch_features(const FeatArgs& a, T* X, hipStream_t st) {
 // Forward pass of n rows already in s->X; Y in FP32.  keep: FP32 activations
 // for the backward pass.
 template <typename T>
-static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st) {
+static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st, float* Yout = nullptr) {
     const int W = s->W, D = s->D;
     const T* Wt = s->prec == CD_SURR_BF16 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
     GemmArgs<T> g{};
@@ -490,9 +601,25 @@ static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st) 
     g.A = (const T*)s->A2l;
     g.B = Wt + s->off[4]; g.sbk = D;
     g.N = D;
-    g.C = s->Y; g.Cl = nullptr; g.ldc = D;
+    g.C = Yout ? Yout : s->Y; g.Cl = nullptr; g.ldc = D;
     g.bias = s->P + s->off[5]; g.relu = 0;
     gemm<T>(g, st);
+}
+
+// bfloat16 inference of n rows (n % 128 == 0, width % 128 == 0) on the tiled
+// GEMM, weights transposed into s->Wt first; rows into Yout [n][D].
+static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float* Yout) {
+    const int W = s->W, D = s->D, npad3 = 128;
+    const uint16_t* X = (const uint16_t*)s->X;
+    uint16_t* W1t = s->Wt;
+    uint16_t* W2t = W1t + (int64_t)W * kFeat;
+    uint16_t* W3t = W2t + (int64_t)W * W;
+    dim3 g1((unsigned)(n / kFT), (unsigned)(W / kFT));
+    k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat);
+    k_gemm_bf16_nt<<<g1, 256, 0, st>>>((const uint16_t*)s->A1l, W2t, s->P + s->off[3], 1, (uint16_t*)s->A2l, nullptr,
+                                       W, W, W);
+    dim3 g3((unsigned)(n / kFT), 1);
+    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W);
 }
 
 // Loss, gradient into s->G (targets in s->Tg, activations kept).
@@ -614,7 +741,7 @@ extern "C" void cd_surrogate_destroy(cd_surrogate* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     free_scratch(s);
-    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb})
+    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -760,20 +887,38 @@ extern "C" int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* t, const 
 template <typename T>
 static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
                       hipStream_t st) {
-    const int64_t total = t->n_leaf;
-    const int64_t batch = std::min<int64_t>(total, (int64_t)1 << 20);
+    const int64_t rows = (int64_t)1 << (3 * kRowLevel);  // level-7 cells
+    const int64_t batch = (int64_t)1 << 20;
     int rc = ensure_cap(s, batch);
     if (rc != CD_OK) return rc;
-    FeatArgs a = feat_args(s, t);
-    for (int64_t c0 = 0; c0 < total; c0 += batch) {
-        const int64_t nb = std::min(batch, total - c0);
-        a.cells = nullptr;
-        a.c0 = c0;
-        a.n = nb;
-        launch_features<T>(a, (T*)s->X, st);
-        forward_rows<T>(s, nb, false, st);
-        k_output<<<nblk(nb), 256, 0, st>>>(il_args(t, w), s->Y, c0, nb, s->norm[2], s->norm[3], chi_scale, N, chi);
+    if (!s->Y7 && hipMalloc((void**)&s->Y7, (size_t)rows * s->D * 4) != hipSuccess) {
+        set_error("hipMalloc of the network rows failed");
+        return CD_ENOMEM;
     }
+    const bool fast = sizeof(T) == 2 && s->W % kFT == 0;
+    if (fast) {
+        const int W = s->W;
+        const int64_t wt = (int64_t)W * kFeat + (int64_t)W * W + (int64_t)128 * W;
+        if (!s->Wt && hipMalloc((void**)&s->Wt, (size_t)wt * 2) != hipSuccess) {
+            set_error("hipMalloc of the transposed weights failed");
+            return CD_ENOMEM;
+        }
+        k_transpose_pad<<<nblk((int64_t)W * kFeat), 256, 0, st>>>(s->Pb + s->off[0], kFeat, W, W, s->Wt);
+        k_transpose_pad<<<nblk((int64_t)W * W), 256, 0, st>>>(s->Pb + s->off[2], W, W, W, s->Wt + (int64_t)W * kFeat);
+        k_transpose_pad<<<nblk((int64_t)128 * W), 256, 0, st>>>(s->Pb + s->off[4], W, s->D, 128,
+                                                               s->Wt + (int64_t)W * kFeat + (int64_t)W * W);
+    }
+    FeatArgs a = feat_args(s, t);
+    a.l7rows = 1;
+    for (int64_t c0 = 0; c0 < rows; c0 += batch) {
+        a.c0 = c0;
+        a.n = batch;
+        launch_features<T>(a, (T*)s->X, st);
+        if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->D);
+        else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->D);
+    }
+    k_output<<<nblk(t->n_leaf), 256, 0, st>>>(il_args(t, w), s->Y7, t->n_leaf, s->norm[2], s->norm[3], chi_scale, N,
+                                              chi);
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
