@@ -196,7 +196,7 @@ def main():
         key = (lv.astype(np.int64) << 60) | ((ijk[:, 2] >> 1) << 40) | ((ijk[:, 1] >> 1) << 20) | (ijk[:, 0] >> 1)
         n_tg = int(np.unique(key).shape[0])
         rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D, args.precision != "fp32")
-        kname = "k_amr_octs (per target oct: shells, internal+local, N and chi rows)"
+        kname = "k_target_octs (per target oct, a lane per direction: shells, internal+local, N and chi rows)"
     else:
         rows_bytes = alg_bytes_rows(tin.n_leaf, D)
         kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"

@@ -117,7 +117,8 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     hipStream_t s = (hipStream_t)stream;
     int rc = CD_OK;
     // host staging buffers live until the stream is synchronised below
-    std::vector<std::vector<float>> wf(cd::kKinds);
+    std::vector<std::vector<float>> wf(cd::kKinds), wtf(cd::kKinds);
+    std::vector<std::vector<int32_t>> otf(cd::kKinds);
     for (int k = 1; k < cd::kKinds && rc == CD_OK; ++k) {
         w->ncombo[k] = w->host.ncombo[k];
         w->len[k] = w->host.len[k];
@@ -125,6 +126,18 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
         rc = upload(w->host.off[k], &w->off[k], s);
         if (rc == CD_OK) rc = upload(wf[k], &w->w[k], s);
         if (rc == CD_OK) rc = upload(w->host.cnt[k], &w->cnt[k], s);
+        // the same lists with the direction fastest, for kernels with a lane per direction
+        const size_t nc = (size_t)w->ncombo[k], len = (size_t)w->len[k];
+        otf[k].assign(nc * len * D, 0);
+        wtf[k].assign(nc * len * D, 0.f);
+        for (size_t c = 0; c < nc; ++c)
+            for (size_t d = 0; d < (size_t)D; ++d)
+                for (size_t e = 0; e < len; ++e) {
+                    otf[k][(c * len + e) * D + d] = w->host.off[k][(c * D + d) * len + e];
+                    wtf[k][(c * len + e) * D + d] = (float)w->host.w[k][(c * D + d) * len + e];
+                }
+        if (rc == CD_OK) rc = upload(otf[k], &w->offT[k], s);
+        if (rc == CD_OK) rc = upload(wtf[k], &w->wT[k], s);
     }
     std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
     std::vector<float> gf(w->host.gloc.begin(), w->host.gloc.end());
@@ -172,6 +185,8 @@ extern "C" void cd_weights_destroy(cd_weights* w) {
         if (w->off[k]) (void)hipFree(w->off[k]);
         if (w->w[k]) (void)hipFree(w->w[k]);
         if (w->cnt[k]) (void)hipFree(w->cnt[k]);
+        if (w->offT[k]) (void)hipFree(w->offT[k]);
+        if (w->wT[k]) (void)hipFree(w->wT[k]);
     }
     if (w->kloc) (void)hipFree(w->kloc);
     if (w->blob) (void)hipFree(w->blob);

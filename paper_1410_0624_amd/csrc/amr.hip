@@ -82,23 +82,49 @@ __global__ void k_oct_mean(int64_t first, int64_t n, const int64_t* __restrict__
 __device__ __forceinline__ int sx8(int v) { return (int)(int8_t)(v & 0xff); }
 
 // Sum over one shell's weight list of (configuration, direction).
+// Lists with the direction fastest: entry e of (configuration, d) at
+// base + e D, base = configuration * len * D + d.  Padding entries carry
+// weight 0 and offset (0, 0, 0), so every entry is evaluated (no data-
+// dependent branch) and four lookups are in flight at a time.
 __device__ __forceinline__ float list_sum(const AmrLookupView& lk, const int32_t* off, const float* w, int len,
-                                          int64_t row, int l, const int64_t (&C)[3]) {
-    float s = 0.f;
-    for (int e = 0; e < len; ++e) {
-        const float wt = w[row + e];
-        if (wt == 0.f) continue;  // padding
-        const int pk = off[row + e];
-        s = fmaf(wt, lk.density(l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16)), s);
+                                          int64_t base, int D, int l, const int64_t (&C)[3]) {
+    float s0 = 0.f, s1 = 0.f;
+    int e = 0;
+    for (; e + 4 <= len; e += 4) {
+        float wt[4], v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = base + (int64_t)(e + j) * D;
+            wt[j] = w[k];
+            const int pk = off[k];
+            v[j] = lk.density(l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16));
+        }
+        s0 = fmaf(wt[0], v[0], s0);
+        s1 = fmaf(wt[1], v[1], s1);
+        s0 = fmaf(wt[2], v[2], s0);
+        s1 = fmaf(wt[3], v[3], s1);
     }
-    return s;
+    for (; e < len; ++e) {
+        const int64_t k = base + (int64_t)e * D;
+        const int pk = off[k];
+        s0 = fmaf(w[k], lk.density(l, C[0] + sx8(pk), C[1] + sx8(pk >> 8), C[2] + sx8(pk >> 16)), s0);
+    }
+    return s0 + s1;
 }
 
-template <int DC>
-__global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.n_tg) return;
-    const int l0 = a.tg_info[4 * g];  // level of the targets; the oct's cell is at l0 - 1
+// One group of DP lanes per target oct, a lane per direction (passes of DP
+// directions when D > DP), 64 / DP octs per wave: the list walks and the
+// density lookups of the directions run in parallel.  chi is summed over the
+// group with lane shuffles.
+template <int DP>
+__global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
+    constexpr int P = 64 / DP;
+    const int lane = threadIdx.x & 63;
+    const int sub = lane / DP, dl = lane % DP;
+    const int64_t g0 = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * P + sub;
+    const bool valid = g0 < a.n_tg;
+    const int64_t g = valid ? g0 : a.n_tg - 1;  // idle groups follow a real oct and write nothing
+    const int l0 = a.tg_info[4 * g];             // level of the targets; the oct's cell is at l0 - 1
     const int64_t A[3] = {a.tg_info[4 * g + 1], a.tg_info[4 * g + 2], a.tg_info[4 * g + 3]};
     float ln[8];
 #pragma unroll
@@ -107,36 +133,28 @@ __global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
         ln[c] = s >= 0 ? a.octden[s] : a.base[-(s + 1)];
     }
     const float dxL = (float)(a.box * ldexp(1.0, -l0));
-    // configuration codes of the shells dl = 1, 2, 3 (bits of A, A >> 1, A >> 2)
-    int combo[4] = {0, 0, 0, 0};
     int st0[3];
-    for (int k = 2; k >= 0; --k) {
-        combo[1] = combo[1] * 2 + (int)(A[k] & 1);
-        combo[2] = combo[2] * 4 + (int)(A[k] & 3);
-        combo[3] = combo[3] * 8 + (int)(A[k] & 7);
-        st0[k] = a.dl4[(A[k] >> 1) & 3];  // inner-limit state at dl = 4
-    }
+    for (int k = 0; k < 3; ++k) st0[k] = a.dl4[(A[k] >> 1) & 3];  // inner-limit state at dl = 4
     float chis[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) chis[c] = 0.f;
-    for (int d0 = 0; d0 < a.D; d0 += DC) {
-        float acc[DC];
-#pragma unroll
-        for (int j = 0; j < DC; ++j) acc[j] = (a.E && d0 + j < a.D) ? a.E[g * a.D + d0 + j] : 0.f;
-        // dl = 1, 2, 3
-#pragma unroll
-        for (int kind = 1; kind <= 3 && !a.E; ++kind) {
-            const int l = l0 - kind;
-            if (l < 0) break;
-            const float dx = (float)(a.box * ldexp(1.0, -l));
-            const int64_t C[3] = {A[0] >> (kind - 1), A[1] >> (kind - 1), A[2] >> (kind - 1)};
-#pragma unroll
-            for (int j = 0; j < DC; ++j) {
-                const int d = d0 + j;
-                if (d < a.D) {
-                    const int64_t row = ((int64_t)combo[kind] * a.D + d) * a.len[kind];
-                    acc[j] = fmaf(dx, list_sum(a.lk, a.off[kind], a.w[kind], a.len[kind], row, l, C), acc[j]);
-                }
+    for (int d0 = 0; d0 < a.D; d0 += DP) {
+        const int d = d0 + dl;
+        const bool live = d < a.D;
+        const int dd = live ? d : a.D - 1;  // idle lanes follow a real direction
+        float acc = a.E ? a.E[g * a.D + dd] : 0.f;
+        if (!a.E) {
+#pragma unroll 1
+            for (int kind = 1; kind <= 3; ++kind) {
+                const int l = l0 - kind;
+                if (l < 0) break;
+                const float dx = (float)(a.box * ldexp(1.0, -l));
+                const int64_t C[3] = {A[0] >> (kind - 1), A[1] >> (kind - 1), A[2] >> (kind - 1)};
+                // configuration: the low `kind` bits of A per axis
+                const int msk = (1 << kind) - 1;
+                const int cfg = (int)(A[0] & msk) | ((int)(A[1] & msk) << kind) | ((int)(A[2] & msk) << (2 * kind));
+                const int64_t base = (int64_t)cfg * a.len[kind] * a.D + dd;
+                acc = fmaf(dx, list_sum(a.lk, a.off[kind], a.w[kind], a.len[kind], base, a.D, l, C), acc);
             }
         }
         // dl >= 4 above the coarse tables: walk the inner-limit automaton
@@ -148,14 +166,8 @@ __global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
             int cb = 0;
             for (int k = 2; k >= 0; --k) cb = cb * 12 + 6 * (int)(C[k] & 1) + st[k];
             const float dx = (float)(a.box * ldexp(1.0, -l));
-#pragma unroll
-            for (int j = 0; j < DC; ++j) {
-                const int d = d0 + j;
-                if (d < a.D) {
-                    const int64_t row = ((int64_t)cb * a.D + d) * a.len[4];
-                    acc[j] = fmaf(dx, list_sum(a.lk, a.off[4], a.w[4], a.len[4], row, l, C), acc[j]);
-                }
-            }
+            const int64_t base = (int64_t)cb * a.len[4] * a.D + dd;
+            acc = fmaf(dx, list_sum(a.lk, a.off[4], a.w[4], a.len[4], base, a.D, l, C), acc);
             for (int k = 0; k < 3; ++k) st[k] = a.next[st[k]][C[k] & 1];
         }
         if (l >= 2) {
@@ -167,36 +179,29 @@ __global__ __launch_bounds__(256) void k_amr_octs(const AmrSweepArgs a) {
             const int64_t code = (a.qcompact && l == a.qtop)
                                      ? cell * 64 + ((A[0] >> 1) & 3) + 4 * ((A[1] >> 1) & 3) + 16 * ((A[2] >> 1) & 3)
                                      : cell * 216 + st[0] + 6 * st[1] + 36 * st[2];
-            const float* qr = a.q[l] + code * a.D;
-#pragma unroll
-            for (int j = 0; j < DC; ++j)
-                if (d0 + j < a.D) acc[j] += qr[d0 + j];
+            acc += a.q[l][code * a.D + dd];
         }
         // internal + local of the oct's leaf children
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int64_t leaf = a.tg_leaf[8 * g + c];
             if (leaf < 0) continue;
-            float* out = a.N + leaf * a.D;
+            float s = 0.f;
 #pragma unroll
-            for (int j = 0; j < DC; ++j) {
-                const int d = d0 + j;
-                if (d < a.D) {
-                    float s = 0.f;
-#pragma unroll
-                    for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(c * 8 + sb) * a.D + d], s);
-                    const float v = fmaf(dxL, s, acc[j]);
-                    out[d] = v;
-                    chis[c] += expf(-a.chi_scale * v);
-                }
-            }
+            for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(c * 8 + sb) * a.D + dd], s);
+            const float v = fmaf(dxL, s, acc);
+            if (live && valid) a.N[leaf * a.D + d] = v;
+            if (live) chis[c] += expf(-a.chi_scale * v);
         }
     }
     if (a.chi) {
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
+            float v = chis[c];
+#pragma unroll
+            for (int m = DP / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
             const int64_t leaf = a.tg_leaf[8 * g + c];
-            if (leaf >= 0) a.chi[leaf] = chis[c] / (float)a.D;
+            if (valid && dl == 0 && leaf >= 0) a.chi[leaf] = v / (float)a.D;
         }
     }
 }
@@ -491,8 +496,8 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     a.octden = A->octden;
     a.base = t->lev[B];
     for (int k = 1; k <= 4; ++k) {
-        a.off[k] = w->off[k];
-        a.w[k] = w->w[k];
+        a.off[k] = w->offT[k];
+        a.w[k] = w->wT[k];
         a.len[k] = w->len[k];
     }
     a.kloc = w->kloc;
@@ -517,11 +522,18 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     return CD_OK;
 }
 
+template <int DP>
+static void launch_octs(const AmrSweepArgs& a, hipStream_t s) {
+    const int64_t per_block = 4 * (64 / DP);
+    k_target_octs<DP><<<(unsigned)((a.n_tg + per_block - 1) / per_block), 256, 0, s>>>(a);
+}
+
 void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
     if (a.n_tg <= 0) return;
-    const unsigned blocks = (unsigned)((a.n_tg + 255) / 256);
-    if (a.D <= 12) k_amr_octs<12><<<blocks, 256, 0, s>>>(a);
-    else k_amr_octs<16><<<blocks, 256, 0, s>>>(a);
+    if (a.D <= 8) launch_octs<8>(a, s);
+    else if (a.D <= 16) launch_octs<16>(a, s);
+    else if (a.D <= 32) launch_octs<32>(a, s);
+    else launch_octs<64>(a, s);
 }
 
 void amr_free(cd_tree* t) {

@@ -126,6 +126,8 @@ struct cd_weights {
     int32_t* off[cd::kKinds] = {nullptr};   // device
     float* w[cd::kKinds] = {nullptr};       // device, FP32 weights
     int32_t* cnt[cd::kKinds] = {nullptr};   // device
+    int32_t* offT[cd::kKinds] = {nullptr};  // device, [ncombo][len][D]: the lists with the direction fastest
+    float* wT[cd::kKinds] = {nullptr};      // device, same layout
     float* kloc = nullptr;                  // device [8][8][D]
     int32_t* blob = nullptr;                // device tiled-sweep tables
     float* gloc = nullptr;                  // device [D][8]

@@ -83,13 +83,15 @@ struct FeatArgs {
 // cell and its leaves share the row.
 constexpr int kRowLevel = 7;
 
-// One thread per (leaf, level): the 64 stencil values of that level.
+// One thread per feature value (row, level, stencil cell): a wave writes the
+// 64 values of one (row, level) contiguously and reads one 4^3 stencil.
 template <typename T>
 __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restrict__ X) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= a.n * kFeatLevels) return;
-    const int64_t i = idx / kFeatLevels;
-    const int l = (int)(idx % kFeatLevels);
+    if (idx >= a.n * kFeat) return;
+    const int64_t i = idx / kFeat;
+    const int f = (int)(idx % kFeat);
+    const int l = f >> 6, s = f & 63;
     const int L = a.L;
     const int64_t nL = (int64_t)1 << L;
     int64_t q;
@@ -99,27 +101,24 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
     } else {
         q = a.cells ? a.cells[i] : a.c0 + i;
     }
-    T* out = X + i * kFeat + l * 64;
     if (q < 0 || q >= nL * nL * nL) {  // not a leaf: NaN features, no access
-        for (int s = 0; s < 64; ++s) out[s] = from_f<T>(__builtin_nanf(""));
+        X[idx] = from_f<T>(__builtin_nanf(""));
         return;
     }
     const int64_t x = q & (nL - 1), y = (q >> L) & (nL - 1), z = q >> (2 * L);
     const int sh = L - l + 1;  // ancestor at level l - 1
-    const int64_t Ax = x >> sh, Ay = y >> sh, Az = z >> sh;
+    const int64_t px = 2 * (x >> sh) - 1 + (s & 3), py = 2 * (y >> sh) - 1 + ((s >> 2) & 3),
+                  pz = 2 * (z >> sh) - 1 + (s >> 4);
     const int64_t nl = (int64_t)1 << l;
     const float* lev = a.lev[l];
-    for (int s = 0; s < 64; ++s) {
-        const int64_t px = 2 * Ax - 1 + (s & 3), py = 2 * Ay - 1 + ((s >> 2) & 3), pz = 2 * Az - 1 + (s >> 4);
-        float v = 0.f;
-        if (l < L) {  // padded level: the zero halo covers -1 and 2^l
-            const int64_t S = nl + 2 * kHalo;
-            v = lev[((pz + kHalo) * S + (py + kHalo)) * S + (px + kHalo)];
-        } else if (px >= 0 && py >= 0 && pz >= 0 && px < nl && py < nl && pz < nl) {
-            v = lev[(pz * nl + py) * nl + px];
-        }
-        out[s] = from_f<T>((logf(fmaxf(v, kFloor)) - a.shift) * a.inv_scale);
+    float v = 0.f;
+    if (l < L) {  // padded level: the zero halo covers -1 and 2^l
+        const int64_t S = nl + 2 * kHalo;
+        v = lev[((pz + kHalo) * S + (py + kHalo)) * S + (px + kHalo)];
+    } else if (px >= 0 && py >= 0 && pz >= 0 && px < nl && py < nl && pz < nl) {
+        v = lev[(pz * nl + py) * nl + px];
     }
+    X[idx] = from_f<T>((logf(fmaxf(v, kFloor)) - a.shift) * a.inv_scale);
 }
 
 template <typename T>
@@ -326,11 +325,31 @@ __global__ __launch_bounds__(256) void k_sum(const float* __restrict__ part, int
 }
 
 // column sums of a [rows][cols] FP32 matrix (bias gradients)
-__global__ void k_colsum(const float* __restrict__ a, int64_t rows, int cols, float* __restrict__ out) {
+// column sums of a [rows][cols] FP32 matrix (bias gradients) in two
+// deterministic passes: blockIdx.y takes a chunk of rows, 4 row phases x 64
+// columns per workgroup, partial sums part[chunk][cols]; then one thread per
+// column adds the chunks.
+constexpr int kColChunks = 32;
+__global__ __launch_bounds__(256) void k_colsum_part(const float* __restrict__ a, int64_t rows, int cols,
+                                                     float* __restrict__ part) {
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int c = blockIdx.x * 64 + tx;
+    const int64_t per = (rows + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = (int64_t)blockIdx.y * per, r1 = std::min<int64_t>(rows, r0 + per);
+    float s = 0.f;
+    if (c < cols)
+        for (int64_t r = r0 + ty; r < r1; r += 4) s += a[r * cols + c];
+    red[ty][tx] = s;
+    __syncthreads();
+    if (ty == 0 && c < cols) part[(int64_t)blockIdx.y * cols + c] = (red[0][tx] + red[1][tx]) + (red[2][tx] + red[3][tx]);
+}
+
+__global__ void k_colsum_final(const float* __restrict__ part, int chunks, int cols, float* __restrict__ out) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cols) return;
     float s = 0.f;
-    for (int64_t r = 0; r < rows; ++r) s += a[r * cols + c];
+    for (int k = 0; k < chunks; ++k) s += part[(int64_t)k * cols + c];
     out[c] = s;
 }
 
@@ -372,6 +391,43 @@ __global__ void k_output(const IlArgs il, const float* __restrict__ Y7, int64_t 
         c += expf(-chi_scale * v);
     }
     if (chi) chi[i] = c / (float)D;
+}
+
+// The same for 256 consecutive leaves per workgroup (row-major, so their rows
+// of N are contiguous): kloc in LDS, rows staged in LDS and written as
+// 16-byte stores.  D <= kOutMaxD; n_leaf a multiple of 256.
+constexpr int kOutMaxD = 48;
+__global__ __launch_bounds__(256) void k_output_tiled(const IlArgs il, const float* __restrict__ Y7, float out_shift,
+                                                      float out_scale, float chi_scale, float* __restrict__ N,
+                                                      float* __restrict__ chi) {
+    extern __shared__ float sm[];  // kloc [64 D], then rows [256 D]
+    const int D = il.D, L = il.L, sh = L - kRowLevel;
+    float* kl = sm;
+    float* st = sm + 64 * D;
+    for (int i = threadIdx.x; i < 64 * D; i += 256) kl[i] = il.kloc[i];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * 256;
+    const int64_t i = base + threadIdx.x;
+    const int64_t n = (int64_t)1 << L;
+    const int64_t x = i & (n - 1), y = (i >> L) & (n - 1), z = i >> (2 * L);
+    const int64_t r = (((z >> sh) << kRowLevel) + (y >> sh)) * ((int64_t)1 << kRowLevel) + (x >> sh);
+    const float* yr = Y7 + r * D;
+    const OctCells oc = oct_cells(il, i);
+    const float* ko = kl + oc.o * 8 * D;
+    float c = 0.f;
+    for (int d = 0; d < D; ++d) {
+        float acc = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2) acc = fmaf(oc.n[s2], ko[s2 * D + d], acc);
+        const float v = il.dxL * acc + fmaxf(expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
+        st[threadIdx.x * D + d] = v;
+        c += expf(-chi_scale * v);
+    }
+    if (chi) chi[i] = c / (float)D;
+    __syncthreads();
+    float4* dst = reinterpret_cast<float4*>(N + base * D);
+    const float4* src = reinterpret_cast<const float4*>(st);
+    for (int k = threadIdx.x; k < 64 * D; k += 256) dst[k] = src[k];  // 256 D floats = 64 D float4
 }
 
 // ------------------------------------------------------- inference GEMM --
@@ -476,6 +532,12 @@ __global__ void k_sample_err(const float* __restrict__ chi_net, const int64_t* _
 
 static unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 
+static void colsum(const float* a, int64_t rows, int cols, float* part, float* out, hipStream_t st) {
+    dim3 grid((unsigned)((cols + 63) / 64), kColChunks);
+    k_colsum_part<<<grid, 256, 0, st>>>(a, rows, cols, part);
+    k_colsum_final<<<nblk(cols), 256, 0, st>>>(part, kColChunks, cols, out);
+}
+
 }  // namespace cd
 
 // ------------------------------------------------------------------ handle --
@@ -505,6 +567,7 @@ struct cd_surrogate {
     float* part = nullptr;
     float* loss = nullptr;
     int64_t* cells = nullptr;  // [cap] scratch index list
+    float* colpart = nullptr;  // [kColChunks][max(W, D)] column-sum partials
     float* Y7 = nullptr;       // [2^21][D] network rows of the level-7 cells (inference)
     uint16_t* Wt = nullptr;    // transposed bfloat16 weights for the inference GEMM
 };
@@ -515,12 +578,13 @@ static size_t esize(const cd_surrogate* s) { return s->prec == CD_SURR_BF16 ? 2 
 
 static void free_scratch(cd_surrogate* s) {
     void* bufs[] = {s->X, s->A1, s->A2, s->A1l, s->A2l, s->Y, s->Tg, s->dY, s->dYl, s->dZ2, s->dZ2l, s->dZ1,
-                    s->dZ1l, s->part, s->loss, s->cells};
+                    s->dZ1l, s->part, s->loss, s->cells, s->colpart};
     for (void* b : bufs)
         if (b) (void)hipFree(b);
     s->X = s->A1l = s->A2l = s->dYl = s->dZ2l = s->dZ1l = nullptr;
     s->A1 = s->A2 = s->Y = s->Tg = s->dY = s->dZ2 = s->dZ1 = s->part = s->loss = nullptr;
     s->cells = nullptr;
+    s->colpart = nullptr;
     s->cap = 0;
 }
 
@@ -538,6 +602,7 @@ static int ensure_cap(cd_surrogate* s, int64_t n) {
         {(void**)&s->dZ2, nr * W * 4},  {&s->dZ2l, nr * W * es},      {(void**)&s->dZ1, nr * W * 4},
         {&s->dZ1l, nr * W * es},        {(void**)&s->part, (nr * std::max<size_t>(W, D) / 256 + 2) * 4},
         {(void**)&s->loss, 16},        {(void**)&s->cells, nr * 8},
+        {(void**)&s->colpart, (size_t)kColChunks * std::max<size_t>(W, D) * 4},
     };
     for (auto& r : req) {
         if (hipMalloc(r.p, r.bytes) != hipSuccess) {
@@ -573,7 +638,7 @@ static FeatArgs feat_args(const cd_surrogate* s, const cd_tree* t) {
 
 template <typename T>
 static void launch_features(const FeatArgs& a, T* X, hipStream_t st) {
-    k_features<T><<<nblk(a.n * kFeatLevels), 256, 0, st>>>(a, X);
+    k_features<T><<<nblk(a.n * kFeat), 256, 0, st>>>(a, X);
 }
 
 // Forward pass of n rows already in s->X; Y in FP32.  keep: FP32 activations
@@ -638,7 +703,7 @@ static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
     g.M = W; g.N = D; g.K = n;
     g.C = s->G + s->off[4]; g.Cl = nullptr; g.ldc = D;
     gemm<T>(g, st);
-    k_colsum<<<nblk(D), 256, 0, st>>>(s->dY, n, D, s->G + s->off[5]);
+    colsum(s->dY, n, D, s->colpart, s->G + s->off[5], st);
     // dZ2 = (dY W3^T) * (A2 > 0): [n][W]
     g.A = (const T*)s->dYl; g.sam = D; g.sak = 1;
     g.B = Wt + s->off[4]; g.sbk = 1; g.sbn = D;
@@ -651,7 +716,7 @@ static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
     g.M = W; g.N = W; g.K = n;
     g.C = s->G + s->off[2]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
     gemm<T>(g, st);
-    k_colsum<<<nblk(W), 256, 0, st>>>(s->dZ2, n, W, s->G + s->off[3]);
+    colsum(s->dZ2, n, W, s->colpart, s->G + s->off[3], st);
     // dZ1 = (dZ2 W2^T) * (A1 > 0)
     g.A = (const T*)s->dZ2l; g.sam = W; g.sak = 1;
     g.B = Wt + s->off[2]; g.sbk = 1; g.sbn = W;
@@ -664,7 +729,7 @@ static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
     g.M = kFeat; g.N = W; g.K = n;
     g.C = s->G + s->off[0]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
     gemm<T>(g, st);
-    k_colsum<<<nblk(W), 256, 0, st>>>(s->dZ1, n, W, s->G + s->off[1]);
+    colsum(s->dZ1, n, W, s->colpart, s->G + s->off[1], st);
 }
 
 static void adam(cd_surrogate* s, float lr, hipStream_t st) {
@@ -917,8 +982,14 @@ static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, fl
         if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->D);
         else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->D);
     }
-    k_output<<<nblk(t->n_leaf), 256, 0, st>>>(il_args(t, w), s->Y7, t->n_leaf, s->norm[2], s->norm[3], chi_scale, N,
-                                              chi);
+    if (s->D <= kOutMaxD && t->n_leaf % 256 == 0) {
+        const size_t lds = (size_t)(64 + 256) * s->D * 4;
+        k_output_tiled<<<(unsigned)(t->n_leaf / 256), 256, lds, st>>>(il_args(t, w), s->Y7, s->norm[2], s->norm[3],
+                                                                      chi_scale, N, chi);
+    } else {
+        k_output<<<nblk(t->n_leaf), 256, 0, st>>>(il_args(t, w), s->Y7, t->n_leaf, s->norm[2], s->norm[3], chi_scale,
+                                                  N, chi);
+    }
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
@@ -951,8 +1022,8 @@ static AmrSweepArgs uniform_oct_args(const cd_tree* t, const cd_weights* w, floa
     a.octden = t->leaf;
     a.base = nullptr;
     for (int k = 1; k <= 4; ++k) {
-        a.off[k] = w->off[k];
-        a.w[k] = w->w[k];
+        a.off[k] = w->offT[k];
+        a.w[k] = w->wT[k];
         a.len[k] = w->len[k];
     }
     a.kloc = w->kloc;

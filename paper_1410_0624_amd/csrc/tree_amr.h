@@ -48,7 +48,7 @@ struct AmrSweepArgs {
     int64_t n_tg;
     const float* octden;
     const float* base;  // padded level B
-    const int32_t* off[5];
+    const int32_t* off[5];  // weight lists with the direction fastest ([combo][len][D])
     const float* w[5];
     int len[5];
     const float* kloc;
