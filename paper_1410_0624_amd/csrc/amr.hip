@@ -50,6 +50,7 @@ struct AmrDev {
     int64_t* tg_leaf = nullptr;
     int32_t* grp = nullptr;
     int32_t* grp_info = nullptr;
+    uint8_t* need[CD_MAX_LEVEL + 1] = {nullptr};  // coarse-table cells that targets read, levels 2 .. qtop
     int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0;
     std::vector<void*> mem;
     AmrHost h;
@@ -375,6 +376,29 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
             }
         A->n_grp = (int64_t)(h.grp_info.size() / 2);
     }
+    // coarse-table cells that are read: the level-lq ancestor of each target
+    // (lq = min(l0 - 4, qtop)) and, recursively, their parents
+    const int qtop = std::min(B, L - 4);
+    std::vector<std::vector<uint8_t>> need(CD_MAX_LEVEL + 1);
+    if (qtop >= 2) {
+        for (int l = 2; l <= qtop; ++l) need[l].assign((size_t)1 << (3 * l), 0);
+        for (int64_t q = 0; q < A->n_tg; ++q) {
+            const int32_t* ti = &h.tg_info[4 * q];
+            const int l0 = ti[0], lq = std::min(l0 - 4, qtop);
+            if (lq < 2) continue;
+            const int sh = l0 - 1 - lq;
+            const int64_t nq = (int64_t)1 << lq;
+            need[lq][(size_t)((((int64_t)ti[3] >> sh) * nq + ((int64_t)ti[2] >> sh)) * nq + ((int64_t)ti[1] >> sh))] = 1;
+        }
+        for (int l = qtop; l > 2; --l) {
+            const int64_t n = (int64_t)1 << l, np = n >> 1;
+            for (int64_t k = 0; k < n; ++k)
+                for (int64_t j = 0; j < n; ++j)
+                    for (int64_t i = 0; i < n; ++i)
+                        if (need[l][(size_t)((k * n + j) * n + i)])
+                            need[l - 1][(size_t)(((k >> 1) * np + (j >> 1)) * np + (i >> 1))] = 1;
+        }
+    }
     // device memory
     int rc = alloc_dense_levels(t, B, s);
     if (rc != CD_OK) return rc;
@@ -399,6 +423,8 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     if ((rc = dev_copy(h.tg_leaf, &A->tg_leaf, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.grp, &A->grp, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.grp_info, &A->grp_info, s, A->mem)) != CD_OK) return rc;
+    for (int l = 2; l <= qtop; ++l)
+        if ((rc = dev_copy(need[l], &A->need[l], s, A->mem)) != CD_OK) return rc;
     CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
     return amr_update(t, leaf_n_dev, s);
 }
@@ -430,7 +456,9 @@ int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
 }
 
 int ensure_q(cd_tree* t, int D, int top, bool compact);                                     // sweep.hip
-void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s);  // sweep.hip
+int ensure_aux(cd_tree* t);                                                                 // sweep.hip
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
+                   const uint8_t* const* need = nullptr);  // sweep.hip
 
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
     AmrDev* A = t->amr;
@@ -448,11 +476,23 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     const bool compact = qtop == L - 4;
     int rc = ensure_q(t, w->D, qtop, compact);
     if (rc != CD_OK) return rc;
-    if (t->prof) {
-        CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
-        CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], s));
+    // the coarse tables on the second stream, concurrent with the split
+    // kernel of the shells dl = 1..3 (FP32: nothing to overlap)
+    const bool split = w->precision == CD_BF16X2;
+    hipStream_t cs = s;
+    if (split) {
+        if ((rc = ensure_aux(t)) != CD_OK) return rc;
+        cs = t->aux;
     }
-    launch_coarse(t, w, qtop, compact, s);
+    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
+    if (split) {
+        CD_HIP(hipEventRecord(t->ev[0], s));
+        CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
+    }
+    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], cs));
+    launch_coarse(t, w, qtop, compact, cs, A->need);
+    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], cs));
+    if (split) CD_HIP(hipEventRecord(t->ev[1], cs));
     AmrLookupView lk{};
     for (int l = 0; l <= B; ++l) lk.lev[l] = t->lev[l];
     for (int l = B + 1; l <= L; ++l) {
@@ -460,12 +500,9 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         lk.den[l] = A->octden + A->h.den_off[l];
     }
     lk.B = B;
-    if (t->prof) {
-        CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], s));
-        CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
-    }
+    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
     const float* E = nullptr;
-    if (w->precision == CD_BF16X2) {
+    if (split) {
         // shells dl = 1..3 on the matrix cores into E[n_tg][D]
         const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
         if (t->ext_bytes < bytes) {
@@ -480,6 +517,7 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         }
         launch_amr_external_mfma(lk, A->tg_info, A->grp, A->grp_info, A->n_grp, w, t->box_cm, t->ext, s);
         E = t->ext;
+        CD_HIP(hipStreamWaitEvent(s, t->ev[1], 0));  // the coarse tables are done
     }
     if (t->prof) {
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][1], s));

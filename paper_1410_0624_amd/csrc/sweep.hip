@@ -139,6 +139,7 @@ struct CoarseArgs {
     int D;
     int8_t next[6][2];
     int8_t dl4[4];
+    const uint8_t* need;  // [8^l] cells whose row is read (nullptr: every cell)
 };
 
 constexpr int kCoarseLen = 12;
@@ -196,6 +197,7 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
         if (q >= ncell) break;
         const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
                           (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
+        if (a.need && !a.need[((int64_t)c[2] * n + c[1]) * n + c[0]]) continue;
         const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
         float prev = 0.f;
         if (a.qprev) {
@@ -256,7 +258,7 @@ bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, f
 // Second stream and events of a tree: the target-row kernel of z-slab j runs
 // there while the external-column kernel of slab j+1 runs on the caller's
 // stream (both at the default priority).
-static int ensure_aux(cd_tree* t) {
+int ensure_aux(cd_tree* t) {
     if (t->aux) return CD_OK;
     CD_HIP(hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking));
     for (int j = 0; j < kMaxSlabs + 1; ++j) CD_HIP(hipEventCreateWithFlags(&t->ev[j], hipEventDisableTiming));
@@ -285,10 +287,12 @@ static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
     k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
 }
 
-void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s) {
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
+                   const uint8_t* const* need) {
     const int D = w->D;
     for (int l = 2; l <= top; ++l) {
         CoarseArgs c{};
+        c.need = need ? need[l] : nullptr;
         c.lev = t->lev[l];
         c.l = l;
         c.dx = (float)(t->box_cm * std::ldexp(1.0, -l));
@@ -343,7 +347,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipEventRecord(t->ev[kMaxSlabs], s));
         CD_HIP(hipStreamWaitEvent(t->aux, t->ev[kMaxSlabs], 0));
         CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
-        launch_coarse(t, w, L - 4, true, t->aux);
+        launch_coarse(t, w, L - 4, true, t->aux, nullptr);
         CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         for (int j = 0; j < nslab; ++j) {
@@ -364,7 +368,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipGetLastError());
         return CD_OK;
     }
-    launch_coarse(t, w, L - 4, true, s);
+    launch_coarse(t, w, L - 4, true, s, nullptr);
     if (L >= 1) {
         FineArgs a{};
         a.leaf = t->leaf;
