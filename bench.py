@@ -99,7 +99,20 @@ def main():
     ap.add_argument("--cpu-sample-leaves", type=int, default=100000,
                     help="adaptive tree: leaves timed with the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="run only an elementwise copy of known size (256 MiB read, 256 MiB written), the "
+                         "reference that scales the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.copy_reference:
+        import torch
+        a = torch.ones(1 << 26, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_reference": "torch.mul(a, 2, out=b)", "bytes_read": a.numel() * 4,
+                          "bytes_written": b.numel() * 4, "launches": 3}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; multi-GPU sharding is a design note only",
                           "n_gpus": args.gpus}))
