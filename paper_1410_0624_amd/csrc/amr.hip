@@ -1,21 +1,22 @@
 // Adaptive trees: a full base grid (level B) plus refined octs up to Lmax
 // (the fully threaded tree of Sect. 3).
 //
-// Storage: the dense padded pyramid levels 0..B (as for uniform grids) and,
-// for each level l > B, the densities of its octs' 8 cells (oct order) and a
-// dense map from the level-(l-1) cells to their oct (or -1).  A level-l
-// position with no cell reads the covering coarser leaf, so every cell
-// reaches the coarser levels (Sect. 3).  A refined cell holds the mean of its
-// children.
+// Storage: for each level l > B, the densities of its octs' 8 cells (oct
+// order) and a dense map from the level-(l-1) cells to their oct (or -1).  A
+// level-l position with no cell reads the covering coarser leaf, so every
+// cell reaches the coarser levels (Sect. 3); a refined cell holds the mean of
+// its children.  Shells only reach levels <= Lmax - 1, so each update also
+// fills dense padded levels B+1 .. Lmax-1 by that rule (8^(Lmax-1) floats at
+// the finest); with the pyramid below B every lookup of the sweep is one load.
 //
-// Sweep: one thread per target oct (an oct, or a 2x2x2 block of base cells,
-// holding at least one leaf).  Shells dl = 1, 2, 3 come from the generic
-// weight lists; shells dl >= 4 at levels above the dense base grid follow the
-// per-axis inner-limit automaton with the dl >= 4 lists; the rest is one read
-// of the dense coarse table Q_l (all 216 state codes, since targets sit at
-// several levels; the table at Lmax - 4 is read only from level Lmax and keeps
-// the 64 codes of dl = 4).  Then the internal + local part of the oct's leaf
-// children, their rows of N and chi.
+// Sweep: a group of lanes per target oct (an oct, or a 2x2x2 block of base
+// cells, holding at least one leaf), a lane per direction.  Shells dl = 1, 2,
+// 3 come from the weight lists (or from the split kernel), shells dl >= 4
+// from one read of the coarse table Q_{l0-4} (all 216 state codes, since
+// targets sit at several levels; the table at Lmax - 4 is read only from
+// level Lmax and keeps the 64 codes of dl = 4; only cells that targets read
+// are computed).  Then the internal + local part of the oct's leaf children,
+// their rows of N and chi.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -158,28 +159,16 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
                 acc = fmaf(dx, list_sum(a.lk, a.off[kind], a.w[kind], a.len[kind], base, a.D, l, C), acc);
             }
         }
-        // dl >= 4 above the coarse tables: walk the inner-limit automaton
-        int st[3] = {st0[0], st0[1], st0[2]};
-        int l = l0 - 4;
-        for (; l >= 2 && l > a.qtop; --l) {
-            const int sh = l0 - 1 - l;
-            const int64_t C[3] = {A[0] >> sh, A[1] >> sh, A[2] >> sh};
-            int cb = 0;
-            for (int k = 2; k >= 0; --k) cb = cb * 12 + 6 * (int)(C[k] & 1) + st[k];
-            const float dx = (float)(a.box * ldexp(1.0, -l));
-            const int64_t base = (int64_t)cb * a.len[4] * a.D + dd;
-            acc = fmaf(dx, list_sum(a.lk, a.off[4], a.w[4], a.len[4], base, a.D, l, C), acc);
-            for (int k = 0; k < 3; ++k) st[k] = a.next[st[k]][C[k] & 1];
-        }
+        // shells dl >= 4, every level at once: Q_l of the level-l ancestor
+        const int l = l0 - 4;
         if (l >= 2) {
-            // every remaining level at once: Q_l of the level-l ancestor
             const int sh = l0 - 1 - l;
             const int64_t nq = (int64_t)1 << l;
             const int64_t cell = ((A[2] >> sh) * nq + (A[1] >> sh)) * nq + (A[0] >> sh);
-            // at qtop == Lmax - 4 only targets at Lmax arrive, with st == st0
+            // the table at qtop == Lmax - 4 is read only by targets at Lmax
             const int64_t code = (a.qcompact && l == a.qtop)
                                      ? cell * 64 + ((A[0] >> 1) & 3) + 4 * ((A[1] >> 1) & 3) + 16 * ((A[2] >> 1) & 3)
-                                     : cell * 216 + st[0] + 6 * st[1] + 36 * st[2];
+                                     : cell * 216 + st0[0] + 6 * st0[1] + 36 * st0[2];
             acc += a.q[l][code * a.D + dd];
         }
         // internal + local of the oct's leaf children
@@ -205,6 +194,18 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
             if (valid && dl == 0 && leaf >= 0) a.chi[leaf] = v / (float)a.D;
         }
     }
+}
+
+// Dense padded level l > B: each cell's density through the maps (the cell,
+// or the covering coarser leaf), so the sweep reads every level below Lmax
+// with one load.
+__global__ void k_inject(const AmrLookupView lk, int l, float* __restrict__ out) {
+    const int64_t n = (int64_t)1 << l;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * n * n) return;
+    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
+    const int64_t S = n + 2 * kHalo;
+    out[((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)] = lk.density(l, i, j, k);
 }
 
 // ------------------------------------------------------------------- host --
@@ -378,7 +379,7 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     }
     // coarse-table cells that are read: the level-lq ancestor of each target
     // (lq = min(l0 - 4, qtop)) and, recursively, their parents
-    const int qtop = std::min(B, L - 4);
+    const int qtop = L - 4;  // every level below Lmax is dense (injected above B)
     std::vector<std::vector<uint8_t>> need(CD_MAX_LEVEL + 1);
     if (qtop >= 2) {
         for (int l = 2; l <= qtop; ++l) need[l].assign((size_t)1 << (3 * l), 0);
@@ -400,7 +401,7 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
         }
     }
     // device memory
-    int rc = alloc_dense_levels(t, B, s);
+    int rc = alloc_dense_levels(t, L - 1, s);
     if (rc != CD_OK) return rc;
     {
         const size_t bytes = (size_t)std::max<int64_t>(total_octs * 8, 1) * sizeof(float);
@@ -444,6 +445,18 @@ int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s) {
             k_oct_mean<<<(unsigned)((no + 255) / 256), 256, 0, s>>>(A->h.oct_first[l], no, A->par_dst, A->octden,
                                                                    t->lev[B]);
     }
+    // levels B+1 .. Lmax-1 as dense injected levels
+    AmrLookupView lk{};
+    for (int l = 0; l <= B; ++l) lk.lev[l] = t->lev[l];
+    for (int l = B + 1; l <= L; ++l) {
+        lk.octidx[l] = t->d_octidx[l];
+        lk.den[l] = A->octden + A->h.den_off[l];
+    }
+    lk.B = B;
+    for (int l = B + 1; l <= L - 1; ++l) {
+        const int64_t cells = (int64_t)1 << (3 * l);
+        k_inject<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(lk, l, t->lev[l]);
+    }
     CD_HIP(hipGetLastError());
     return build_dense_below(t, B, s);
 }
@@ -463,7 +476,7 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
     AmrDev* A = t->amr;
     const int B = t->base, L = t->lmax;
-    const int qtop = std::min(B, L - 4);  // coarse tables only on dense levels
+    const int qtop = L - 4;  // every level below Lmax is dense
     if (w->precision == CD_FP16X2) {
         set_error("cd_column_densities: adaptive trees take CD_FP32 or CD_BF16X2 weights "
                   "(binary16 needs the per-tile scale of the uniform-grid kernel)");
@@ -493,13 +506,10 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     launch_coarse(t, w, qtop, compact, cs, A->need);
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], cs));
     if (split) CD_HIP(hipEventRecord(t->ev[1], cs));
+    // shells reach levels <= Lmax - 1, all dense (injected above B by the update)
     AmrLookupView lk{};
-    for (int l = 0; l <= B; ++l) lk.lev[l] = t->lev[l];
-    for (int l = B + 1; l <= L; ++l) {
-        lk.octidx[l] = t->d_octidx[l];
-        lk.den[l] = A->octden + A->h.den_off[l];
-    }
-    lk.B = B;
+    for (int l = 0; l <= L - 1; ++l) lk.lev[l] = t->lev[l];
+    lk.B = L - 1;
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
     const float* E = nullptr;
     if (split) {
