@@ -204,6 +204,8 @@ int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per
  * run).  Stages: CD_STAGE_PYRAMID (cd_tree_update), CD_STAGE_COARSE (shells
  * dl >= 4), CD_STAGE_EXTERNAL (shells dl = 1..3), CD_STAGE_ROWS (internal +
  * local, N and chi), CD_STAGE_SWEEP (the whole cd_column_densities call).
+ * When a uniform sweep runs in z-slabs (its two kernels overlapping), the
+ * external and row stages are the sums of their launches.
  * Errors: CD_EINVAL (NULL tree or output), CD_EDEVICE.
  */
 enum { CD_STAGE_PYRAMID = 0, CD_STAGE_COARSE = 1, CD_STAGE_EXTERNAL = 2, CD_STAGE_ROWS = 3, CD_STAGE_SWEEP = 4,

@@ -165,6 +165,8 @@ struct cd_tree {
     bool prof = false;                       // stage timing enabled
     hipEvent_t pev[CD_NUM_STAGES][2] = {};   // start/stop events per stage
     bool pran[CD_NUM_STAGES] = {};           // stage ran in the last call
+    hipEvent_t pslab[2][cd::kMaxSlabs][2] = {};  // per-slab launches: external, rows
+    int pslabs = 0;                          // slabs of the last profiled uniform sweep
     hipEvent_t ev[cd::kMaxSlabs + 1] = {};  // slab hand-over and join events
     std::vector<void*> scratch;  // other device allocations to free
 };

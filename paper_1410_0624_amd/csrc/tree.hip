@@ -187,8 +187,12 @@ extern "C" int cd_profile_enable(cd_tree* t, int on) {
     if (on && !t->pev[0][0]) {
         for (auto& st : t->pev)
             for (auto& e : st) CD_HIP(hipEventCreate(&e));
+        for (auto& k : t->pslab)
+            for (auto& sl : k)
+                for (auto& e : sl) CD_HIP(hipEventCreate(&e));
     }
     t->prof = on != 0;
+    t->pslabs = 0;
     for (auto& r : t->pran) r = false;
     return CD_OK;
 }
@@ -204,6 +208,19 @@ extern "C" int cd_profile_read(cd_tree* t, float* ms) {
         if (!t->pran[k]) continue;
         CD_HIP(hipEventSynchronize(t->pev[k][1]));
         CD_HIP(hipEventElapsedTime(&ms[k], t->pev[k][0], t->pev[k][1]));
+    }
+    // a sweep cut into z-slabs: the external and row stages are the sums of
+    // their launches (the spans would include waits on the other stream)
+    for (int k = 0; k < 2 && t->pslabs > 1; ++k) {
+        const int stage = k == 0 ? CD_STAGE_EXTERNAL : CD_STAGE_ROWS;
+        float sum = 0.f;
+        for (int j = 0; j < t->pslabs; ++j) {
+            float m = 0.f;
+            CD_HIP(hipEventSynchronize(t->pslab[k][j][1]));
+            CD_HIP(hipEventElapsedTime(&m, t->pslab[k][j][0], t->pslab[k][j][1]));
+            sum += m;
+        }
+        ms[stage] = sum;
     }
     return CD_OK;
 }
@@ -248,6 +265,10 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
     for (auto& st : t->pev)
         for (auto& e : st)
             if (e) (void)hipEventDestroy(e);
+    for (auto& k : t->pslab)
+        for (auto& sl : k)
+            for (auto& e : sl)
+                if (e) (void)hipEventDestroy(e);
     if (t->aux) {
         (void)hipStreamSynchronize(t->aux);
         for (auto& e : t->ev)

@@ -69,7 +69,8 @@ def test_uniform_parity_all_leaves(colden, L):
 
 @pytest.mark.parametrize("name,dirs", [
     ("healpix2", oracle.dirs_healpix(2)), ("axes6", oracle.dirs_axes6()),
-    ("mn3x4", oracle.dirs_mn(3, 4)), ("mn5x8", oracle.dirs_mn(5, 8)), ("mn7x12", oracle.dirs_mn(7, 12))])
+    ("mn3x4", oracle.dirs_mn(3, 4)), ("mn3x8", oracle.dirs_mn(3, 8)), ("mn5x8", oracle.dirs_mn(5, 8)),
+    ("mn7x12", oracle.dirs_mn(7, 12))])
 def test_direction_families_parity(colden, name, dirs):
     tin = synth.workload_uniform(6, sigma=1.5, mean=10.0, seed=3)
     N, chi = _run(colden, tin, dirs)
@@ -78,6 +79,24 @@ def test_direction_families_parity(colden, name, dirs):
     print(f"{name} D={dirs.shape[0]}: max rel {rel.max():.3e}")
     assert rel.max() <= REL_FP32
     assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
+
+
+def test_sweep_in_z_slabs_128(colden):
+    """D = 48 on a 128^3 grid: the sweep runs in 4 z-slabs whose row and
+    external kernels overlap; every slab boundary is checked."""
+    tin = synth.workload_uniform(7, sigma=1.5, mean=10.0, seed=13)
+    dirs = oracle.dirs_healpix(2)
+    N, chi = _run(colden, tin, dirs)
+    n = 128
+    z = np.concatenate([np.arange(n)[::9], [31, 32, 63, 64, 95, 96, 127]])
+    rng = np.random.default_rng(6)
+    tg = np.unique(np.concatenate([(zz * n + rng.integers(0, n, 40)) * n + rng.integers(0, n, 40) for zz in z]))
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    rel = _rel(N[tg], ref)
+    print(f"slabs D=48 128^3: {tg.size} targets, max rel {rel.max():.3e}")
+    assert np.isfinite(N).all()
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
 
 
 def test_c2_256_sampled_parity(colden):
