@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", choices=["uniform", "amr", "surrogate"], default="uniform")
+    ap.add_argument("--amr-threshold", type=float, default=100.0,
+                    help="adaptive tree: refine cells with averaged n above this (cm^-3)")
     ap.add_argument("--train-fields", type=int, default=16, help="surrogate: seeded 256^3 training fields")
     ap.add_argument("--train-steps", type=int, default=6000, help="surrogate: Adam steps")
     ap.add_argument("--train-batch", type=int, default=8192, help="surrogate: leaves per step")
@@ -131,8 +133,8 @@ def main():
     nside = args.nside or (2 if amr else 1)
     t0 = time.time()
     if amr:
-        tin = synth.workload_amr()
-        wl = (f"AMR tree: 128^3 base + 2 refined levels on cells with averaged n > 100 cm^-3 "
+        tin = synth.workload_amr(threshold=args.amr_threshold)
+        wl = (f"AMR tree: 128^3 base + 2 refined levels on cells with averaged n > {args.amr_threshold:g} cm^-3 "
               f"(log-normal, sigma_ln n=2, mean 10 cm^-3, generated at 512^3, box 20 pc, seed 3)")
         L = tin.max_level
     else:

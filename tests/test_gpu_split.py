@@ -100,6 +100,37 @@ def test_split_c3_amr_sampled(colden):
     assert err.max() <= LN_GATE
 
 
+def test_c4_512_all_forms_sampled(colden):
+    """The 512^3 workload (134M leaves, D = 12) in the launch configuration
+    the benchmark times, all three forms against the oracle on 20k sampled
+    leaves (every tile layer of the grid represented)."""
+    tin = synth.workload_uniform(9, sigma=1.5, mean=10.0, seed=4)
+    dirs = oracle.dirs_healpix(1)
+    rng = np.random.default_rng(9)
+    tg = np.concatenate([rng.choice(tin.n_leaf, 20000, replace=False), [0, tin.n_leaf - 1]])
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    dev = torch.device("cuda:0")
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    tree = colden.Tree(tin, leaf)
+    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    idx = torch.from_numpy(tg).to(dev)
+    for pname, prec, gate in [("fp32", 0, None), ("bf16x2", 1, LN_GATE), ("fp16x2", 2, LN_GATE)]:
+        w = colden.Weights(dirs, precision=prec)
+        N.fill_(float("nan"))
+        colden.column_densities(tree, w, N)
+        got = N[idx].cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all()
+        err = _lnerr(got, ref)
+        rel = np.abs(got - ref) / ref
+        print(f"512^3 {pname}: max rel {rel.max():.3e}, max |d ln N| {err.max():.3e}")
+        if gate is None:
+            assert rel.max() <= 1e-5
+        else:
+            assert err.max() <= gate
+        w.close()
+    assert torch.isfinite(N).all()
+
+
 def test_split_unsupported_cases(colden):
     dev = torch.device("cuda:0")
     # binary16 on an adaptive tree (no LDS tile to scale)
