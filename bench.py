@@ -73,11 +73,12 @@ PREC = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
 
-def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int, split: bool) -> float:
+def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int, rows_from_e: bool) -> float:
     """Algorithmic HBM bytes of the adaptive-tree target kernel: per leaf the
     row of N (4 D B), chi (4 B) and its density (4 B); per target oct its row
-    of the coarse table (4 D B) and, for split forms, of E (4 D B)."""
-    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * (2 if split else 1)
+    of the coarse table (4 D B) and, when a tiled or split kernel computed the
+    shells dl = 1..3 of every target, its row of E (4 D B)."""
+    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * (2 if rows_from_e else 1)
 
 
 def main():
@@ -196,7 +197,7 @@ def main():
     forms = {args.precision: main_form}
     if not args.no_forms:
         for p in PREC:
-            if p == args.precision or (amr and p == "fp16x2"):
+            if p == args.precision or (amr and p == "fp16x2" and tin.base_level < 5):
                 continue
             forms[p] = measure(p)
             print(f"# form {p}: {forms[p]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
@@ -210,8 +211,11 @@ def main():
         ijk = tin.leaf_ijk.astype(np.int64)
         key = (lv.astype(np.int64) << 60) | ((ijk[:, 2] >> 1) << 40) | ((ijk[:, 1] >> 1) << 20) | (ijk[:, 0] >> 1)
         n_tg = int(np.unique(key).shape[0])
-        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D, args.precision != "fp32")
-        kname = "k_target_octs (per target oct, a lane per direction: shells, internal+local, N and chi rows)"
+        from_e = args.precision != "fp32" or tin.base_level >= 5
+        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D, from_e)
+        kname = (f"k_target_leaves<{D}> (a lane per target: external row + coarse table, internal+local, N and chi rows)"
+                 if from_e and D in (6, 12, 24, 40, 48) else
+                 "k_target_octs (per target oct, a lane per direction: shells, internal+local, N and chi rows)")
     else:
         rows_bytes = alg_bytes_rows(tin.n_leaf, D)
         kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"

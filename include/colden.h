@@ -148,9 +148,11 @@ void cd_tree_destroy(cd_tree* tree);
  *              16-bit halves (rounded from the FP64 weights here) and run
  *              the contraction on the matrix cores with FP32 accumulation;
  *              measured error |d ln N| <= 3e-5 (bf16) and <= 1e-6 (fp16).
- *              CD_FP16X2 divides each LDS density tile by a power of two and
- *              is offered on uniform grids only.  Split forms on uniform
- *              grids need 2^L >= 32 and D in {6, 12, 24, 40, 48}.
+ *              CD_FP16X2 divides each LDS density tile by a power of two:
+ *              it needs the tiled kernel, i.e. D in {6, 12, 24, 40, 48} and
+ *              2^L >= 32 on uniform grids, base level >= 5 on adaptive
+ *              trees.  CD_BF16X2 on uniform grids needs the same; on
+ *              adaptive trees it takes any D and base level.
  * Errors: CD_EINVAL, CD_EUNSUPPORTED, CD_ENOMEM, CD_EDEVICE.
  */
 int cd_precompute_weights(const double* dirs, int D, int mode, int precision,

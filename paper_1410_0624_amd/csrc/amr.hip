@@ -24,6 +24,8 @@
 
 #include "tree_amr.h"
 
+#define CD_CONST __attribute__((address_space(4)))
+
 namespace cd {
 
 struct AmrHost {
@@ -37,6 +39,10 @@ struct AmrHost {
     std::vector<int64_t> tg_leaf;    // [n_tg][8]: leaf index of the child or -1
     std::vector<int8_t> leaf_level;
     std::vector<int32_t> leaf_ijk;
+    std::vector<int64_t> erow;      // per target: row of its external columns in the tiled buffer, or -1
+    std::vector<int32_t> tiles[CD_MAX_LEVEL + 1];  // [l0]: active 16^3-oct tiles of the level-(l0-1) grid
+    int64_t ebase[CD_MAX_LEVEL + 1] = {0};         // [l0]: first row of those tiles' external columns
+    int64_t erows = 0;                             // rows of the tiled buffer
     std::vector<int32_t> grp;       // [ngroups][64]: target octs of one level and class (-1: none)
     std::vector<int32_t> grp_info;  // [ngroups][2]: level, class (A mod 4 per axis)
 };
@@ -52,6 +58,8 @@ struct AmrDev {
     int32_t* grp = nullptr;
     int32_t* grp_info = nullptr;
     uint8_t* need[CD_MAX_LEVEL + 1] = {nullptr};  // coarse-table cells that targets read, levels 2 .. qtop
+    int64_t* erow = nullptr;
+    int32_t* tiles[CD_MAX_LEVEL + 1] = {nullptr};
     int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0;
     std::vector<void*> mem;
     AmrHost h;
@@ -144,8 +152,10 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
         const int d = d0 + dl;
         const bool live = d < a.D;
         const int dd = live ? d : a.D - 1;  // idle lanes follow a real direction
-        float acc = a.E ? a.E[g * a.D + dd] : 0.f;
-        if (!a.E) {
+        // shells dl = 1..3: a row of E (per target, or at erow), else the lists
+        const int64_t er = a.E ? (a.erow ? a.erow[g] : g) : -1;
+        float acc = er >= 0 ? a.E[er * a.D + dd] : 0.f;
+        if (er < 0) {
 #pragma unroll 1
             for (int kind = 1; kind <= 3; ++kind) {
                 const int l = l0 - kind;
@@ -171,14 +181,23 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
                                      : cell * 216 + st0[0] + 6 * st0[1] + 36 * st0[2];
             acc += a.q[l][code * a.D + dd];
         }
-        // internal + local of the oct's leaf children
+        // internal + local of the oct's leaf children (Sect. 3.2).  With the
+        // ray mirrored into the positive octant, child c reaches its sibling
+        // c ^ m across the axis set m only if c is on the low side of every
+        // axis of m (bit of c == sign bit of u); the chord is G[d][m].
+        float G[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) G[m] = a.gloc[dd * 8 + m];
+        const int sg = a.sgn[dd];
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             const int64_t leaf = a.tg_leaf[8 * g + c];
             if (leaf < 0) continue;
+            const int allowed = ~(c ^ sg) & 7;
             float s = 0.f;
 #pragma unroll
-            for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(c * 8 + sb) * a.D + dd], s);
+            for (int m = 0; m < 8; ++m)
+                if ((m & allowed) == m) s = fmaf(ln[c ^ m], G[m], s);
             const float v = fmaf(dxL, s, acc);
             if (live && valid) a.N[leaf * a.D + d] = v;
             if (live) chis[c] += expf(-a.chi_scale * v);
@@ -193,6 +212,130 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
             const int64_t leaf = a.tg_leaf[8 * g + c];
             if (valid && dl == 0 && leaf >= 0) a.chi[leaf] = v / (float)a.D;
         }
+    }
+}
+
+// Rows of the targets whose shells dl = 1..3 are all in E, for the direction
+// counts of the tiled kernels: a lane per target (8 lanes per target oct, a
+// wave holds 8 octs) and the directions wave-uniform, so the chords and sign
+// bits of a direction are scalar loads.  Child c of the oct reaches its
+// sibling c ^ m only if, on every axis of m, bit of c == sign bit of u (the
+// ray mirrored into the positive octant); with the factors a_k = [bit k of c
+// == bit k of sgn] the sum over the allowed m nests as
+//   ((y0 + a0 y1) + a1 (y2 + a0 y3)) + a2 ((y4 + a0 y5) + a1 (y6 + a0 y7)),
+// y_m = n(c ^ m) G[d][m].  Rows leave through LDS, 32 targets at a time, as
+// consecutive vector stores (targets of consecutive octs are mostly
+// consecutive leaves).
+template <int D>
+__global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
+    constexpr int V = D % 4 == 0 ? 4 : (D % 2 == 0 ? 2 : 1);  // floats per store
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int c = lane & 7;
+    const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 8 + (lane >> 3);
+    const bool valid = g0 < a.n_tg;
+    const int64_t g = valid ? g0 : a.n_tg - 1;  // idle lanes follow a real oct and write nothing
+    const int l0 = a.tg_info[4 * g];
+    const int64_t Ax = a.tg_info[4 * g + 1], Ay = a.tg_info[4 * g + 2], Az = a.tg_info[4 * g + 3];
+    const int64_t src = a.tg_src[8 * g + c];
+    const float nc = src >= 0 ? a.octden[src] : a.base[-(src + 1)];
+    const int64_t leaf = valid ? a.tg_leaf[8 * g + c] : -1;
+    float nx[8];
+    nx[0] = nc;
+#pragma unroll
+    for (int m = 1; m < 8; ++m) nx[m] = __shfl_xor(nc, m);  // sibling c ^ m (same 8-lane group)
+
+    // external part: the row of E plus, for l0 - 4 >= 2, the coarse table
+    float out[D];
+    {
+        const int64_t er = a.erow ? a.erow[g] : g;
+        const float* ep = a.E + er * D;
+#pragma unroll
+        for (int d = 0; d < D; d += V) {
+            if constexpr (V == 4) {
+                const float4 v = *reinterpret_cast<const float4*>(ep + d);
+                out[d] = v.x, out[d + 1] = v.y, out[d + 2] = v.z, out[d + 3] = v.w;
+            } else if constexpr (V == 2) {
+                const float2 v = *reinterpret_cast<const float2*>(ep + d);
+                out[d] = v.x, out[d + 1] = v.y;
+            } else {
+                out[d] = ep[d];
+            }
+        }
+        const int l = l0 - 4;
+        if (l >= 2) {
+            const int sh = l0 - 1 - l;
+            const int64_t nq = (int64_t)1 << l;
+            const int64_t cell = ((Az >> sh) * nq + (Ay >> sh)) * nq + (Ax >> sh);
+            int64_t code;
+            if (a.qcompact && l == a.qtop) {
+                code = cell * 64 + ((Ax >> 1) & 3) + 4 * ((Ay >> 1) & 3) + 16 * ((Az >> 1) & 3);
+            } else {
+                const int s0 = a.dl4[(Ax >> 1) & 3], s1 = a.dl4[(Ay >> 1) & 3], s2 = a.dl4[(Az >> 1) & 3];
+                code = cell * 216 + s0 + 6 * s1 + 36 * s2;
+            }
+            const float* qp = a.q[l] + code * D;
+#pragma unroll
+            for (int d = 0; d < D; d += V) {
+                if constexpr (V == 4) {
+                    const float4 v = *reinterpret_cast<const float4*>(qp + d);
+                    out[d] += v.x, out[d + 1] += v.y, out[d + 2] += v.z, out[d + 3] += v.w;
+                } else if constexpr (V == 2) {
+                    const float2 v = *reinterpret_cast<const float2*>(qp + d);
+                    out[d] += v.x, out[d + 1] += v.y;
+                } else {
+                    out[d] += qp[d];
+                }
+            }
+        }
+    }
+    // internal + local (Sect. 3.2) and the screening sum (Eq. 5)
+    const float dxL = (float)(a.box * ldexp(1.0, -l0));
+    const float b0 = (float)(c & 1), b1 = (float)((c >> 1) & 1), b2 = (float)(c >> 2);
+    float chi = 0.f;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int sg = ((const CD_CONST int32_t*)a.sgn)[d];
+        const CD_CONST float* gl = (const CD_CONST float*)a.gloc + d * 8;
+        const float a0 = (sg & 1) ? b0 : 1.f - b0;
+        const float a1 = (sg & 2) ? b1 : 1.f - b1;
+        const float a2 = (sg & 4) ? b2 : 1.f - b2;
+        const float u0 = fmaf(a0, nx[1] * gl[1], nx[0] * gl[0]);
+        const float u1 = fmaf(a0, nx[3] * gl[3], nx[2] * gl[2]);
+        const float u2 = fmaf(a0, nx[5] * gl[5], nx[4] * gl[4]);
+        const float u3 = fmaf(a0, nx[7] * gl[7], nx[6] * gl[6]);
+        const float s = fmaf(a2, fmaf(a1, u3, u2), fmaf(a1, u1, u0));
+        out[d] = fmaf(dxL, s, out[d]);
+        chi += __expf(-a.chi_scale * out[d]);
+    }
+    if (a.chi && leaf >= 0) a.chi[leaf] = chi * (1.f / (float)D);
+
+    // rows through LDS: lanes 32 p .. 32 p + 31 in pass p
+    __shared__ __align__(16) float stage[4][32 * D];
+    __shared__ int64_t rows[4][32];
+    float* st = stage[w];
+#pragma unroll 1
+    for (int p = 0; p < 2; ++p) {
+        if ((lane >> 5) == p) {
+            float* r = st + (lane & 31) * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d) r[d] = out[d];
+            rows[w][lane & 31] = leaf;
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+        constexpr int nv = 32 * D / V;
+        for (int i = lane; i < nv; i += 64) {
+            const int r = (i * V) / D, col = i * V - r * D;
+            const int64_t lf = rows[w][r];
+            if (lf < 0) continue;
+            float* dst = a.N + lf * D + col;
+            if constexpr (V == 4) *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(st + i * V);
+            else if constexpr (V == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(st + i * V);
+            else *dst = st[i];
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -377,6 +520,37 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
             }
         A->n_grp = (int64_t)(h.grp_info.size() / 2);
     }
+    // targets whose oct grid has 16^3-oct tiles (2^(l0-1) >= 16): their
+    // shells dl = 1..3 come from the tiled kernel run on the active tiles of
+    // their level (the grid below Lmax is dense), one row per oct of a tile
+    h.erow.assign((size_t)A->n_tg, -1);
+    {
+        std::vector<std::vector<int64_t>> tl(L + 1);
+        for (int64_t q = 0; q < A->n_tg; ++q) {
+            const int32_t* ti = &h.tg_info[4 * q];
+            const int l0 = ti[0];
+            if (l0 - 1 < 4) continue;
+            const int64_t tpa = (int64_t)1 << (l0 - 1 - 4);
+            tl[l0].push_back(((int64_t)(ti[3] >> 4) * tpa + (ti[2] >> 4)) * tpa + (ti[1] >> 4));
+        }
+        for (int l0 = 0; l0 <= L; ++l0) {
+            std::sort(tl[l0].begin(), tl[l0].end());
+            tl[l0].erase(std::unique(tl[l0].begin(), tl[l0].end()), tl[l0].end());
+            h.tiles[l0].assign(tl[l0].begin(), tl[l0].end());
+            h.ebase[l0] = h.erows;
+            h.erows += (int64_t)tl[l0].size() * 4096;
+        }
+        for (int64_t q = 0; q < A->n_tg; ++q) {
+            const int32_t* ti = &h.tg_info[4 * q];
+            const int l0 = ti[0];
+            if (l0 - 1 < 4) continue;
+            const int64_t tpa = (int64_t)1 << (l0 - 1 - 4);
+            const int64_t tile = ((int64_t)(ti[3] >> 4) * tpa + (ti[2] >> 4)) * tpa + (ti[1] >> 4);
+            const int64_t pos = std::lower_bound(h.tiles[l0].begin(), h.tiles[l0].end(), (int32_t)tile) - h.tiles[l0].begin();
+            const int64_t local = (((int64_t)(ti[3] & 15) * 16) + (ti[2] & 15)) * 16 + (ti[1] & 15);
+            h.erow[(size_t)q] = h.ebase[l0] + pos * 4096 + local;
+        }
+    }
     // coarse-table cells that are read: the level-lq ancestor of each target
     // (lq = min(l0 - 4, qtop)) and, recursively, their parents
     const int qtop = L - 4;  // every level below Lmax is dense (injected above B)
@@ -426,6 +600,9 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     if ((rc = dev_copy(h.grp_info, &A->grp_info, s, A->mem)) != CD_OK) return rc;
     for (int l = 2; l <= qtop; ++l)
         if ((rc = dev_copy(need[l], &A->need[l], s, A->mem)) != CD_OK) return rc;
+    if ((rc = dev_copy(h.erow, &A->erow, s, A->mem)) != CD_OK) return rc;
+    for (int l0 = 0; l0 <= L; ++l0)
+        if (!h.tiles[l0].empty() && (rc = dev_copy(h.tiles[l0], &A->tiles[l0], s, A->mem)) != CD_OK) return rc;
     CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
     return amr_update(t, leaf_n_dev, s);
 }
@@ -470,6 +647,13 @@ int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
 
 int ensure_q(cd_tree* t, int D, int top, bool compact);                                     // sweep.hip
 int ensure_aux(cd_tree* t);                                                                 // sweep.hip
+bool tiled_weights_ok(const cd_weights* w);                                                 // sweep_tile.hip
+void launch_external_mfma_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
+                               const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E,
+                               hipStream_t s);                                              // split.hip
+void launch_external_tiled_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
+                                const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E,
+                                hipStream_t s);                                             // sweep_tile.hip
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const uint8_t* const* need = nullptr);  // sweep.hip
 
@@ -477,9 +661,14 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     AmrDev* A = t->amr;
     const int B = t->base, L = t->lmax;
     const int qtop = L - 4;  // every level below Lmax is dense
-    if (w->precision == CD_FP16X2) {
-        set_error("cd_column_densities: adaptive trees take CD_FP32 or CD_BF16X2 weights "
-                  "(binary16 needs the per-tile scale of the uniform-grid kernel)");
+    // every target on a level with 16^3-oct tiles: the shells dl = 1..3 come
+    // from the tiled kernels (FP32 or split) on the active tiles
+    const int D = w->D;
+    const bool all_tiled = B >= 5;
+    const bool split_tiled = all_tiled && (D == 6 || D == 12 || D == 24 || D == 40 || D == 48);
+    if (w->precision == CD_FP16X2 && !split_tiled) {
+        set_error("cd_column_densities: CD_FP16X2 on adaptive trees needs a base level >= 5 and D in "
+                  "{6, 12, 24, 40, 48} (binary16 needs the per-tile scale of the tiled kernel)");
         return CD_EUNSUPPORTED;
     }
     if (w->len[4] != 12) {
@@ -489,30 +678,60 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     const bool compact = qtop == L - 4;
     int rc = ensure_q(t, w->D, qtop, compact);
     if (rc != CD_OK) return rc;
-    // the coarse tables on the second stream, concurrent with the split
-    // kernel of the shells dl = 1..3 (FP32: nothing to overlap)
-    const bool split = w->precision == CD_BF16X2;
+    // the coarse tables on the second stream, concurrent with the kernel of
+    // the shells dl = 1..3 (none for FP32 weights the tiled kernel cannot take)
+    const bool split = w->precision != CD_FP32;
+    const bool tiled = (split ? split_tiled : tiled_weights_ok(w)) && A->h.erows > 0;
+    const bool overlap = split || tiled;  // an external kernel runs beside the coarse tables
     hipStream_t cs = s;
-    if (split) {
+    if (overlap) {
         if ((rc = ensure_aux(t)) != CD_OK) return rc;
         cs = t->aux;
     }
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
-    if (split) {
+    if (overlap) {
         CD_HIP(hipEventRecord(t->ev[0], s));
         CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
     }
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], cs));
     launch_coarse(t, w, qtop, compact, cs, A->need);
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], cs));
-    if (split) CD_HIP(hipEventRecord(t->ev[1], cs));
+    if (overlap) CD_HIP(hipEventRecord(t->ev[1], cs));
     // shells reach levels <= Lmax - 1, all dense (injected above B by the update)
     AmrLookupView lk{};
     for (int l = 0; l <= L - 1; ++l) lk.lev[l] = t->lev[l];
     lk.B = L - 1;
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
     const float* E = nullptr;
-    if (split) {
+    const int64_t* erow = nullptr;
+    if (tiled) {
+        // shells dl = 1..3 of the targets on tiles: the tiled kernel per level
+        const size_t bytes = (size_t)A->h.erows * w->D * sizeof(float);
+        if (t->ext_bytes < bytes) {
+            if (t->ext) (void)hipFree(t->ext);
+            t->ext = nullptr;
+            t->ext_bytes = 0;
+            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
+                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
+                return CD_ENOMEM;
+            }
+            t->ext_bytes = bytes;
+        }
+        for (int l0 = 5; l0 <= L; ++l0) {
+            const int64_t nt = (int64_t)A->h.tiles[l0].size();
+            float* El = t->ext + A->h.ebase[l0] * w->D;
+            if (split)
+                launch_external_mfma_list(t->lev[l0 - 1], t->lev[l0 - 2], t->lev[l0 - 3], l0, t->box_cm, w,
+                                          A->tiles[l0], nt, El, s);
+            else
+                launch_external_tiled_list(t->lev[l0 - 1], t->lev[l0 - 2], t->lev[l0 - 3], l0, t->box_cm, w,
+                                           A->tiles[l0], nt, El, s);
+        }
+        E = t->ext;
+        erow = A->erow;
+        CD_HIP(hipStreamWaitEvent(s, t->ev[1], 0));  // the coarse tables are done
+    }
+    if (split && !tiled) {
         // shells dl = 1..3 on the matrix cores into E[n_tg][D]
         const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
         if (t->ext_bytes < bytes) {
@@ -537,6 +756,8 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     AmrSweepArgs a{};
     a.lk = lk;
     a.E = E;
+    a.erow = erow;
+    a.all_rows = (E && (!erow || all_tiled)) ? 1 : 0;
     a.tg_info = A->tg_info;
     a.tg_src = A->tg_src;
     a.tg_leaf = A->tg_leaf;
@@ -549,6 +770,8 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         a.len[k] = w->len[k];
     }
     a.kloc = w->kloc;
+    a.gloc = w->gloc;
+    a.sgn = w->sgn;
     for (int l = 2; l <= qtop; ++l) a.q[l] = t->q[l];
     a.qtop = qtop;
     a.qcompact = compact ? 1 : 0;
@@ -578,6 +801,18 @@ static void launch_octs(const AmrSweepArgs& a, hipStream_t s) {
 
 void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
     if (a.n_tg <= 0) return;
+    if (a.E && (!a.erow || a.all_rows) && (reinterpret_cast<uintptr_t>(a.N) & 15) == 0 &&
+        (a.D == 6 || a.D == 12 || a.D == 24 || a.D == 40 || a.D == 48)) {
+        const unsigned nb = (unsigned)((a.n_tg + 31) / 32);
+        switch (a.D) {
+            case 6: k_target_leaves<6><<<nb, 256, 0, s>>>(a); break;
+            case 12: k_target_leaves<12><<<nb, 256, 0, s>>>(a); break;
+            case 24: k_target_leaves<24><<<nb, 256, 0, s>>>(a); break;
+            case 40: k_target_leaves<40><<<nb, 256, 0, s>>>(a); break;
+            default: k_target_leaves<48><<<nb, 256, 0, s>>>(a); break;
+        }
+        return;
+    }
     if (a.D <= 8) launch_octs<8>(a, s);
     else if (a.D <= 16) launch_octs<16>(a, s);
     else if (a.D <= 32) launch_octs<32>(a, s);

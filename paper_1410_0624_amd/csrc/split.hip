@@ -107,6 +107,7 @@ struct MfmaArgs {
     int D;
     int L;
     int tiles_per_axis;
+    const int32_t* tile_list;  // nullptr: every tile; else linear tile indices, E rows per list position
 };
 
 #define CD_CONST __attribute__((address_space(4)))
@@ -120,7 +121,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
     __shared__ uint32_t smax[3];
 
     const int tpa = a.tiles_per_axis;
-    const int tile_id = blockIdx.x;
+    const int tile_id = a.tile_list ? a.tile_list[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;
     const int L1 = a.L - 1;
@@ -260,7 +261,10 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
                     for (int i = 0; i < 4; ++i) {
                         const int q = 4 * g + i;  // row = oct (q & 3, q >> 2, rb) of the wave
                         const int Ax = X1 + 4 * (q & 3) + cx, Ay = Y1 + 4 * (q >> 2) + cy, Az = Z1 + 4 * rb + cz;
-                        const int64_t oct = ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
+                        const int64_t oct =
+                            a.tile_list
+                                ? (int64_t)blockIdx.x * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
+                                : ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
                         a.E[oct * a.D + d] = out_scale * fmaf(lo_w, al[rb][i], ah[rb][i]);
                     }
             }
@@ -289,6 +293,32 @@ bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipSt
     if (w->precision == CD_BF16X2) k_external_mfma<CD_BF16X2><<<ntiles, tile::kThreads, 0, s>>>(a);
     else k_external_mfma<CD_FP16X2><<<ntiles, tile::kThreads, 0, s>>>(a);
     return true;
+}
+
+// The listed tiles of a virtual uniform grid at level l0 whose levels
+// l0-1 .. l0-3 are the dense padded arrays lev1 .. lev3 (an adaptive tree's
+// injected levels); E rows per list position.
+void launch_external_mfma_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
+                               const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E, hipStream_t s) {
+    if (ntiles <= 0) return;
+    MfmaArgs a{};
+    a.lev1 = lev1;
+    a.lev2 = lev2;
+    a.lev3 = lev3;
+    a.dx1 = (float)(box * std::ldexp(1.0, -(l0 - 1)));
+    a.dx2 = (float)(box * std::ldexp(1.0, -(l0 - 2)));
+    a.dx3 = (float)(box * std::ldexp(1.0, -(l0 - 3)));
+    a.hdr = w->split_hdr;
+    a.ent = w->split_ent;
+    a.bank = reinterpret_cast<const u32x4*>(w->split_bank);
+    a.ntiles = w->split_ntiles;
+    a.E = E;
+    a.D = w->D;
+    a.L = l0;
+    a.tiles_per_axis = 1 << (l0 - 1 - 4);
+    a.tile_list = tiles;
+    if (w->precision == CD_BF16X2) k_external_mfma<CD_BF16X2><<<(unsigned)ntiles, tile::kThreads, 0, s>>>(a);
+    else k_external_mfma<CD_FP16X2><<<(unsigned)ntiles, tile::kThreads, 0, s>>>(a);
 }
 
 // ---------------------------------------------------------- adaptive trees --

@@ -1031,6 +1031,8 @@ static AmrSweepArgs uniform_oct_args(const cd_tree* t, const cd_weights* w, floa
         a.len[k] = w->len[k];
     }
     a.kloc = w->kloc;
+    a.gloc = w->gloc;
+    a.sgn = w->sgn;
     a.qtop = L - 4;
     a.qcompact = 1;
     for (int l = 2; l <= L - 4; ++l) a.q[l] = t->q[l];

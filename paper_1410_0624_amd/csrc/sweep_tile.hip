@@ -37,6 +37,8 @@ struct TileArgs {
     float* E;           // [n_oct][D] external columns (output)
     int tiles_per_axis;
     int tz0;            // first tile layer along z of this launch
+    const int32_t* tile_list;  // nullptr: every tile of the layers; else linear tile indices, and E is
+                               // written per list position: row (blockIdx * 4096 + local oct)
 };
 
 __device__ __forceinline__ float as_float(int32_t b) { return __int_as_float(b); }
@@ -58,8 +60,9 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     __shared__ int4 tab[kTabWords / 4];
 
     const int tpa = a.tiles_per_axis;
-    const int tile_id = blockIdx.x;
-    const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = a.tz0 + tile_id / (tpa * tpa);
+    const int tile_id = a.tile_list ? a.tile_list[blockIdx.x] : (int)blockIdx.x;
+    const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa,
+              tz = (a.tile_list ? 0 : a.tz0) + tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;  // tile origin, level L-1 cells
     const int L1 = a.L - 1;
     const int64_t S1 = ((int64_t)1 << L1) + 2 * kHalo;
@@ -153,7 +156,9 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
         const int cx = ci & 3, cy = (ci >> 2) & 3, cz = ci >> 4;
         const int Ax = X1 + 4 * lx + cx, Ay = Y1 + 4 * ly + cy, Az = Z1 + 4 * lz + cz;
 
-        const int64_t oct = ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
+        const int64_t oct = a.tile_list
+                                ? (int64_t)blockIdx.x * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
+                                : ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
 #pragma unroll 1
         for (int k = 0; k < kChunks; ++k) {
             const int d0 = k * DC;
@@ -243,6 +248,13 @@ static void launch(const TileArgs& a, int nz, hipStream_t s) {
 
 // The tiled external kernel and the target-row kernel handle this tree and
 // direction set.
+// The tiled kernels handle this direction set.
+bool tiled_weights_ok(const cd_weights* w) {
+    const int D = w->D;
+    if (!(D == 6 || D == 12 || D == 24 || D == 40 || D == 48)) return false;
+    return w->host.tile_dc == tile_chunk(D) && w->host.blob_words > 0 && w->host.blob_words <= tile::kTabWords;
+}
+
 bool tiled_supported(const cd_tree* t, const cd_weights* w) {
     const int L = t->lmax;
     const int D = w->D;
@@ -252,6 +264,39 @@ bool tiled_supported(const cd_tree* t, const cd_weights* w) {
 }
 
 // Tile layers [tz0, tz0 + nz) along z.
+// External columns of the octs of the listed tiles (linear indices over the
+// 16^3-oct tiles of the level-(l0-1) grid) of a virtual uniform grid at level
+// l0 whose levels l0-1 .. l0-3 are the dense padded arrays lev1 .. lev3 (an
+// adaptive tree's injected levels); E rows per list position.
+void launch_external_tiled_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
+                                const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E, hipStream_t s) {
+    TileArgs a{};
+    a.L = l0;
+    a.lev1 = lev1;
+    a.lev2 = lev2;
+    a.lev3 = lev3;
+    a.dx1 = (float)(box * std::ldexp(1.0, -(l0 - 1)));
+    a.dx2 = (float)(box * std::ldexp(1.0, -(l0 - 2)));
+    a.dx3 = (float)(box * std::ldexp(1.0, -(l0 - 3)));
+    a.dxL = (float)(box * std::ldexp(1.0, -l0));
+    a.blob = w->blob;
+    a.blob_words = w->host.blob_words;
+    a.gloc = w->gloc;
+    a.sgn = w->sgn;
+    a.E = E;
+    a.tiles_per_axis = 1 << (l0 - 1 - 4);
+    a.tile_list = tiles;
+    if (ntiles <= 0) return;
+    const unsigned nb = (unsigned)ntiles;
+    switch (w->D) {
+        case 6: k_external_tiled<6, 6><<<nb, tile::kThreads, 0, s>>>(a); break;
+        case 12: k_external_tiled<12, 12><<<nb, tile::kThreads, 0, s>>>(a); break;
+        case 24: k_external_tiled<24, 12><<<nb, tile::kThreads, 0, s>>>(a); break;
+        case 40: k_external_tiled<40, 8><<<nb, tile::kThreads, 0, s>>>(a); break;
+        default: k_external_tiled<48, 16><<<nb, tile::kThreads, 0, s>>>(a); break;
+    }
+}
+
 bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s) {
     const int L = t->lmax;
     const int D = w->D;

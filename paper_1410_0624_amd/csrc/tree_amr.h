@@ -52,6 +52,8 @@ struct AmrSweepArgs {
     const float* w[5];
     int len[5];
     const float* kloc;
+    const float* gloc;     // [D][8] internal + local chord by crossed-axis set (mirrored rays)
+    const int32_t* sgn;    // [D] sign bits of u
     const float* q[CD_MAX_LEVEL + 1];  // coarse tables of levels 2 .. qtop, 216 codes
     int qtop;
     int qcompact;  // Q_qtop holds only the 64 codes of dl = 4 (qtop == Lmax - 4)
@@ -59,7 +61,9 @@ struct AmrSweepArgs {
     int8_t dl4[4];
     double box;
     int D;
-    const float* E;  // [n_tg][D] shells dl = 1..3 computed by the split kernel, or nullptr
+    const float* E;        // shells dl = 1..3 computed by a tiled or split kernel, or nullptr
+    const int64_t* erow;   // row of E per target (-1: lists), or nullptr: row g
+    int all_rows;          // every target has a row of E (no -1 in erow)
     float* N;
     float* chi;
     float chi_scale;

@@ -56,6 +56,7 @@ CASES = [
     (7, 2, 30.0, 6, "healpix1"),   # shells dl >= 4 at level 3 > base: automaton, then the level-2 table
     (6, 1, 14.0, 7, "axes6"),      # base 2^1, no coarse table at all
     (8, 3, 60.0, 8, "healpix1"),   # five refined levels above an 8^3 base
+    (7, 5, 30.0, 7, "healpix2"),   # base 32^3: tiled shells on the active tiles of levels 5 .. 7
 ]
 DIRS = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2), "axes6": oracle.dirs_axes6()}
 

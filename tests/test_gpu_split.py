@@ -72,31 +72,36 @@ def test_split_c2_256_sampled(colden, pname):
     assert err.max() <= LN_GATE
 
 
-@pytest.mark.parametrize("Lf,B,th,seed,dname", [(6, 3, 14.0, 5, "healpix1"), (7, 4, 30.0, 5, "healpix2"),
-                                                (7, 2, 30.0, 6, "healpix1")])
-def test_split_amr_all_leaves(colden, Lf, B, th, seed, dname):
+@pytest.mark.parametrize("pname,Lf,B,th,seed,dname", [
+    # base level < 5: targets gathered group by group (bf16 only)
+    ("bf16x2", 6, 3, 14.0, 5, "healpix1"), ("bf16x2", 7, 4, 30.0, 5, "healpix2"), ("bf16x2", 7, 2, 30.0, 6, "healpix1"),
+    # base level >= 5: the tiled kernel on the active tiles of every level
+    ("bf16x2", 7, 5, 30.0, 7, "healpix2"), ("fp16x2", 7, 5, 30.0, 7, "healpix2"),
+    ("fp16x2", 7, 6, 14.0, 8, "healpix1")])
+def test_split_amr_all_leaves(colden, pname, Lf, B, th, seed, dname):
     tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, seed), B, th, 10 * synth.PC_CM)
     dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2)}[dname]
-    N, chi = _run(colden, tin, dirs, 1)
+    N, chi = _run(colden, tin, dirs, PREC[pname])
     ref = oracle.Tree(tin).columns(dirs)
     err = _lnerr(N, ref)
-    print(f"bf16x2 AMR {Lf}/{B}/{th} {dname}: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    print(f"{pname} AMR {Lf}/{B}/{th} {dname}: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
     assert err.max() <= LN_GATE
     assert np.abs(chi - oracle.screening(ref)).max() <= 1e-3
 
 
-def test_split_c3_amr_sampled(colden):
-    """The AMR workload (128^3 base + 2 levels, D = 48) in bf16 x 2."""
+@pytest.mark.parametrize("pname", ["bf16x2", "fp16x2"])
+def test_split_c3_amr_sampled(colden, pname):
+    """The AMR workload (128^3 base + 2 levels, D = 48) in both split forms."""
     tin = synth.workload_amr()
     dirs = oracle.dirs_healpix(2)
-    N, _ = _run(colden, tin, dirs, 1, chi=False)
+    N, _ = _run(colden, tin, dirs, PREC[pname], chi=False)
     assert np.isfinite(N).all() and (N > 0).all()
     rng = np.random.default_rng(2)
     tg = np.concatenate([rng.choice(np.nonzero(tin.leaf_level == l)[0], 8000, replace=False)
                          for l in range(tin.base_level, tin.max_level + 1)])
     ref = oracle.Tree(tin).columns(dirs, tg)
     err = _lnerr(N[tg], ref)
-    print(f"bf16x2 C3 sampled: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    print(f"{pname} C3 sampled: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
     assert err.max() <= LN_GATE
 
 
@@ -133,7 +138,7 @@ def test_c4_512_all_forms_sampled(colden):
 
 def test_split_unsupported_cases(colden):
     dev = torch.device("cuda:0")
-    # binary16 on an adaptive tree (no LDS tile to scale)
+    # binary16 on an adaptive tree with base level < 5 (no 16^3-oct tile to scale)
     tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
     tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
     w = colden.Weights(oracle.dirs_healpix(1), precision=2)
