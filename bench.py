@@ -99,7 +99,7 @@ def main():
     ap.add_argument("--no-forms", action="store_true", help="skip timing the other precision forms")
     ap.add_argument("--cpu-sample-octs", type=int, default=2097152,
                     help="uniform grids: octs timed with the CPU oracle (bounded sample)")
-    ap.add_argument("--cpu-sample-leaves", type=int, default=100000,
+    ap.add_argument("--cpu-sample-leaves", type=int, default=400000,
                     help="adaptive tree: leaves timed with the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--copy-reference", action="store_true",
