@@ -306,9 +306,8 @@ int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w
  * entirely with the method (N and chi).  Writes the number of such tiles and
  * of all tiles, and the largest sampled relative chi error (may be NULL).
  * When more than a quarter of the tiles fail, the method runs once over the
- * whole grid into a scratch copy held by the handle (n_leaf (D + 1) floats)
- * and the failing tiles are copied from it.  Synchronises the stream (the
- * host picks the tiles).
+ * whole grid straight into N_dev and chi_dev instead, so every tile then holds
+ * the method's values.  Synchronises the stream (the host picks the tiles).
  * Errors: CD_EINVAL (frac outside (0, 1], tree not uniform, w not FP32),
  * CD_ENOMEM, CD_EDEVICE. */
 int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* tree, const cd_weights* w, double frac, double tol_chi,

@@ -569,8 +569,6 @@ struct cd_surrogate {
     int64_t* cells = nullptr;  // [cap] scratch index list
     float* colpart = nullptr;  // [kColChunks][max(W, D)] column-sum partials
     float* Y7 = nullptr;       // [2^21][D] network rows of the level-7 cells (inference)
-    float* Nplain = nullptr;   // [n_leaf][D] + [n_leaf] the method's columns and chi (fallback)
-    size_t nplain_bytes = 0;
     uint16_t* Wt = nullptr;    // transposed bfloat16 weights for the inference GEMM
 };
 
@@ -808,8 +806,7 @@ extern "C" void cd_surrogate_destroy(cd_surrogate* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     free_scratch(s);
-    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt,
-                    (void*)s->Nplain})
+    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -1116,21 +1113,6 @@ __global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__
     put_oct(info, src, out, k, L, 4 * tx + (o & 3), 4 * ty + ((o >> 2) & 3), 4 * tz + (o >> 4), 8, 0);
 }
 
-// rows of N and chi of every leaf of the listed 8^3 tiles, from src to dst
-__global__ void k_copy_tiles(const int64_t* __restrict__ tiles, int64_t nfail, int L, int64_t tpa, int D,
-                             const float* __restrict__ srcN, const float* __restrict__ srcChi, float* __restrict__ N,
-                             float* __restrict__ chi) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nfail * 512) return;
-    const int64_t tl = tiles[k >> 9];
-    const int o = (int)(k & 511);
-    const int64_t tx = tl % tpa, ty = (tl / tpa) % tpa, tz = tl / (tpa * tpa);
-    const int64_t n = (int64_t)1 << L;
-    const int64_t q = ((8 * tz + (o >> 6)) * n + 8 * ty + ((o >> 3) & 7)) * n + 8 * tx + (o & 7);
-    for (int d = 0; d < D; ++d) N[q * D + d] = srcN[q * D + d];
-    chi[q] = srcChi[q];
-}
-
 namespace cd {
 int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
 }
@@ -1215,24 +1197,10 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
         }
         CD_HIP(hipMemcpyAsync(dfail, fail.data(), nfail * 8, hipMemcpyHostToDevice, st));
         if (nfail * 4 > nt) {
-            // many tiles: one tiled sweep of the whole grid into scratch, then
-            // the failing tiles' rows (cheaper than the per-oct kernel there)
-            const size_t bytes = (size_t)t->n_leaf * (w->D + 1) * 4;
-            if (s->nplain_bytes < bytes) {
-                if (s->Nplain) (void)hipFree(s->Nplain);
-                s->Nplain = nullptr;
-                s->nplain_bytes = 0;
-                if (hipMalloc((void**)&s->Nplain, bytes) != hipSuccess) {
-                    set_error("hipMalloc of %zu bytes (fallback columns) failed", bytes);
-                    return CD_ENOMEM;
-                }
-                s->nplain_bytes = bytes;
-            }
-            float* pchi = s->Nplain + (size_t)t->n_leaf * w->D;
-            if ((rc = uniform_columns(t, w, s->Nplain, pchi, cs, st)) != CD_OK) return rc;
-            k_copy_tiles<<<nblk(nfail * 512), 256, 0, st>>>(dfail, nfail, L, tpa, w->D, s->Nplain, pchi, N_dev,
-                                                            chi_dev);
-            CD_HIP(hipGetLastError());
+            // many tiles: one tiled sweep of the whole grid, straight into N
+            // and chi (cheaper than the per-oct kernel on the failing tiles;
+            // the passing tiles then hold the method's values too)
+            if ((rc = uniform_columns(t, w, N_dev, chi_dev, cs, st)) != CD_OK) return rc;
             CD_HIP(hipStreamSynchronize(st));
         } else {
             OctLists fl;

@@ -230,6 +230,24 @@ def test_zero_tolerance_falls_back_everywhere(colden, trained):
     assert rel <= 1e-5
 
 
+def test_many_failing_tiles_take_the_whole_grid_route(colden, trained):
+    """An untrained network fails the check on most tiles: the method then
+    sweeps the whole grid into N and chi, which equal the plain sweep's."""
+    _, w, nrm, _, _, runs = trained
+    tree, leaf, N, chi = runs[0]
+    s = colden.Surrogate(w.D, 256, colden.CD_SURR_BF16, 5, norm=nrm)
+    Ns = torch.empty_like(N)
+    chis = torch.empty_like(chi)
+    s.infer(tree, w, Ns, chis)
+    nf, nt, _ = s.check_fallback(tree, w, Ns, chis, frac=0.01, tol_chi=0.03, seed=3)
+    torch.cuda.synchronize()
+    print(f"untrained: fallback {nf}/{nt} tiles")
+    assert 4 * nf > nt
+    assert (torch.abs(Ns - N) / N).max().item() <= 1e-5
+    assert (torch.abs(chis - chi) / chi).max().item() <= 1e-5
+    s.close()
+
+
 def test_save_load_round_trip(colden, trained):
     s = trained[0]
     with tempfile.TemporaryDirectory() as d:
