@@ -30,7 +30,8 @@
  *    the x, y, z child bits) skipping refined ones.  A uniform 2^L grid
  *    (base_level == max_level) is plain row-major order.
  *  - Densities are in cm^-3, columns in cm^-2; densities must be finite and
- *    >= 0 (not checked on the device).
+ *    >= 0: cd_build_tree checks them (CD_EINVAL), cd_tree_update does not
+ *    (cd_check_densities counts the offending entries of any buffer).
  *  - Boundary: non-periodic; no matter outside the box.
  */
 #ifndef COLDEN_H
@@ -108,13 +109,21 @@ int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D)
  *                    tree copies the leaves.
  *   n_leaf           number of leaves implied by the structure.
  * The structure is copied; the pyramid is built on `stream`.  Device
- * memory for the pyramid and the index maps is owned by the handle.
- * Errors: CD_EINVAL (malformed structure, wrong n_leaf), CD_ENOMEM,
- * CD_EDEVICE.
+ * memory for the pyramid and the index maps is owned by the handle.  The
+ * leaf densities are checked (finite, >= 0), which synchronises `stream`.
+ * Errors: CD_EINVAL (malformed structure, wrong n_leaf, a density that is
+ * negative, NaN or infinite), CD_ENOMEM, CD_EDEVICE.
  */
 int cd_build_tree(double box_cm, int base_level, int max_level,
                   const int64_t* n_octs, const int32_t* const* oct_parents,
                   const float* leaf_n_dev, int64_t n_leaf, void* stream, cd_tree** out);
+
+/* Number of entries of leaf_n_dev[n_leaf] (device float) that are
+ * negative, NaN or infinite, written to *n_invalid; -0.0 and subnormal
+ * values are valid.  Synchronises `stream`.
+ * Errors: CD_EINVAL (NULL n_invalid, n_leaf < 0, NULL buffer with n_leaf >
+ * 0), CD_ENOMEM, CD_EDEVICE. */
+int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid, void* stream);
 
 /* New leaf densities for an existing structure (one hydro step later):
  * rebuilds the pyramid on `stream`.  Same layout and lifetime rules as

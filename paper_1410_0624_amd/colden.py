@@ -22,7 +22,7 @@ EXPORTS = [
     "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
     "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
-    "cd_profile_enable", "cd_profile_read",
+    "cd_profile_enable", "cd_profile_read", "cd_check_densities",
 ]
 STAGES = ["pyramid", "coarse", "external", "rows", "sweep"]
 
@@ -62,6 +62,7 @@ def lib():
         L.cd_screening_factor.argtypes = [P, I64, I, D, D, P, P, P]
         L.cd_profile_enable.argtypes = [P, I]
         L.cd_profile_read.argtypes = [P, P]
+        L.cd_check_densities.argtypes = [P, I64, P, P]
         _lib = L
     return _lib
 
@@ -184,6 +185,14 @@ def column_densities(tree: Tree, w: Weights, N, chi=None, av_per_nh: float = AV_
     chip = _dev_f32(chi) if chi is not None else None
     _check(lib().cd_column_densities(tree.h, w.h, _dev_f32(N), chip, av_per_nh, gamma, _stream(stream)))
     return N
+
+
+def check_densities(leaf_n, stream=None) -> int:
+    """Number of entries of a float32 CUDA tensor that are negative, NaN or
+    infinite (synchronises the stream)."""
+    bad = C.c_int64(0)
+    _check(lib().cd_check_densities(_dev_f32(leaf_n), int(leaf_n.numel()), C.byref(bad), _stream(stream)))
+    return bad.value
 
 
 def screening_factor(N, chi, av=None, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):

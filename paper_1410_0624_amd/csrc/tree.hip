@@ -1,5 +1,6 @@
 // Tree construction: the pyramid of coarse densities (Sect. 3: a refined cell
 // holds the mean of its 8 children) stored as zero-padded dense levels.
+#include <algorithm>
 #include <cstring>
 
 #include "cd_internal.h"
@@ -11,6 +12,45 @@ static inline int64_t padded_side(int l) { return ((int64_t)1 << l) + 2 * kHalo;
 static inline int64_t padded_cells(int l) {
     int64_t s = padded_side(l);
     return s * s * s;
+}
+
+// Number of entries that are negative, NaN or infinite (grid-stride, one
+// atomic per wave that found any).
+__global__ void k_count_invalid(const float* __restrict__ v, int64_t n, unsigned long long* __restrict__ count) {
+    unsigned int c = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = v[i];
+        c += (x >= 0.f && x <= 3.402823466e38f) ? 0u : 1u;  // NaN fails both comparisons
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_down(c, off);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
+}
+
+int count_invalid(const float* v, int64_t n, int64_t* out, hipStream_t s) {
+    *out = 0;
+    if (n <= 0) return CD_OK;
+    unsigned long long* d = nullptr;
+    if (hipMalloc((void**)&d, sizeof(unsigned long long)) != hipSuccess) {
+        set_error("hipMalloc of the density-check counter failed");
+        return CD_ENOMEM;
+    }
+    unsigned long long h = 0;
+    hipError_t e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) {
+        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+        k_count_invalid<<<(unsigned)blocks, 256, 0, s>>>(v, n, d);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) {
+        set_error("density check: %s", hipGetErrorString(e));
+        return CD_EDEVICE;
+    }
+    *out = (int64_t)h;
+    return CD_OK;
 }
 
 // Level L-1 from the leaves of a uniform 2^L grid (row-major, x fastest).
@@ -148,12 +188,30 @@ extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const
         t->uniform = false;
         rc = cd::amr_build(t, n_octs, oct_parents, leaf_n_dev, n_leaf, s);
     }
+    if (rc == CD_OK) {
+        // densities must be finite and >= 0 (Sect. 3: n in cm^-3)
+        int64_t bad = 0;
+        rc = cd::count_invalid(leaf_n_dev, n_leaf, &bad, s);
+        if (rc == CD_OK && bad > 0) {
+            cd::set_error("cd_build_tree: %lld leaf densities are negative, NaN or infinite", (long long)bad);
+            rc = CD_EINVAL;
+        }
+    }
     if (rc != CD_OK) {
         cd_tree_destroy(t);
         return rc;
     }
     *out = t;
     return CD_OK;
+}
+
+extern "C" int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid, void* stream) {
+    cd::clear_error();
+    if (!n_invalid || n_leaf < 0 || (n_leaf > 0 && !leaf_n_dev)) {
+        cd::set_error("cd_check_densities: NULL argument or n_leaf %lld < 0", (long long)n_leaf);
+        return CD_EINVAL;
+    }
+    return cd::count_invalid(leaf_n_dev, n_leaf, n_invalid, (hipStream_t)stream);
 }
 
 extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, void* stream) {

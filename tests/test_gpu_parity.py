@@ -162,6 +162,35 @@ def test_screening_factor_kernel(colden):
     colden.screening_factor(Nt[:0], chi[:0])
 
 
+def test_invalid_densities_are_rejected(colden):
+    """Negative, NaN or infinite leaf densities: cd_build_tree returns
+    CD_EINVAL (uniform and AMR); cd_check_densities counts them exactly;
+    -0.0 and subnormals are valid."""
+    dev = torch.device("cuda:0")
+    tin = synth.workload_uniform(5, seed=2)
+    base = torch.from_numpy(tin.leaf_n).to(dev)
+    assert colden.check_densities(base) == 0
+    for bad in (float("nan"), -1e-30, float("inf"), float("-inf")):
+        leaf = base.clone()
+        leaf[[7, 4000, 32767]] = bad
+        assert colden.check_densities(leaf) == 3
+        with pytest.raises(colden.ColdenError) as e:
+            colden.Tree(tin, leaf)
+        assert e.value.rc == colden.CD_EINVAL
+    ok = base.clone()
+    ok[0] = -0.0
+    ok[1] = 1e-44  # subnormal
+    assert colden.check_densities(ok) == 0
+    colden.Tree(tin, ok)
+    assert colden.check_densities(ok[:0]) == 0
+    tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    leaf[tin.n_leaf - 1] = float("nan")
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Tree(tin, leaf)
+    assert e.value.rc == colden.CD_EINVAL
+
+
 def test_error_paths(colden):
     with pytest.raises(colden.ColdenError) as e:
         colden.Weights(np.zeros((0, 3)))
