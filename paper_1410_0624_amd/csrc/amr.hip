@@ -200,7 +200,7 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
                 if ((m & allowed) == m) s = fmaf(ln[c ^ m], G[m], s);
             const float v = fmaf(dxL, s, acc);
             if (live && valid) a.N[leaf * a.D + d] = v;
-            if (live) chis[c] += expf(-a.chi_scale * v);
+            if (live) chis[c] += __expf(-a.chi_scale * v);
         }
     }
     if (a.chi) {

@@ -75,6 +75,7 @@ struct FeatArgs {
     const int64_t* cells;  // leaf indices, or nullptr: c0 + i
     int64_t c0, n;
     int l7rows;            // rows are level-7 cells c0 + i (x fastest), read through their first leaf
+    int logged;            // lev[l] (every l) are padded arrays of the finished scaled feature values
     float shift, inv_scale;
 };
 
@@ -111,6 +112,11 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
                   pz = 2 * (z >> sh) - 1 + (s >> 4);
     const int64_t nl = (int64_t)1 << l;
     const float* lev = a.lev[l];
+    if (a.logged) {  // the zero halo's value covers -1 and 2^l
+        const int64_t S = nl + 2 * kHalo;
+        X[idx] = from_f<T>(lev[((pz + kHalo) * S + (py + kHalo)) * S + (px + kHalo)]);
+        return;
+    }
     float v = 0.f;
     if (l < L) {  // padded level: the zero halo covers -1 and 2^l
         const int64_t S = nl + 2 * kHalo;
@@ -119,6 +125,24 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
         v = lev[(pz * nl + py) * nl + px];
     }
     X[idx] = from_f<T>((logf(fmaxf(v, kFloor)) - a.shift) * a.inv_scale);
+}
+
+// Scaled feature value (ln max(n, floor) - shift) / scale of every cell of a
+// padded level, halo included (zero density there); src is the padded
+// pyramid level, or (padded_src == 0) the unpadded leaves of level l.
+__global__ void k_log_level(const float* __restrict__ src, int l, int padded_src, float shift, float inv_scale,
+                            float* __restrict__ dst) {
+    const int64_t n = (int64_t)1 << l, S = n + 2 * kHalo;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= S * S * S) return;
+    float v;
+    if (padded_src) {
+        v = src[idx];
+    } else {
+        const int64_t i = idx % S - kHalo, j = (idx / S) % S - kHalo, k = idx / (S * S) - kHalo;
+        v = (i >= 0 && j >= 0 && k >= 0 && i < n && j < n && k < n) ? src[(k * n + j) * n + i] : 0.f;
+    }
+    dst[idx] = (logf(fmaxf(v, kFloor)) - shift) * inv_scale;
 }
 
 template <typename T>
@@ -386,9 +410,9 @@ __global__ void k_output(const IlArgs il, const float* __restrict__ Y7, int64_t 
     const OctCells oc = oct_cells(il, i);
     float c = 0.f;
     for (int d = 0; d < D; ++d) {
-        const float v = internal_local(il, oc, d) + fmaxf(expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
+        const float v = internal_local(il, oc, d) + fmaxf(__expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
         N[i * D + d] = v;
-        c += expf(-chi_scale * v);
+        c += __expf(-chi_scale * v);
     }
     if (chi) chi[i] = c / (float)D;
 }
@@ -419,9 +443,9 @@ __global__ __launch_bounds__(256) void k_output_tiled(const IlArgs il, const flo
         float acc = 0.f;
 #pragma unroll
         for (int s2 = 0; s2 < 8; ++s2) acc = fmaf(oc.n[s2], ko[s2 * D + d], acc);
-        const float v = il.dxL * acc + fmaxf(expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
+        const float v = il.dxL * acc + fmaxf(__expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
         st[threadIdx.x * D + d] = v;
-        c += expf(-chi_scale * v);
+        c += __expf(-chi_scale * v);
     }
     if (chi) chi[i] = c / (float)D;
     __syncthreads();
@@ -440,12 +464,28 @@ constexpr int kFT = 128, kFK = 32, kFP = 40;
 
 __global__ __launch_bounds__(256) void k_gemm_bf16_nt(const uint16_t* __restrict__ A, const uint16_t* __restrict__ Bt,
                                                       const float* __restrict__ bias, int relu, uint16_t* __restrict__ C16,
-                                                      float* __restrict__ C32, int64_t ldc, int n_valid, int K) {
+                                                      float* __restrict__ C32, int64_t ldc, int n_valid, int K,
+                                                      int ntn) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kFT][kFP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kFT][kFP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * kFT;
-    const int n0 = blockIdx.y * kFT;
+    // 1-D grid of (row tile, column tile): the ntn column tiles of one row
+    // tile get ids 8 apart, so they run on the same XCD (workgroups are
+    // dealt to the 8 XCDs in turn) at about the same time and the second
+    // reads its A panel from that XCD's L2; row-tile counts that are not a
+    // multiple of 8 take the plain order
+    const int64_t id = blockIdx.x;
+    const int64_t mtiles = (int64_t)gridDim.x / ntn;
+    int64_t mt, nt;
+    if (mtiles % 8 == 0) {
+        mt = (id / (8 * ntn)) * 8 + (id & 7);
+        nt = (id >> 3) % ntn;
+    } else {
+        mt = id / ntn;
+        nt = id % ntn;
+    }
+    const int64_t m0 = mt * kFT;
+    const int n0 = (int)nt * kFT;
     const int wm = (wave & 1) * 64, wn = (wave >> 1) * 64;
     const int r = lane & 15, g = lane >> 4;
     // this thread's two 16-byte pieces of each operand tile
@@ -552,6 +592,8 @@ struct cd_surrogate {
     // batch scratch
     int64_t cap = 0;
     void* X = nullptr;     // [cap][576] storage type
+    float* lpyr = nullptr; // scaled feature values of padded levels 0..8 (inference)
+    size_t lpyr_bytes = 0;
     float* A1 = nullptr;   // [cap][W] FP32 activations (masks)
     float* A2 = nullptr;
     void* A1l = nullptr;   // storage-type copies
@@ -679,12 +721,13 @@ static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float*
     uint16_t* W1t = s->Wt;
     uint16_t* W2t = W1t + (int64_t)W * kFeat;
     uint16_t* W3t = W2t + (int64_t)W * W;
-    dim3 g1((unsigned)(n / kFT), (unsigned)(W / kFT));
-    k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat);
+    const int ntn = W / kFT;
+    const unsigned g1 = (unsigned)(n / kFT * ntn);
+    k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat, ntn);
     k_gemm_bf16_nt<<<g1, 256, 0, st>>>((const uint16_t*)s->A1l, W2t, s->P + s->off[3], 1, (uint16_t*)s->A2l, nullptr,
-                                       W, W, W);
-    dim3 g3((unsigned)(n / kFT), 1);
-    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W);
+                                       W, W, W, ntn);
+    const unsigned g3 = (unsigned)(n / kFT);
+    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W, 1);
 }
 
 // Loss, gradient into s->G (targets in s->Tg, activations kept).
@@ -806,7 +849,8 @@ extern "C" void cd_surrogate_destroy(cd_surrogate* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     free_scratch(s);
-    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt})
+    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt,
+                    (void*)s->lpyr})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -975,6 +1019,35 @@ static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, fl
     }
     FeatArgs a = feat_args(s, t);
     a.l7rows = 1;
+    {
+        // every row reads the same pyramid cells many times (a level-l
+        // stencil serves the 8^(8-l) rows below its centre): take the
+        // logarithms once per cell instead of once per feature
+        size_t total = 0;
+        int64_t off[kFeatLevels];
+        for (int l = 0; l < kFeatLevels; ++l) {
+            const int64_t S = ((int64_t)1 << l) + 2 * kHalo;
+            off[l] = (int64_t)total;
+            total += (size_t)(S * S * S);
+        }
+        if (s->lpyr_bytes < total * 4) {
+            if (s->lpyr) (void)hipFree(s->lpyr);
+            s->lpyr = nullptr;
+            s->lpyr_bytes = 0;
+            if (hipMalloc((void**)&s->lpyr, total * 4) != hipSuccess) {
+                set_error("hipMalloc of %zu bytes (feature pyramid) failed", total * 4);
+                return CD_ENOMEM;
+            }
+            s->lpyr_bytes = total * 4;
+        }
+        for (int l = 0; l < kFeatLevels; ++l) {
+            const int64_t S = ((int64_t)1 << l) + 2 * kHalo;
+            k_log_level<<<nblk(S * S * S), 256, 0, st>>>(a.lev[l], l, l < t->lmax ? 1 : 0, a.shift, a.inv_scale,
+                                                          s->lpyr + off[l]);
+            a.lev[l] = s->lpyr + off[l];
+        }
+        a.logged = 1;
+    }
     for (int64_t c0 = 0; c0 < rows; c0 += batch) {
         a.c0 = c0;
         a.n = batch;
@@ -1049,19 +1122,21 @@ struct OctLists {
     int32_t* info = nullptr;
     int64_t* src = nullptr;
     int64_t* out = nullptr;
+    int64_t* erow = nullptr;  // row-major oct index (the row of the uniform grid's E), when wanted
     int64_t n = 0;
-    int alloc(int64_t count) {
+    int alloc(int64_t count, bool with_erow = false) {
         n = count;
         if (count == 0) return CD_OK;
         if (hipMalloc((void**)&info, count * 16) != hipSuccess || hipMalloc((void**)&src, count * 64) != hipSuccess ||
-            hipMalloc((void**)&out, count * 64) != hipSuccess) {
+            hipMalloc((void**)&out, count * 64) != hipSuccess ||
+            (with_erow && hipMalloc((void**)&erow, count * 8) != hipSuccess)) {
             set_error("hipMalloc of %lld target octs failed", (long long)count);
             return CD_ENOMEM;
         }
         return CD_OK;
     }
     ~OctLists() {
-        for (void* p : {(void*)info, (void*)src, (void*)out})
+        for (void* p : {(void*)info, (void*)src, (void*)out, (void*)erow})
             if (p) (void)hipFree(p);
     }
 };
@@ -1073,9 +1148,11 @@ __device__ __forceinline__ uint64_t d_splitmix64(uint64_t x) {
     return x ^ (x >> 31);
 }
 
-__device__ __forceinline__ void put_oct(int32_t* info, int64_t* src, int64_t* out, int64_t k, int L, int64_t ox,
-                                        int64_t oy, int64_t oz, int want /* child octant, or 8: all */, int64_t row) {
+__device__ __forceinline__ void put_oct(int32_t* info, int64_t* src, int64_t* out, int64_t* erow, int64_t k, int L,
+                                        int64_t ox, int64_t oy, int64_t oz, int want /* child octant, or 8: all */,
+                                        int64_t row) {
     const int64_t n = (int64_t)1 << L;
+    if (erow) erow[k] = (((oz << (L - 1)) + oy) << (L - 1)) + ox;
     info[4 * k] = L;
     info[4 * k + 1] = (int32_t)ox;
     info[4 * k + 2] = (int32_t)oy;
@@ -1090,7 +1167,7 @@ __device__ __forceinline__ void put_oct(int32_t* info, int64_t* src, int64_t* ou
 // sample j of tile tl (tiles of 8^3 leaves, tpa per axis): a leaf drawn from
 // the seed, its oct as a target writing row tl * per + j
 __global__ void k_make_samples(int L, int64_t tpa, int per, uint64_t seed, int64_t ns, int32_t* info, int64_t* src,
-                               int64_t* out, int64_t* cells) {
+                               int64_t* out, int64_t* erow, int64_t* cells) {
     const int64_t si = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (si >= ns) return;
     const int64_t tl = si / per, j = si % per;
@@ -1099,27 +1176,39 @@ __global__ void k_make_samples(int L, int64_t tpa, int per, uint64_t seed, int64
     const int64_t x = 8 * tx + (int64_t)(r & 7), y = 8 * ty + (int64_t)((r >> 3) & 7), z = 8 * tz + (int64_t)((r >> 6) & 7);
     const int64_t n = (int64_t)1 << L;
     cells[si] = (z * n + y) * n + x;
-    put_oct(info, src, out, si, L, x >> 1, y >> 1, z >> 1, (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)), si);
+    put_oct(info, src, out, erow, si, L, x >> 1, y >> 1, z >> 1, (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2)), si);
 }
 
 // every oct (64 per tile) of the listed tiles, all 8 leaves written in place
 __global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__ tiles, int64_t nfail, int32_t* info,
-                                 int64_t* src, int64_t* out) {
+                                 int64_t* src, int64_t* out, int64_t* erow) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nfail * 64) return;
     const int64_t tl = tiles[k >> 6];
     const int o = (int)(k & 63);
     const int64_t tx = tl % tpa, ty = (tl / tpa) % tpa, tz = tl / (tpa * tpa);
-    put_oct(info, src, out, k, L, 4 * tx + (o & 3), 4 * ty + ((o >> 2) & 3), 4 * tz + (o >> 4), 8, 0);
+    put_oct(info, src, out, erow, k, L, 4 * tx + (o & 3), 4 * ty + ((o >> 2) & 3), 4 * tz + (o >> 4), 8, 0);
 }
 
 namespace cd {
 int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
+int ensure_ext(cd_tree* t, int D);                                                                          // sweep.hip
+bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
+bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);                            // sweep_rows.hip
 }
 
+// The method on listed octs; E != nullptr: the grid's external columns
+// (shells dl = 1..3) are already in E, row ol.erow[k] for oct k.
 static void run_octs(const cd_tree* t, const cd_weights* w, float chi_scale, const OctLists& ol, float* N, float* chi,
-                     hipStream_t st) {
+                     hipStream_t st, const float* E = nullptr) {
     AmrSweepArgs a = uniform_oct_args(t, w, chi_scale);
+    if (E) {
+        a.E = E;
+        a.erow = ol.erow;
+        a.all_rows = 1;
+    }
     a.tg_info = ol.info;
     a.tg_src = ol.src;
     a.tg_leaf = ol.out;
@@ -1142,16 +1231,25 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     hipStream_t st = (hipStream_t)stream;
     const float cs = (float)(gamma * av_per_nh);
     const int L = t->lmax;
-    // coarse tables of the method (shells dl >= 4)
+    // coarse tables of the method (shells dl >= 4) and, where the tiled
+    // kernels take this direction set, the external columns E of every oct:
+    // the samples and the fallback then read their shells dl = 1..3 from E
     int rc = ensure_q(t, w->D, L - 4, true);
     if (rc != CD_OK) return rc;
     launch_coarse(t, w, L - 4, true, st);
+    const bool tiled = tiled_supported(t, w);
+    const float* E = nullptr;
+    if (tiled) {
+        if ((rc = ensure_ext(t, w->D)) != CD_OK) return rc;
+        launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), st);
+        E = t->ext;
+    }
     // samples: ceil(frac * 512) leaves per tile of 8^3
     const int64_t tpa = ((int64_t)1 << L) / 8, nt = tpa * tpa * tpa;
     const int per = (int)std::ceil(frac * 512.0 - 1e-9);
     const int64_t ns = nt * per;
     OctLists sl;
-    if ((rc = sl.alloc(ns)) != CD_OK) return rc;
+    if ((rc = sl.alloc(ns, tiled)) != CD_OK) return rc;
     float *sN = nullptr, *sChi = nullptr, *err = nullptr;
     int64_t* cells = nullptr;
     struct Free {
@@ -1170,8 +1268,8 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
         set_error("hipMalloc of the check samples failed");
         return CD_ENOMEM;
     }
-    k_make_samples<<<nblk(ns), 256, 0, st>>>(L, tpa, per, seed, ns, sl.info, sl.src, sl.out, cells);
-    run_octs(t, w, cs, sl, sN, sChi, st);
+    k_make_samples<<<nblk(ns), 256, 0, st>>>(L, tpa, per, seed, ns, sl.info, sl.src, sl.out, sl.erow, cells);
+    run_octs(t, w, cs, sl, sN, sChi, st, E);
     k_sample_err<<<nblk(ns), 256, 0, st>>>(chi_dev, cells, ns, sChi, err);
     std::vector<float> e((size_t)ns);
     CD_HIP(hipMemcpyAsync(e.data(), err, ns * 4, hipMemcpyDeviceToHost, st));
@@ -1197,16 +1295,24 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
         }
         CD_HIP(hipMemcpyAsync(dfail, fail.data(), nfail * 8, hipMemcpyHostToDevice, st));
         if (nfail * 4 > nt) {
-            // many tiles: one tiled sweep of the whole grid, straight into N
-            // and chi (cheaper than the per-oct kernel on the failing tiles;
-            // the passing tiles then hold the method's values too)
-            if ((rc = uniform_columns(t, w, N_dev, chi_dev, cs, st)) != CD_OK) return rc;
+            // many tiles: the method over the whole grid, straight into N
+            // and chi (the passing tiles then hold the method's values too);
+            // with E in hand only the target rows remain
+            if (E) {
+                if (!launch_target_rows(t, w, E, N_dev, chi_dev, cs, 0, (int64_t)1 << L, st)) {
+                    set_error("cd_surrogate_check_fallback: the target-row kernel does not take D = %d", w->D);
+                    return CD_EUNSUPPORTED;
+                }
+            } else if ((rc = uniform_columns(t, w, N_dev, chi_dev, cs, st)) != CD_OK) {
+                return rc;
+            }
+            CD_HIP(hipGetLastError());
             CD_HIP(hipStreamSynchronize(st));
         } else {
             OctLists fl;
-            if ((rc = fl.alloc(nfail * 64)) != CD_OK) return rc;
-            k_make_tile_octs<<<nblk(nfail * 64), 256, 0, st>>>(L, tpa, dfail, nfail, fl.info, fl.src, fl.out);
-            run_octs(t, w, cs, fl, N_dev, chi_dev, st);
+            if ((rc = fl.alloc(nfail * 64, tiled)) != CD_OK) return rc;
+            k_make_tile_octs<<<nblk(nfail * 64), 256, 0, st>>>(L, tpa, dfail, nfail, fl.info, fl.src, fl.out, fl.erow);
+            run_octs(t, w, cs, fl, N_dev, chi_dev, st, E);
             CD_HIP(hipGetLastError());
             CD_HIP(hipStreamSynchronize(st));  // lists are freed on return
         }

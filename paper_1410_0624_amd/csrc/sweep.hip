@@ -112,7 +112,7 @@ __global__ __launch_bounds__(256) void k_fine_uniform(const FineArgs a) {
                     for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(o * 8 + sb) * a.D + d], s);
                     const float v = fmaf(a.dxL, s, acc[j]);
                     out[d] = v;
-                    chis[o] += expf(-a.chi_scale * v);
+                    chis[o] += __expf(-a.chi_scale * v);
                 }
             }
         }
@@ -268,7 +268,7 @@ bool tiled_supported(const cd_tree* t, const cd_weights* w);
 bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
 
 // Per-oct external columns E[n_oct][D] owned by the tree.
-static int ensure_ext(cd_tree* t, int D) {
+int ensure_ext(cd_tree* t, int D) {
     const size_t bytes = ((size_t)1 << (3 * (t->lmax - 1))) * D * sizeof(float);
     if (t->ext_bytes >= bytes) return CD_OK;
     if (t->ext) (void)hipFree(t->ext);

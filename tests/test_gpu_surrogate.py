@@ -194,6 +194,31 @@ def test_training_lowers_the_loss_and_beats_baselines(colden, trained):
     assert np.percentile(e_tr, 99) < 0.5 * np.percentile(e_cst, 99)
 
 
+def test_infer_matches_features_and_forward(colden, trained):
+    """Inference (network once per level-7 cell on the logarithms taken once
+    per pyramid cell, then each leaf's output) equals, at sampled leaves,
+    the same network run row by row on cd_surrogate_features, plus the
+    oracle's internal + local part (Sect. 3.2)."""
+    s, w, nrm, _, _, _ = trained
+    tin = _field(122)
+    tree, leaf, N, chi = _plain(colden, tin, w)
+    Ns = torch.empty_like(N)
+    s.infer(tree, w, Ns)
+    tg = np.random.default_rng(8).choice(tin.n_leaf, 3000, replace=False)
+    cells = torch.from_numpy(tg).to(DEV)
+    X = torch.empty((tg.size, 576), dtype=torch.float32, device=DEV)
+    s.features(tree, cells, X)
+    Y = torch.empty((tg.size, w.D), dtype=torch.float32, device=DEV)
+    s.forward(X, Y)
+    torch.cuda.synchronize()
+    nil = oracle.Tree(tin).internal_local(oracle.dirs_healpix(1), tg)
+    ref = S.columns_from_output(Y.cpu().numpy().astype(np.float64), nil, nrm[2], nrm[3])
+    got = Ns.cpu().numpy().astype(np.float64)[tg]
+    err = np.abs(np.log(got) - np.log(ref))
+    print(f"infer vs features + forward: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
+    assert err.max() <= 2e-3
+
+
 def test_check_and_fallback_meet_the_chi_gate(colden, trained):
     s, w, nrm, _, _, _ = trained
     tin = _field(121)
@@ -246,6 +271,38 @@ def test_many_failing_tiles_take_the_whole_grid_route(colden, trained):
     assert (torch.abs(Ns - N) / N).max().item() <= 1e-5
     assert (torch.abs(chis - chi) / chi).max().item() <= 1e-5
     s.close()
+
+
+def test_few_failing_tiles_take_the_per_tile_route(colden, trained):
+    """A loose tolerance leaves at most a quarter of the tiles failing: each
+    failing 8^3 tile is recomputed by the method (equal to the plain sweep),
+    every other tile keeps the network's values, and the counts agree."""
+    s, w, _, _, _, runs = trained
+    tree, leaf, N, chi = runs[1]
+    Ns0 = torch.empty_like(N)
+    chis0 = torch.empty_like(chi)
+    s.infer(tree, w, Ns0, chis0)
+    for tol in (0.3, 0.5, 1.0, 2.0, 5.0):
+        Ns, chis = Ns0.clone(), chis0.clone()
+        nf, nt, _ = s.check_fallback(tree, w, Ns, chis, frac=0.01, tol_chi=tol, seed=4)
+        if 0 < 4 * nf <= nt:
+            break
+    torch.cuda.synchronize()
+    print(f"tol {tol}: fallback {nf}/{nt} tiles")
+    assert 0 < 4 * nf <= nt
+    n = round(N.shape[0] ** (1 / 3))
+    t = n // 8
+
+    def tiles(a):  # [tiles][512 leaves][...]
+        a = a.reshape(t, 8, t, 8, t, 8, -1).permute(0, 2, 4, 1, 3, 5, 6)
+        return a.reshape(t ** 3, 512, -1)
+    new, old, plain = tiles(Ns), tiles(Ns0), tiles(N)
+    kept = (new == old).all(dim=2).all(dim=1)
+    redone = (torch.abs(new - plain) <= 1e-5 * plain).all(dim=2).all(dim=1)
+    assert bool((kept | redone).all())
+    assert int((~kept).sum()) <= nf <= int(redone.sum())
+    cn, cp = tiles(chis[:, None]), tiles(chi[:, None])
+    assert bool((torch.abs(cn - cp)[~kept] <= 1e-5 * cp[~kept]).all())
 
 
 def test_save_load_round_trip(colden, trained):
