@@ -127,6 +127,54 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
     X[idx] = from_f<T>((logf(fmaxf(v, kFloor)) - a.shift) * a.inv_scale);
 }
 
+// Features of 64 consecutive level-7 rows (x fastest, same y and z; c0 a
+// multiple of 64) from the padded arrays of scaled values (a.logged): each
+// level's stencil footprint of the 64 rows, 4 x 4 cells in y and z by
+// 4 .. 130 in x, is staged in LDS, then the rows' features are written out
+// contiguously (576 per row).
+constexpr int kFeatBlockRows = 64;
+constexpr int kFeatStage = 16 * (130 + 66 + 34 + 18 + 10 + 6 + 4 + 4 + 4);
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_features_rows(const FeatArgs a, T* __restrict__ X) {
+    __shared__ float stage[kFeatStage];
+    const int64_t m = (int64_t)1 << kRowLevel;
+    const int64_t r0 = a.c0 + (int64_t)blockIdx.x * kFeatBlockRows;
+    const int64_t X0 = r0 & (m - 1), Y = (r0 >> kRowLevel) & (m - 1), Z = r0 >> (2 * kRowLevel);
+    int off[kFeatLevels], width[kFeatLevels];
+    int64_t xb[kFeatLevels];
+    int o = 0;
+#pragma unroll
+    for (int l = 0; l < kFeatLevels; ++l) {
+        const int sh = kRowLevel + 1 - l;  // the row's ancestor at level l - 1: X >> sh
+        xb[l] = 2 * (X0 >> sh) - 1;
+        width[l] = (int)(2 * (((X0 + kFeatBlockRows - 1) >> sh) - (X0 >> sh)) + 4);
+        off[l] = o;
+        o += 16 * width[l];
+    }
+    for (int l = 0; l < kFeatLevels; ++l) {
+        const int sh = kRowLevel + 1 - l;
+        const int64_t nl = (int64_t)1 << l, S = nl + 2 * kHalo;
+        const int64_t yb = 2 * (Y >> sh) - 1, zb = 2 * (Z >> sh) - 1;
+        const float* lev = a.lev[l];
+        const int w = width[l];
+        for (int k = threadIdx.x; k < 16 * w; k += 256) {
+            const int lx = k % w, yz = k / w;  // yz = 4 sz + sy
+            const int64_t gx = xb[l] + lx, gy = yb + (yz & 3), gz = zb + (yz >> 2);
+            stage[off[l] + k] = lev[((gz + kHalo) * S + (gy + kHalo)) * S + (gx + kHalo)];
+        }
+    }
+    __syncthreads();
+    T* out = X + (r0 - a.c0) * kFeat;
+    for (int k = threadIdx.x; k < kFeatBlockRows * kFeat; k += 256) {
+        const int i = k / kFeat, f = k % kFeat;
+        const int l = f >> 6, sx = f & 3, sy = (f >> 2) & 3, sz = f >> 4 & 3;
+        const int sh = kRowLevel + 1 - l;
+        const int lx = (int)(2 * ((X0 + i) >> sh) - 1 + sx - xb[l]);
+        out[k] = from_f<T>(stage[off[l] + (4 * sz + sy) * width[l] + lx]);
+    }
+}
+
 // Scaled feature value (ln max(n, floor) - shift) / scale of every cell of a
 // padded level, halo included (zero density there); src is the padded
 // pyramid level, or (padded_src == 0) the unpadded leaves of level l.
@@ -993,6 +1041,11 @@ extern "C" int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* t, const 
     return CD_OK;
 }
 
+namespace cd {
+bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y7, float y_scale, float y_shift,
+                           float y_floor, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep_rows.hip
+}
+
 template <typename T>
 static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
                       hipStream_t st) {
@@ -1051,11 +1104,16 @@ static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, fl
     for (int64_t c0 = 0; c0 < rows; c0 += batch) {
         a.c0 = c0;
         a.n = batch;
-        launch_features<T>(a, (T*)s->X, st);
+        k_features_rows<T><<<(unsigned)(batch / kFeatBlockRows), 256, 0, st>>>(a, (T*)s->X);
         if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->D);
         else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->D);
     }
-    if (s->D <= kOutMaxD && t->n_leaf % 256 == 0) {
+    // per leaf N = N_il + max(exp(y out_scale + out_shift) - floor, 0) and chi:
+    // the method's row kernel with the network rows as the external part
+    if ((reinterpret_cast<uintptr_t>(N) & 15) == 0 &&
+        launch_surrogate_rows(t, w, s->Y7, s->norm[3], s->norm[2], kExtFloor, N, chi, chi_scale, st)) {
+        // done
+    } else if (s->D <= kOutMaxD && t->n_leaf % 256 == 0) {
         const size_t lds = (size_t)(64 + 256) * s->D * 4;
         k_output_tiled<<<(unsigned)(t->n_leaf / 256), 256, lds, st>>>(il_args(t, w), s->Y7, s->norm[2], s->norm[3],
                                                                       chi_scale, N, chi);
