@@ -157,8 +157,8 @@ def main():
     rng = np.random.default_rng(0)
     check = rng.choice(tin.n_leaf, size=min(2000, tin.n_leaf), replace=False)
 
-    def measure(prec: str) -> dict:
-        w = colden.Weights(dirs, precision=PREC[prec])
+    def measure(prec: str, mode: int = colden.CD_PRECALC73) -> dict:
+        w = colden.Weights(dirs, precision=PREC[prec], mode=mode)
 
         def step():
             tree.update(leaf)
@@ -195,6 +195,30 @@ def main():
 
     main_form = measure(args.precision)
     forms = {args.precision: main_form}
+    insitu = None
+    if not args.no_forms and not amr and args.precision == "fp32" and L >= 5 and D in (6, 12, 24, 40, 48):
+        # in-situ reference points (every shell seen from the oct centre):
+        # timed on the same field, and compared with the precalculated form
+        # over every output
+        N_prec, chi_prec = N.clone(), chi.clone()
+        insitu = measure("fp32", mode=colden.CD_INSITU)
+        dchi = (chi_prec - chi).abs()
+        flatN, flatP = N.reshape(-1), N_prec.reshape(-1)
+        tot, cnt = 0.0, 0
+        for k in range(0, flatN.numel(), 1 << 28):
+            a, b = flatN[k:k + (1 << 28)].double(), flatP[k:k + (1 << 28)].double()
+            tot += float(((b - a).abs() / a).sum())
+            cnt += a.numel()
+        g = torch.Generator(device=dev)
+        g.manual_seed(0)
+        pick = torch.randint(0, flatN.numel(), (1 << 20,), device=dev, generator=g)
+        dn = ((flatP[pick].double() - flatN[pick].double()).abs() / flatN[pick].double()).cpu().numpy()
+        insitu["vs_precalc"] = {"mean_abs_dchi": float(dchi.double().mean()), "max_abs_dchi": float(dchi.max()),
+                                "mean_rel_dN": tot / cnt, "p99_rel_dN_sample": float(np.percentile(dn, 99)),
+                                "what": "|chi_prec - chi_insitu| over every leaf; |N_prec - N_insitu| / N_insitu "
+                                        "over every output (p99 on 2^20 sampled outputs)"}
+        del N_prec, chi_prec
+        print(f"# in-situ form: {insitu['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_forms:
         for p in PREC:
             if p == args.precision or (amr and p == "fp16x2" and tin.base_level < 5):
@@ -224,6 +248,7 @@ def main():
 
     cpu = None
     ref_check = None
+    ref_check_insitu = None
     if not args.no_cpu:
         import oracle
         tr = oracle.Tree(tin)
@@ -247,6 +272,7 @@ def main():
                "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{what}, FP64 OpenMP oracle, {dt:.1f} s"}
         ref_check = tr.columns(dirs, check, nthreads=threads)
+        ref_check_insitu = tr.columns(dirs, check, mode=oracle.INSITU, nthreads=threads) if insitu else None
 
     def errs(f):
         if ref_check is None:
@@ -270,6 +296,15 @@ def main():
             o["mfma"] = {"kernel": f"k_external_mfma<{p}>", "flops_per_launch": flops, "achieved_tflops": tf,
                          "peak_tflops": MFMA_PEAK_TFLOPS, "frac": tf / MFMA_PEAK_TFLOPS}
         forms_out[p] = o
+    if insitu is not None:
+        o = {"ms_per_step": insitu["ms_per_step"], "value": insitu["value"],
+             "slowdown_vs_precalc": insitu["ms_per_step"] / main_form["ms_per_step"],
+             "external_ms": insitu["stages_ms"]["external"], "insitu_coarse_ms": insitu["stages_ms"]["coarse"],
+             "rows_ms": insitu["stages_ms"]["rows"], "vs_precalc": insitu["vs_precalc"]}
+        if ref_check_insitu is not None:
+            o["max_rel_err_vs_oracle_insitu"] = float(np.max(np.abs(insitu["sample"] - ref_check_insitu)
+                                                             / ref_check_insitu))
+        forms_out["fp32_insitu"] = o
     relerr, lnerr = errs(main_form)
 
     dtype = {"fp32": "f32", "bf16x2": "bf16x2 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)"}[args.precision]

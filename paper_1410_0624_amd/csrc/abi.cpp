@@ -80,10 +80,6 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
         cd::set_error("cd_precompute_weights: unknown mode %d", mode);
         return CD_EINVAL;
     }
-    if (mode == CD_INSITU) {
-        cd::set_error("cd_precompute_weights: in-situ reference points are not provided by this build");
-        return CD_EUNSUPPORTED;
-    }
     if (precision != CD_FP32 && precision != CD_BF16X2 && precision != CD_FP16X2) {
         cd::set_error("cd_precompute_weights: unknown precision %d", precision);
         return CD_EINVAL;
@@ -145,6 +141,10 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     if (rc == CD_OK) rc = upload(w->host.blob, &w->blob, s);
     if (rc == CD_OK) rc = upload(gf, &w->gloc, s);
     if (rc == CD_OK) rc = upload(w->host.sgn, &w->sgn, s);
+    std::vector<double> du((size_t)D * 3);
+    for (int d = 0; d < D; ++d)
+        for (int k = 0; k < 3; ++k) du[(size_t)d * 3 + k] = std::fabs(u[d][k]) < 1e-14 ? 0.0 : u[d][k];
+    if (rc == CD_OK) rc = upload(du, &w->dirs, s);
     if (rc == CD_OK && precision != CD_FP32) rc = cd::upload_split_banks(w, s);
     if (rc == CD_OK && hipStreamSynchronize(s) != hipSuccess) {
         cd::set_error("cd_precompute_weights: upload failed");
@@ -192,6 +192,7 @@ extern "C" void cd_weights_destroy(cd_weights* w) {
     if (w->blob) (void)hipFree(w->blob);
     if (w->gloc) (void)hipFree(w->gloc);
     if (w->sgn) (void)hipFree(w->sgn);
+    if (w->dirs) (void)hipFree(w->dirs);
     cd::free_split_banks(w);
     delete w;
 }

@@ -658,6 +658,10 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
                    const uint8_t* const* need = nullptr);  // sweep.hip
 
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+    if (w->mode != CD_PRECALC73) {
+        set_error("cd_column_densities: in-situ reference points are offered on uniform grids only");
+        return CD_EUNSUPPORTED;
+    }
     AmrDev* A = t->amr;
     const int B = t->base, L = t->lmax;
     const int qtop = L - 4;  // every level below Lmax is dense

@@ -132,6 +132,7 @@ struct cd_weights {
     int32_t* blob = nullptr;                // device tiled-sweep tables
     float* gloc = nullptr;                  // device [D][8]
     int32_t* sgn = nullptr;                 // device [D]
+    double* dirs = nullptr;                 // device [D][3] unit vectors (components < 1e-14 snapped to 0)
     // split-precision banks (hi/lo) for the MFMA sweep
     int split_ntiles = 0;
     int32_t* split_hdr = nullptr;    // device, see cd::SplitHost

@@ -1284,7 +1284,7 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     SURR_CHECK(s && t && w && N_dev && chi_dev && n_fallback_tiles && n_tiles, "cd_surrogate_check_fallback: NULL argument");
     SURR_CHECK(frac > 0 && frac <= 1 && tol_chi >= 0, "cd_surrogate_check_fallback: frac %g, tol %g", frac, tol_chi);
     SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_check_fallback: the surrogate needs a uniform grid with 2^L >= 256");
-    SURR_CHECK(w->precision == CD_FP32 && w->D == s->D, "cd_surrogate_check_fallback: needs FP32 weights of D = %d",
+    SURR_CHECK(w->precision == CD_FP32 && w->mode == CD_PRECALC73 && w->D == s->D, "cd_surrogate_check_fallback: needs FP32 precalculated weights of D = %d",
                s->D);
     hipStream_t st = (hipStream_t)stream;
     const float cs = (float)(gamma * av_per_nh);

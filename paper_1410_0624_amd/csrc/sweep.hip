@@ -266,6 +266,7 @@ int ensure_aux(cd_tree* t) {
 }
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
 bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
+void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);  // insitu.hip
 
 // Per-oct external columns E[n_oct][D] owned by the tree.
 int ensure_ext(cd_tree* t, int D) {
@@ -319,6 +320,37 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         return CD_EINVAL;
     }
     const bool split = w->precision != CD_FP32;
+    if (w->mode == CD_INSITU) {
+        if (!tiled_supported(t, w)) {
+            set_error("cd_column_densities: in-situ reference points need the tiled kernels (2^L >= 32 cells per "
+                      "axis and D in {6, 12, 24, 40, 48})");
+            return CD_EUNSUPPORTED;
+        }
+        // shells dl = 1..3 (the same in both schemes), then the in-situ
+        // shells dl >= 4 added per oct, then the target rows
+        int rc = ensure_ext(t, D);
+        if (rc != CD_OK) return rc;
+        auto mark = [t](int stage, int edge, hipStream_t st) -> hipError_t {
+            if (!t->prof) return hipSuccess;
+            t->pran[stage] = true;
+            return hipEventRecord(t->pev[stage][edge], st);
+        };
+        t->pslabs = 0;
+        CD_HIP(mark(CD_STAGE_SWEEP, 0, s));
+        CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
+        if (split) launch_external_mfma(t, w, t->ext, s);
+        else launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), s);
+        CD_HIP(mark(CD_STAGE_EXTERNAL, 1, s));
+        CD_HIP(mark(CD_STAGE_COARSE, 0, s));
+        launch_insitu_coarse(t, w, t->ext, s);
+        CD_HIP(mark(CD_STAGE_COARSE, 1, s));
+        CD_HIP(mark(CD_STAGE_ROWS, 0, s));
+        launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s);
+        CD_HIP(mark(CD_STAGE_ROWS, 1, s));
+        CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
+        CD_HIP(hipGetLastError());
+        return CD_OK;
+    }
     if (split && !tiled_supported(t, w)) {
         set_error("cd_column_densities: split precision on uniform grids needs 2^L >= 32 cells per axis "
                   "and D in {6, 12, 24, 40, 48}");

@@ -243,7 +243,8 @@ bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, f
     a.leaf = t->leaf;
     a.L = t->lmax;
     a.E = E;
-    a.q4 = (t->lmax - 4 >= 2) ? t->q[t->lmax - 4] : nullptr;
+    // the in-situ mode has the shells dl >= 4 in E already
+    a.q4 = (w->mode == CD_PRECALC73 && t->lmax - 4 >= 2) ? t->q[t->lmax - 4] : nullptr;
     a.gloc = w->gloc;
     a.sgn = w->sgn;
     a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));

@@ -198,9 +198,6 @@ def test_error_paths(colden):
     with pytest.raises(colden.ColdenError) as e:
         colden.Weights(np.array([[1.0, 1.0, 0.0]]))
     assert e.value.rc == colden.CD_EINVAL
-    with pytest.raises(colden.ColdenError) as e:
-        colden.Weights(oracle.dirs_healpix(1), mode=colden.CD_INSITU)
-    assert e.value.rc == colden.CD_EUNSUPPORTED
     with pytest.raises(colden.ColdenError):
         colden.directions(7, 1, 1)
     dev = torch.device("cuda:0")
