@@ -86,7 +86,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", choices=["uniform", "amr", "surrogate"], default="uniform")
+    ap.add_argument("--workload", choices=["uniform", "amr", "sphere", "surrogate"], default="uniform")
+    ap.add_argument("--sphere-sample", type=int, default=1500,
+                    help="sphere: midplane leaves checked against the exact-ray reference")
     ap.add_argument("--amr-threshold", type=float, default=100.0,
                     help="adaptive tree: refine cells with averaged n above this (cm^-3)")
     ap.add_argument("--train-fields", type=int, default=16, help="surrogate: seeded 256^3 training fields")
@@ -130,10 +132,16 @@ def main():
     from paper_1410_0624_amd import colden, synth
 
     dev = torch.device("cuda:0")
-    amr = args.workload == "amr"
+    sphere = args.workload == "sphere"
+    amr = args.workload in ("amr", "sphere")
     nside = args.nside or (2 if amr else 1)
     t0 = time.time()
-    if amr:
+    if sphere:
+        tin = synth.workload_sphere()
+        wl = ("uniform sphere (R 12.5 pc, 1000 cm^-3 inside, 10 cm^-3 outside, box 50 pc): 128^3 base, "
+              "every cell with sphere matter refined to 512^3 effective")
+        L = tin.max_level
+    elif amr:
         tin = synth.workload_amr(threshold=args.amr_threshold)
         wl = (f"AMR tree: 128^3 base + 2 refined levels on cells with averaged n > {args.amr_threshold:g} cm^-3 "
               f"(log-normal, sigma_ln n=2, mean 10 cm^-3, generated at 512^3, box 20 pc, seed 3)")
@@ -144,7 +152,14 @@ def main():
         tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=seed)
         wl = (f"uniform {1 << L}^3 log-normal turbulent field (sigma_ln n=1.5, mean 10 cm^-3, "
               f"box 10 pc, seed {seed})")
-    dirs = colden.directions(colden.CD_DIR_HEALPIX, nside)
+    # the sphere test uses the paper's own direction sets (M x N, axes)
+    dirs = (colden.directions(colden.CD_DIR_PAPER_MN, 3, 4) if sphere
+            else colden.directions(colden.CD_DIR_HEALPIX, nside))
+    sets = {}
+    if sphere:
+        sets = {"axes6": colden.directions(colden.CD_DIR_AXES6, 0), "mn3x4": dirs,
+                "mn5x8": colden.directions(colden.CD_DIR_PAPER_MN, 5, 8),
+                "mn7x12": colden.directions(colden.CD_DIR_PAPER_MN, 7, 12)}
     D = dirs.shape[0]
     print(f"# generated workload in {time.time() - t0:.1f}s: {tin.n_leaf} leaves, D={D}",
           file=sys.stderr, flush=True)
@@ -249,6 +264,7 @@ def main():
     cpu = None
     ref_check = None
     ref_check_insitu = None
+    e1 = None
     if not args.no_cpu:
         import oracle
         tr = oracle.Tree(tin)
@@ -273,6 +289,43 @@ def main():
                "sample": f"{what}, FP64 OpenMP oracle, {dt:.1f} s"}
         ref_check = tr.columns(dirs, check, nthreads=threads)
         ref_check_insitu = tr.columns(dirs, check, mode=oracle.INSITU, nthreads=threads) if insitu else None
+        if sphere:
+            # the paper's first test: midplane chi of the method against
+            # exact rays (768 HEALPix N_side = 8 centres per target through
+            # every leaf), for its four direction sets
+            mid = synth.midplane_leaves(tin)
+            ms = np.sort(np.random.default_rng(11).choice(mid, size=min(args.sphere_sample, mid.size),
+                                                          replace=False))
+            t1 = time.time()
+            chi_ref = oracle.screening(tr.raymarch(oracle.dirs_healpix(8), ms, nthreads=threads))
+            t_ray = time.time() - t1
+            e1 = {"targets": f"{ms.size} random leaves just below the z = box/2 plane",
+                  "reference": "exact rays: 768 HEALPix N_side = 8 centres per target, FP64 oracle",
+                  "raymarch_s": t_ray, "sets": {}}
+            paper = {"axes6": 0.036, "mn3x4": 0.017, "mn5x8": 0.014, "mn7x12": 0.018}
+            for name, u in sets.items():
+                w = colden.Weights(u)
+                Ns = torch.empty((tin.n_leaf, u.shape[0]), dtype=torch.float32, device=dev)
+                cs = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
+                colden.column_densities(tree, w, Ns, cs)
+                ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                ev0.record(stream)
+                for _ in range(3):
+                    colden.column_densities(tree, w, Ns, cs)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                ms_sweep = ev0.elapsed_time(ev1) / 3
+                got = cs[torch.from_numpy(ms).to(dev)].cpu().numpy().astype(np.float64)
+                ref_tree = tr.columns(u, ms[:300], nthreads=threads)
+                gotN = Ns[torch.from_numpy(ms[:300]).to(dev)].cpu().numpy().astype(np.float64)
+                d = np.abs(got - chi_ref)
+                e1["sets"][name] = {"D": int(u.shape[0]), "sweep_ms": ms_sweep,
+                                    "cell_dir_per_s": tin.n_leaf * u.shape[0] / (ms_sweep * 1e-3),
+                                    "mean_abs_dchi_vs_rays": float(d.mean()), "max_abs_dchi_vs_rays": float(d.max()),
+                                    "paper_mean_abs_dchi": paper[name],
+                                    "max_rel_err_vs_oracle_tree": float(np.max(np.abs(gotN - ref_tree) / ref_tree))}
+                w.close()
+                del Ns, cs
 
     def errs(f):
         if ref_check is None:
@@ -321,7 +374,8 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"{wl}, {D} HEALPix sectors, {args.precision} external shells + fused screening",
+        "config": {"workload": f"{wl}, {D} {'paper M x N (3 x 4)' if sphere else 'HEALPix'} sectors, "
+                               f"{args.precision} external shells + fused screening",
                    "n_leaf": tin.n_leaf, "n_dirs": D, "levels": L + 1, "precision": args.precision,
                    "step": "pyramid rebuild + column sweep"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -334,6 +388,7 @@ def main():
                   "GB_per_s": sweep_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},
         "forms": forms_out,
         "cpu_baseline": cpu,
+        **({"sphere_test": e1} if e1 is not None else {}),
         "max_rel_err_vs_oracle_sample": relerr,
         "max_abs_dlnN_vs_oracle_sample": lnerr,
     }

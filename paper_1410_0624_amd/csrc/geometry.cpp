@@ -267,6 +267,28 @@ int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables
     t.tile_dc = DC;
     t.blob.clear();
     t.blob_words = 0;
+    // internal + local, for every direction count (the row kernels read
+    // these whether or not the tiled sweep takes D): after mirroring u into
+    // the positive octant, a target reaches the sibling across axis a only if
+    // it lies on the low side of a; the chord through the sibling reached
+    // across the axis set m is the same for every target: box [0.5, 1.5]
+    // along the crossed axes, [-0.5, 0.5] along the others, ray from the
+    // origin along |u|.
+    t.gloc.assign((size_t)D * 8, 0.0);
+    t.sgn.assign(D, 0);
+    for (int d = 0; d < D; ++d) {
+        const double au[3] = {std::fabs(dirs[d][0]), std::fabs(dirs[d][1]), std::fabs(dirs[d][2])};
+        t.sgn[d] = (dirs[d][0] < 0) | ((dirs[d][1] < 0) << 1) | ((dirs[d][2] < 0) << 2);
+        const double org[3] = {0, 0, 0};
+        for (int m = 0; m < 8; ++m) {
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = ((m >> a) & 1) ? 0.5 : -0.5;
+                hi[a] = lo[a] + 1.0;
+            }
+            t.gloc[(size_t)d * 8 + m] = chord(lo, hi, org, au);
+        }
+    }
     if (DC == 0) return CD_OK;  // no tiled sweep for this direction count
     const int nchunks = D / DC;
     std::vector<std::vector<int32_t>> blobs;
@@ -382,26 +404,6 @@ int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables
     t.blob.assign(words * blobs.size(), 0);
     for (size_t i = 0; i < blobs.size(); ++i) std::copy(blobs[i].begin(), blobs[i].end(), t.blob.begin() + i * words);
 
-    // internal + local: after mirroring u into the positive octant, a target
-    // reaches the sibling across axis a only if it lies on the low side of a;
-    // the chord through the sibling reached across the axis set m is the same
-    // for every target: box [0.5, 1.5] along the crossed axes, [-0.5, 0.5]
-    // along the others, ray from the origin along |u|.
-    t.gloc.assign((size_t)D * 8, 0.0);
-    t.sgn.assign(D, 0);
-    for (int d = 0; d < D; ++d) {
-        const double au[3] = {std::fabs(dirs[d][0]), std::fabs(dirs[d][1]), std::fabs(dirs[d][2])};
-        t.sgn[d] = (dirs[d][0] < 0) | ((dirs[d][1] < 0) << 1) | ((dirs[d][2] < 0) << 2);
-        const double org[3] = {0, 0, 0};
-        for (int m = 0; m < 8; ++m) {
-            double lo[3], hi[3];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = ((m >> a) & 1) ? 0.5 : -0.5;
-                hi[a] = lo[a] + 1.0;
-            }
-            t.gloc[(size_t)d * 8 + m] = chord(lo, hi, org, au);
-        }
-    }
     return CD_OK;
 }
 

@@ -195,3 +195,23 @@ def sphere_field(L: int, radius_frac: float = 0.25, n_in: float = 1000.0,
     c = (np.arange(n) + 0.5) / n - 0.5
     r2 = c[:, None, None] ** 2 + c[None, :, None] ** 2 + c[None, None, :] ** 2
     return np.where(r2 <= radius_frac ** 2, n_in, n_out).astype(np.float64)
+
+
+def workload_sphere(base_level: int = 7, max_level: int = 9, box_pc: float = 50.0, radius_pc: float = 12.5,
+                    n_in: float = 1000.0, n_out: float = 10.0) -> TreeInput:
+    """The paper's sphere test cloud: a uniform sphere (n_in inside radius R,
+    n_out outside) at the centre of the box, a full base grid and every cell
+    that holds sphere matter refined down to max_level (the sphere resolved
+    at 2^max_level effective)."""
+    f = sphere_field(max_level, radius_pc / box_pc, n_in, n_out)
+    # refine every cell whose mean density exceeds the ambient value
+    return amr_tree(f, base_level, n_out * 1.0000001, box_pc * PC_CM)
+
+
+def midplane_leaves(tin: TreeInput) -> np.ndarray:
+    """Leaves whose cell lies just below the z = box / 2 plane (every level
+    has a cell face there)."""
+    lv = tin.leaf_level.astype(np.int64)
+    kz = tin.leaf_ijk[:, 2].astype(np.int64)
+    return np.nonzero(kz == (np.int64(1) << lv) // 2 - 1)[0]
+

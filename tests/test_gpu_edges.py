@@ -67,10 +67,13 @@ def test_direction_counts_outside_the_tiled_set_uniform(colden, L, D):
     print(f"uniform L={L} D={D}: max rel {_check(N, chi, ref, tin):.3e}")
 
 
-@pytest.mark.parametrize("Lf,B,th,D", [(6, 3, 14.0, 5), (7, 5, 30.0, 7), (6, 2, 14.0, 1)])
+@pytest.mark.parametrize("Lf,B,th,D", [(6, 3, 14.0, 5), (7, 5, 30.0, 7), (6, 2, 14.0, 1),
+                                        # D > 16 with no tile chunk: the per-oct kernel's local chord tables
+                                        (6, 3, 14.0, 63), (6, 3, 14.0, 65), (7, 5, 30.0, 84)])
 def test_direction_counts_outside_the_tiled_set_amr(colden, Lf, B, th, D):
     """Adaptive trees with D outside the tiled set: every target walks the
-    weight lists through the dense levels (a lane per direction)."""
+    weight lists through the dense levels (a lane per direction, passes of
+    64 directions above 64)."""
     tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, 60 + D), B, th, 10 * synth.PC_CM)
     dirs = _dirs(D, 200 + D)
     N, chi = _run(colden, tin, dirs)
