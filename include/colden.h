@@ -216,6 +216,34 @@ int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per
                         double gamma, float* chi_dev, float* av_dev, void* stream);
 
 /*
+ * Gas heating from the screening factor (Sect. 5), per cell:
+ *   G0_eff = chi G0 (G0 = 1.7 for the Draine field in Habing units);
+ *   Gamma_UV = 1e-24 eps G0_eff n  erg cm^-3 s^-1, photoelectric heating with
+ *   the efficiency of Wolfire et al. (1995), x = G0_eff T^(1/2) / n_e:
+ *   eps = 4.9e-2 / (1 + (x/1925)^0.73) + 3.7e-2 (T/1e4)^0.7 / (1 + x/5000);
+ *   Gamma_CR = 1e-27 n  erg cm^-3 s^-1 (cosmic rays).
+ * Device float arrays [n_cells]: chi_dev (cd_heating_rates: input), n_dev
+ * (cm^-3), T_dev (K), ne_dev (electron density, cm^-3; the paper takes it
+ * from a model it does not state, so it is an input here); outputs
+ * g0eff_dev and gamma_cr_dev may be NULL.  n_e <= 0 with UV gives eps = 0.
+ * Asynchronous on `stream`.
+ * Errors: CD_EINVAL (n_cells < 0, NULL buffers, G0 negative or non-finite).
+ */
+int cd_heating_rates(const float* chi_dev, const float* n_dev, const float* T_dev, const float* ne_dev,
+                     int64_t n_cells, double G0, float* g0eff_dev, float* gamma_uv_dev, float* gamma_cr_dev,
+                     void* stream);
+
+/*
+ * Screening factor (Eq. 5) fused with the heating rates: reads each cell's
+ * row of N_dev [n_cells][D] once, writes chi_dev (may be NULL) and the rates
+ * as cd_heating_rates.  Errors: CD_EINVAL (as cd_heating_rates, D outside
+ * 1..CD_MAX_DIRS, non-finite av_per_nh or gamma).
+ */
+int cd_screening_heating(const float* N_dev, int64_t n_cells, int D, double av_per_nh, double gamma,
+                         const float* n_dev, const float* T_dev, const float* ne_dev, double G0, float* chi_dev,
+                         float* g0eff_dev, float* gamma_uv_dev, float* gamma_cr_dev, void* stream);
+
+/*
  * Stage timing.  When enabled on a tree, cd_column_densities and
  * cd_tree_update record HIP events around each of their stages on the
  * streams the stages run on; cd_profile_read waits for the last call's events

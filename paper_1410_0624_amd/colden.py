@@ -22,8 +22,9 @@ EXPORTS = [
     "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
     "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
-    "cd_profile_enable", "cd_profile_read", "cd_check_densities",
+    "cd_profile_enable", "cd_profile_read", "cd_check_densities", "cd_heating_rates", "cd_screening_heating",
 ]
+G0_DRAINE = 1.7
 STAGES = ["pyramid", "coarse", "external", "rows", "sweep"]
 
 
@@ -63,6 +64,8 @@ def lib():
         L.cd_profile_enable.argtypes = [P, I]
         L.cd_profile_read.argtypes = [P, P]
         L.cd_check_densities.argtypes = [P, I64, P, P]
+        L.cd_heating_rates.argtypes = [P, P, P, P, I64, D, P, P, P, P]
+        L.cd_screening_heating.argtypes = [P, I64, I, D, D, P, P, P, D, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -193,6 +196,27 @@ def check_densities(leaf_n, stream=None) -> int:
     bad = C.c_int64(0)
     _check(lib().cd_check_densities(_dev_f32(leaf_n), int(leaf_n.numel()), C.byref(bad), _stream(stream)))
     return bad.value
+
+
+def _opt(t):
+    return _dev_f32(t) if t is not None else None
+
+
+def heating_rates(chi, n, T, ne, gamma_uv, g0eff=None, gamma_cr=None, G0: float = G0_DRAINE, stream=None):
+    """Photoelectric and cosmic-ray heating rates (Sect. 5) from chi."""
+    _check(lib().cd_heating_rates(_dev_f32(chi), _dev_f32(n), _dev_f32(T), _dev_f32(ne), int(chi.numel()), G0,
+                                  _opt(g0eff), _dev_f32(gamma_uv), _opt(gamma_cr), _stream(stream)))
+    return gamma_uv
+
+
+def screening_heating(N, n, T, ne, gamma_uv, chi=None, g0eff=None, gamma_cr=None, G0: float = G0_DRAINE,
+                      av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):
+    """chi (Eq. 5) from N and the heating rates in one pass."""
+    cells, D = N.shape
+    _check(lib().cd_screening_heating(_dev_f32(N), cells, D, av_per_nh, gamma, _dev_f32(n), _dev_f32(T),
+                                      _dev_f32(ne), G0, _opt(chi), _opt(g0eff), _dev_f32(gamma_uv),
+                                      _opt(gamma_cr), _stream(stream)))
+    return gamma_uv
 
 
 def screening_factor(N, chi, av=None, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):
