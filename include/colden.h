@@ -154,11 +154,10 @@ void cd_tree_destroy(cd_tree* tree);
  *              configurations of Sect. 3.3 (tabulated, coarse tables for
  *              dl >= 4); CD_INSITU: every shell seen from the centre of
  *              the target's oct (Sect. 4.4).  The two differ only for
- *              dl >= 4, which the in-situ form computes per oct by walking
- *              each ray through the shells' cells (FP64); it is offered on
- *              uniform grids with the tiled kernels (2^L >= 32, D in
- *              {6, 12, 24, 40, 48}), else cd_column_densities returns
- *              CD_EUNSUPPORTED.
+ *              dl >= 4, which the in-situ form computes per target oct by
+ *              walking each ray through the shells' cells (FP64), on
+ *              uniform grids and adaptive trees, for any D; with a split
+ *              precision it has the split forms' own limits (below).
  *   precision  CD_FP32, CD_BF16X2 or CD_FP16X2: the arithmetic of the
  *              external shells dl = 1, 2, 3 in cd_column_densities.  The
  *              split forms keep densities and weights as hi + lo pairs of

@@ -60,6 +60,8 @@ struct AmrDev {
     uint8_t* need[CD_MAX_LEVEL + 1] = {nullptr};  // coarse-table cells that targets read, levels 2 .. qtop
     int64_t* erow = nullptr;
     int32_t* tiles[CD_MAX_LEVEL + 1] = {nullptr};
+    float* x4 = nullptr;  // in-situ mode: shells dl >= 4 per target [n_tg][D]
+    size_t x4_bytes = 0;
     int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0;
     std::vector<void*> mem;
     AmrHost h;
@@ -170,8 +172,11 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
             }
         }
         // shells dl >= 4, every level at once: Q_l of the level-l ancestor
+        // (in-situ mode: the target's own row of x4)
         const int l = l0 - 4;
-        if (l >= 2) {
+        if (a.x4) {
+            acc += a.x4[g * a.D + dd];
+        } else if (l >= 2) {
             const int sh = l0 - 1 - l;
             const int64_t nq = (int64_t)1 << l;
             const int64_t cell = ((A[2] >> sh) * nq + (A[1] >> sh)) * nq + (A[0] >> sh);
@@ -263,7 +268,11 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
             }
         }
         const int l = l0 - 4;
-        if (l >= 2) {
+        if (a.x4) {  // in-situ mode: the target's own row
+            const float* xp = a.x4 + g * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d) out[d] += xp[d];
+        } else if (l >= 2) {
             const int sh = l0 - 1 - l;
             const int64_t nq = (int64_t)1 << l;
             const int64_t cell = ((Az >> sh) * nq + (Ay >> sh)) * nq + (Ax >> sh);
@@ -656,12 +665,11 @@ void launch_external_tiled_list(const float* lev1, const float* lev2, const floa
                                 hipStream_t s);                                             // sweep_tile.hip
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const uint8_t* const* need = nullptr);  // sweep.hip
+void launch_insitu_targets(const cd_tree* t, const cd_weights* w, const int32_t* info, int64_t n_tg, float* X,
+                           hipStream_t s);  // insitu.hip
 
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
-    if (w->mode != CD_PRECALC73) {
-        set_error("cd_column_densities: in-situ reference points are offered on uniform grids only");
-        return CD_EUNSUPPORTED;
-    }
+    const bool insitu = w->mode == CD_INSITU;
     AmrDev* A = t->amr;
     const int B = t->base, L = t->lmax;
     const int qtop = L - 4;  // every level below Lmax is dense
@@ -680,10 +688,26 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         return CD_EINVAL;
     }
     const bool compact = qtop == L - 4;
-    int rc = ensure_q(t, w->D, qtop, compact);
-    if (rc != CD_OK) return rc;
-    // the coarse tables on the second stream, concurrent with the kernel of
-    // the shells dl = 1..3 (none for FP32 weights the tiled kernel cannot take)
+    int rc = CD_OK;
+    if (insitu) {
+        // the ray walks of the shells dl >= 4 take the place of the coarse tables
+        const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
+        if (A->x4_bytes < bytes) {
+            if (A->x4) (void)hipFree(A->x4);
+            A->x4 = nullptr;
+            A->x4_bytes = 0;
+            if (hipMalloc((void**)&A->x4, bytes) != hipSuccess) {
+                set_error("hipMalloc of %zu bytes (in-situ columns) failed", bytes);
+                return CD_ENOMEM;
+            }
+            A->x4_bytes = bytes;
+        }
+    } else if ((rc = ensure_q(t, w->D, qtop, compact)) != CD_OK) {
+        return rc;
+    }
+    // the coarse tables (or the in-situ walks) on the second stream, concurrent
+    // with the kernel of the shells dl = 1..3 (none for FP32 weights the tiled
+    // kernel cannot take)
     const bool split = w->precision != CD_FP32;
     const bool tiled = (split ? split_tiled : tiled_weights_ok(w)) && A->h.erows > 0;
     const bool overlap = split || tiled;  // an external kernel runs beside the coarse tables
@@ -698,7 +722,10 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
         CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
     }
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], cs));
-    launch_coarse(t, w, qtop, compact, cs, A->need);
+    if (insitu)
+        launch_insitu_targets(t, w, A->tg_info, A->n_tg, A->x4, cs);
+    else
+        launch_coarse(t, w, qtop, compact, cs, A->need);
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], cs));
     if (overlap) CD_HIP(hipEventRecord(t->ev[1], cs));
     // shells reach levels <= Lmax - 1, all dense (injected above B by the update)
@@ -776,7 +803,9 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     a.kloc = w->kloc;
     a.gloc = w->gloc;
     a.sgn = w->sgn;
-    for (int l = 2; l <= qtop; ++l) a.q[l] = t->q[l];
+    if (!insitu)
+        for (int l = 2; l <= qtop; ++l) a.q[l] = t->q[l];
+    a.x4 = insitu ? A->x4 : nullptr;
     a.qtop = qtop;
     a.qcompact = compact ? 1 : 0;
     for (int sc = 0; sc < 6; ++sc)
@@ -826,6 +855,7 @@ void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
 void amr_free(cd_tree* t) {
     if (!t->amr) return;
     for (void* p : t->amr->mem) (void)hipFree(p);
+    if (t->amr->x4) (void)hipFree(t->amr->x4);
     delete t->amr;
     t->amr = nullptr;
 }

@@ -18,7 +18,8 @@ struct InsituArgs {
     const double* dirs;                   // [D][3]
     int D;
     double box;                           // cm
-    float* E;                             // [n_oct][D], the sum is added in place
+    float* E;                             // [n_oct][D]
+    int accumulate;                       // 1: added to E, 0: written
     int64_t n_oct;
 };
 
@@ -35,91 +36,115 @@ __device__ __forceinline__ double exit_t(const double (&c)[3], const double (&u)
     return t;
 }
 
+// Column (box units x density) of the in-situ shells dl >= 4 of the oct A
+// (level l0 - 1 coordinates, targets at level l0) along u: the levels
+// l0 - 4 .. 0 of the padded arrays lev.
+__device__ double insitu_column(const float* const* lev, int l0, const int64_t (&A)[3], const double (&u)[3]) {
+    const int L1 = l0 - 1;
+    if (L1 - 3 < 0) return 0.0;
+    const double iu[3] = {u[0] != 0.0 ? 1.0 / u[0] : 0.0, u[1] != 0.0 ? 1.0 / u[1] : 0.0,
+                          u[2] != 0.0 ? 1.0 / u[2] : 0.0};
+    // inner limit of the level l0 - 4 shell: the outer limits of dl = 1, 2, 3
+    int64_t ilo[3], ihi[3];
+    for (int k = 0; k < 3; ++k) {
+        int64_t lo = A[k], hi = A[k];
+        for (int l = L1; l > L1 - 3; --l) {
+            int64_t olo = lo - 2, ohi = hi + 2;
+            if (olo & 1) olo -= 1;  // the outer box covers whole parent cells
+            if (!(ohi & 1)) ohi += 1;
+            lo = olo / 2;           // olo is even, ohi + 1 is even
+            hi = (ohi + 1) / 2 - 1;
+        }
+        ilo[k] = lo;
+        ihi[k] = hi;
+    }
+    const double dx1 = ldexp(1.0, -L1);
+    const double c[3] = {((double)A[0] + 0.5) * dx1, ((double)A[1] + 0.5) * dx1, ((double)A[2] + 0.5) * dx1};
+    double sum = 0.0;
+    for (int l = L1 - 3; l >= 0; --l) {
+        const int64_t nl = (int64_t)1 << l;
+        // an inner box that covers the whole level leaves this shell and
+        // every coarser one outside the box (no matter there)
+        if (ilo[0] <= 0 && ilo[1] <= 0 && ilo[2] <= 0 && ihi[0] >= nl - 1 && ihi[1] >= nl - 1 && ihi[2] >= nl - 1)
+            break;
+        const double dx = ldexp(1.0, -l);
+        int64_t olo[3], ohi[3];
+        double blo[3], bhi[3], ilo_b[3], ihi_b[3];
+        for (int k = 0; k < 3; ++k) {
+            olo[k] = ilo[k] - 2;
+            ohi[k] = ihi[k] + 2;
+            if (olo[k] & 1) olo[k] -= 1;
+            if (!(ohi[k] & 1)) ohi[k] += 1;
+            blo[k] = (double)olo[k] * dx;
+            bhi[k] = (double)(ohi[k] + 1) * dx;
+            ilo_b[k] = (double)ilo[k] * dx;
+            ihi_b[k] = (double)(ihi[k] + 1) * dx;
+        }
+        const double t_in = exit_t(c, u, iu, ilo_b, ihi_b), t_out = exit_t(c, u, iu, blo, bhi);
+        // first cell past the inner box: the axes that leave it at t_in
+        // step out of it by index, the others contain c + t_in u
+        int64_t i[3];
+        for (int k = 0; k < 3; ++k) {
+            const double tk = u[k] > 0.0 ? (ihi_b[k] - c[k]) * iu[k] : (u[k] < 0.0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
+            const double pk = (c[k] + t_in * u[k]) / dx;
+            if (tk == t_in) i[k] = u[k] > 0.0 ? ihi[k] + 1 : ilo[k] - 1;
+            else i[k] = (int64_t)(u[k] < 0.0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
+        }
+        const int64_t S = nl + 2 * kHalo;
+        const float* lv = lev[l];
+        double t = t_in;
+        // at most (width of the outer box) crossings per axis
+        for (int step = 0; step < 96 && t < t_out; ++step) {
+            double tn[3];
+            for (int k = 0; k < 3; ++k)
+                tn[k] = u[k] > 0.0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
+                                   : (u[k] < 0.0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
+            const double te = fmin(fmin(fmin(tn[0], tn[1]), tn[2]), t_out);
+            const float n = lv[((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo)];
+            sum += (double)n * (te - t);
+            for (int k = 0; k < 3; ++k)
+                if (tn[k] == te) i[k] += u[k] > 0.0 ? 1 : -1;
+            t = te;
+        }
+        for (int k = 0; k < 3; ++k) {
+            ilo[k] = olo[k] / 2;
+            ihi[k] = (ohi[k] + 1) / 2 - 1;
+        }
+    }
+    return sum;
+}
+
 __global__ __launch_bounds__(256) void k_insitu_coarse(const InsituArgs a) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= a.n_oct) return;
     const int L1 = a.L - 1;
     const int64_t n1 = (int64_t)1 << L1;
     const int64_t A[3] = {o & (n1 - 1), (o >> L1) & (n1 - 1), o >> (2 * L1)};
-    // inner limit of the level L-4 shell: the outer limits of dl = 1, 2, 3
-    int64_t ilo0[3], ihi0[3];
-    for (int k = 0; k < 3; ++k) {
-        int64_t lo = A[k], hi = A[k];
-        for (int l = L1; l > L1 - 3; --l) {
-            int64_t olo = lo - 2, ohi = hi + 2;
-            if (olo & 1) olo -= 1;     // the outer box covers whole parent cells
-            if (!(ohi & 1)) ohi += 1;
-            lo = olo / 2;              // olo is even, ohi + 1 is even
-            hi = (ohi + 1) / 2 - 1;
-        }
-        ilo0[k] = lo;
-        ihi0[k] = hi;
-    }
-    const double dx1 = ldexp(1.0, -L1);
-    const double c[3] = {((double)A[0] + 0.5) * dx1, ((double)A[1] + 0.5) * dx1, ((double)A[2] + 0.5) * dx1};
     float* row = a.E + o * a.D;
     for (int d = 0; d < a.D; ++d) {
         const double u[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
-        const double iu[3] = {u[0] != 0.0 ? 1.0 / u[0] : 0.0, u[1] != 0.0 ? 1.0 / u[1] : 0.0,
-                              u[2] != 0.0 ? 1.0 / u[2] : 0.0};
-        int64_t ilo[3] = {ilo0[0], ilo0[1], ilo0[2]}, ihi[3] = {ihi0[0], ihi0[1], ihi0[2]};
-        double sum = 0.0;
-        for (int l = L1 - 3; l >= 0; --l) {
-            const int64_t nl = (int64_t)1 << l;
-            // an inner box that covers the whole level leaves this shell and
-            // every coarser one outside the box (no matter there)
-            if (ilo[0] <= 0 && ilo[1] <= 0 && ilo[2] <= 0 && ihi[0] >= nl - 1 && ihi[1] >= nl - 1 && ihi[2] >= nl - 1)
-                break;
-            const double dx = ldexp(1.0, -l);
-            int64_t olo[3], ohi[3];
-            double blo[3], bhi[3], ilo_b[3], ihi_b[3];
-            for (int k = 0; k < 3; ++k) {
-                olo[k] = ilo[k] - 2;
-                ohi[k] = ihi[k] + 2;
-                if (olo[k] & 1) olo[k] -= 1;
-                if (!(ohi[k] & 1)) ohi[k] += 1;
-                blo[k] = (double)olo[k] * dx;
-                bhi[k] = (double)(ohi[k] + 1) * dx;
-                ilo_b[k] = (double)ilo[k] * dx;
-                ihi_b[k] = (double)(ihi[k] + 1) * dx;
-            }
-            const double t_in = exit_t(c, u, iu, ilo_b, ihi_b), t_out = exit_t(c, u, iu, blo, bhi);
-            // first cell past the inner box: the axes that leave it at t_in
-            // step out of it by index, the others contain c + t_in u
-            int64_t i[3];
-            for (int k = 0; k < 3; ++k) {
-                const double tk = u[k] > 0.0 ? (ihi_b[k] - c[k]) * iu[k] : (u[k] < 0.0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
-                const double pk = (c[k] + t_in * u[k]) / dx;
-                if (tk == t_in) i[k] = u[k] > 0.0 ? ihi[k] + 1 : ilo[k] - 1;
-                else i[k] = (int64_t)(u[k] < 0.0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
-            }
-            const int64_t S = nl + 2 * kHalo;
-            const float* lev = a.lev[l];
-            double t = t_in;
-            // at most (width of the outer box) crossings per axis
-            for (int step = 0; step < 96 && t < t_out; ++step) {
-                double tn[3];
-                for (int k = 0; k < 3; ++k)
-                    tn[k] = u[k] > 0.0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
-                                       : (u[k] < 0.0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
-                const double te = fmin(fmin(fmin(tn[0], tn[1]), tn[2]), t_out);
-                const float n = lev[((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo)];
-                sum += (double)n * (te - t);
-                for (int k = 0; k < 3; ++k)
-                    if (tn[k] == te) i[k] += u[k] > 0.0 ? 1 : -1;
-                t = te;
-            }
-            for (int k = 0; k < 3; ++k) {
-                ilo[k] = olo[k] / 2;
-                ihi[k] = (ohi[k] + 1) / 2 - 1;
-            }
-        }
-        row[d] += (float)(sum * a.box);
+        const float v = (float)(insitu_column(a.lev, a.L, A, u) * a.box);
+        row[d] = a.accumulate ? row[d] + v : v;
     }
 }
 
-// Adds the in-situ shells dl >= 4 of every oct of a uniform 2^L grid to E.
-void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s) {
+// Adaptive trees: the in-situ shells dl >= 4 of every target oct (level of
+// its targets and oct coordinates in info[4 g .. 4 g + 3]) into X[g][D].
+__global__ __launch_bounds__(256) void k_insitu_targets(const InsituArgs a, const int32_t* __restrict__ info,
+                                                        int64_t n_tg, float* __restrict__ X) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_tg) return;
+    const int l0 = info[4 * g];
+    const int64_t A[3] = {info[4 * g + 1], info[4 * g + 2], info[4 * g + 3]};
+    for (int d = 0; d < a.D; ++d) {
+        const double u[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
+        X[g * a.D + d] = (float)(insitu_column(a.lev, l0, A, u) * a.box);
+    }
+}
+
+// The in-situ shells dl >= 4 of every oct of a uniform 2^L grid (L >= 4),
+// added to E or written into it.
+void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, bool accumulate, hipStream_t s) {
     const int L = t->lmax;
     if (L - 4 < 0) return;
     InsituArgs a{};
@@ -129,8 +154,21 @@ void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, hipSt
     a.D = w->D;
     a.box = t->box_cm;
     a.E = E;
+    a.accumulate = accumulate ? 1 : 0;
     a.n_oct = (int64_t)1 << (3 * (L - 1));
     k_insitu_coarse<<<(unsigned)((a.n_oct + 255) / 256), 256, 0, s>>>(a);
+}
+
+void launch_insitu_targets(const cd_tree* t, const cd_weights* w, const int32_t* info, int64_t n_tg, float* X,
+                           hipStream_t s) {
+    if (n_tg <= 0) return;
+    InsituArgs a{};
+    for (int l = 0; l <= t->lmax - 1; ++l) a.lev[l] = t->lev[l];  // every level below Lmax is dense
+    a.L = t->lmax;
+    a.dirs = w->dirs;
+    a.D = w->D;
+    a.box = t->box_cm;
+    k_insitu_targets<<<(unsigned)((n_tg + 255) / 256), 256, 0, s>>>(a, info, n_tg, X);
 }
 
 }  // namespace cd

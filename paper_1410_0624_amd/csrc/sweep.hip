@@ -29,6 +29,7 @@ struct FineArgs {
     float dx[4];          // their cell size (cm)
     float dxL;            // leaf cell size (cm)
     const float* q4;      // [8^(L-4)][64][D] or nullptr
+    const float* x4;      // in-situ mode: shells dl >= 4 per oct [8^(L-1)][D] (instead of q4)
     KindTable kt[4];      // kinds 1..3
     const float* kloc;    // [8][8][D]
     int D;
@@ -92,7 +93,12 @@ __global__ __launch_bounds__(256) void k_fine_uniform(const FineArgs a) {
         if (a.lev[1]) shell_sum<DC>(acc, a.lev[1], a.L - 1, ax, ay, az, c1, a.kt[1], a.D, d0, a.dx[1]);
         if (a.lev[2]) shell_sum<DC>(acc, a.lev[2], a.L - 2, ax >> 1, ay >> 1, az >> 1, c2, a.kt[2], a.D, d0, a.dx[2]);
         if (a.lev[3]) shell_sum<DC>(acc, a.lev[3], a.L - 3, ax >> 2, ay >> 2, az >> 2, c3, a.kt[3], a.D, d0, a.dx[3]);
-        if (a.q4) {
+        if (a.x4) {
+            const float* x = a.x4 + oct * a.D;
+#pragma unroll
+            for (int j = 0; j < DC; ++j)
+                if (d0 + j < a.D) acc[j] += x[d0 + j];
+        } else if (a.q4) {
             const float* q = a.q4 + (q4cell * 64 + c4) * a.D;
 #pragma unroll
             for (int j = 0; j < DC; ++j)
@@ -266,7 +272,8 @@ int ensure_aux(cd_tree* t) {
 }
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
 bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
-void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);  // insitu.hip
+void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, bool accumulate,
+                          hipStream_t s);  // insitu.hip
 
 // Per-oct external columns E[n_oct][D] owned by the tree.
 int ensure_ext(cd_tree* t, int D) {
@@ -286,6 +293,35 @@ int ensure_ext(cd_tree* t, int D) {
 template <int DC>
 static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
     k_fine_uniform<DC><<<(unsigned)((n_oct + 255) / 256), 256, 0, s>>>(a);
+}
+
+// Per-oct kernel over a uniform 2^L grid (L >= 1): shells dl = 1..3 from the
+// weight lists, dl >= 4 from the coarse table q4 or the in-situ rows x4.
+static void launch_fine_path(const cd_tree* t, const cd_weights* w, const float* q4, const float* x4, float* N,
+                             float* chi, float chi_scale, hipStream_t s) {
+    const int L = t->lmax, D = w->D;
+    FineArgs a{};
+    a.leaf = t->leaf;
+    a.L = L;
+    for (int k = 1; k <= 3; ++k) {
+        const int l = L - k;
+        a.lev[k] = (l >= 0) ? t->lev[l] : nullptr;
+        a.dx[k] = (l >= 0) ? (float)(t->box_cm * std::ldexp(1.0, -l)) : 0.f;
+        a.kt[k] = {w->off[k], w->w[k], w->len[k]};
+    }
+    a.dxL = (float)(t->box_cm * std::ldexp(1.0, -L));
+    a.q4 = q4;
+    a.x4 = x4;
+    a.kloc = w->kloc;
+    a.D = D;
+    a.N = N;
+    a.chi = chi;
+    a.chi_scale = chi_scale;
+    const int64_t n_oct = (int64_t)1 << (3 * (L - 1));
+    if (D <= 12) launch_fine<12>(a, n_oct, s);
+    else if (D <= 16) launch_fine<16>(a, n_oct, s);
+    else if (D <= 24) launch_fine<24>(a, n_oct, s);
+    else launch_fine<48>(a, n_oct, s);
 }
 
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
@@ -320,12 +356,26 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         return CD_EINVAL;
     }
     const bool split = w->precision != CD_FP32;
+    if (split && !tiled_supported(t, w)) {
+        set_error("cd_column_densities: split precision on uniform grids needs 2^L >= 32 cells per axis "
+                  "and D in {6, 12, 24, 40, 48}");
+        return CD_EUNSUPPORTED;
+    }
+    if (L < 1) {
+        set_error("cd_column_densities: a single-cell tree has no oct");
+        return CD_EINVAL;
+    }
+    if (w->mode == CD_INSITU && !tiled_supported(t, w)) {
+        // the per-oct kernel, with the walked shells dl >= 4 of each oct
+        // written to a row per oct in place of the coarse tables
+        int rc = ensure_ext(t, D);
+        if (rc != CD_OK) return rc;
+        launch_insitu_coarse(t, w, t->ext, false, s);
+        launch_fine_path(t, w, nullptr, L >= 4 ? t->ext : nullptr, N, chi, chi_scale, s);
+        CD_HIP(hipGetLastError());
+        return CD_OK;
+    }
     if (w->mode == CD_INSITU) {
-        if (!tiled_supported(t, w)) {
-            set_error("cd_column_densities: in-situ reference points need the tiled kernels (2^L >= 32 cells per "
-                      "axis and D in {6, 12, 24, 40, 48})");
-            return CD_EUNSUPPORTED;
-        }
         // shells dl = 1..3 (the same in both schemes), then the in-situ
         // shells dl >= 4 added per oct, then the target rows
         int rc = ensure_ext(t, D);
@@ -342,7 +392,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         else launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), s);
         CD_HIP(mark(CD_STAGE_EXTERNAL, 1, s));
         CD_HIP(mark(CD_STAGE_COARSE, 0, s));
-        launch_insitu_coarse(t, w, t->ext, s);
+        launch_insitu_coarse(t, w, t->ext, true, s);
         CD_HIP(mark(CD_STAGE_COARSE, 1, s));
         CD_HIP(mark(CD_STAGE_ROWS, 0, s));
         launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s);
@@ -350,11 +400,6 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
         CD_HIP(hipGetLastError());
         return CD_OK;
-    }
-    if (split && !tiled_supported(t, w)) {
-        set_error("cd_column_densities: split precision on uniform grids needs 2^L >= 32 cells per axis "
-                  "and D in {6, 12, 24, 40, 48}");
-        return CD_EUNSUPPORTED;
     }
     int rc = ensure_q(t, D, L - 4, true);
     if (rc != CD_OK) return rc;
@@ -411,32 +456,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         return CD_OK;
     }
     launch_coarse(t, w, L - 4, true, s, nullptr);
-    if (L >= 1) {
-        FineArgs a{};
-        a.leaf = t->leaf;
-        a.L = L;
-        for (int k = 1; k <= 3; ++k) {
-            const int l = L - k;
-            a.lev[k] = (l >= 0) ? t->lev[l] : nullptr;
-            a.dx[k] = (l >= 0) ? (float)(t->box_cm * std::ldexp(1.0, -l)) : 0.f;
-            a.kt[k] = {w->off[k], w->w[k], w->len[k]};
-        }
-        a.dxL = (float)(t->box_cm * std::ldexp(1.0, -L));
-        a.q4 = (L - 4 >= 2) ? t->q[L - 4] : nullptr;
-        a.kloc = w->kloc;
-        a.D = D;
-        a.N = N;
-        a.chi = chi;
-        a.chi_scale = chi_scale;
-        const int64_t n_oct = (int64_t)1 << (3 * (L - 1));
-        if (D <= 12) launch_fine<12>(a, n_oct, s);
-        else if (D <= 16) launch_fine<16>(a, n_oct, s);
-        else if (D <= 24) launch_fine<24>(a, n_oct, s);
-        else launch_fine<48>(a, n_oct, s);
-    } else {
-        set_error("cd_column_densities: a single-cell tree has no oct");
-        return CD_EINVAL;
-    }
+    launch_fine_path(t, w, (L - 4 >= 2) ? t->q[L - 4] : nullptr, nullptr, N, chi, chi_scale, s);
     CD_HIP(hipGetLastError());
     return CD_OK;
 }

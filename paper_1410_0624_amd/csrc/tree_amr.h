@@ -64,6 +64,7 @@ struct AmrSweepArgs {
     const float* E;        // shells dl = 1..3 computed by a tiled or split kernel, or nullptr
     const int64_t* erow;   // row of E per target (-1: lists), or nullptr: row g
     int all_rows;          // every target has a row of E (no -1 in erow)
+    const float* x4;       // in-situ mode: shells dl >= 4 per target [n_tg][D] (instead of the q tables)
     float* N;
     float* chi;
     float chi_scale;

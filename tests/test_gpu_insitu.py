@@ -60,6 +60,21 @@ def test_insitu_parity(colden, L, dname, sample):
     assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
 
 
+@pytest.mark.parametrize("L,D", [(2, 12), (3, 12), (4, 12), (5, 7), (6, 7), (6, 13), (7, 3)])
+def test_insitu_per_oct_kernel(colden, L, D):
+    """Uniform grids without the tiled kernels (2^L < 32 or D outside the
+    tiled set): the per-oct kernel with the walked rows of each oct."""
+    tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=60 + L)
+    dirs = DIRS["healpix1"] if D == 12 else _rand_dirs(D, 70 + D)
+    N, chi = _run(colden, tin, dirs, colden.CD_INSITU)
+    ref = oracle.Tree(tin).columns(dirs, mode=oracle.INSITU)
+    rel = np.abs(N - ref) / ref
+    print(f"insitu per-oct L={L} D={D}: max rel {rel.max():.3e}")
+    assert np.isfinite(N).all()
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
+
+
 @pytest.mark.parametrize("prec,pname", [(1, "bf16x2"), (2, "fp16x2")])
 def test_insitu_split_forms(colden, prec, pname):
     tin = synth.workload_uniform(6, sigma=1.5, mean=10.0, seed=33)
@@ -88,22 +103,73 @@ def test_insitu_differs_from_precalc_as_the_paper_reports(colden):
     assert dchi.mean() < 0.02
 
 
+@pytest.mark.parametrize("Lf,B,th,dname", [(6, 3, 14.0, "healpix1"), (6, 2, 14.0, "axes6"), (7, 5, 30.0, "healpix2"),
+                                           (7, 5, 30.0, "mn3x8"), (6, 3, 14.0, "rand7")])
+def test_insitu_amr_parity(colden, Lf, B, th, dname):
+    """Adaptive trees: the walk of the shells dl >= 4 per target oct (any
+    level), the shells dl = 1..3 from the tiled kernels where the target's
+    level has tiles, else from the weight lists (D = 7 everywhere)."""
+    tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, 50 + B), B, th, 10 * synth.PC_CM)
+    assert tin.max_level > tin.base_level
+    dirs = DIRS[dname] if dname in DIRS else _rand_dirs(7, 3)
+    N, chi = _run(colden, tin, dirs, colden.CD_INSITU)
+    ref = oracle.Tree(tin).columns(dirs, mode=oracle.INSITU)
+    rel = np.abs(N - ref) / ref
+    print(f"insitu AMR {Lf}/{B} {dname} ({tin.n_leaf} leaves): max rel {rel.max():.3e}")
+    assert np.isfinite(N).all()
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
+
+
+@pytest.mark.parametrize("prec,pname", [(1, "bf16x2"), (2, "fp16x2")])
+def test_insitu_amr_split_forms(colden, prec, pname):
+    tin = synth.amr_tree(synth.lognormal_field(128, 2.0, 10.0, 55), 5, 30.0, 10 * synth.PC_CM)
+    dirs = DIRS["healpix1"]
+    N, _ = _run(colden, tin, dirs, colden.CD_INSITU, precision=prec)
+    ref = oracle.Tree(tin).columns(dirs, mode=oracle.INSITU)
+    err = np.abs(np.log(N) - np.log(ref))
+    print(f"insitu AMR {pname}: max |d ln N| {err.max():.3e}")
+    assert err.max() <= 1e-3
+
+
+def test_insitu_amr_c3_sampled(colden):
+    """The 128^3-base, 512^3-finest clump workload (base 7, Lmax 9), 48
+    directions, sampled leaves of every level."""
+    tin = synth.workload_amr(7, 9)
+    dirs = DIRS["healpix2"]
+    N, chi = _run(colden, tin, dirs, colden.CD_INSITU)
+    rng = np.random.default_rng(9)
+    lv = tin.leaf_level
+    tg = np.concatenate([rng.choice(np.flatnonzero(lv == l), min(4000, int((lv == l).sum())), replace=False)
+                         for l in np.unique(lv)])
+    ref = oracle.Tree(tin).columns(dirs, tg, mode=oracle.INSITU)
+    rel = np.abs(N[tg] - ref) / ref
+    print(f"insitu C3: {tg.size} leaves, max rel {rel.max():.3e}")
+    assert np.isfinite(N).all()
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
+
+
+def _rand_dirs(D, seed):
+    u = np.random.default_rng(seed).normal(size=(D, 3))
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
 def test_insitu_unsupported_cases(colden):
     dev = torch.device("cuda:0")
-    # adaptive tree
+    # binary16 on an adaptive tree without 16^3-oct tiles on every level
     tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
     tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
-    w = colden.Weights(DIRS["healpix1"], mode=colden.CD_INSITU)
+    w = colden.Weights(DIRS["healpix1"], mode=colden.CD_INSITU, precision=2)
     N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
     with pytest.raises(colden.ColdenError) as e:
         colden.column_densities(tree, w, N)
     assert e.value.rc == colden.CD_EUNSUPPORTED
-    # grid below 32^3, and a direction count outside the tiled set
-    for L, dirs in ((4, DIRS["healpix1"]), (6, DIRS["healpix1"][:7])):
-        tin = synth.workload_uniform(L, seed=1)
-        tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
-        w = colden.Weights(dirs, mode=colden.CD_INSITU)
-        N = torch.empty((tin.n_leaf, dirs.shape[0]), dtype=torch.float32, device=dev)
-        with pytest.raises(colden.ColdenError) as e:
-            colden.column_densities(tree, w, N)
-        assert e.value.rc == colden.CD_EUNSUPPORTED
+    # split precision on a uniform grid below 32^3
+    tin = synth.workload_uniform(4, seed=1)
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    w = colden.Weights(DIRS["healpix1"], mode=colden.CD_INSITU, precision=1)
+    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.column_densities(tree, w, N)
+    assert e.value.rc == colden.CD_EUNSUPPORTED
