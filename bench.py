@@ -81,6 +81,30 @@ def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int, rows_from_e: bool) -> flo
     return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * (2 if rows_from_e else 1)
 
 
+def hbm_ceiling(torch, n_floats):
+    """Plain torch copy and fill on this GPU, sized like the row kernel's
+    output (at most 2^28 floats): the rate a streaming kernel reaches here,
+    as context for roofline.frac (whose peak is the published 8 TB/s)."""
+    n = int(min(n_floats, 1 << 28))
+    a = torch.ones(n, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {"n_bytes": n * 4}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 8 * n), ("fill", lambda: b.fill_(1.0), 4 * n)):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(20):
+            fn()
+        e1.record()
+        e1.synchronize()
+        out[f"{name}_GBps"] = nbytes / (e0.elapsed_time(e1) / 20 * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -383,6 +407,7 @@ def main():
                      "traffic": (measured_traffic(f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}")
                                  if not amr else None),
                      "kernel": kname, "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
+        "hbm_ceiling": hbm_ceiling(torch, tin.n_leaf * D),
         "stages_ms": stage_ms,
         "sweep": {"alg_bytes": sweep_bytes, "ms": stage_ms["sweep"],
                   "GB_per_s": sweep_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},

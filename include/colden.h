@@ -105,8 +105,9 @@ int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D)
  *   leaf_n_dev       device float [n_leaf] leaf densities in leaf order.
  *                    A uniform grid keeps reading this buffer in every
  *                    later cd_column_densities until the next
- *                    cd_tree_update: keep it alive and unchanged.  An AMR
- *                    tree copies the leaves.
+ *                    cd_tree_update: keep it alive and unchanged (and
+ *                    8-byte aligned, else CD_EINVAL).  An AMR tree copies
+ *                    the leaves.
  *   n_leaf           number of leaves implied by the structure.
  * The structure is copied; the pyramid is built on `stream`.  Device
  * memory for the pyramid and the index maps is owned by the handle.  The
@@ -198,8 +199,9 @@ void cd_weights_destroy(cd_weights* w);
  * using av_per_nh and gamma (ignored otherwise).  The contraction runs in
  * the precision of the weights handle (see cd_precompute_weights); the
  * coarse shells (dl >= 4), the internal + local part, the level sums and chi
- * are FP32 in every form.  Asynchronous on `stream`.
- * Errors: CD_EINVAL (NULL handles or output), CD_EUNSUPPORTED (a split
+ * are FP32 in every form.  N_dev must be 16-byte aligned and chi_dev 8-byte
+ * aligned (any device allocation is).  Asynchronous on `stream`.
+ * Errors: CD_EINVAL (NULL handles or output, misaligned buffers), CD_EUNSUPPORTED (a split
  * form on a tree it is not offered for), CD_ENOMEM, CD_EDEVICE.
  */
 int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
@@ -338,7 +340,8 @@ int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* tree, const cd_weigh
 
 /* Columns of every leaf of a uniform tree from the network plus the exact
  * internal + local parts (weights w): N_dev[n_leaf][D] (cm^-2) and, if
- * chi_dev is not NULL, chi (Eq. 5) with av_per_nh, gamma.
+ * chi_dev is not NULL, chi (Eq. 5) with av_per_nh, gamma.  N_dev 16-byte
+ * and chi_dev 8-byte aligned.
  * Errors: CD_EINVAL, CD_ENOMEM. */
 int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
                        double av_per_nh, double gamma, void* stream);
@@ -352,8 +355,9 @@ int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w
  * When more than a quarter of the tiles fail, the method runs once over the
  * whole grid straight into N_dev and chi_dev instead, so every tile then holds
  * the method's values.  Synchronises the stream (the host picks the tiles).
- * Errors: CD_EINVAL (frac outside (0, 1], tree not uniform, w not FP32),
- * CD_ENOMEM, CD_EDEVICE. */
+ * N_dev 16-byte and chi_dev 8-byte aligned.
+ * Errors: CD_EINVAL (frac outside (0, 1], tree not uniform, w not FP32,
+ * misaligned buffers), CD_ENOMEM, CD_EDEVICE. */
 int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* tree, const cd_weights* w, double frac, double tol_chi,
                                 uint64_t seed, float* N_dev, float* chi_dev, double av_per_nh, double gamma,
                                 int64_t* n_fallback_tiles, int64_t* n_tiles, float* max_sample_err, void* stream);

@@ -106,6 +106,7 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     w->precision = precision;
     int brc = cd::build_tables(u, w->host);
     if (brc == CD_OK) brc = cd::build_tile_tables(u, w->host);
+    if (brc == CD_OK) brc = cd::build_gather_tables(w->host);
     if (brc != CD_OK) {
         delete w;
         return brc;
@@ -141,6 +142,8 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     if (rc == CD_OK) rc = upload(w->host.blob, &w->blob, s);
     if (rc == CD_OK) rc = upload(gf, &w->gloc, s);
     if (rc == CD_OK) rc = upload(w->host.sgn, &w->sgn, s);
+    if (rc == CD_OK) rc = upload(w->host.ghdr, &w->ghdr, s);
+    if (rc == CD_OK) rc = upload(w->host.gent, &w->gent, s);
     std::vector<double> du((size_t)D * 3);
     for (int d = 0; d < D; ++d)
         for (int k = 0; k < 3; ++k) du[(size_t)d * 3 + k] = std::fabs(u[d][k]) < 1e-14 ? 0.0 : u[d][k];
@@ -192,6 +195,8 @@ extern "C" void cd_weights_destroy(cd_weights* w) {
     if (w->blob) (void)hipFree(w->blob);
     if (w->gloc) (void)hipFree(w->gloc);
     if (w->sgn) (void)hipFree(w->sgn);
+    if (w->ghdr) (void)hipFree(w->ghdr);
+    if (w->gent) (void)hipFree(w->gent);
     if (w->dirs) (void)hipFree(w->dirs);
     cd::free_split_banks(w);
     delete w;

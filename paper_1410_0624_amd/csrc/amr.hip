@@ -28,6 +28,12 @@
 
 namespace cd {
 
+// A 16^3-oct tile with fewer targets than this (1/8 of its octs) is not
+// swept whole unless a round of the tiled launch has room for it: its
+// targets are gathered one by one (the tiled kernel's cost is per tile, the
+// gather's per target; they break even near a tenth of the octs).
+constexpr int64_t kDenseTileTargets = 512;
+
 struct AmrHost {
     std::vector<int64_t> base_dst;   // per base leaf: padded index in level B
     std::vector<int64_t> oct_dst;    // per oct leaf: index into the oct densities
@@ -40,11 +46,15 @@ struct AmrHost {
     std::vector<int8_t> leaf_level;
     std::vector<int32_t> leaf_ijk;
     std::vector<int64_t> erow;      // per target: row of its external columns in the tiled buffer, or -1
-    std::vector<int32_t> tiles[CD_MAX_LEVEL + 1];  // [l0]: active 16^3-oct tiles of the level-(l0-1) grid
+    std::vector<int32_t> tiles[CD_MAX_LEVEL + 1];  // [l0]: dense 16^3-oct tiles of the level-(l0-1) grid
+    std::vector<int32_t> tile_all, tile_lvl;       // those of every level in order, with their l0
     int64_t ebase[CD_MAX_LEVEL + 1] = {0};         // [l0]: first row of those tiles' external columns
-    int64_t erows = 0;                             // rows of the tiled buffer
+    int64_t erows = 0;                             // rows of the external-column buffer
+    int64_t tile_rows = 0;                         // of which rows of tiles
     std::vector<int32_t> grp;       // [ngroups][64]: target octs of one level and class (-1: none)
     std::vector<int32_t> grp_info;  // [ngroups][2]: level, class (A mod 4 per axis)
+    std::vector<int32_t> sgrp;      // the same groups over the targets outside the tiles (gathered)
+    std::vector<int32_t> sgrp_info;
 };
 
 struct AmrDev {
@@ -57,12 +67,16 @@ struct AmrDev {
     int64_t* tg_leaf = nullptr;
     int32_t* grp = nullptr;
     int32_t* grp_info = nullptr;
-    uint8_t* need[CD_MAX_LEVEL + 1] = {nullptr};  // coarse-table cells that targets read, levels 2 .. qtop
+    int32_t* sgrp = nullptr;
+    int32_t* sgrp_info = nullptr;
+    int64_t* need[CD_MAX_LEVEL + 1] = {nullptr};  // coarse-table entries that are read, levels 2 .. qtop
+    int64_t n_need[CD_MAX_LEVEL + 1] = {0};
     int64_t* erow = nullptr;
-    int32_t* tiles[CD_MAX_LEVEL + 1] = {nullptr};
+    int32_t* tile_all = nullptr;
+    int32_t* tile_lvl = nullptr;
     float* x4 = nullptr;  // in-situ mode: shells dl >= 4 per target [n_tg][D]
     size_t x4_bytes = 0;
-    int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0;
+    int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0, n_sgrp = 0;
     std::vector<void*> mem;
     AmrHost h;
 };
@@ -220,24 +234,150 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
     }
 }
 
+// Shells dl = 1, 2, 3 of target octs gathered straight from the dense
+// levels (Sect. 3.2-3.3, the weights of Sect. 3.3): a wave per group of up
+// to 64 target octs of one level and configuration class (A mod 4 per axis)
+// and V directions, so a direction's non-zero weights are the same for every
+// lane and come through scalar loads, while each lane reads its own
+// densities (one wave per direction chunk keeps enough waves in flight for
+// these dependent gathers).  Writes V entries of the target's row of E.  For the targets the tiled kernel would cover only at
+// the cost of whole, mostly empty, 16^3-oct tiles, and for every target of a
+// direction count the tiled kernel does not take.
+struct GatherArgs {
+    const float* lev[CD_MAX_LEVEL + 1];  // padded dense levels
+    const int32_t* tg_info;
+    const int32_t* grp;       // [ngroups][64] targets (-1: none; slot 0 always a target)
+    const int32_t* grp_info;  // [ngroups][2] level of the targets, class
+    int64_t ngroups;
+    const int32_t* ghdr;      // [64][D][4]
+    const int32_t* gent;      // [n][2]
+    const int64_t* erow;      // row of E per target (nullptr: the target's index)
+    float* E;
+    int D;
+    double box;
+};
+
+template <int V>
+__global__ __launch_bounds__(256) void k_external_gather(const GatherArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int nchunk = a.D / V;
+    const int64_t wv = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t gi = wv / nchunk;
+    if (gi >= a.ngroups) return;  // wave-uniform
+    const int d0 = (int)(wv - gi * nchunk) * V;
+    const int l0 = __builtin_amdgcn_readfirstlane(a.grp_info[2 * gi]);
+    const int ci = __builtin_amdgcn_readfirstlane(a.grp_info[2 * gi + 1]);
+    const int32_t tq = a.grp[gi * 64 + lane];
+    const bool live = tq >= 0;
+    const int64_t t = live ? tq : a.grp[gi * 64];
+    const int64_t A[3] = {a.tg_info[4 * t + 1], a.tg_info[4 * t + 2], a.tg_info[4 * t + 3]};
+    // per kind: the ancestor C = A >> (kind - 1) as a padded index of level l0 - kind
+    int64_t base[4] = {0, 0, 0, 0}, S[4] = {0, 0, 0, 0};
+    float dx[4] = {0.f, 0.f, 0.f, 0.f};
+    const float* lv[4] = {nullptr, nullptr, nullptr, nullptr};
+#pragma unroll
+    for (int k = 1; k <= 3; ++k) {
+        const int l = l0 - k;
+        if (l < 0) continue;
+        S[k] = ((int64_t)1 << l) + 2 * kHalo;
+        base[k] = (((A[2] >> (k - 1)) + kHalo) * S[k] + ((A[1] >> (k - 1)) + kHalo)) * S[k] + (A[0] >> (k - 1)) + kHalo;
+        dx[k] = (float)(a.box * ldexp(1.0, -l));
+        lv[k] = a.lev[l];
+    }
+    const int pbit = 24 + (int)(((A[0] >> 2) & 1) | (((A[1] >> 2) & 1) << 1) | (((A[2] >> 2) & 1) << 2));
+    const CD_CONST int32_t* hdr = (const CD_CONST int32_t*)a.ghdr + (int64_t)ci * a.D * 4;
+    const CD_CONST int32_t* ent = (const CD_CONST int32_t*)a.gent;
+    float* out = a.E + (a.erow ? a.erow[t] : t) * a.D;
+    {
+        float acc[V];
+#pragma unroll
+        for (int j = 0; j < V; ++j) {
+            const CD_CONST int32_t* h = hdr + (d0 + j) * 4;
+            int e = h[0];
+            const int n3 = h[3];
+            const int cnt[4] = {0, h[1], h[2], n3 & 0xffff};
+            float s[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 1; k <= 3; ++k) {
+                if (lv[k]) {
+#pragma unroll 4
+                    for (int i = 0; i < cnt[k]; ++i) {
+                        const int32_t pk = ent[2 * (e + i)];
+                        const int64_t dlt = ((int64_t)(int8_t)(pk >> 16) * S[k] + (int8_t)(pk >> 8)) * S[k] + (int8_t)pk;
+                        s[k] = fmaf(__int_as_float(ent[2 * (e + i) + 1]), lv[k][base[k] + dlt], s[k]);
+                    }
+                }
+                e += cnt[k];
+            }
+            if (lv[3]) {
+                // entries of the dl = 3 box of some parities of A >> 2 only
+#pragma unroll 4
+                for (int i = 0, n = n3 >> 16; i < n; ++i) {
+                    const int32_t pk = ent[2 * (e + i)];
+                    const int64_t dlt = ((int64_t)(int8_t)(pk >> 16) * S[3] + (int8_t)(pk >> 8)) * S[3] + (int8_t)pk;
+                    const float v = lv[3][base[3] + dlt];
+                    s[3] = fmaf(__int_as_float(ent[2 * (e + i) + 1]), ((pk >> pbit) & 1) ? v : 0.f, s[3]);
+                }
+            }
+            acc[j] = fmaf(dx[1], s[1], fmaf(dx[2], s[2], fmaf(dx[3], s[3], 0.f)));
+        }
+        if (live) {
+            if constexpr (V == 4) {
+                *reinterpret_cast<float4*>(out + d0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+            } else {
+#pragma unroll
+                for (int j = 0; j < V; ++j) out[d0 + j] = acc[j];
+            }
+        }
+    }
+}
+
+void launch_external_gather(const cd_tree* t, const cd_weights* w, const int32_t* tg_info, const int32_t* grp,
+                            const int32_t* grp_info, int64_t ngroups, const int64_t* erow, float* E, hipStream_t s) {
+    if (ngroups <= 0) return;
+    GatherArgs a{};
+    for (int l = 0; l <= t->lmax - 1; ++l) a.lev[l] = t->lev[l];  // every level below Lmax is dense
+    a.tg_info = tg_info;
+    a.grp = grp;
+    a.grp_info = grp_info;
+    a.ngroups = ngroups;
+    a.ghdr = w->ghdr;
+    a.gent = w->gent;
+    a.erow = erow;
+    a.E = E;
+    a.D = w->D;
+    a.box = t->box_cm;
+    const int V = w->D % 4 == 0 ? 4 : 1;
+    const unsigned blocks = (unsigned)((ngroups * (w->D / V) + 3) / 4);
+    if (V == 4) k_external_gather<4><<<blocks, 256, 0, s>>>(a);
+    else k_external_gather<1><<<blocks, 256, 0, s>>>(a);
+}
+
 // Rows of the targets whose shells dl = 1..3 are all in E, for the direction
 // counts of the tiled kernels: a lane per target (8 lanes per target oct, a
 // wave holds 8 octs) and the directions wave-uniform, so the chords and sign
-// bits of a direction are scalar loads.  Child c of the oct reaches its
-// sibling c ^ m only if, on every axis of m, bit of c == sign bit of u (the
-// ray mirrored into the positive octant); with the factors a_k = [bit k of c
-// == bit k of sgn] the sum over the allowed m nests as
+// bits of a direction are scalar loads.  Above 24 directions a pair of waves
+// shares 8 octs, each wave taking half of the directions (H = 2): half the
+// registers per lane, twice the waves in flight.  Child c of the oct
+// reaches its sibling c ^ m only if, on every axis of m, bit of c == sign bit
+// of u (the ray mirrored into the positive octant); with the factors a_k =
+// [bit k of c == bit k of sgn] the sum over the allowed m nests as
 //   ((y0 + a0 y1) + a1 (y2 + a0 y3)) + a2 ((y4 + a0 y5) + a1 (y6 + a0 y7)),
 // y_m = n(c ^ m) G[d][m].  Rows leave through LDS, 32 targets at a time, as
 // consecutive vector stores (targets of consecutive octs are mostly
 // consecutive leaves).
-template <int D>
+template <int D, int H>
 __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
-    constexpr int V = D % 4 == 0 ? 4 : (D % 2 == 0 ? 2 : 1);  // floats per store
+    constexpr int DH = D / H;                                     // directions of this wave
+    constexpr int V = DH % 4 == 0 ? 4 : (DH % 2 == 0 ? 2 : 1);   // floats per load of a row piece
+    constexpr int VS = D % 4 == 0 ? 4 : (D % 2 == 0 ? 2 : 1);    // floats per store of a row
+    constexpr int NG = 4 / H;                                     // oct groups of a workgroup
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int grp = w / H, h = w % H;  // wave-uniform
+    const int dh0 = h * DH;
     const int c = lane & 7;
-    const int64_t g0 = ((int64_t)blockIdx.x * 4 + w) * 8 + (lane >> 3);
+    const int64_t g0 = ((int64_t)blockIdx.x * NG + grp) * 8 + (lane >> 3);
     const bool valid = g0 < a.n_tg;
     const int64_t g = valid ? g0 : a.n_tg - 1;  // idle lanes follow a real oct and write nothing
     const int l0 = a.tg_info[4 * g];
@@ -251,27 +391,30 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
     for (int m = 1; m < 8; ++m) nx[m] = __shfl_xor(nc, m);  // sibling c ^ m (same 8-lane group)
 
     // external part: the row of E plus, for l0 - 4 >= 2, the coarse table
-    float out[D];
-    {
-        const int64_t er = a.erow ? a.erow[g] : g;
-        const float* ep = a.E + er * D;
+    // (in-situ mode: the target's row of walked shells instead)
+    float out[DH];
+    auto add_row = [&](const float* p, bool first) {
 #pragma unroll
-        for (int d = 0; d < D; d += V) {
+        for (int d = 0; d < DH; d += V) {
             if constexpr (V == 4) {
-                const float4 v = *reinterpret_cast<const float4*>(ep + d);
-                out[d] = v.x, out[d + 1] = v.y, out[d + 2] = v.z, out[d + 3] = v.w;
+                const float4 v = *reinterpret_cast<const float4*>(p + d);
+                if (first) out[d] = v.x, out[d + 1] = v.y, out[d + 2] = v.z, out[d + 3] = v.w;
+                else out[d] += v.x, out[d + 1] += v.y, out[d + 2] += v.z, out[d + 3] += v.w;
             } else if constexpr (V == 2) {
-                const float2 v = *reinterpret_cast<const float2*>(ep + d);
-                out[d] = v.x, out[d + 1] = v.y;
+                const float2 v = *reinterpret_cast<const float2*>(p + d);
+                if (first) out[d] = v.x, out[d + 1] = v.y;
+                else out[d] += v.x, out[d + 1] += v.y;
             } else {
-                out[d] = ep[d];
+                if (first) out[d] = p[d];
+                else out[d] += p[d];
             }
         }
+    };
+    add_row(a.E + (a.erow ? a.erow[g] : g) * D + dh0, true);
+    {
         const int l = l0 - 4;
-        if (a.x4) {  // in-situ mode: the target's own row
-            const float* xp = a.x4 + g * D;
-#pragma unroll
-            for (int d = 0; d < D; ++d) out[d] += xp[d];
+        if (a.x4) {
+            add_row(a.x4 + g * D + dh0, false);
         } else if (l >= 2) {
             const int sh = l0 - 1 - l;
             const int64_t nq = (int64_t)1 << l;
@@ -283,19 +426,7 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
                 const int s0 = a.dl4[(Ax >> 1) & 3], s1 = a.dl4[(Ay >> 1) & 3], s2 = a.dl4[(Az >> 1) & 3];
                 code = cell * 216 + s0 + 6 * s1 + 36 * s2;
             }
-            const float* qp = a.q[l] + code * D;
-#pragma unroll
-            for (int d = 0; d < D; d += V) {
-                if constexpr (V == 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(qp + d);
-                    out[d] += v.x, out[d + 1] += v.y, out[d + 2] += v.z, out[d + 3] += v.w;
-                } else if constexpr (V == 2) {
-                    const float2 v = *reinterpret_cast<const float2*>(qp + d);
-                    out[d] += v.x, out[d + 1] += v.y;
-                } else {
-                    out[d] += qp[d];
-                }
-            }
+            add_row(a.q[l] + code * D + dh0, false);
         }
     }
     // internal + local (Sect. 3.2) and the screening sum (Eq. 5)
@@ -303,9 +434,9 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
     const float b0 = (float)(c & 1), b1 = (float)((c >> 1) & 1), b2 = (float)(c >> 2);
     float chi = 0.f;
 #pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const int sg = ((const CD_CONST int32_t*)a.sgn)[d];
-        const CD_CONST float* gl = (const CD_CONST float*)a.gloc + d * 8;
+    for (int d = 0; d < DH; ++d) {
+        const int sg = ((const CD_CONST int32_t*)a.sgn)[dh0 + d];
+        const CD_CONST float* gl = (const CD_CONST float*)a.gloc + (dh0 + d) * 8;
         const float a0 = (sg & 1) ? b0 : 1.f - b0;
         const float a1 = (sg & 2) ? b1 : 1.f - b1;
         const float a2 = (sg & 4) ? b2 : 1.f - b2;
@@ -317,47 +448,77 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
         out[d] = fmaf(dxL, s, out[d]);
         chi += __expf(-a.chi_scale * out[d]);
     }
-    if (a.chi && leaf >= 0) a.chi[leaf] = chi * (1.f / (float)D);
+    __shared__ float chip[NG][64];
+    if constexpr (H == 2) {
+        // the two halves of the screening sum meet in LDS
+        if (h == 1) chip[grp][lane] = chi;
+        __syncthreads();
+        if (h == 0) chi += chip[grp][lane];
+    }
+    if (a.chi && leaf >= 0 && h == 0) a.chi[leaf] = chi * (1.f / (float)D);
 
-    // rows through LDS: lanes 32 p .. 32 p + 31 in pass p
-    __shared__ __align__(16) float stage[4][32 * D];
-    __shared__ int64_t rows[4][32];
-    float* st = stage[w];
+    // rows through LDS: lanes 32 p .. 32 p + 31 in pass p (both halves of a pair)
+    __shared__ __align__(16) float stage[NG][32 * D];
+    __shared__ int64_t rows[NG][32];
+    float* st = stage[grp];
+    auto sync = [&]() {
+        if constexpr (H == 1) {
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+        } else {
+            __syncthreads();
+        }
+    };
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
         if ((lane >> 5) == p) {
-            float* r = st + (lane & 31) * D;
+            float* r = st + (lane & 31) * D + dh0;
 #pragma unroll
-            for (int d = 0; d < D; ++d) r[d] = out[d];
-            rows[w][lane & 31] = leaf;
+            for (int d = 0; d < DH; ++d) r[d] = out[d];
+            if (h == 0) rows[grp][lane & 31] = leaf;
         }
-        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
-        __builtin_amdgcn_wave_barrier();
-        constexpr int nv = 32 * D / V;
-        for (int i = lane; i < nv; i += 64) {
-            const int r = (i * V) / D, col = i * V - r * D;
-            const int64_t lf = rows[w][r];
+        sync();
+        constexpr int nv = 32 * D / VS;
+        for (int i = h * 64 + lane; i < nv; i += 64 * H) {
+            const int r = (i * VS) / D, col = i * VS - r * D;
+            const int64_t lf = rows[grp][r];
             if (lf < 0) continue;
             float* dst = a.N + lf * D + col;
-            if constexpr (V == 4) *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(st + i * V);
-            else if constexpr (V == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(st + i * V);
+            if constexpr (VS == 4) *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(st + i * VS);
+            else if constexpr (VS == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(st + i * VS);
             else *dst = st[i];
         }
-        __builtin_amdgcn_s_waitcnt(0xc07f);
-        __builtin_amdgcn_wave_barrier();
+        sync();
     }
 }
 
-// Dense padded level l > B: each cell's density through the maps (the cell,
-// or the covering coarser leaf), so the sweep reads every level below Lmax
-// with one load.
-__global__ void k_inject(const AmrLookupView lk, int l, float* __restrict__ out) {
-    const int64_t n = (int64_t)1 << l;
+// Dense padded level l > B, so that the sweep reads every level below Lmax
+// with one load: a thread per level-(l-1) cell P writes its 8 children, the
+// oct's densities where P is refined, else P's own density (the covering
+// coarser leaf), read from the dense level l-1 built before this one.
+__global__ void k_inject(const int32_t* __restrict__ octidx, const float* __restrict__ den,
+                         const float* __restrict__ coarse, int l, float* __restrict__ out) {
+    const int lp = l - 1;
+    const int64_t np = (int64_t)1 << lp;
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n * n) return;
-    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
-    const int64_t S = n + 2 * kHalo;
-    out[((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)] = lk.density(l, i, j, k);
+    if (idx >= np * np * np) return;
+    const int64_t i = idx & (np - 1), j = (idx >> lp) & (np - 1), k = idx >> (2 * lp);
+    const int32_t o = octidx[idx];
+    float v[8];
+    if (o >= 0) {
+        const float4 lo = *reinterpret_cast<const float4*>(den + (int64_t)o * 8);
+        const float4 hi = *reinterpret_cast<const float4*>(den + (int64_t)o * 8 + 4);
+        v[0] = lo.x, v[1] = lo.y, v[2] = lo.z, v[3] = lo.w, v[4] = hi.x, v[5] = hi.y, v[6] = hi.z, v[7] = hi.w;
+    } else {
+        const int64_t Sp = np + 2 * kHalo;
+        const float c = coarse[((k + kHalo) * Sp + (j + kHalo)) * Sp + (i + kHalo)];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = c;
+    }
+    const int64_t S = 2 * np + 2 * kHalo;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+        out[((2 * k + (q >> 2) + kHalo) * S + (2 * j + ((q >> 1) & 1) + kHalo)) * S + (2 * i + (q & 1) + kHalo)] = v[q];
 }
 
 // ------------------------------------------------------------------- host --
@@ -513,74 +674,144 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
             }
         }
     A->n_tg = (int64_t)(h.tg_info.size() / 4);
-    // groups of the split-precision kernel: up to 64 targets of one level and class
-    {
+    // groups of up to 64 targets of one level and configuration class (A mod
+    // 4 per axis): the gather kernels take a wave per group.  Within a key
+    // the targets follow the Morton order of A >> 2, so that a group's
+    // neighbourhoods overlap (shared cache lines) as far as the tree allows.
+    auto morton = [](const int32_t* ti) {
+        uint64_t m = 0;
+        for (int b = 0; b < 20; ++b)
+            for (int a = 0; a < 3; ++a) m |= (uint64_t)(((uint32_t)ti[1 + a] >> (b + 2)) & 1u) << (3 * b + a);
+        return m;
+    };
+    auto make_groups = [&](const std::vector<uint8_t>* pick, std::vector<int32_t>& grp,
+                           std::vector<int32_t>& info) {
         std::vector<std::vector<int32_t>> bykey((size_t)(L + 1) * 64);
         for (int64_t q = 0; q < A->n_tg; ++q) {
+            if (pick && !(*pick)[(size_t)q]) continue;
             const int32_t* ti = &h.tg_info[4 * q];
             bykey[(size_t)ti[0] * 64 + (ti[1] & 3) + 4 * (ti[2] & 3) + 16 * (ti[3] & 3)].push_back((int32_t)q);
         }
+        for (auto& v : bykey)
+            std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
+                return morton(&h.tg_info[4 * (size_t)x]) < morton(&h.tg_info[4 * (size_t)y]);
+            });
         for (size_t key = 0; key < bykey.size(); ++key)
             for (size_t f = 0; f < bykey[key].size(); f += 64) {
-                for (size_t e = 0; e < 64; ++e)
-                    h.grp.push_back(f + e < bykey[key].size() ? bykey[key][f + e] : -1);
-                h.grp_info.push_back((int32_t)(key / 64));
-                h.grp_info.push_back((int32_t)(key % 64));
+                for (size_t e = 0; e < 64; ++e) grp.push_back(f + e < bykey[key].size() ? bykey[key][f + e] : -1);
+                info.push_back((int32_t)(key / 64));
+                info.push_back((int32_t)(key % 64));
             }
-        A->n_grp = (int64_t)(h.grp_info.size() / 2);
-    }
-    // targets whose oct grid has 16^3-oct tiles (2^(l0-1) >= 16): their
-    // shells dl = 1..3 come from the tiled kernel run on the active tiles of
-    // their level (the grid below Lmax is dense), one row per oct of a tile
+        return (int64_t)(info.size() / 2);
+    };
+    A->n_grp = make_groups(nullptr, h.grp, h.grp_info);
+    // Every target gets a row of external columns (shells dl = 1..3).  Where
+    // the oct grid has 16^3-oct tiles (2^(l0-1) >= 16) and a tile holds at
+    // least kDenseTileTargets targets, the tiled kernel computes the whole
+    // tile (one row per oct of the tile); the targets of sparser tiles and
+    // of coarser levels are gathered per target into rows after the tiles'.
     h.erow.assign((size_t)A->n_tg, -1);
+    std::vector<uint8_t> gathered((size_t)A->n_tg, 1);
     {
+        auto tile_of = [](const int32_t* ti) {
+            const int64_t tpa = (int64_t)1 << (ti[0] - 1 - 4);
+            return ((int64_t)(ti[3] >> 4) * tpa + (ti[2] >> 4)) * tpa + (ti[1] >> 4);
+        };
         std::vector<std::vector<int64_t>> tl(L + 1);
         for (int64_t q = 0; q < A->n_tg; ++q) {
             const int32_t* ti = &h.tg_info[4 * q];
-            const int l0 = ti[0];
-            if (l0 - 1 < 4) continue;
-            const int64_t tpa = (int64_t)1 << (l0 - 1 - 4);
-            tl[l0].push_back(((int64_t)(ti[3] >> 4) * tpa + (ti[2] >> 4)) * tpa + (ti[1] >> 4));
+            if (ti[0] - 1 >= 4) tl[ti[0]].push_back(tile_of(ti));
         }
+        int dev = 0, n_cu = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            n_cu = 1;
+        // occupied tiles (count, level, tile): the dense ones, and then the
+        // next densest up to a whole number of workgroup rounds (one tile per
+        // compute unit and round), which the tiled launch takes at no extra time
+        std::vector<std::array<int64_t, 3>> occ;
         for (int l0 = 0; l0 <= L; ++l0) {
-            std::sort(tl[l0].begin(), tl[l0].end());
-            tl[l0].erase(std::unique(tl[l0].begin(), tl[l0].end()), tl[l0].end());
-            h.tiles[l0].assign(tl[l0].begin(), tl[l0].end());
+            std::vector<int64_t>& v = tl[l0];
+            std::sort(v.begin(), v.end());
+            for (size_t i = 0; i < v.size();) {
+                size_t j = i;
+                while (j < v.size() && v[j] == v[i]) ++j;
+                occ.push_back({(int64_t)(j - i), l0, v[i]});
+                i = j;
+            }
+        }
+        std::sort(occ.begin(), occ.end(), [](const std::array<int64_t, 3>& x, const std::array<int64_t, 3>& y) {
+            return x[0] != y[0] ? x[0] > y[0] : (x[1] != y[1] ? x[1] < y[1] : x[2] < y[2]);
+        });
+        int64_t ndense = 0;
+        while (ndense < (int64_t)occ.size() && occ[(size_t)ndense][0] >= kDenseTileTargets) ++ndense;
+        const int64_t round = std::max(1, n_cu);
+        const int64_t ntile = std::min<int64_t>((int64_t)occ.size(), (ndense + round - 1) / round * round);
+        for (int l0 = 0; l0 <= L; ++l0) h.tiles[l0].clear();
+        for (int64_t i = 0; i < ntile; ++i) h.tiles[occ[(size_t)i][1]].push_back((int32_t)occ[(size_t)i][2]);
+        for (int l0 = 0; l0 <= L; ++l0) {
+            std::sort(h.tiles[l0].begin(), h.tiles[l0].end());
             h.ebase[l0] = h.erows;
-            h.erows += (int64_t)tl[l0].size() * 4096;
+            h.erows += (int64_t)h.tiles[l0].size() * 4096;
+            h.tile_all.insert(h.tile_all.end(), h.tiles[l0].begin(), h.tiles[l0].end());
+            h.tile_lvl.insert(h.tile_lvl.end(), h.tiles[l0].size(), l0);
         }
         for (int64_t q = 0; q < A->n_tg; ++q) {
             const int32_t* ti = &h.tg_info[4 * q];
             const int l0 = ti[0];
             if (l0 - 1 < 4) continue;
-            const int64_t tpa = (int64_t)1 << (l0 - 1 - 4);
-            const int64_t tile = ((int64_t)(ti[3] >> 4) * tpa + (ti[2] >> 4)) * tpa + (ti[1] >> 4);
-            const int64_t pos = std::lower_bound(h.tiles[l0].begin(), h.tiles[l0].end(), (int32_t)tile) - h.tiles[l0].begin();
+            const int64_t tile = tile_of(ti);
+            const auto it = std::lower_bound(h.tiles[l0].begin(), h.tiles[l0].end(), (int32_t)tile);
+            if (it == h.tiles[l0].end() || *it != (int32_t)tile) continue;
             const int64_t local = (((int64_t)(ti[3] & 15) * 16) + (ti[2] & 15)) * 16 + (ti[1] & 15);
-            h.erow[(size_t)q] = h.ebase[l0] + pos * 4096 + local;
+            h.erow[(size_t)q] = h.ebase[l0] + (int64_t)(it - h.tiles[l0].begin()) * 4096 + local;
+            gathered[(size_t)q] = 0;
         }
+        h.tile_rows = h.erows;
+        for (int64_t q = 0; q < A->n_tg; ++q)
+            if (gathered[(size_t)q]) h.erow[(size_t)q] = h.erows++;
     }
-    // coarse-table cells that are read: the level-lq ancestor of each target
-    // (lq = min(l0 - 4, qtop)) and, recursively, their parents
+    A->n_sgrp = make_groups(&gathered, h.sgrp, h.sgrp_info);
+    // coarse-table entries that are read: (cell, code) of the level-(l0-4)
+    // ancestor of each target (the table at qtop holds the 64 codes of dl = 4,
+    // the others the 216 inner-limit states), and recursively the (parent
+    // cell, parent code) each entry adds; sorted keys cell * ncodes + code
     const int qtop = L - 4;  // every level below Lmax is dense (injected above B)
-    std::vector<std::vector<uint8_t>> need(CD_MAX_LEVEL + 1);
+    std::vector<std::vector<int64_t>> need(CD_MAX_LEVEL + 1);
     if (qtop >= 2) {
-        for (int l = 2; l <= qtop; ++l) need[l].assign((size_t)1 << (3 * l), 0);
+        int dl4[4], nxt[6][2];
+        for (int q = 0; q < 4; ++q) dl4[q] = state_code_dl4(q >> 1, q & 1);
+        for (int sc = 0; sc < 6; ++sc)
+            for (int p = 0; p < 2; ++p) nxt[sc][p] = next_state_code(sc, p);
         for (int64_t q = 0; q < A->n_tg; ++q) {
             const int32_t* ti = &h.tg_info[4 * q];
-            const int l0 = ti[0], lq = std::min(l0 - 4, qtop);
+            const int l0 = ti[0], lq = l0 - 4;
             if (lq < 2) continue;
             const int sh = l0 - 1 - lq;
             const int64_t nq = (int64_t)1 << lq;
-            need[lq][(size_t)((((int64_t)ti[3] >> sh) * nq + ((int64_t)ti[2] >> sh)) * nq + ((int64_t)ti[1] >> sh))] = 1;
+            const int64_t cell = (((int64_t)ti[3] >> sh) * nq + ((int64_t)ti[2] >> sh)) * nq + ((int64_t)ti[1] >> sh);
+            const int b[3] = {(ti[1] >> 1) & 3, (ti[2] >> 1) & 3, (ti[3] >> 1) & 3};
+            const int64_t code = lq == qtop ? b[0] + 4 * b[1] + 16 * b[2] : dl4[b[0]] + 6 * dl4[b[1]] + 36 * dl4[b[2]];
+            need[lq].push_back(cell * (lq == qtop ? 64 : 216) + code);
         }
-        for (int l = qtop; l > 2; --l) {
-            const int64_t n = (int64_t)1 << l, np = n >> 1;
-            for (int64_t k = 0; k < n; ++k)
-                for (int64_t j = 0; j < n; ++j)
-                    for (int64_t i = 0; i < n; ++i)
-                        if (need[l][(size_t)((k * n + j) * n + i)])
-                            need[l - 1][(size_t)(((k >> 1) * np + (j >> 1)) * np + (i >> 1))] = 1;
+        for (int l = qtop; l >= 2; --l) {
+            std::vector<int64_t>& v = need[l];
+            std::sort(v.begin(), v.end());
+            v.erase(std::unique(v.begin(), v.end()), v.end());
+            if (l == 2) break;
+            const int64_t ncodes = l == qtop ? 64 : 216, n = (int64_t)1 << l, np = n >> 1;
+            for (const int64_t key : v) {
+                const int64_t cell = key / ncodes;
+                const int code = (int)(key % ncodes);
+                const int64_t c[3] = {cell & (n - 1), (cell >> l) & (n - 1), cell >> (2 * l)};
+                int pcode = 0, mul = 1;
+                for (int k = 0; k < 3; ++k) {
+                    const int st = l == qtop ? dl4[(code >> (2 * k)) & 3] : (code / mul) % 6;
+                    pcode += nxt[st][c[k] & 1] * mul;
+                    mul *= 6;
+                }
+                need[l - 1].push_back((((c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1)) * 216 + pcode);
+            }
         }
     }
     // device memory
@@ -607,11 +838,19 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     if ((rc = dev_copy(h.tg_leaf, &A->tg_leaf, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.grp, &A->grp, s, A->mem)) != CD_OK) return rc;
     if ((rc = dev_copy(h.grp_info, &A->grp_info, s, A->mem)) != CD_OK) return rc;
-    for (int l = 2; l <= qtop; ++l)
+    if (!h.sgrp.empty()) {
+        if ((rc = dev_copy(h.sgrp, &A->sgrp, s, A->mem)) != CD_OK) return rc;
+        if ((rc = dev_copy(h.sgrp_info, &A->sgrp_info, s, A->mem)) != CD_OK) return rc;
+    }
+    for (int l = 2; l <= qtop; ++l) {
         if ((rc = dev_copy(need[l], &A->need[l], s, A->mem)) != CD_OK) return rc;
+        A->n_need[l] = (int64_t)need[l].size();
+    }
     if ((rc = dev_copy(h.erow, &A->erow, s, A->mem)) != CD_OK) return rc;
-    for (int l0 = 0; l0 <= L; ++l0)
-        if (!h.tiles[l0].empty() && (rc = dev_copy(h.tiles[l0], &A->tiles[l0], s, A->mem)) != CD_OK) return rc;
+    if (!h.tile_all.empty()) {
+        if ((rc = dev_copy(h.tile_all, &A->tile_all, s, A->mem)) != CD_OK) return rc;
+        if ((rc = dev_copy(h.tile_lvl, &A->tile_lvl, s, A->mem)) != CD_OK) return rc;
+    }
     CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
     return amr_update(t, leaf_n_dev, s);
 }
@@ -640,8 +879,9 @@ int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s) {
     }
     lk.B = B;
     for (int l = B + 1; l <= L - 1; ++l) {
-        const int64_t cells = (int64_t)1 << (3 * l);
-        k_inject<<<(unsigned)((cells + 255) / 256), 256, 0, s>>>(lk, l, t->lev[l]);
+        const int64_t parents = (int64_t)1 << (3 * (l - 1));
+        k_inject<<<(unsigned)((parents + 255) / 256), 256, 0, s>>>(t->d_octidx[l], lk.den[l], t->lev[l - 1], l,
+                                                                      t->lev[l]);
     }
     CD_HIP(hipGetLastError());
     return build_dense_below(t, B, s);
@@ -657,30 +897,33 @@ int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
 int ensure_q(cd_tree* t, int D, int top, bool compact);                                     // sweep.hip
 int ensure_aux(cd_tree* t);                                                                 // sweep.hip
 bool tiled_weights_ok(const cd_weights* w);                                                 // sweep_tile.hip
-void launch_external_mfma_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
-                               const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E,
-                               hipStream_t s);                                              // split.hip
-void launch_external_tiled_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
-                                const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E,
-                                hipStream_t s);                                             // sweep_tile.hip
+void launch_external_mfma_list(const float* const* levs, int nlev, double box, const cd_weights* w,
+                               const int32_t* tiles, const int32_t* lvls, int64_t ntiles, float* E,
+                               hipStream_t s);  // split.hip
+void launch_external_tiled_list(const float* const* levs, int nlev, double box, const cd_weights* w,
+                                const int32_t* tiles, const int32_t* lvls, int64_t ntiles, float* E,
+                                hipStream_t s);  // sweep_tile.hip
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
-                   const uint8_t* const* need = nullptr);  // sweep.hip
+                   const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);  // sweep.hip
 void launch_insitu_targets(const cd_tree* t, const cd_weights* w, const int32_t* info, int64_t n_tg, float* X,
                            hipStream_t s);  // insitu.hip
+void launch_external_gather(const cd_tree* t, const cd_weights* w, const int32_t* tg_info, const int32_t* grp,
+                            const int32_t* grp_info, int64_t ngroups, const int64_t* erow, float* E, hipStream_t s);
 
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
     const bool insitu = w->mode == CD_INSITU;
     AmrDev* A = t->amr;
-    const int B = t->base, L = t->lmax;
+    const int L = t->lmax;
     const int qtop = L - 4;  // every level below Lmax is dense
-    // every target on a level with 16^3-oct tiles: the shells dl = 1..3 come
-    // from the tiled kernels (FP32 or split) on the active tiles
+    // the shells dl = 1..3 of the targets in densely occupied 16^3-oct tiles
+    // come from the tiled kernels (FP32 or split), those of the others from
+    // the FP32 gather; direction counts the tiled kernels do not take are
+    // gathered for every target (FP32, or on the matrix cores in bf16x2)
     const int D = w->D;
-    const bool all_tiled = B >= 5;
-    const bool split_tiled = all_tiled && (D == 6 || D == 12 || D == 24 || D == 40 || D == 48);
-    if (w->precision == CD_FP16X2 && !split_tiled) {
-        set_error("cd_column_densities: CD_FP16X2 on adaptive trees needs a base level >= 5 and D in "
-                  "{6, 12, 24, 40, 48} (binary16 needs the per-tile scale of the tiled kernel)");
+    const bool dset = D == 6 || D == 12 || D == 24 || D == 40 || D == 48;
+    if (w->precision == CD_FP16X2 && !dset) {
+        set_error("cd_column_densities: CD_FP16X2 on adaptive trees needs D in {6, 12, 24, 40, 48} "
+                  "(binary16 needs the per-tile scale of the tiled kernel)");
         return CD_EUNSUPPORTED;
     }
     if (w->len[4] != 12) {
@@ -705,96 +948,87 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     } else if ((rc = ensure_q(t, w->D, qtop, compact)) != CD_OK) {
         return rc;
     }
-    // the coarse tables (or the in-situ walks) on the second stream, concurrent
-    // with the kernel of the shells dl = 1..3 (none for FP32 weights the tiled
-    // kernel cannot take)
     const bool split = w->precision != CD_FP32;
-    const bool tiled = (split ? split_tiled : tiled_weights_ok(w)) && A->h.erows > 0;
-    const bool overlap = split || tiled;  // an external kernel runs beside the coarse tables
-    hipStream_t cs = s;
-    if (overlap) {
-        if ((rc = ensure_aux(t)) != CD_OK) return rc;
-        cs = t->aux;
+    const bool tiled = split ? dset : tiled_weights_ok(w);
+    if ((rc = ensure_aux(t)) != CD_OK) return rc;
+    hipStream_t cs = t->aux;
+    const int64_t* erow = tiled ? A->erow : nullptr;
+    {
+        // rows of the tiles and of the gathered targets, or one per target
+        const size_t bytes = (size_t)std::max<int64_t>(tiled ? A->h.erows : A->n_tg, 1) * w->D * sizeof(float);
+        if (t->ext_bytes < bytes) {
+            if (t->ext) (void)hipFree(t->ext);
+            t->ext = nullptr;
+            t->ext_bytes = 0;
+            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
+                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
+                return CD_ENOMEM;
+            }
+            t->ext_bytes = bytes;
+        }
     }
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
-    if (overlap) {
-        CD_HIP(hipEventRecord(t->ev[0], s));
-        CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
-    }
-    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], cs));
-    if (insitu)
-        launch_insitu_targets(t, w, A->tg_info, A->n_tg, A->x4, cs);
-    else
-        launch_coarse(t, w, qtop, compact, cs, A->need);
-    if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], cs));
-    if (overlap) CD_HIP(hipEventRecord(t->ev[1], cs));
+    CD_HIP(hipEventRecord(t->ev[0], s));
+    CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
+    // shells dl >= 4: the coarse tables, or the in-situ walks
+    auto coarse = [&](hipStream_t st) -> int {
+        if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][0], st));
+        if (insitu)
+            launch_insitu_targets(t, w, A->tg_info, A->n_tg, A->x4, st);
+        else
+            launch_coarse(t, w, qtop, compact, st, A->need, A->n_need);
+        if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_COARSE][1], st));
+        return CD_OK;
+    };
     // shells reach levels <= Lmax - 1, all dense (injected above B by the update)
     AmrLookupView lk{};
     for (int l = 0; l <= L - 1; ++l) lk.lev[l] = t->lev[l];
     lk.B = L - 1;
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][0], s));
-    const float* E = nullptr;
-    const int64_t* erow = nullptr;
     if (tiled) {
-        // shells dl = 1..3 of the targets on tiles: the tiled kernel per level
-        const size_t bytes = (size_t)A->h.erows * w->D * sizeof(float);
-        if (t->ext_bytes < bytes) {
-            if (t->ext) (void)hipFree(t->ext);
-            t->ext = nullptr;
-            t->ext_bytes = 0;
-            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
-                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
-                return CD_ENOMEM;
-            }
-            t->ext_bytes = bytes;
+        // the dense tiles of every level in one launch (a workgroup per tile
+        // fills the chip only with all levels together), beside it on the
+        // second stream the gathered targets; the coarse tables (small
+        // kernels that would wait behind either) after the tiles.  The
+        // in-situ walks, long themselves, take the second stream instead.
+        const int64_t nt = (int64_t)A->h.tile_all.size();
+        if (split)
+            launch_external_mfma_list(t->lev, L, t->box_cm, w, A->tile_all, A->tile_lvl, nt, t->ext, s);
+        else
+            launch_external_tiled_list(t->lev, L, t->box_cm, w, A->tile_all, A->tile_lvl, nt, t->ext, s);
+        if (insitu) {
+            if ((rc = coarse(cs)) != CD_OK) return rc;
+            launch_external_gather(t, w, A->tg_info, A->sgrp, A->sgrp_info, A->n_sgrp, A->erow, t->ext, s);
+        } else {
+            launch_external_gather(t, w, A->tg_info, A->sgrp, A->sgrp_info, A->n_sgrp, A->erow, t->ext, cs);
+            if ((rc = coarse(s)) != CD_OK) return rc;
         }
-        for (int l0 = 5; l0 <= L; ++l0) {
-            const int64_t nt = (int64_t)A->h.tiles[l0].size();
-            float* El = t->ext + A->h.ebase[l0] * w->D;
-            if (split)
-                launch_external_mfma_list(t->lev[l0 - 1], t->lev[l0 - 2], t->lev[l0 - 3], l0, t->box_cm, w,
-                                          A->tiles[l0], nt, El, s);
-            else
-                launch_external_tiled_list(t->lev[l0 - 1], t->lev[l0 - 2], t->lev[l0 - 3], l0, t->box_cm, w,
-                                           A->tiles[l0], nt, El, s);
-        }
-        E = t->ext;
-        erow = A->erow;
-        CD_HIP(hipStreamWaitEvent(s, t->ev[1], 0));  // the coarse tables are done
+    } else {
+        if ((rc = coarse(cs)) != CD_OK) return rc;
+        if (split)  // bf16x2 for a direction count the tiled kernels do not take: matrix-core gather
+            launch_amr_external_mfma(lk, A->tg_info, A->grp, A->grp_info, A->n_grp, w, t->box_cm, t->ext, s);
+        else
+            launch_external_gather(t, w, A->tg_info, A->grp, A->grp_info, A->n_grp, nullptr, t->ext, s);
     }
-    if (split && !tiled) {
-        // shells dl = 1..3 on the matrix cores into E[n_tg][D]
-        const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
-        if (t->ext_bytes < bytes) {
-            if (t->ext) (void)hipFree(t->ext);
-            t->ext = nullptr;
-            t->ext_bytes = 0;
-            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
-                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
-                return CD_ENOMEM;
-            }
-            t->ext_bytes = bytes;
-        }
-        launch_amr_external_mfma(lk, A->tg_info, A->grp, A->grp_info, A->n_grp, w, t->box_cm, t->ext, s);
-        E = t->ext;
-        CD_HIP(hipStreamWaitEvent(s, t->ev[1], 0));  // the coarse tables are done
-    }
+    const float* E = t->ext;
+    CD_HIP(hipEventRecord(t->ev[1], cs));
+    CD_HIP(hipStreamWaitEvent(s, t->ev[1], 0));  // the coarse tables (and gathered rows) are done
     if (t->prof) {
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_EXTERNAL][1], s));
         CD_HIP(hipEventRecord(t->pev[CD_STAGE_ROWS][0], s));
-        t->pran[CD_STAGE_EXTERNAL] = E != nullptr;
+        t->pran[CD_STAGE_EXTERNAL] = true;
     }
     AmrSweepArgs a{};
     a.lk = lk;
     a.E = E;
     a.erow = erow;
-    a.all_rows = (E && (!erow || all_tiled)) ? 1 : 0;
+    a.all_rows = 1;  // every target has a row of E
     a.tg_info = A->tg_info;
     a.tg_src = A->tg_src;
     a.tg_leaf = A->tg_leaf;
     a.n_tg = A->n_tg;
     a.octden = A->octden;
-    a.base = t->lev[B];
+    a.base = t->lev[t->base];
     for (int k = 1; k <= 4; ++k) {
         a.off[k] = w->offT[k];
         a.w[k] = w->wT[k];
@@ -836,13 +1070,13 @@ void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
     if (a.n_tg <= 0) return;
     if (a.E && (!a.erow || a.all_rows) && (reinterpret_cast<uintptr_t>(a.N) & 15) == 0 &&
         (a.D == 6 || a.D == 12 || a.D == 24 || a.D == 40 || a.D == 48)) {
-        const unsigned nb = (unsigned)((a.n_tg + 31) / 32);
+        const unsigned nb = (unsigned)((a.n_tg + 31) / 32), nb2 = (unsigned)((a.n_tg + 15) / 16);
         switch (a.D) {
-            case 6: k_target_leaves<6><<<nb, 256, 0, s>>>(a); break;
-            case 12: k_target_leaves<12><<<nb, 256, 0, s>>>(a); break;
-            case 24: k_target_leaves<24><<<nb, 256, 0, s>>>(a); break;
-            case 40: k_target_leaves<40><<<nb, 256, 0, s>>>(a); break;
-            default: k_target_leaves<48><<<nb, 256, 0, s>>>(a); break;
+            case 6: k_target_leaves<6, 1><<<nb, 256, 0, s>>>(a); break;
+            case 12: k_target_leaves<12, 1><<<nb, 256, 0, s>>>(a); break;
+            case 24: k_target_leaves<24, 1><<<nb, 256, 0, s>>>(a); break;
+            case 40: k_target_leaves<40, 2><<<nb2, 256, 0, s>>>(a); break;
+            default: k_target_leaves<48, 2><<<nb2, 256, 0, s>>>(a); break;
         }
         return;
     }

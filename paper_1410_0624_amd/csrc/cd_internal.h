@@ -15,6 +15,11 @@ namespace cd {
 struct AmrDev;
 
 // ----------------------------------------------------------------- errors --
+// Device buffers are read and written with 8- and 16-byte vector accesses:
+// the entry points require that alignment of the caller's pointers (every
+// hipMalloc or torch allocation has it).
+inline bool is_aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) & (a - 1)) == 0; }
+
 void set_error(const char* fmt, ...);
 void clear_error();
 
@@ -84,9 +89,16 @@ struct HostTables {
     std::vector<int32_t> blob;             // [rounds][D / tile_dc][blob_words]
     std::vector<double> gloc;              // [D][8] internal+local chords by crossed-axis set m
     std::vector<int32_t> sgn;              // [D] sign bits of u (1 = negative component)
+    // gather tables (any D): per configuration class c (A mod 4 per axis,
+    // A the oct at level l0-1) and direction, the non-zero weights of the
+    // shells dl = 1, 2, 3 relative to A, A >> 1, A >> 2; for dl = 3 the union
+    // over the parity of A >> 2 with a per-entry parity mask
+    std::vector<int32_t> ghdr;             // [64][D][4]: first entry, n1, n2, n3 common | n3 masked << 16
+    std::vector<int32_t> gent;             // [n][2]: (ox, oy, oz) int8 | parity mask << 24, weight bits
 };
 int build_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
 int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
+int build_gather_tables(HostTables& t);
 int tile_chunk(int D);
 
 // Split-precision banks of the MFMA sweep (shells dl = 1, 2, 3).  For each
@@ -132,6 +144,8 @@ struct cd_weights {
     int32_t* blob = nullptr;                // device tiled-sweep tables
     float* gloc = nullptr;                  // device [D][8]
     int32_t* sgn = nullptr;                 // device [D]
+    int32_t* ghdr = nullptr;                // device gather tables (cd::HostTables::ghdr, gent)
+    int32_t* gent = nullptr;
     double* dirs = nullptr;                 // device [D][3] unit vectors (components < 1e-14 snapped to 0)
     // split-precision banks (hi/lo) for the MFMA sweep
     int split_ntiles = 0;

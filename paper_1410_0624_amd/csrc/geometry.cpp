@@ -407,6 +407,66 @@ int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables
     return CD_OK;
 }
 
+int build_gather_tables(HostTables& t) {
+    const int D = t.D;
+    t.ghdr.assign((size_t)64 * D * 4, 0);
+    t.gent.clear();
+    for (int ci = 0; ci < 64; ++ci) {
+        const int c[3] = {ci & 3, (ci >> 2) & 3, ci >> 4};
+        for (int d = 0; d < D; ++d) {
+            int32_t* h = &t.ghdr[((size_t)ci * D + d) * 4];
+            h[0] = (int32_t)(t.gent.size() / 2);
+            // dl = 1: configuration = parity of A; dl = 2: A mod 4
+            for (int kind = 1; kind <= 2; ++kind) {
+                const int combo = kind == 1 ? (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1) : c[0] + 4 * c[1] + 16 * c[2];
+                const size_t row = (size_t)combo * D + d;
+                for (int e = 0; e < t.cnt[kind][row]; ++e) {
+                    t.gent.push_back(t.off[kind][row * t.len[kind] + e] & 0xffffff);
+                    t.gent.push_back(fbits(t.w[kind][row * t.len[kind] + e]));
+                }
+                h[kind] = t.cnt[kind][row];
+            }
+            // dl = 3: the reference is fixed by A mod 4, the outer box by the
+            // parity p3 of A >> 2: union over p3 with a mask of the parities
+            // whose list holds the entry (the chord is the same in all)
+            std::map<int32_t, std::pair<double, int>> uni;
+            for (int p3 = 0; p3 < 8; ++p3) {
+                int combo = 0, mul = 1;
+                for (int a = 0; a < 3; ++a) {
+                    combo += (4 * ((p3 >> a) & 1) + c[a]) * mul;
+                    mul *= 8;
+                }
+                const size_t row = (size_t)combo * D + d;
+                for (int e = 0; e < t.cnt[3][row]; ++e) {
+                    const int32_t pk = t.off[3][row * t.len[3] + e] & 0xffffff;
+                    const double wv = t.w[3][row * t.len[3] + e];
+                    auto it = uni.find(pk);
+                    if (it == uni.end()) {
+                        uni[pk] = {wv, 1 << p3};
+                    } else {
+                        if (std::fabs(it->second.first - wv) > 1e-12) {
+                            set_error("internal: dl=3 weights differ across parities");
+                            return CD_EINVAL;
+                        }
+                        it->second.second |= 1 << p3;
+                    }
+                }
+            }
+            int ncommon = 0, nmasked = 0;
+            for (int pass = 0; pass < 2; ++pass)  // entries of every parity first, then the masked ones
+                for (auto& kv : uni) {
+                    const bool common = kv.second.second == 0xff;
+                    if (common != (pass == 0)) continue;
+                    t.gent.push_back(kv.first | (common ? 0 : kv.second.second << 24));
+                    t.gent.push_back(fbits(kv.second.first));
+                    (common ? ncommon : nmasked) += 1;
+                }
+            h[3] = ncommon | (nmasked << 16);
+        }
+    }
+    return CD_OK;
+}
+
 }  // namespace cd
 
 namespace cd {

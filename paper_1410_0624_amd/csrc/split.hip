@@ -108,6 +108,12 @@ struct MfmaArgs {
     int L;
     int tiles_per_axis;
     const int32_t* tile_list;  // nullptr: every tile; else linear tile indices, E rows per list position
+    // list over several levels: entry i is a tile of level tile_lvl[i] (the
+    // targets' level l0) with padded levels l0-1 .. l0-3 in levs[]; L,
+    // lev1..3, dx1..3 and tiles_per_axis are then per entry
+    const int32_t* tile_lvl;
+    const float* levs[CD_MAX_LEVEL + 1];
+    double box;
 };
 
 #define CD_CONST __attribute__((address_space(4)))
@@ -120,11 +126,16 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
     __shared__ uint32_t s3[k3Size];
     __shared__ uint32_t smax[3];
 
-    const int tpa = a.tiles_per_axis;
+    const int Lw = a.tile_lvl ? __builtin_amdgcn_readfirstlane(a.tile_lvl[blockIdx.x]) : a.L;
+    const float* lev1 = a.tile_lvl ? a.levs[Lw - 1] : a.lev1;
+    const float* lev2 = a.tile_lvl ? a.levs[Lw - 2] : a.lev2;
+    const float* lev3 = a.tile_lvl ? a.levs[Lw - 3] : a.lev3;
+    const float dx1 = a.tile_lvl ? (float)(a.box * ldexp(1.0, 1 - Lw)) : a.dx1;
+    const int tpa = a.tile_lvl ? 1 << (Lw - 5) : a.tiles_per_axis;
     const int tile_id = a.tile_list ? a.tile_list[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa, tz = tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;
-    const int L1 = a.L - 1;
+    const int L1 = Lw - 1;
     const int64_t S1 = ((int64_t)1 << L1) + 2 * kHalo;
     const int64_t S2 = ((int64_t)1 << (L1 - 1)) + 2 * kHalo;
     const int64_t S3 = ((int64_t)1 << (L1 - 2)) + 2 * kHalo;
@@ -147,7 +158,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
             v1[q] = 0.f;
             if (i < n1) {
                 const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
-                v1[q] = a.lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
+                v1[q] = lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
                 m = fmaxf(m, v1[q]);
             }
         }
@@ -157,7 +168,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
             v2[q] = 0.f;
             if (i < n2) {
                 const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
-                v2[q] = 2.f * a.lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
+                v2[q] = 2.f * lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
                 m = fmaxf(m, v2[q]);
             }
         }
@@ -167,7 +178,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
             v3[q] = 0.f;
             if (i < n3) {
                 const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
-                v3[q] = 4.f * a.lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
+                v3[q] = 4.f * lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
                 m = fmaxf(m, v3[q]);
             }
         }
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_mfma(const MfmaArgs
     __syncthreads();
 
     const float lo_w = P == CD_BF16X2 ? 0.f : 1.f / 2048.f;  // bf16: one accumulator
-    const float out_scale = sc * a.dx1;
+    const float out_scale = sc * dx1;
     const int r = lane & 15;  // A-operand row of this lane
     const int g = lane >> 4;  // k group (A, B) and row quad (C)
     const int rx = r & 3, ry = r >> 2;
@@ -295,27 +306,22 @@ bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipSt
     return true;
 }
 
-// The listed tiles of a virtual uniform grid at level l0 whose levels
-// l0-1 .. l0-3 are the dense padded arrays lev1 .. lev3 (an adaptive tree's
-// injected levels); E rows per list position.
-void launch_external_mfma_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
-                               const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E, hipStream_t s) {
+// Listed tiles of virtual uniform grids: entry i is tile tiles[i] of the
+// level-lvls[i] grid, whose levels l0-1 .. l0-3 are the dense padded arrays
+// levs[] (an adaptive tree's injected levels); E rows per list position.
+void launch_external_mfma_list(const float* const* levs, int nlev, double box, const cd_weights* w,
+                               const int32_t* tiles, const int32_t* lvls, int64_t ntiles, float* E, hipStream_t s) {
     if (ntiles <= 0) return;
     MfmaArgs a{};
-    a.lev1 = lev1;
-    a.lev2 = lev2;
-    a.lev3 = lev3;
-    a.dx1 = (float)(box * std::ldexp(1.0, -(l0 - 1)));
-    a.dx2 = (float)(box * std::ldexp(1.0, -(l0 - 2)));
-    a.dx3 = (float)(box * std::ldexp(1.0, -(l0 - 3)));
+    for (int l = 0; l < nlev; ++l) a.levs[l] = levs[l];
+    a.box = box;
+    a.tile_lvl = lvls;
     a.hdr = w->split_hdr;
     a.ent = w->split_ent;
     a.bank = reinterpret_cast<const u32x4*>(w->split_bank);
     a.ntiles = w->split_ntiles;
     a.E = E;
     a.D = w->D;
-    a.L = l0;
-    a.tiles_per_axis = 1 << (l0 - 1 - 4);
     a.tile_list = tiles;
     if (w->precision == CD_BF16X2) k_external_mfma<CD_BF16X2><<<(unsigned)ntiles, tile::kThreads, 0, s>>>(a);
     else k_external_mfma<CD_FP16X2><<<(unsigned)ntiles, tile::kThreads, 0, s>>>(a);

@@ -1132,6 +1132,8 @@ extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_we
     SURR_CHECK(w->D == s->D, "cd_surrogate_infer: weights of D = %d for a network of D = %d", w->D, s->D);
     SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_infer: the surrogate needs a uniform grid with 2^L >= 256");
     SURR_CHECK(!chi_dev || (std::isfinite(av_per_nh) && std::isfinite(gamma)), "cd_surrogate_infer: bad chi parameters");
+    SURR_CHECK(is_aligned(N_dev, 16) && (!chi_dev || is_aligned(chi_dev, 8)),
+               "cd_surrogate_infer: N must be 16-byte aligned and chi 8-byte aligned");
     hipStream_t st = (hipStream_t)stream;
     const float cs = (float)(gamma * av_per_nh);
     return s->prec == CD_SURR_BF16 ? infer_impl<uint16_t>(s, t, w, N_dev, chi_dev, cs, st)
@@ -1141,7 +1143,7 @@ extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_we
 namespace cd {
 int ensure_q(cd_tree* t, int D, int top, bool compact);
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
-                   const uint8_t* const* need = nullptr);
+                   const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);
 }
 
 // Generic per-oct arguments for target octs of a uniform tree (children at
@@ -1283,6 +1285,8 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     clear_error();
     SURR_CHECK(s && t && w && N_dev && chi_dev && n_fallback_tiles && n_tiles, "cd_surrogate_check_fallback: NULL argument");
     SURR_CHECK(frac > 0 && frac <= 1 && tol_chi >= 0, "cd_surrogate_check_fallback: frac %g, tol %g", frac, tol_chi);
+    SURR_CHECK(is_aligned(N_dev, 16) && is_aligned(chi_dev, 8),
+               "cd_surrogate_check_fallback: N must be 16-byte aligned and chi 8-byte aligned");
     SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_check_fallback: the surrogate needs a uniform grid with 2^L >= 256");
     SURR_CHECK(w->precision == CD_FP32 && w->mode == CD_PRECALC73 && w->D == s->D, "cd_surrogate_check_fallback: needs FP32 precalculated weights of D = %d",
                s->D);

@@ -145,7 +145,6 @@ struct CoarseArgs {
     int D;
     int8_t next[6][2];
     int8_t dl4[4];
-    const uint8_t* need;  // [8^l] cells whose row is read (nullptr: every cell)
 };
 
 constexpr int kCoarseLen = 12;
@@ -203,7 +202,6 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
         if (q >= ncell) break;
         const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
                           (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
-        if (a.need && !a.need[((int64_t)c[2] * n + c[1]) * n + c[0]]) continue;
         const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
         float prev = 0.f;
         if (a.qprev) {
@@ -216,6 +214,56 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
         const int64_t cell = ((int64_t)c[2] * n + c[1]) * n + c[0];
         a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
     }
+}
+
+// The same entries for listed keys cell * ncodes + code only (the entries
+// an adaptive tree's targets read, and those they add up from): a lane per
+// (entry, direction), 16 entries x 16 directions per workgroup.
+__global__ __launch_bounds__(256) void k_coarse_listed(const CoarseArgs a, const int64_t* __restrict__ keys,
+                                                       int64_t nkeys) {
+    const int64_t ki = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int d = blockIdx.y * 16 + (threadIdx.x & 15);
+    if (ki >= nkeys || d >= a.D) return;
+    const int ncodes = a.compact ? 64 : 216;
+    const int64_t key = keys[ki];
+    const int64_t cell = key / ncodes;
+    const int code = (int)(key - cell * ncodes);
+    const int64_t n = (int64_t)1 << a.l;
+    const int c[3] = {(int)(cell & (n - 1)), (int)((cell >> a.l) & (n - 1)), (int)(cell >> (2 * a.l))};
+    int st[3];
+    if (a.compact) {
+        st[0] = a.dl4[code & 3];
+        st[1] = a.dl4[(code >> 2) & 3];
+        st[2] = a.dl4[(code >> 4) & 3];
+    } else {
+        st[0] = code % 6;
+        st[1] = (code / 6) % 6;
+        st[2] = code / 36;
+    }
+    int combo = 0, pcode = 0, mul = 1, pmul = 1;
+    for (int k = 0; k < 3; ++k) {
+        const int p = c[k] & 1;
+        combo += (6 * p + st[k]) * mul;
+        pcode += a.next[st[k]][p] * pmul;
+        mul *= 12;
+        pmul *= 6;
+    }
+    const int S = (int)n + 2 * kHalo;
+    const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
+    const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
+    float s = 0.f;
+#pragma unroll
+    for (int e = 0; e < kCoarseLen; ++e) {
+        const int pk = a.kt.off[row + e];
+        s = fmaf(a.kt.w[row + e], base[(sext8(pk >> 16) * S + sext8(pk >> 8)) * S + sext8(pk)], s);
+    }
+    float prev = 0.f;
+    if (a.qprev) {
+        const int64_t np = n >> 1;
+        const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
+        prev = a.qprev[(pcell * 216 + pcode) * a.D + d];
+    }
+    a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
 }
 
 // -------------------------------------------------------------- screening --
@@ -325,11 +373,10 @@ static void launch_fine_path(const cd_tree* t, const cd_weights* w, const float*
 }
 
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
-                   const uint8_t* const* need) {
+                   const int64_t* const* need, const int64_t* n_need) {
     const int D = w->D;
     for (int l = 2; l <= top; ++l) {
         CoarseArgs c{};
-        c.need = need ? need[l] : nullptr;
         c.lev = t->lev[l];
         c.l = l;
         c.dx = (float)(t->box_cm * std::ldexp(1.0, -l));
@@ -341,6 +388,12 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
         for (int sc = 0; sc < 6; ++sc)
             for (int p = 0; p < 2; ++p) c.next[sc][p] = (int8_t)next_state_code(sc, p);
         for (int q = 0; q < 4; ++q) c.dl4[q] = (int8_t)state_code_dl4(q >> 1, q & 1);
+        if (need) {
+            if (n_need[l] > 0)
+                k_coarse_listed<<<dim3((unsigned)((n_need[l] + 15) / 16), (unsigned)((D + 15) / 16)), 256, 0, s>>>(
+                    c, need[l], n_need[l]);
+            continue;
+        }
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
         dim3 grid((c.compact ? 64 : 216) * 8 * ((D + 15) / 16),
                   (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
@@ -429,7 +482,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipEventRecord(t->ev[kMaxSlabs], s));
         CD_HIP(hipStreamWaitEvent(t->aux, t->ev[kMaxSlabs], 0));
         CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
-        launch_coarse(t, w, L - 4, true, t->aux, nullptr);
+        launch_coarse(t, w, L - 4, true, t->aux, nullptr, nullptr);
         CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         t->pslabs = t->prof ? nslab : 0;
@@ -455,7 +508,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipGetLastError());
         return CD_OK;
     }
-    launch_coarse(t, w, L - 4, true, s, nullptr);
+    launch_coarse(t, w, L - 4, true, s, nullptr, nullptr);
     launch_fine_path(t, w, (L - 4 >= 2) ? t->q[L - 4] : nullptr, nullptr, N, chi, chi_scale, s);
     CD_HIP(hipGetLastError());
     return CD_OK;
@@ -472,6 +525,10 @@ extern "C" int cd_column_densities(cd_tree* t, const cd_weights* w, float* N_dev
     }
     if (chi_dev && !(std::isfinite(av_per_nh) && std::isfinite(gamma))) {
         cd::set_error("cd_column_densities: non-finite screening parameters");
+        return CD_EINVAL;
+    }
+    if (!cd::is_aligned(N_dev, 16) || (chi_dev && !cd::is_aligned(chi_dev, 8))) {
+        cd::set_error("cd_column_densities: N must be 16-byte aligned and chi 8-byte aligned");
         return CD_EINVAL;
     }
     const float scale = (float)(gamma * av_per_nh);

@@ -39,6 +39,12 @@ struct TileArgs {
     int tz0;            // first tile layer along z of this launch
     const int32_t* tile_list;  // nullptr: every tile of the layers; else linear tile indices, and E is
                                // written per list position: row (blockIdx * 4096 + local oct)
+    // list over several levels: entry i is a tile of level tile_lvl[i] (the
+    // targets' level l0), whose padded levels l0-1 .. l0-3 are levs[]; the
+    // fields L, lev1..3, dx1..3 and tiles_per_axis are then per entry
+    const int32_t* tile_lvl;
+    const float* levs[CD_MAX_LEVEL + 1];
+    double box;
 };
 
 __device__ __forceinline__ float as_float(int32_t b) { return __int_as_float(b); }
@@ -59,12 +65,19 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     __shared__ float s3[k3Size];
     __shared__ int4 tab[kTabWords / 4];
 
-    const int tpa = a.tiles_per_axis;
+    const int Lw = a.tile_lvl ? __builtin_amdgcn_readfirstlane(a.tile_lvl[blockIdx.x]) : a.L;
+    const float* lev1 = a.tile_lvl ? a.levs[Lw - 1] : a.lev1;
+    const float* lev2 = a.tile_lvl ? a.levs[Lw - 2] : a.lev2;
+    const float* lev3 = a.tile_lvl ? a.levs[Lw - 3] : a.lev3;
+    const float dx1 = a.tile_lvl ? (float)(a.box * ldexp(1.0, 1 - Lw)) : a.dx1;
+    const float dx2 = a.tile_lvl ? (float)(a.box * ldexp(1.0, 2 - Lw)) : a.dx2;
+    const float dx3 = a.tile_lvl ? (float)(a.box * ldexp(1.0, 3 - Lw)) : a.dx3;
+    const int tpa = a.tile_lvl ? 1 << (Lw - 5) : a.tiles_per_axis;
     const int tile_id = a.tile_list ? a.tile_list[blockIdx.x] : (int)blockIdx.x;
     const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa,
               tz = (a.tile_list ? 0 : a.tz0) + tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;  // tile origin, level L-1 cells
-    const int L1 = a.L - 1;
+    const int L1 = Lw - 1;
     const int64_t S1 = ((int64_t)1 << L1) + 2 * kHalo;
     const int64_t S2 = ((int64_t)1 << (L1 - 1)) + 2 * kHalo;
     const int64_t S3 = ((int64_t)1 << (L1 - 2)) + 2 * kHalo;
@@ -82,7 +95,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
             if (i < n1) {
                 const int xx = i % k1Side, yy = (i / k1Side) % k1Side, zz = i / (k1Side * k1Side);
                 // level L-1 coordinate X1 + xx - 4, padded index + kHalo
-                v1[q] = a.lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
+                v1[q] = lev1[((int64_t)(Z1 + zz + 1) * S1 + (Y1 + yy + 1)) * S1 + (X1 + xx + 1)];
             }
         }
 #pragma unroll
@@ -90,7 +103,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
             const int i = threadIdx.x + q * kThreads;
             if (i < n2) {
                 const int xx = i & 15, yy = (i >> 4) & 15, zz = i >> 8;
-                v2[q] = a.lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
+                v2[q] = lev2[((int64_t)(Z1 / 2 + zz + 1) * S2 + (Y1 / 2 + yy + 1)) * S2 + (X1 / 2 + xx + 1)];
             }
         }
 #pragma unroll
@@ -98,7 +111,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
             const int i = threadIdx.x + q * kThreads;
             if (i < n3) {
                 const int xx = i % k3Side, yy = (i / k3Side) % k3Side, zz = i / (k3Side * k3Side);
-                v3[q] = a.lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
+                v3[q] = lev3[((int64_t)(Z1 / 4 + zz) * S3 + (Y1 / 4 + yy)) * S3 + (X1 / 4 + xx)];
             }
         }
 #pragma unroll
@@ -132,7 +145,6 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
     const int pbit = 16 + ((lx & 1) | ((ly & 1) << 1) | ((lz & 1) << 2));  // parity mask bit of dl = 3
     const int b1 = lane1(lx, ly, lz), b2 = lane2(lx, ly, lz), b3 = lane3(lx, ly, lz);
-    const int64_t n = (int64_t)1 << a.L;
     constexpr int kChunks = D / DC;
     const int4* hdr = tab + wave * DC;   // this wave's headers
     const int4* ent0 = tab + 16 * DC;    // entry pairs
@@ -221,7 +233,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
                     u = fmaf(as_float(p.y), ((p.x >> pbit) & 1) ? v0 : 0.f, u);
                     u = fmaf(as_float(p.w), ((p.z >> pbit) & 1) ? v1 : 0.f, u);
                 }
-                acc[j] = fmaf(a.dx1, s, fmaf(a.dx2, t, fmaf(a.dx3, u, acc[j])));
+                acc[j] = fmaf(dx1, s, fmaf(dx2, t, fmaf(dx3, u, acc[j])));
             }
 
             // the oct's row piece of external columns, back-to-back stores
@@ -263,28 +275,22 @@ bool tiled_supported(const cd_tree* t, const cd_weights* w) {
     return w->host.tile_dc == tile_chunk(D) && w->host.blob_words > 0 && w->host.blob_words <= tile::kTabWords;
 }
 
-// Tile layers [tz0, tz0 + nz) along z.
-// External columns of the octs of the listed tiles (linear indices over the
-// 16^3-oct tiles of the level-(l0-1) grid) of a virtual uniform grid at level
-// l0 whose levels l0-1 .. l0-3 are the dense padded arrays lev1 .. lev3 (an
-// adaptive tree's injected levels); E rows per list position.
-void launch_external_tiled_list(const float* lev1, const float* lev2, const float* lev3, int l0, double box,
-                                const cd_weights* w, const int32_t* tiles, int64_t ntiles, float* E, hipStream_t s) {
+// External columns of the octs of listed tiles of virtual uniform grids:
+// entry i is tile tiles[i] (linear index over the 16^3-oct tiles of the
+// level-(l0-1) grid) with l0 = lvls[i], whose levels l0-1 .. l0-3 are the
+// dense padded arrays levs[] (an adaptive tree's injected levels); E rows
+// per list position, so one launch covers every level.
+void launch_external_tiled_list(const float* const* levs, int nlev, double box, const cd_weights* w,
+                                const int32_t* tiles, const int32_t* lvls, int64_t ntiles, float* E, hipStream_t s) {
     TileArgs a{};
-    a.L = l0;
-    a.lev1 = lev1;
-    a.lev2 = lev2;
-    a.lev3 = lev3;
-    a.dx1 = (float)(box * std::ldexp(1.0, -(l0 - 1)));
-    a.dx2 = (float)(box * std::ldexp(1.0, -(l0 - 2)));
-    a.dx3 = (float)(box * std::ldexp(1.0, -(l0 - 3)));
-    a.dxL = (float)(box * std::ldexp(1.0, -l0));
+    for (int l = 0; l < nlev; ++l) a.levs[l] = levs[l];
+    a.box = box;
+    a.tile_lvl = lvls;
     a.blob = w->blob;
     a.blob_words = w->host.blob_words;
     a.gloc = w->gloc;
     a.sgn = w->sgn;
     a.E = E;
-    a.tiles_per_axis = 1 << (l0 - 1 - 4);
     a.tile_list = tiles;
     if (ntiles <= 0) return;
     const unsigned nb = (unsigned)ntiles;

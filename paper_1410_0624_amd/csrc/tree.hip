@@ -111,6 +111,45 @@ __global__ void k_pyramid_two(const float* __restrict__ in, bool in_is_leaf, int
     out0[((k + kHalo) * S0 + (j + kHalo)) * S0 + (i + kHalo)] = 0.125f * s0;
 }
 
+// The same two levels with a lane per level-(l+1) cell (l >= 3): a wave
+// covers 16 x 2 x 2 of them, reads their 2^3 blocks (rows of 128 contiguous
+// bytes; float2 pairs from unpadded leaves at an 8-byte aligned address),
+// and forms each level-l mean across lanes x^1, y^16, z^32 in the
+// order of k_pyramid_two.  Eight times the lanes of k_pyramid_two in flight
+// for the read of the finest level.
+__device__ __forceinline__ float2 ld_pair(const float* p, bool aligned) {
+    if (aligned) return *reinterpret_cast<const float2*>(p);
+    return make_float2(p[0], p[1]);
+}
+
+__global__ __launch_bounds__(256) void k_pyramid_two_wide(const float* __restrict__ in, bool in_is_leaf, int l,
+                                                          float* __restrict__ out1, float* __restrict__ out0) {
+    const int64_t n1 = (int64_t)2 << l;  // level-(l+1) cells per axis (>= 16)
+    const int lane = threadIdx.x & 63;
+    const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwx = n1 >> 4, nwy = n1 >> 1;  // waves per x row, per (y pair) plane
+    if (wv >= nwx * nwy * (n1 >> 1)) return;    // whole wave: uniform
+    const int64_t wx = wv % nwx, wy = (wv / nwx) % nwy, wz = wv / (nwx * nwy);
+    const int64_t i = wx * 16 + (lane & 15), j = 2 * wy + ((lane >> 4) & 1), k = 2 * wz + (lane >> 5);
+    const int64_t n2 = 2 * n1;
+    const int64_t Si = in_is_leaf ? n2 : n2 + 2 * kHalo;
+    const int64_t h = in_is_leaf ? 0 : kHalo;
+    const float* p = in + ((2 * k + h) * Si + (2 * j + h)) * Si + (2 * i + h);
+    const bool al = in_is_leaf && ((reinterpret_cast<uintptr_t>(in) & 7) == 0);
+    const float2 a = ld_pair(p, al);
+    const float2 b = ld_pair(p + Si, al);
+    const float2 c = ld_pair(p + Si * Si, al);
+    const float2 d = ld_pair(p + Si * Si + Si, al);
+    const float m1 = 0.125f * (((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y)));
+    const int64_t S1 = n1 + 2 * kHalo, S0 = (n1 >> 1) + 2 * kHalo;
+    out1[((k + kHalo) * S1 + (j + kHalo)) * S1 + (i + kHalo)] = m1;
+    const float sx = m1 + __shfl_xor(m1, 1);
+    const float sy = sx + __shfl_xor(sx, 16);
+    const float sz = sy + __shfl_xor(sy, 32);
+    if ((lane & 49) == 0)  // x, y, z bits of the level-(l+1) cell all 0
+        out0[(((k >> 1) + kHalo) * S0 + ((j >> 1) + kHalo)) * S0 + ((i >> 1) + kHalo)] = 0.125f * sz;
+}
+
 static int launch_blocks(int64_t n) { return (int)((n + 255) / 256); }
 
 // Rebuild the dense padded levels below `top`, the finest level already
@@ -124,7 +163,11 @@ int build_dense_below(cd_tree* t, int top, hipStream_t s) {
         const int64_t n = (int64_t)1 << l;
         const bool leaf_in = from_leaf && cur == top;
         const float* in = leaf_in ? t->leaf : t->lev[cur];
-        k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1], t->lev[l]);
+        if (l >= 3)
+            k_pyramid_two_wide<<<launch_blocks(8 * n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1],
+                                                                             t->lev[l]);
+        else
+            k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1], t->lev[l]);
         cur = l;
     }
     if (cur == 1) {
@@ -163,6 +206,10 @@ extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const
     if (!(box_cm > 0) || base_level < 0 || max_level < base_level || max_level > CD_MAX_LEVEL) {
         cd::set_error("cd_build_tree: bad box or levels (box %g, base %d, max %d)", box_cm, base_level,
                       max_level);
+        return CD_EINVAL;
+    }
+    if (base_level == max_level && !cd::is_aligned(leaf_n_dev, 8)) {
+        cd::set_error("cd_build_tree: the leaf densities of a uniform grid must be 8-byte aligned");
         return CD_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -218,6 +265,10 @@ extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, void* stream)
     cd::clear_error();
     if (!t || !leaf_n_dev) {
         cd::set_error("cd_tree_update: NULL argument");
+        return CD_EINVAL;
+    }
+    if (t->uniform && !cd::is_aligned(leaf_n_dev, 8)) {
+        cd::set_error("cd_tree_update: the leaf densities of a uniform grid must be 8-byte aligned");
         return CD_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;

@@ -157,11 +157,11 @@ def _rand_dirs(D, seed):
 
 def test_insitu_unsupported_cases(colden):
     dev = torch.device("cuda:0")
-    # binary16 on an adaptive tree without 16^3-oct tiles on every level
+    # binary16 on an adaptive tree for a direction count outside the tiled set
     tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
     tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
-    w = colden.Weights(DIRS["healpix1"], mode=colden.CD_INSITU, precision=2)
-    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    w = colden.Weights(_rand_dirs(7, 4), mode=colden.CD_INSITU, precision=2)
+    N = torch.empty((tin.n_leaf, 7), dtype=torch.float32, device=dev)
     with pytest.raises(colden.ColdenError) as e:
         colden.column_densities(tree, w, N)
     assert e.value.rc == colden.CD_EUNSUPPORTED

@@ -206,3 +206,37 @@ def test_error_paths(colden):
     with pytest.raises(colden.ColdenError) as e:
         colden.Tree(tin, leaf)
     assert e.value.rc == colden.CD_EINVAL
+
+
+def test_misaligned_buffers_are_rejected(colden):
+    """The kernels move N in 16-byte and chi and uniform leaves in 8-byte
+    vectors: views that start one float into an allocation are refused."""
+    dev = torch.device("cuda:0")
+    tin = synth.workload_uniform(5, seed=3)
+    D = 12
+    leaf_buf = torch.empty(tin.n_leaf + 1, dtype=torch.float32, device=dev)
+    leaf_buf[1:] = torch.from_numpy(tin.leaf_n).to(dev)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.Tree(tin, leaf_buf[1:])
+    assert e.value.rc == colden.CD_EINVAL
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    with pytest.raises(colden.ColdenError) as e:
+        tree.update(leaf_buf[1:])
+    assert e.value.rc == colden.CD_EINVAL
+    w = colden.Weights(oracle.dirs_healpix(1))
+    nbuf = torch.empty(tin.n_leaf * D + 4, dtype=torch.float32, device=dev)
+    cbuf = torch.empty(tin.n_leaf + 1, dtype=torch.float32, device=dev)
+    N_bad = nbuf[1:1 + tin.n_leaf * D].view(tin.n_leaf, D)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.column_densities(tree, w, N_bad)
+    assert e.value.rc == colden.CD_EINVAL
+    N_ok = nbuf[4:].view(tin.n_leaf, D)
+    with pytest.raises(colden.ColdenError) as e:
+        colden.column_densities(tree, w, N_ok, cbuf[1:])
+    assert e.value.rc == colden.CD_EINVAL
+    # the aligned views are accepted and give the oracle's columns
+    colden.column_densities(tree, w, N_ok, cbuf[:-1])
+    torch.cuda.synchronize()
+    ref = oracle.Tree(tin).columns(oracle.dirs_healpix(1))
+    got = N_ok.cpu().numpy().astype(np.float64)
+    assert (np.abs(got - ref) / ref).max() <= 1e-5

@@ -73,14 +73,19 @@ def test_split_c2_256_sampled(colden, pname):
 
 
 @pytest.mark.parametrize("pname,Lf,B,th,seed,dname", [
-    # base level < 5: targets gathered group by group (bf16 only)
+    # base level < 5: targets of levels without tiles and of sparse tiles
+    # gathered in FP32, dense tiles on the matrix cores
     ("bf16x2", 6, 3, 14.0, 5, "healpix1"), ("bf16x2", 7, 4, 30.0, 5, "healpix2"), ("bf16x2", 7, 2, 30.0, 6, "healpix1"),
-    # base level >= 5: the tiled kernel on the active tiles of every level
+    ("fp16x2", 6, 3, 14.0, 5, "healpix1"), ("fp16x2", 7, 4, 30.0, 5, "healpix2"),
+    # base level >= 5
     ("bf16x2", 7, 5, 30.0, 7, "healpix2"), ("fp16x2", 7, 5, 30.0, 7, "healpix2"),
-    ("fp16x2", 7, 6, 14.0, 8, "healpix1")])
+    ("fp16x2", 7, 6, 14.0, 8, "healpix1"),
+    # direction counts outside the tiled set: every target on the matrix cores, grouped (bf16 only)
+    ("bf16x2", 6, 3, 14.0, 5, "rand7"), ("bf16x2", 7, 5, 30.0, 7, "rand13")])
 def test_split_amr_all_leaves(colden, pname, Lf, B, th, seed, dname):
     tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, seed), B, th, 10 * synth.PC_CM)
-    dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2)}[dname]
+    dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2),
+            "rand7": _rand_dirs(7, 11), "rand13": _rand_dirs(13, 12)}[dname]
     N, chi = _run(colden, tin, dirs, PREC[pname])
     ref = oracle.Tree(tin).columns(dirs)
     err = _lnerr(N, ref)
@@ -136,13 +141,18 @@ def test_c4_512_all_forms_sampled(colden):
     assert torch.isfinite(N).all()
 
 
+def _rand_dirs(D, seed):
+    u = np.random.default_rng(seed).normal(size=(D, 3))
+    return u / np.linalg.norm(u, axis=1, keepdims=True)
+
+
 def test_split_unsupported_cases(colden):
     dev = torch.device("cuda:0")
-    # binary16 on an adaptive tree with base level < 5 (no 16^3-oct tile to scale)
+    # binary16 on an adaptive tree for a direction count outside the tiled set
     tin = synth.amr_tree(synth.lognormal_field(32, 2.0, 10.0, 5), 3, 14.0, 1e19)
     tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
-    w = colden.Weights(oracle.dirs_healpix(1), precision=2)
-    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    w = colden.Weights(_rand_dirs(7, 3), precision=2)
+    N = torch.empty((tin.n_leaf, 7), dtype=torch.float32, device=dev)
     with pytest.raises(colden.ColdenError) as e:
         colden.column_densities(tree, w, N)
     assert e.value.rc == colden.CD_EUNSUPPORTED
