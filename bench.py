@@ -73,12 +73,11 @@ PREC = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
 
-def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int, rows_from_e: bool) -> float:
+def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int) -> float:
     """Algorithmic HBM bytes of the adaptive-tree target kernel: per leaf the
     row of N (4 D B), chi (4 B) and its density (4 B); per target oct its row
-    of the coarse table (4 D B) and, when a tiled or split kernel computed the
-    shells dl = 1..3 of every target, its row of E (4 D B)."""
-    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * (2 if rows_from_e else 1)
+    of the coarse table and its row of E (shells dl = 1..3), 4 D B each."""
+    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * 2
 
 
 def hbm_ceiling(torch, n_floats):
@@ -274,11 +273,11 @@ def main():
         ijk = tin.leaf_ijk.astype(np.int64)
         key = (lv.astype(np.int64) << 60) | ((ijk[:, 2] >> 1) << 40) | ((ijk[:, 1] >> 1) << 20) | (ijk[:, 0] >> 1)
         n_tg = int(np.unique(key).shape[0])
-        from_e = args.precision != "fp32" or tin.base_level >= 5
-        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D, from_e)
+        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D)
         kname = (f"k_target_leaves<{D}> (a lane per target: external row + coarse table, internal+local, N and chi rows)"
-                 if from_e and D in (6, 12, 24, 40, 48) else
-                 "k_target_octs (per target oct, a lane per direction: shells, internal+local, N and chi rows)")
+                 if D in (6, 12, 24, 40, 48) else
+                 "k_target_octs (per target oct, a lane per direction: external row + coarse table, internal+local, "
+                 "N and chi rows)")
     else:
         rows_bytes = alg_bytes_rows(tin.n_leaf, D)
         kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"
@@ -404,8 +403,8 @@ def main():
                    "step": "pyramid rebuild + column sweep"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": (measured_traffic(f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}")
-                                 if not amr else None),
+                     "traffic": measured_traffic(f"k_target_leaves<{D}>|adaptive {tin.n_leaf} leaves D={D}" if amr
+                                                 else f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}"),
                      "kernel": kname, "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
         "hbm_ceiling": hbm_ceiling(torch, tin.n_leaf * D),
         "stages_ms": stage_ms,

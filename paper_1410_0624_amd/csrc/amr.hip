@@ -677,7 +677,9 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     // groups of up to 64 targets of one level and configuration class (A mod
     // 4 per axis): the gather kernels take a wave per group.  Within a key
     // the targets follow the Morton order of A >> 2, so that a group's
-    // neighbourhoods overlap (shared cache lines) as far as the tree allows.
+    // neighbourhoods overlap (shared cache lines) as far as the tree allows,
+    // and the groups run in the Morton order of their first target, so that
+    // the groups of all classes of a region run close together in time.
     auto morton = [](const int32_t* ti) {
         uint64_t m = 0;
         for (int b = 0; b < 20; ++b)
@@ -696,12 +698,17 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
             std::stable_sort(v.begin(), v.end(), [&](int32_t x, int32_t y) {
                 return morton(&h.tg_info[4 * (size_t)x]) < morton(&h.tg_info[4 * (size_t)y]);
             });
+        std::vector<std::array<uint64_t, 3>> order;  // (level, Morton code of the first target, key | f << 16)
         for (size_t key = 0; key < bykey.size(); ++key)
-            for (size_t f = 0; f < bykey[key].size(); f += 64) {
-                for (size_t e = 0; e < 64; ++e) grp.push_back(f + e < bykey[key].size() ? bykey[key][f + e] : -1);
-                info.push_back((int32_t)(key / 64));
-                info.push_back((int32_t)(key % 64));
-            }
+            for (size_t f = 0; f < bykey[key].size(); f += 64)
+                order.push_back({key / 64, morton(&h.tg_info[4 * (size_t)bykey[key][f]]), key | (f << 16)});
+        std::sort(order.begin(), order.end());
+        for (const auto& o : order) {
+            const size_t key = o[2] & 0xffff, f = o[2] >> 16;
+            for (size_t e = 0; e < 64; ++e) grp.push_back(f + e < bykey[key].size() ? bykey[key][f + e] : -1);
+            info.push_back((int32_t)(key / 64));
+            info.push_back((int32_t)(key % 64));
+        }
         return (int64_t)(info.size() / 2);
     };
     A->n_grp = make_groups(nullptr, h.grp, h.grp_info);
