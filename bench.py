@@ -234,7 +234,7 @@ def main():
     main_form = measure(args.precision)
     forms = {args.precision: main_form}
     insitu = None
-    if not args.no_forms and not amr and args.precision == "fp32" and L >= 5 and D in (6, 12, 24, 40, 48):
+    if not args.no_forms and args.precision == "fp32":
         # in-situ reference points (every shell seen from the oct centre):
         # timed on the same field, and compared with the precalculated form
         # over every output
@@ -259,7 +259,7 @@ def main():
         print(f"# in-situ form: {insitu['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_forms:
         for p in PREC:
-            if p == args.precision or (amr and p == "fp16x2" and tin.base_level < 5):
+            if p == args.precision or (amr and p == "fp16x2" and D not in (6, 12, 24, 40, 48)):
                 continue
             forms[p] = measure(p)
             print(f"# form {p}: {forms[p]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)

@@ -144,9 +144,15 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
     if (rc == CD_OK) rc = upload(w->host.sgn, &w->sgn, s);
     if (rc == CD_OK) rc = upload(w->host.ghdr, &w->ghdr, s);
     if (rc == CD_OK) rc = upload(w->host.gent, &w->gent, s);
-    std::vector<double> du((size_t)D * 3);
+    // [D][6]: the unit vector (components below 1e-14 snapped to 0) and the
+    // reciprocals of its components (0 where a component is 0)
+    std::vector<double> du((size_t)D * 6);
     for (int d = 0; d < D; ++d)
-        for (int k = 0; k < 3; ++k) du[(size_t)d * 3 + k] = std::fabs(u[d][k]) < 1e-14 ? 0.0 : u[d][k];
+        for (int k = 0; k < 3; ++k) {
+            const double c = std::fabs(u[d][k]) < 1e-14 ? 0.0 : u[d][k];
+            du[(size_t)d * 6 + k] = c;
+            du[(size_t)d * 6 + 3 + k] = c != 0.0 ? 1.0 / c : 0.0;
+        }
     if (rc == CD_OK) rc = upload(du, &w->dirs, s);
     if (rc == CD_OK && precision != CD_FP32) rc = cd::upload_split_banks(w, s);
     if (rc == CD_OK && hipStreamSynchronize(s) != hipSuccess) {

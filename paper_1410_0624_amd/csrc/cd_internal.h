@@ -146,7 +146,7 @@ struct cd_weights {
     int32_t* sgn = nullptr;                 // device [D]
     int32_t* ghdr = nullptr;                // device gather tables (cd::HostTables::ghdr, gent)
     int32_t* gent = nullptr;
-    double* dirs = nullptr;                 // device [D][3] unit vectors (components < 1e-14 snapped to 0)
+    double* dirs = nullptr;                 // device [D][6] unit vectors (components < 1e-14 snapped to 0), reciprocals
     // split-precision banks (hi/lo) for the MFMA sweep
     int split_ntiles = 0;
     int32_t* split_hdr = nullptr;    // device, see cd::SplitHost

@@ -15,7 +15,7 @@ namespace cd {
 struct InsituArgs {
     const float* lev[CD_MAX_LEVEL + 1];  // padded levels 0 .. L-4
     int L;                                // leaf level; octs at L-1
-    const double* dirs;                   // [D][3]
+    const double* dirs;                   // [D][6]: u, then 1 / u per axis (0 where u has no component)
     int D;
     double box;                           // cm
     float* E;                             // [n_oct][D]
@@ -36,16 +36,17 @@ __device__ __forceinline__ double exit_t(const double (&c)[3], const double (&u)
     return t;
 }
 
-// Column (box units x density) of the in-situ shells dl >= 4 of the oct A
-// (level l0 - 1 coordinates, targets at level l0) along u: the levels
-// l0 - 4 .. 0 of the padded arrays lev.
-__device__ double insitu_column(const float* const* lev, int l0, const int64_t (&A)[3], const double (&u)[3]) {
-    const int L1 = l0 - 1;
-    if (L1 - 3 < 0) return 0.0;
-    const double iu[3] = {u[0] != 0.0 ? 1.0 / u[0] : 0.0, u[1] != 0.0 ? 1.0 / u[1] : 0.0,
-                          u[2] != 0.0 ? 1.0 / u[2] : 0.0};
-    // inner limit of the level l0 - 4 shell: the outer limits of dl = 1, 2, 3
+// The oct A's (level l0 - 1 coordinates, targets at level l0) centre c in
+// box units and the inner limit of its level-(l0 - 4) shell: the outer
+// limits of the shells dl = 1, 2, 3 (the same for every direction).
+struct InsituOct {
+    double c[3];
     int64_t ilo[3], ihi[3];
+};
+
+__device__ __forceinline__ InsituOct insitu_oct(int l0, const int64_t (&A)[3]) {
+    InsituOct o;
+    const int L1 = l0 - 1;
     for (int k = 0; k < 3; ++k) {
         int64_t lo = A[k], hi = A[k];
         for (int l = L1; l > L1 - 3; --l) {
@@ -55,11 +56,26 @@ __device__ double insitu_column(const float* const* lev, int l0, const int64_t (
             lo = olo / 2;           // olo is even, ohi + 1 is even
             hi = (ohi + 1) / 2 - 1;
         }
-        ilo[k] = lo;
-        ihi[k] = hi;
+        o.ilo[k] = lo;
+        o.ihi[k] = hi;
+        o.c[k] = ((double)A[k] + 0.5) * ldexp(1.0, -L1);
     }
-    const double dx1 = ldexp(1.0, -L1);
-    const double c[3] = {((double)A[0] + 0.5) * dx1, ((double)A[1] + 0.5) * dx1, ((double)A[2] + 0.5) * dx1};
+    return o;
+}
+
+// Column (box units x density) of the in-situ shells dl >= 4 of the oct
+// along u: the levels l0 - 4 .. 0 of the padded arrays lev.  Each shell is
+// walked cell by cell from the ray's exit of the inner box to its exit of
+// the outer box, the next crossing per axis advanced by one cell's extent
+// along the ray.
+__device__ double insitu_column(const float* const* lev, int l0, const InsituOct& oc, const double (&u)[3],
+                                const double (&iu)[3]) {
+    const int L1 = l0 - 1;
+    if (L1 - 3 < 0) return 0.0;
+    int64_t ilo[3] = {oc.ilo[0], oc.ilo[1], oc.ilo[2]}, ihi[3] = {oc.ihi[0], oc.ihi[1], oc.ihi[2]};
+    const double(&c)[3] = oc.c;
+    const int sgn[3] = {u[0] > 0.0 ? 1 : (u[0] < 0.0 ? -1 : 0), u[1] > 0.0 ? 1 : (u[1] < 0.0 ? -1 : 0),
+                        u[2] > 0.0 ? 1 : (u[2] < 0.0 ? -1 : 0)};
     double sum = 0.0;
     for (int l = L1 - 3; l >= 0; --l) {
         const int64_t nl = (int64_t)1 << l;
@@ -67,7 +83,7 @@ __device__ double insitu_column(const float* const* lev, int l0, const int64_t (
         // every coarser one outside the box (no matter there)
         if (ilo[0] <= 0 && ilo[1] <= 0 && ilo[2] <= 0 && ihi[0] >= nl - 1 && ihi[1] >= nl - 1 && ihi[2] >= nl - 1)
             break;
-        const double dx = ldexp(1.0, -l);
+        const double dx = ldexp(1.0, -l), idx_scale = ldexp(1.0, l);
         int64_t olo[3], ohi[3];
         double blo[3], bhi[3], ilo_b[3], ihi_b[3];
         for (int k = 0; k < 3; ++k) {
@@ -82,28 +98,40 @@ __device__ double insitu_column(const float* const* lev, int l0, const int64_t (
         }
         const double t_in = exit_t(c, u, iu, ilo_b, ihi_b), t_out = exit_t(c, u, iu, blo, bhi);
         // first cell past the inner box: the axes that leave it at t_in
-        // step out of it by index, the others contain c + t_in u
+        // step out of it by index, the others contain c + t_in u; then the
+        // first crossing along each axis and the distance between crossings
         int64_t i[3];
+        double tn[3], dt[3];
         for (int k = 0; k < 3; ++k) {
-            const double tk = u[k] > 0.0 ? (ihi_b[k] - c[k]) * iu[k] : (u[k] < 0.0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
-            const double pk = (c[k] + t_in * u[k]) / dx;
-            if (tk == t_in) i[k] = u[k] > 0.0 ? ihi[k] + 1 : ilo[k] - 1;
-            else i[k] = (int64_t)(u[k] < 0.0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
+            const double tk = sgn[k] > 0 ? (ihi_b[k] - c[k]) * iu[k] : (sgn[k] < 0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
+            const double pk = (c[k] + t_in * u[k]) * idx_scale;  // exact: a power of two
+            if (tk == t_in) i[k] = sgn[k] > 0 ? ihi[k] + 1 : ilo[k] - 1;
+            else i[k] = (int64_t)(sgn[k] < 0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
+            tn[k] = sgn[k] > 0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
+                               : (sgn[k] < 0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
+            dt[k] = sgn[k] != 0 ? dx * fabs(iu[k]) : 0.0;
         }
         const int64_t S = nl + 2 * kHalo;
+        const int64_t step[3] = {sgn[0], sgn[1] * S, sgn[2] * S * S};
         const float* lv = lev[l];
+        int64_t idx = ((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo);
         double t = t_in;
-        // at most (width of the outer box) crossings per axis
-        for (int step = 0; step < 96 && t < t_out; ++step) {
-            double tn[3];
-            for (int k = 0; k < 3; ++k)
-                tn[k] = u[k] > 0.0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
-                                   : (u[k] < 0.0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
+        // at most (width of the outer box) crossings per axis; the walk
+        // stops when a crossing leaves the outer box (the advanced crossing
+        // times can round a face crossing to just before t_out)
+        for (int n = 0; n < 96 && t < t_out; ++n) {
             const double te = fmin(fmin(fmin(tn[0], tn[1]), tn[2]), t_out);
-            const float n = lv[((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo)];
-            sum += (double)n * (te - t);
+            sum += (double)lv[idx] * (te - t);
+            bool out = false;
+#pragma unroll
             for (int k = 0; k < 3; ++k)
-                if (tn[k] == te) i[k] += u[k] > 0.0 ? 1 : -1;
+                if (tn[k] == te) {
+                    idx += step[k];
+                    i[k] += sgn[k];
+                    tn[k] += dt[k];
+                    out |= i[k] < olo[k] || i[k] > ohi[k];
+                }
+            if (out) break;
             t = te;
         }
         for (int k = 0; k < 3; ++k) {
@@ -121,9 +149,11 @@ __global__ __launch_bounds__(256) void k_insitu_coarse(const InsituArgs a) {
     const int64_t n1 = (int64_t)1 << L1;
     const int64_t A[3] = {o & (n1 - 1), (o >> L1) & (n1 - 1), o >> (2 * L1)};
     float* row = a.E + o * a.D;
+    const InsituOct oc = insitu_oct(a.L, A);
     for (int d = 0; d < a.D; ++d) {
-        const double u[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
-        const float v = (float)(insitu_column(a.lev, a.L, A, u) * a.box);
+        const double u[3] = {a.dirs[6 * d], a.dirs[6 * d + 1], a.dirs[6 * d + 2]};
+        const double iu[3] = {a.dirs[6 * d + 3], a.dirs[6 * d + 4], a.dirs[6 * d + 5]};
+        const float v = (float)(insitu_column(a.lev, a.L, oc, u, iu) * a.box);
         row[d] = a.accumulate ? row[d] + v : v;
     }
 }
@@ -136,9 +166,11 @@ __global__ __launch_bounds__(256) void k_insitu_targets(const InsituArgs a, cons
     if (g >= n_tg) return;
     const int l0 = info[4 * g];
     const int64_t A[3] = {info[4 * g + 1], info[4 * g + 2], info[4 * g + 3]};
+    const InsituOct oc = insitu_oct(l0, A);
     for (int d = 0; d < a.D; ++d) {
-        const double u[3] = {a.dirs[3 * d], a.dirs[3 * d + 1], a.dirs[3 * d + 2]};
-        X[g * a.D + d] = (float)(insitu_column(a.lev, l0, A, u) * a.box);
+        const double u[3] = {a.dirs[6 * d], a.dirs[6 * d + 1], a.dirs[6 * d + 2]};
+        const double iu[3] = {a.dirs[6 * d + 3], a.dirs[6 * d + 4], a.dirs[6 * d + 5]};
+        X[g * a.D + d] = (float)(insitu_column(a.lev, l0, oc, u, iu) * a.box);
     }
 }
 
