@@ -25,6 +25,7 @@
 #include "tree_amr.h"
 
 #define CD_CONST __attribute__((address_space(4)))
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 namespace cd {
 
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
             for (int m = 0; m < 8; ++m)
                 if ((m & allowed) == m) s = fmaf(ln[c ^ m], G[m], s);
             const float v = fmaf(dxL, s, acc);
-            if (live && valid) a.N[leaf * a.D + d] = v;
+            if (live && valid) __builtin_nontemporal_store(v, a.N + leaf * a.D + d);  // not read again
             if (live) chis[c] += __expf(-a.chi_scale * v);
         }
     }
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(256) void k_target_octs(const AmrSweepArgs a) {
 #pragma unroll
             for (int m = DP / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m);
             const int64_t leaf = a.tg_leaf[8 * g + c];
-            if (valid && dl == 0 && leaf >= 0) a.chi[leaf] = v / (float)a.D;
+            if (valid && dl == 0 && leaf >= 0) __builtin_nontemporal_store(v / (float)a.D, a.chi + leaf);
         }
     }
 }
@@ -455,7 +456,7 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
         __syncthreads();
         if (h == 0) chi += chip[grp][lane];
     }
-    if (a.chi && leaf >= 0 && h == 0) a.chi[leaf] = chi * (1.f / (float)D);
+    if (a.chi && leaf >= 0 && h == 0) __builtin_nontemporal_store(chi * (1.f / (float)D), a.chi + leaf);
 
     // rows through LDS: lanes 32 p .. 32 p + 31 in pass p (both halves of a pair)
     __shared__ __align__(16) float stage[NG][32 * D];
@@ -484,7 +485,9 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
             const int64_t lf = rows[grp][r];
             if (lf < 0) continue;
             float* dst = a.N + lf * D + col;
-            if constexpr (VS == 4) *reinterpret_cast<float4*>(dst) = *reinterpret_cast<const float4*>(st + i * VS);
+            // streaming stores: N is not read again by the sweep
+            if constexpr (VS == 4)
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(st + i * VS), reinterpret_cast<v4f*>(dst));
             else if constexpr (VS == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(st + i * VS);
             else *dst = st[i];
         }

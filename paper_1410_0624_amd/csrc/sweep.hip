@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void k_fine_uniform(const FineArgs a) {
 #pragma unroll
                     for (int sb = 0; sb < 8; ++sb) s = fmaf(ln[sb], a.kloc[(o * 8 + sb) * a.D + d], s);
                     const float v = fmaf(a.dxL, s, acc[j]);
-                    out[d] = v;
+                    __builtin_nontemporal_store(v, out + d);  // not read again
                     chis[o] += __expf(-a.chi_scale * v);
                 }
             }
@@ -128,7 +128,7 @@ __global__ __launch_bounds__(256) void k_fine_uniform(const FineArgs a) {
 #pragma unroll
         for (int o = 0; o < 8; ++o) {
             const int64_t T = ((int64_t)(2 * az + (o >> 2)) * n + (2 * ay + ((o >> 1) & 1))) * n + 2 * ax + (o & 1);
-            a.chi[T] = chis[o] * invD;
+            __builtin_nontemporal_store(chis[o] * invD, a.chi + T);
         }
     }
 }
