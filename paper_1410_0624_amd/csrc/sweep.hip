@@ -467,10 +467,10 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         // once its external columns are done, overlapping the next slab
         const int tpa = 1 << (L - 5);  // tiles per axis (16 octs each)
         // z-slabs: the row kernel of slab j overlaps the external kernel of
-        // slab j+1 (measured +4 % at D = 48 with 4 slabs, within noise at
-        // D = 12, where one launch each is kept); the split kernel covers the
-        // whole grid in one launch
-        int nslab = (split || D <= 24) ? 1 : 4;
+        // slab j+1 (measured +4 % at D = 48 with 4 slabs, +7 % at 512^3 and
+        // D = 12 with 2, within noise at 256^3 and D = 12, where one launch
+        // each is kept); the split kernel covers the whole grid in one launch
+        int nslab = split ? 1 : (D > 24 ? 4 : (L >= 9 ? 2 : 1));
         while (nslab > 1 && tpa % nslab) nslab >>= 1;
         const int per = tpa / nslab;
         auto mark = [t](int stage, int edge, hipStream_t st) -> hipError_t {
