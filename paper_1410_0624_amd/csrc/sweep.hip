@@ -464,7 +464,9 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         if (rc != CD_OK) return rc;
         // stream s: the tiled kernel slab by slab (whole tile layers along z);
         // stream aux: the coarse tables, then the target rows of each slab
-        // once its external columns are done, overlapping the next slab
+        // once its external columns are done, overlapping the next slab.
+        // With one slab the rows follow the tiled kernel on s itself (no
+        // hand-over between the streams before and after them)
         const int tpa = 1 << (L - 5);  // tiles per axis (16 octs each)
         // z-slabs: the row kernel of slab j overlaps the external kernel of
         // slab j+1 (measured +4 % at D = 48 with 4 slabs, +7 % at 512^3 and
@@ -484,6 +486,8 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
         launch_coarse(t, w, L - 4, true, t->aux, nullptr, nullptr);
         CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
+        const bool rows_on_s = nslab == 1;
+        if (rows_on_s) CD_HIP(hipEventRecord(t->ev[kMaxSlabs - 1], t->aux));  // coarse tables done
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         t->pslabs = t->prof ? nslab : 0;
         for (int j = 0; j < nslab; ++j) {
@@ -494,6 +498,15 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
             CD_HIP(hipEventRecord(t->ev[j], s));
         }
         CD_HIP(mark(CD_STAGE_EXTERNAL, 1, s));
+        if (rows_on_s) {
+            CD_HIP(hipStreamWaitEvent(s, t->ev[kMaxSlabs - 1], 0));
+            CD_HIP(mark(CD_STAGE_ROWS, 0, s));
+            launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s);
+            CD_HIP(mark(CD_STAGE_ROWS, 1, s));
+            CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
+            CD_HIP(hipGetLastError());
+            return CD_OK;
+        }
         for (int j = 0; j < nslab; ++j) {
             CD_HIP(hipStreamWaitEvent(t->aux, t->ev[j], 0));
             if (j == 0) CD_HIP(mark(CD_STAGE_ROWS, 0, t->aux));
