@@ -53,70 +53,52 @@ int count_invalid(const float* v, int64_t n, int64_t* out, hipStream_t s) {
     return CD_OK;
 }
 
-// Level L-1 from the leaves of a uniform 2^L grid (row-major, x fastest).
-__global__ void k_pyramid_from_leaves(const float* __restrict__ leaf, int L, float* __restrict__ out) {
-    const int64_t n1 = (int64_t)1 << (L - 1);
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n1 * n1 * n1) return;
-    const int64_t i = idx & (n1 - 1), j = (idx >> (L - 1)) & (n1 - 1), k = idx >> (2 * (L - 1));
-    const int64_t n = 2 * n1;
-    const float* p = leaf + ((2 * k) * n + 2 * j) * n + 2 * i;
-    float2 a = *reinterpret_cast<const float2*>(p);
-    float2 b = *reinterpret_cast<const float2*>(p + n);
-    float2 c = *reinterpret_cast<const float2*>(p + n * n);
-    float2 d = *reinterpret_cast<const float2*>(p + n * n + n);
-    const float s = ((a.x + a.y) + (b.x + b.y)) + ((c.x + c.y) + (d.x + d.y));
-    const int64_t S = n1 + 2 * kHalo;
-    out[((k + kHalo) * S + (j + kHalo)) * S + (i + kHalo)] = 0.125f * s;
-}
+// The coarsest levels top-1 .. 0 (top <= 4) from level top (the leaves of a
+// uniform grid when in_is_leaf, else a padded level) in one workgroup: each
+// level's means go to its padded array and, unpadded, to LDS for the next
+// (same order of operations as the other pyramid kernels).  One launch
+// instead of one per level for levels too small to fill the chip.
+struct TailArgs {
+    const float* in;
+    bool in_is_leaf;
+    int top;
+    float* lev[4];  // padded levels 0 .. top-1
+};
 
-// Level l from padded level l+1.
-__global__ void k_pyramid_level(const float* __restrict__ in, int l, float* __restrict__ out) {
-    const int64_t n = (int64_t)1 << l;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n * n) return;
-    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
-    const int64_t Si = 2 * n + 2 * kHalo, So = n + 2 * kHalo;
-    const float* p = in + ((2 * k + kHalo) * Si + (2 * j + kHalo)) * Si + (2 * i + kHalo);
-    const float s = ((p[0] + p[1]) + (p[Si] + p[Si + 1])) +
-                    ((p[Si * Si] + p[Si * Si + 1]) + (p[Si * Si + Si] + p[Si * Si + Si + 1]));
-    out[((k + kHalo) * So + (j + kHalo)) * So + (i + kHalo)] = 0.125f * s;
-}
-
-// Levels l+1 and l from level l+2 (the leaves of a uniform grid when
-// l + 2 == L, else a padded level): each thread averages a 4^3 block into its
-// 8 level-(l+1) means and their level-l mean (same order of operations as
-// one level at a time).
-__global__ void k_pyramid_two(const float* __restrict__ in, bool in_is_leaf, int l, float* __restrict__ out1,
-                              float* __restrict__ out0) {
-    const int64_t n = (int64_t)1 << l;
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= n * n * n) return;
-    const int64_t i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
-    const int64_t n2 = 4 * n;                                  // cells per axis at level l+2
-    const int64_t Si = in_is_leaf ? n2 : n2 + 2 * kHalo;       // row pitch of the input
-    const int64_t h = in_is_leaf ? 0 : kHalo;
-    const int64_t S1 = 2 * n + 2 * kHalo, S0 = n + 2 * kHalo;
-    float m1[8];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-        const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
-        const float* p = in + ((4 * k + 2 * cz + h) * Si + (4 * j + 2 * cy + h)) * Si + (4 * i + 2 * cx + h);
-        const float sum = ((p[0] + p[1]) + (p[Si] + p[Si + 1])) +
-                          ((p[Si * Si] + p[Si * Si + 1]) + (p[Si * Si + Si] + p[Si * Si + Si + 1]));
-        m1[c] = 0.125f * sum;
-        out1[((2 * k + cz + kHalo) * S1 + (2 * j + cy + kHalo)) * S1 + (2 * i + cx + kHalo)] = m1[c];
+__global__ __launch_bounds__(512) void k_pyramid_tail(const TailArgs a) {
+    __shared__ float buf[2][512];
+    int cur = 0;
+    for (int l = a.top - 1; l >= 0; --l) {
+        const int n = 1 << l, n2 = 2 * n;
+        const int64_t So = n + 2 * kHalo;
+        for (int idx = threadIdx.x; idx < n * n * n; idx += blockDim.x) {
+            const int i = idx & (n - 1), j = (idx >> l) & (n - 1), k = idx >> (2 * l);
+            float v[8];
+            if (l == a.top - 1) {
+                const int64_t Si = a.in_is_leaf ? n2 : n2 + 2 * kHalo, h = a.in_is_leaf ? 0 : kHalo;
+                const float* p = a.in + ((2 * k + h) * Si + (2 * j + h)) * Si + (2 * i + h);
+                v[0] = p[0], v[1] = p[1], v[2] = p[Si], v[3] = p[Si + 1];
+                v[4] = p[Si * Si], v[5] = p[Si * Si + 1], v[6] = p[Si * Si + Si], v[7] = p[Si * Si + Si + 1];
+            } else {
+                const float* p = buf[cur] + ((2 * k) * n2 + 2 * j) * n2 + 2 * i;
+                v[0] = p[0], v[1] = p[1], v[2] = p[n2], v[3] = p[n2 + 1];
+                v[4] = p[n2 * n2], v[5] = p[n2 * n2 + 1], v[6] = p[n2 * n2 + n2], v[7] = p[n2 * n2 + n2 + 1];
+            }
+            const float m = 0.125f * (((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])));
+            a.lev[l][((k + kHalo) * So + (j + kHalo)) * So + (i + kHalo)] = m;
+            buf[cur ^ 1][idx] = m;
+        }
+        __syncthreads();
+        cur ^= 1;
     }
-    const float s0 = ((m1[0] + m1[1]) + (m1[2] + m1[3])) + ((m1[4] + m1[5]) + (m1[6] + m1[7]));
-    out0[((k + kHalo) * S0 + (j + kHalo)) * S0 + (i + kHalo)] = 0.125f * s0;
 }
 
-// The same two levels with a lane per level-(l+1) cell (l >= 3): a wave
+// Levels l+1 and l (l >= 3) from level l+2 (the leaves of a uniform grid
+// when l + 2 == L, else a padded level), with a lane per level-(l+1) cell: a wave
 // covers 16 x 2 x 2 of them, reads their 2^3 blocks (rows of 128 contiguous
 // bytes; float2 pairs from unpadded leaves at an 8-byte aligned address),
 // and forms each level-l mean across lanes x^1, y^16, z^32 in the
-// order of k_pyramid_two.  Eight times the lanes of k_pyramid_two in flight
-// for the read of the finest level.
+// order of one level at a time.
 __device__ __forceinline__ float2 ld_pair(const float* p, bool aligned) {
     if (aligned) return *reinterpret_cast<const float2*>(p);
     return make_float2(p[0], p[1]);
@@ -158,21 +140,21 @@ static int launch_blocks(int64_t n) { return (int)((n + 255) / 256); }
 int build_dense_below(cd_tree* t, int top, hipStream_t s) {
     const bool from_leaf = t->uniform;
     int cur = top;
-    while (cur >= 2) {
+    while (cur > 4) {
         const int l = cur - 2;
         const int64_t n = (int64_t)1 << l;
         const bool leaf_in = from_leaf && cur == top;
         const float* in = leaf_in ? t->leaf : t->lev[cur];
-        if (l >= 3)
-            k_pyramid_two_wide<<<launch_blocks(8 * n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1],
-                                                                             t->lev[l]);
-        else
-            k_pyramid_two<<<launch_blocks(n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1], t->lev[l]);
+        k_pyramid_two_wide<<<launch_blocks(8 * n * n * n), 256, 0, s>>>(in, leaf_in, l, t->lev[l + 1], t->lev[l]);
         cur = l;
     }
-    if (cur == 1) {
-        if (from_leaf && top == 1) k_pyramid_from_leaves<<<1, 256, 0, s>>>(t->leaf, 1, t->lev[0]);
-        else k_pyramid_level<<<1, 256, 0, s>>>(t->lev[1], 0, t->lev[0]);
+    if (cur >= 1) {
+        TailArgs a{};
+        a.in_is_leaf = from_leaf && cur == top;
+        a.in = a.in_is_leaf ? t->leaf : t->lev[cur];
+        a.top = cur;
+        for (int l = 0; l < cur; ++l) a.lev[l] = t->lev[l];
+        k_pyramid_tail<<<1, 512, 0, s>>>(a);
     }
     CD_HIP(hipGetLastError());
     return CD_OK;
