@@ -166,10 +166,15 @@ void cd_tree_destroy(cd_tree* tree);
  *              the contraction on the matrix cores with FP32 accumulation;
  *              measured error |d ln N| <= 3e-5 (bf16) and <= 1e-6 (fp16).
  *              CD_FP16X2 divides each LDS density tile by a power of two:
- *              it needs the tiled kernel, i.e. D in {6, 12, 24, 40, 48} and
- *              2^L >= 32 on uniform grids, base level >= 5 on adaptive
- *              trees.  CD_BF16X2 on uniform grids needs the same; on
- *              adaptive trees it takes any D and base level.
+ *              it needs the tiled kernel, i.e. D in {6, 12, 24, 40, 48}, and
+ *              on uniform grids 2^L >= 32.  CD_BF16X2 on uniform grids
+ *              needs the same; on adaptive trees it takes any D.  On
+ *              adaptive trees the split forms cover the targets of the
+ *              16^3-oct tiles that the tiled kernel sweeps (the densely
+ *              occupied ones); the other targets (sparse tiles, levels
+ *              without tiles) are gathered in FP32 in every form, except
+ *              that CD_BF16X2 for a D outside that set gathers every target
+ *              on the matrix cores.
  * Errors: CD_EINVAL, CD_EUNSUPPORTED, CD_ENOMEM, CD_EDEVICE.
  */
 int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
