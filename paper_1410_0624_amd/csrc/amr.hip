@@ -411,11 +411,15 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
             }
         }
     };
-    add_row(a.E + (a.erow ? a.erow[g] : g) * D + dh0, true);
+    // the oct's rows of E and of the coarse table (or of x4): with 16-byte
+    // pieces, the lanes of the oct's 8-lane group load distinct pieces (one
+    // load instead of DH / 4 per lane) and share them through LDS
+    const float* erow_p = a.E + (a.erow ? a.erow[g] : g) * D + dh0;
+    const float* qrow_p = nullptr;
     {
         const int l = l0 - 4;
         if (a.x4) {
-            add_row(a.x4 + g * D + dh0, false);
+            qrow_p = a.x4 + g * D + dh0;
         } else if (l >= 2) {
             const int sh = l0 - 1 - l;
             const int64_t nq = (int64_t)1 << l;
@@ -427,8 +431,27 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
                 const int s0 = a.dl4[(Ax >> 1) & 3], s1 = a.dl4[(Ay >> 1) & 3], s2 = a.dl4[(Az >> 1) & 3];
                 code = cell * 216 + s0 + 6 * s1 + 36 * s2;
             }
-            add_row(a.q[l] + code * D + dh0, false);
+            qrow_p = a.q[l] + code * D + dh0;
         }
+    }
+    if constexpr (V == 4) {
+        constexpr int NV = DH / 4;  // pieces per row (<= 6 < 8 lanes)
+        __shared__ float4 xe[4][8][NV], xq[4][8][NV];
+        const int o = lane >> 3;
+        if (c < NV) {
+            xe[w][o][c] = *reinterpret_cast<const float4*>(erow_p + 4 * c);
+            xq[w][o][c] = qrow_p ? *reinterpret_cast<const float4*>(qrow_p + 4 * c) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            const float4 e = xe[w][o][k], q = xq[w][o][k];
+            out[4 * k] = e.x + q.x, out[4 * k + 1] = e.y + q.y, out[4 * k + 2] = e.z + q.z, out[4 * k + 3] = e.w + q.w;
+        }
+    } else {
+        add_row(erow_p, true);
+        if (qrow_p) add_row(qrow_p, false);
     }
     // internal + local (Sect. 3.2) and the screening sum (Eq. 5)
     const float dxL = (float)(a.box * ldexp(1.0, -l0));
