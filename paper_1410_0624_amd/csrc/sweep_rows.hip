@@ -78,7 +78,13 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
     // then come through one L2 (workgroups are spread over the XCDs).
     const int lane = threadIdx.x & 63;
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
-    const int64_t blk = blockIdx.x;
+    // Workgroup b runs on XCD b % 8 (each XCD with its own L2): XCD x takes
+    // the contiguous range of (segment, oct row) items [x q + min(x, r),
+    // ...) of its count q + (x < r), q = nb / 8, r = nb % 8, so that the rows
+    // one XCD streams out are neighbours (with the streaming stores: 0.162
+    // -> 0.152 ms at 256^3, D = 12)
+    const int64_t nbk = gridDim.x, bx = blockIdx.x % 8, kx = blockIdx.x / 8;
+    const int64_t blk = bx * (nbk / 8) + (bx < nbk % 8 ? bx : nbk % 8) + kx;
     const int64_t seg_i = blk % segs;
     const int64_t orow = blk / segs;                 // oct row (Y, Z) within this launch
     if (orow >= (a.nz >> 1) * n1) return;  // whole workgroup: uniform
