@@ -57,6 +57,8 @@ CASES = [
     (6, 1, 14.0, 7, "axes6"),      # base 2^1, no coarse table at all
     (8, 3, 60.0, 8, "healpix1"),   # five refined levels above an 8^3 base
     (7, 5, 30.0, 7, "healpix2"),   # base 32^3: tiled shells on the active tiles of levels 5 .. 7
+    (4, 2, 8.0, 9, "healpix1"),    # finest level 4: no 16^3-oct tile anywhere, every target gathered
+    (5, 1, 10.0, 10, "healpix2"),  # one tile at level 5 beside gathered targets of levels 1 .. 4
 ]
 DIRS = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2), "axes6": oracle.dirs_axes6()}
 

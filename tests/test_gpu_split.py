@@ -77,6 +77,7 @@ def test_split_c2_256_sampled(colden, pname):
     # gathered in FP32, dense tiles on the matrix cores
     ("bf16x2", 6, 3, 14.0, 5, "healpix1"), ("bf16x2", 7, 4, 30.0, 5, "healpix2"), ("bf16x2", 7, 2, 30.0, 6, "healpix1"),
     ("fp16x2", 6, 3, 14.0, 5, "healpix1"), ("fp16x2", 7, 4, 30.0, 5, "healpix2"),
+    ("fp16x2", 4, 2, 8.0, 9, "healpix1"),  # no 16^3-oct tile: every target gathered in FP32
     # base level >= 5
     ("bf16x2", 7, 5, 30.0, 7, "healpix2"), ("fp16x2", 7, 5, 30.0, 7, "healpix2"),
     ("fp16x2", 7, 6, 14.0, 8, "healpix1"),
