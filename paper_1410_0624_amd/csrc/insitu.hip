@@ -67,54 +67,61 @@ __device__ __forceinline__ InsituOct insitu_oct(int l0, const int64_t (&A)[3]) {
 // along u: the levels l0 - 4 .. 0 of the padded arrays lev.  Each shell is
 // walked cell by cell from the ray's exit of the inner box to its exit of
 // the outer box, the next crossing per axis advanced by one cell's extent
-// along the ray.
+// along the ray.  The inner box of a shell is the outer box of the shell
+// below (both limits are whole cells of the coarser level), so its exit is
+// the previous shell's outer exit, bit for bit.  Cell indexes fit 32 bits:
+// the walked levels are at most CD_MAX_LEVEL - 4.
 __device__ double insitu_column(const float* const* lev, int l0, const InsituOct& oc, const double (&u)[3],
                                 const double (&iu)[3]) {
     const int L1 = l0 - 1;
     if (L1 - 3 < 0) return 0.0;
-    int64_t ilo[3] = {oc.ilo[0], oc.ilo[1], oc.ilo[2]}, ihi[3] = {oc.ihi[0], oc.ihi[1], oc.ihi[2]};
+    int ilo[3] = {(int)oc.ilo[0], (int)oc.ilo[1], (int)oc.ilo[2]};
+    int ihi[3] = {(int)oc.ihi[0], (int)oc.ihi[1], (int)oc.ihi[2]};
     const double(&c)[3] = oc.c;
     const int sgn[3] = {u[0] > 0.0 ? 1 : (u[0] < 0.0 ? -1 : 0), u[1] > 0.0 ? 1 : (u[1] < 0.0 ? -1 : 0),
                         u[2] > 0.0 ? 1 : (u[2] < 0.0 ? -1 : 0)};
     double sum = 0.0;
+    double t_in = -1.0;  // set for the first shell, then the previous shell's outer exit
     for (int l = L1 - 3; l >= 0; --l) {
-        const int64_t nl = (int64_t)1 << l;
+        const int nl = 1 << l;
         // an inner box that covers the whole level leaves this shell and
         // every coarser one outside the box (no matter there)
         if (ilo[0] <= 0 && ilo[1] <= 0 && ilo[2] <= 0 && ihi[0] >= nl - 1 && ihi[1] >= nl - 1 && ihi[2] >= nl - 1)
             break;
         const double dx = ldexp(1.0, -l), idx_scale = ldexp(1.0, l);
-        int64_t olo[3], ohi[3];
+        int olo[3], ohi[3], lim[3];
         double blo[3], bhi[3], ilo_b[3], ihi_b[3];
         for (int k = 0; k < 3; ++k) {
             olo[k] = ilo[k] - 2;
             ohi[k] = ihi[k] + 2;
             if (olo[k] & 1) olo[k] -= 1;
             if (!(ohi[k] & 1)) ohi[k] += 1;
+            lim[k] = sgn[k] > 0 ? ohi[k] + 1 : olo[k] - 1;  // the first index past the outer box ahead
             blo[k] = (double)olo[k] * dx;
             bhi[k] = (double)(ohi[k] + 1) * dx;
             ilo_b[k] = (double)ilo[k] * dx;
             ihi_b[k] = (double)(ihi[k] + 1) * dx;
         }
-        const double t_in = exit_t(c, u, iu, ilo_b, ihi_b), t_out = exit_t(c, u, iu, blo, bhi);
+        if (t_in < 0.0) t_in = exit_t(c, u, iu, ilo_b, ihi_b);
+        const double t_out = exit_t(c, u, iu, blo, bhi);
         // first cell past the inner box: the axes that leave it at t_in
         // step out of it by index, the others contain c + t_in u; then the
         // first crossing along each axis and the distance between crossings
-        int64_t i[3];
+        int i[3];
         double tn[3], dt[3];
         for (int k = 0; k < 3; ++k) {
             const double tk = sgn[k] > 0 ? (ihi_b[k] - c[k]) * iu[k] : (sgn[k] < 0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
             const double pk = (c[k] + t_in * u[k]) * idx_scale;  // exact: a power of two
             if (tk == t_in) i[k] = sgn[k] > 0 ? ihi[k] + 1 : ilo[k] - 1;
-            else i[k] = (int64_t)(sgn[k] < 0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
+            else i[k] = (int)(sgn[k] < 0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
             tn[k] = sgn[k] > 0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
                                : (sgn[k] < 0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
             dt[k] = sgn[k] != 0 ? dx * fabs(iu[k]) : 0.0;
         }
-        const int64_t S = nl + 2 * kHalo;
-        const int64_t step[3] = {sgn[0], sgn[1] * S, sgn[2] * S * S};
+        const int S = nl + 2 * kHalo;
+        const int step[3] = {sgn[0], sgn[1] * S, sgn[2] * S * S};
         const float* lv = lev[l];
-        int64_t idx = ((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo);
+        int idx = ((i[2] + kHalo) * S + (i[1] + kHalo)) * S + (i[0] + kHalo);
         double t = t_in;
         // at most (width of the outer box) crossings per axis; the walk
         // stops when a crossing leaves the outer box (the advanced crossing
@@ -129,11 +136,12 @@ __device__ double insitu_column(const float* const* lev, int l0, const InsituOct
                     idx += step[k];
                     i[k] += sgn[k];
                     tn[k] += dt[k];
-                    out |= i[k] < olo[k] || i[k] > ohi[k];
+                    out |= i[k] == lim[k];
                 }
             if (out) break;
             t = te;
         }
+        t_in = t_out;
         for (int k = 0; k < 3; ++k) {
             ilo[k] = olo[k] / 2;
             ihi[k] = (ohi[k] + 1) / 2 - 1;
