@@ -23,19 +23,6 @@ struct InsituArgs {
     int64_t n_oct;
 };
 
-// Distance from c (inside the box [lo, hi]) to the box's boundary along u
-// (iu = 1 / u per axis, 0 where u has no component).
-__device__ __forceinline__ double exit_t(const double (&c)[3], const double (&u)[3], const double (&iu)[3],
-                                         const double (&lo)[3], const double (&hi)[3]) {
-    double t = 1e300;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (u[a] > 0.0) t = fmin(t, (hi[a] - c[a]) * iu[a]);
-        else if (u[a] < 0.0) t = fmin(t, (lo[a] - c[a]) * iu[a]);
-    }
-    return t;
-}
-
 // The oct A's (level l0 - 1 coordinates, targets at level l0) centre c in
 // box units and the inner limit of its level-(l0 - 4) shell: the outer
 // limits of the shells dl = 1, 2, 3 (the same for every direction).
@@ -89,30 +76,31 @@ __device__ double insitu_column(const float* const* lev, int l0, const InsituOct
         if (ilo[0] <= 0 && ilo[1] <= 0 && ilo[2] <= 0 && ihi[0] >= nl - 1 && ihi[1] >= nl - 1 && ihi[2] >= nl - 1)
             break;
         const double dx = ldexp(1.0, -l), idx_scale = ldexp(1.0, l);
+        // per axis only the faces ahead of the ray matter: the inner box's
+        // (where the ray leaves it) and the outer box's
         int olo[3], ohi[3], lim[3];
-        double blo[3], bhi[3], ilo_b[3], ihi_b[3];
+        double t_out = 1e300, fin[3];
         for (int k = 0; k < 3; ++k) {
             olo[k] = ilo[k] - 2;
             ohi[k] = ihi[k] + 2;
             if (olo[k] & 1) olo[k] -= 1;
             if (!(ohi[k] & 1)) ohi[k] += 1;
             lim[k] = sgn[k] > 0 ? ohi[k] + 1 : olo[k] - 1;  // the first index past the outer box ahead
-            blo[k] = (double)olo[k] * dx;
-            bhi[k] = (double)(ohi[k] + 1) * dx;
-            ilo_b[k] = (double)ilo[k] * dx;
-            ihi_b[k] = (double)(ihi[k] + 1) * dx;
+            fin[k] = 1e300;
+            if (sgn[k] != 0) {
+                fin[k] = ((double)(sgn[k] > 0 ? ihi[k] + 1 : ilo[k]) * dx - c[k]) * iu[k];
+                t_out = fmin(t_out, ((double)(sgn[k] > 0 ? ohi[k] + 1 : olo[k]) * dx - c[k]) * iu[k]);
+            }
         }
-        if (t_in < 0.0) t_in = exit_t(c, u, iu, ilo_b, ihi_b);
-        const double t_out = exit_t(c, u, iu, blo, bhi);
+        if (t_in < 0.0) t_in = fmin(fmin(fin[0], fin[1]), fin[2]);
         // first cell past the inner box: the axes that leave it at t_in
         // step out of it by index, the others contain c + t_in u; then the
         // first crossing along each axis and the distance between crossings
         int i[3];
         double tn[3], dt[3];
         for (int k = 0; k < 3; ++k) {
-            const double tk = sgn[k] > 0 ? (ihi_b[k] - c[k]) * iu[k] : (sgn[k] < 0 ? (ilo_b[k] - c[k]) * iu[k] : 1e300);
             const double pk = (c[k] + t_in * u[k]) * idx_scale;  // exact: a power of two
-            if (tk == t_in) i[k] = sgn[k] > 0 ? ihi[k] + 1 : ilo[k] - 1;
+            if (fin[k] == t_in) i[k] = sgn[k] > 0 ? ihi[k] + 1 : ilo[k] - 1;
             else i[k] = (int)(sgn[k] < 0 ? ceil(pk) - 1.0 : floor(pk));  // a face hit: the cell ahead
             tn[k] = sgn[k] > 0 ? ((double)(i[k] + 1) * dx - c[k]) * iu[k]
                                : (sgn[k] < 0 ? ((double)i[k] * dx - c[k]) * iu[k] : 1e300);
