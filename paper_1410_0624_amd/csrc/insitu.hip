@@ -155,7 +155,11 @@ __global__ __launch_bounds__(256) void k_insitu_coarse(const InsituArgs a) {
 }
 
 // Adaptive trees: the in-situ shells dl >= 4 of every target oct (level of
-// its targets and oct coordinates in info[4 g .. 4 g + 3]) into X[g][D].
+// its targets and oct coordinates in info[4 g .. 4 g + 3]) into X[g][D]; a
+// thread per target oct and chunk of up to kInsituChunk directions
+// (blockIdx.y), so that a tree with few target octs still fills the GPU.
+constexpr int kInsituChunk = 12;
+
 __global__ __launch_bounds__(256) void k_insitu_targets(const InsituArgs a, const int32_t* __restrict__ info,
                                                         int64_t n_tg, float* __restrict__ X) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -163,7 +167,8 @@ __global__ __launch_bounds__(256) void k_insitu_targets(const InsituArgs a, cons
     const int l0 = info[4 * g];
     const int64_t A[3] = {info[4 * g + 1], info[4 * g + 2], info[4 * g + 3]};
     const InsituOct oc = insitu_oct(l0, A);
-    for (int d = 0; d < a.D; ++d) {
+    const int d0 = (int)blockIdx.y * kInsituChunk, d1 = min(a.D, d0 + kInsituChunk);
+    for (int d = d0; d < d1; ++d) {
         const double u[3] = {a.dirs[6 * d], a.dirs[6 * d + 1], a.dirs[6 * d + 2]};
         const double iu[3] = {a.dirs[6 * d + 3], a.dirs[6 * d + 4], a.dirs[6 * d + 5]};
         X[g * a.D + d] = (float)(insitu_column(a.lev, l0, oc, u, iu) * a.box);
@@ -196,7 +201,8 @@ void launch_insitu_targets(const cd_tree* t, const cd_weights* w, const int32_t*
     a.dirs = w->dirs;
     a.D = w->D;
     a.box = t->box_cm;
-    k_insitu_targets<<<(unsigned)((n_tg + 255) / 256), 256, 0, s>>>(a, info, n_tg, X);
+    const dim3 grid((unsigned)((n_tg + 255) / 256), (unsigned)((a.D + kInsituChunk - 1) / kInsituChunk));
+    k_insitu_targets<<<grid, 256, 0, s>>>(a, info, n_tg, X);
 }
 
 }  // namespace cd

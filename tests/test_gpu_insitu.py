@@ -104,14 +104,15 @@ def test_insitu_differs_from_precalc_as_the_paper_reports(colden):
 
 
 @pytest.mark.parametrize("Lf,B,th,dname", [(6, 3, 14.0, "healpix1"), (6, 2, 14.0, "axes6"), (7, 5, 30.0, "healpix2"),
-                                           (7, 5, 30.0, "mn3x8"), (6, 3, 14.0, "rand7")])
+                                           (7, 5, 30.0, "mn3x8"), (6, 3, 14.0, "rand7"), (6, 3, 14.0, "rand13")])
 def test_insitu_amr_parity(colden, Lf, B, th, dname):
     """Adaptive trees: the walk of the shells dl >= 4 per target oct (any
     level), the shells dl = 1..3 from the tiled kernels where the target's
-    level has tiles, else from the weight lists (D = 7 everywhere)."""
+    level has tiles, else from the weight lists (D = 7 and 13 everywhere;
+    13 directions leave a last chunk of one direction in the walk kernel)."""
     tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, 50 + B), B, th, 10 * synth.PC_CM)
     assert tin.max_level > tin.base_level
-    dirs = DIRS[dname] if dname in DIRS else _rand_dirs(7, 3)
+    dirs = DIRS[dname] if dname in DIRS else _rand_dirs(int(dname[4:]), 3)
     N, chi = _run(colden, tin, dirs, colden.CD_INSITU)
     ref = oracle.Tree(tin).columns(dirs, mode=oracle.INSITU)
     rel = np.abs(N - ref) / ref
