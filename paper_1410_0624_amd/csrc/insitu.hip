@@ -158,7 +158,9 @@ __global__ __launch_bounds__(256) void k_insitu_coarse(const InsituArgs a) {
 // its targets and oct coordinates in info[4 g .. 4 g + 3]) into X[g][D]; a
 // thread per target oct and chunk of up to kInsituChunk directions
 // (blockIdx.y), so that a tree with few target octs still fills the GPU.
-constexpr int kInsituChunk = 12;
+// On uniform grids a thread keeps the whole row: the octs alone fill the
+// GPU there, and rows split over threads measured slower.
+constexpr int kInsituChunk = 4;
 
 __global__ __launch_bounds__(256) void k_insitu_targets(const InsituArgs a, const int32_t* __restrict__ info,
                                                         int64_t n_tg, float* __restrict__ X) {
