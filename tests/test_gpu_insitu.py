@@ -75,6 +75,36 @@ def test_insitu_per_oct_kernel(colden, L, D):
     assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
 
 
+def test_insitu_c4_512_sampled(colden):
+    """The 512^3 workload (134M leaves) in the launch configuration the
+    benchmark times, 12 and 48 directions: the walk covers six coarse shell
+    levels; sampled leaves (and both corners) against the oracle."""
+    tin = synth.workload_uniform(9, sigma=1.5, mean=10.0, seed=4)
+    dev = torch.device("cuda:0")
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    rng = np.random.default_rng(19)
+    tr = oracle.Tree(tin)
+    for dname, ns in [("healpix1", 10000), ("healpix2", 3000)]:
+        dirs = DIRS[dname]
+        D = dirs.shape[0]
+        tg = np.concatenate([rng.choice(tin.n_leaf, ns, replace=False), [0, tin.n_leaf - 1]])
+        ref = tr.columns(dirs, tg, mode=oracle.INSITU)
+        w = colden.Weights(dirs, mode=colden.CD_INSITU)
+        N = torch.full((tin.n_leaf, D), float("nan"), dtype=torch.float32, device=dev)
+        chi = torch.full((tin.n_leaf,), float("nan"), dtype=torch.float32, device=dev)
+        colden.column_densities(tree, w, N, chi)
+        idx = torch.from_numpy(tg).to(dev)
+        got = N[idx].cpu().numpy().astype(np.float64)
+        gchi = chi[idx].cpu().numpy().astype(np.float64)
+        rel = np.abs(got - ref) / ref
+        print(f"insitu 512^3 {dname}: max rel {rel.max():.3e}")
+        assert rel.max() <= REL_FP32
+        assert np.abs(gchi - oracle.screening(ref)).max() <= 2e-6
+        assert bool(torch.isfinite(N).all())
+        w.close()
+        del N, chi
+
+
 @pytest.mark.parametrize("prec,pname", [(1, "bf16x2"), (2, "fp16x2")])
 def test_insitu_split_forms(colden, prec, pname):
     tin = synth.workload_uniform(6, sigma=1.5, mean=10.0, seed=33)
