@@ -103,6 +103,46 @@ def test_c3_amr_sampled_parity(colden):
     assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
 
 
+def test_c3b_amr_34m_leaves_sampled_all_forms(colden):
+    """The same field refined above 5 cm^-3 (34M leaves, most of them at the
+    finest level), D = 48, in the launch configuration the benchmark times:
+    FP32 and both split forms on 3k sampled leaves of every level."""
+    tin = synth.workload_amr(threshold=5.0)
+    assert tin.n_leaf > 25_000_000
+    dirs = oracle.dirs_healpix(2)
+    rng = np.random.default_rng(2)
+    tg = []
+    for l in range(tin.base_level, tin.max_level + 1):
+        idx = np.nonzero(tin.leaf_level == l)[0]
+        tg.append(rng.choice(idx, min(3000, idx.size), replace=False))
+    tg = np.concatenate(tg + [[0, tin.n_leaf - 1]])
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    dev = torch.device("cuda:0")
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    N = torch.empty((tin.n_leaf, 48), dtype=torch.float32, device=dev)
+    chi = torch.empty((tin.n_leaf,), dtype=torch.float32, device=dev)
+    idx = torch.from_numpy(tg).to(dev)
+    for pname, prec in [("fp32", 0), ("bf16x2", 1), ("fp16x2", 2)]:
+        w = colden.Weights(dirs, precision=prec)
+        N.fill_(float("nan"))
+        chi.fill_(float("nan"))
+        colden.column_densities(tree, w, N, chi)
+        got = N[idx].cpu().numpy().astype(np.float64)
+        assert np.isfinite(got).all()
+        assert bool(torch.isfinite(chi).all())
+        if prec == 0:
+            rel = _rel(got, ref)
+            print(f"C3b {pname}: {tg.size} targets, max rel {rel.max():.3e}")
+            assert rel.max() <= REL_FP32
+            gchi = chi[idx].cpu().numpy().astype(np.float64)
+            assert np.abs(gchi - oracle.screening(ref)).max() <= 2e-6
+        else:
+            err = np.abs(np.log(got) - np.log(ref))
+            print(f"C3b {pname}: {tg.size} targets, max |d ln N| {err.max():.3e}")
+            assert err.max() <= 1e-3
+        w.close()
+
+
 def test_fully_refined_amr_equals_uniform_on_gpu(colden):
     """A tree refined everywhere is the uniform grid (Sect. 3): same columns,
     leaves permuted into oct order."""
