@@ -180,6 +180,35 @@ void cd_tree_destroy(cd_tree* tree);
 int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
                           void* stream, cd_weights** out);
 
+/*
+ * The precalculated geometric factors K of Sect. 3.3 (Eqs. 10-11) as the
+ * library computes them in FP64 on the host before cd_precompute_weights
+ * rounds and uploads them; a host-only query that touches no device.
+ *   kind 1, 2, 3: the shells dl = 1, 2, 3; kind 4: dl >= 4; kind 0: the
+ *   internal + local factors of the target's own oct (Sect. 3.2).
+ * Shells (kind 1..4): combo c indexes the per-axis shapes x + na (y + na z)
+ * (na = 2, 4, 8, 12 shapes per axis: parity of the level-l ancestor A_l,
+ * octant bits of A_(l+1), A_(l+2), and for kind 4 the inner-limit state).
+ * For each (c, d) the cnt[c][d] non-zero entries: off[c][d][e][3] the cell
+ * offset from A_l (level-l cells, each in -5..5: the 11^3 standard cube),
+ * w[c][d][e] the chord of the ray from the reference point along u_d through
+ * that cell, in level-l cell widths; entries e >= cnt are zero padding.
+ * ref[c][3] is the reference point relative to the centre of A_l and
+ * box[c][3][4] = (inner lo, inner hi, outer lo, outer hi) per axis: the
+ * entries are the cells of the outer box that are not in the inner box.
+ * Kind 0: c = octant a of the target (bits x, y, z), entries e = the 8 cells
+ * of the oct (off = their bits), w = chord from the target centre ref[a]
+ * (oct coordinates, cell width 1) through each cell; box unused.
+ * Call with off == NULL to get *ncombo and *len (entries per (c, d)); then
+ * off [ncombo][D][len][3], w [ncombo][D][len], cnt [ncombo][D], ref
+ * [ncombo][3], box [ncombo][3][4] (host buffers; w, cnt, ref, box may be NULL).
+ * Errors: CD_EINVAL (NULL dirs/ncombo/len, D or kind out of range, a
+ * direction that is not a unit vector),
+ * CD_EUNSUPPORTED (a direction set needing more than 12 entries per coarse list).
+ */
+int cd_weight_lists(const double* dirs, int D, int kind, int* ncombo, int* len, int32_t* off, double* w,
+                    int32_t* cnt, double* ref, int32_t* box);
+
 /* Number of directions of a weights handle. */
 int cd_weights_n_dirs(const cd_weights* w, int* D);
 

@@ -23,6 +23,7 @@ EXPORTS = [
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
     "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
     "cd_profile_enable", "cd_profile_read", "cd_check_densities", "cd_heating_rates", "cd_screening_heating",
+    "cd_weight_lists",
 ]
 G0_DRAINE = 1.7
 STAGES = ["pyramid", "coarse", "external", "rows", "sweep"]
@@ -66,6 +67,7 @@ def lib():
         L.cd_check_densities.argtypes = [P, I64, P, P]
         L.cd_heating_rates.argtypes = [P, P, P, P, I64, D, P, P, P, P]
         L.cd_screening_heating.argtypes = [P, I64, I, D, D, P, P, P, D, P, P, P, P, P]
+        L.cd_weight_lists.argtypes = [P, I, I, P, P, P, P, P, P, P]
         _lib = L
     return _lib
 
@@ -92,6 +94,26 @@ def directions(scheme: int, p1: int, p2: int = 0) -> np.ndarray:
     D = C.c_int(0)
     _check(lib().cd_directions(scheme, p1, p2, _np(out), cap, C.byref(D)))
     return out[:D.value].copy()
+
+
+def weight_lists(dirs: np.ndarray, kind: int) -> dict:
+    """The library's FP64 geometric factors K of one shell kind (1..4: dl = 1,
+    2, 3, >= 4; 0: internal + local), as cd_weight_lists returns them (host
+    only, no device): off [c][d][e][3], w [c][d][e], cnt [c][d], ref [c][3],
+    box [c][3][4]."""
+    dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+    D = dirs.shape[0]
+    nc, ln = C.c_int(0), C.c_int(0)
+    _check(lib().cd_weight_lists(_np(dirs), D, kind, C.byref(nc), C.byref(ln), None, None, None, None, None))
+    nc, ln = nc.value, ln.value
+    off = np.zeros((nc, D, ln, 3), np.int32)
+    w = np.zeros((nc, D, ln))
+    cnt = np.zeros((nc, D), np.int32)
+    ref = np.zeros((nc, 3))
+    box = np.zeros((nc, 3, 4), np.int32)
+    _check(lib().cd_weight_lists(_np(dirs), D, kind, C.byref(C.c_int(0)), C.byref(C.c_int(0)), _np(off), _np(w),
+                                 _np(cnt), _np(ref), _np(box)))
+    return {"off": off, "w": w, "cnt": cnt, "ref": ref, "box": box}
 
 
 def _dev_f32(t):

@@ -64,6 +64,27 @@ int upload_split_banks(cd_weights* w, hipStream_t s);  // split.hip
 void free_split_banks(cd_weights* w);
 }
 
+// Directions as unit vectors (finite, |u| = 1 within 1e-9).
+static bool unit_dirs(const char* who, const double* dirs, int D, std::vector<std::array<double, 3>>& u) {
+    u.assign(D, {0.0, 0.0, 0.0});
+    for (int d = 0; d < D; ++d) {
+        double n2 = 0;
+        for (int k = 0; k < 3; ++k) {
+            u[d][k] = dirs[3 * d + k];
+            if (!std::isfinite(u[d][k])) {
+                cd::set_error("%s: direction %d is not finite", who, d);
+                return false;
+            }
+            n2 += u[d][k] * u[d][k];
+        }
+        if (std::fabs(std::sqrt(n2) - 1.0) > 1e-9) {
+            cd::set_error("%s: direction %d is not a unit vector", who, d);
+            return false;
+        }
+    }
+    return true;
+}
+
 extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int precision, void* stream,
                                      cd_weights** out) {
     cd::clear_error();
@@ -84,22 +105,8 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
         cd::set_error("cd_precompute_weights: unknown precision %d", precision);
         return CD_EINVAL;
     }
-    std::vector<std::array<double, 3>> u(D);
-    for (int d = 0; d < D; ++d) {
-        double n2 = 0;
-        for (int k = 0; k < 3; ++k) {
-            u[d][k] = dirs[3 * d + k];
-            if (!std::isfinite(u[d][k])) {
-                cd::set_error("cd_precompute_weights: direction %d is not finite", d);
-                return CD_EINVAL;
-            }
-            n2 += u[d][k] * u[d][k];
-        }
-        if (std::fabs(std::sqrt(n2) - 1.0) > 1e-9) {
-            cd::set_error("cd_precompute_weights: direction %d is not a unit vector", d);
-            return CD_EINVAL;
-        }
-    }
+    std::vector<std::array<double, 3>> u;
+    if (!unit_dirs("cd_precompute_weights", dirs, D, u)) return CD_EINVAL;
     cd_weights* w = new cd_weights();
     w->D = D;
     w->mode = mode;
@@ -164,6 +171,70 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
         return rc;
     }
     *out = w;
+    return CD_OK;
+}
+
+extern "C" int cd_weight_lists(const double* dirs, int D, int kind, int* ncombo, int* len, int32_t* off,
+                               double* w, int32_t* cnt, double* ref, int32_t* box) {
+    cd::clear_error();
+    if (!dirs || !ncombo || !len || D < 1 || D > CD_MAX_DIRS || kind < 0 || kind > 4) {
+        cd::set_error("cd_weight_lists: bad arguments (D %d, kind %d)", D, kind);
+        return CD_EINVAL;
+    }
+    std::vector<std::array<double, 3>> u;
+    if (!unit_dirs("cd_weight_lists", dirs, D, u)) return CD_EINVAL;
+    cd::HostTables t;
+    int rc = cd::build_tables(u, t);
+    if (rc != CD_OK) return rc;
+    if (kind == 0) {
+        // internal + local: combo = octant a of the target in its oct, the 8
+        // oct cells s = i + 2j + 4k as entries
+        *ncombo = 8;
+        *len = 8;
+        if (!off) return CD_OK;
+        for (int a = 0; a < 8; ++a) {
+            if (ref)
+                for (int k = 0; k < 3; ++k) ref[3 * a + k] = ((a >> k) & 1) + 0.5;
+            for (int d = 0; d < D; ++d) {
+                if (cnt) cnt[a * D + d] = 8;
+                for (int s8 = 0; s8 < 8; ++s8) {
+                    const size_t e = ((size_t)a * D + d) * 8 + s8;
+                    for (int k = 0; k < 3; ++k) off[3 * e + k] = (s8 >> k) & 1;
+                    if (w) w[e] = t.kloc[((size_t)a * 8 + s8) * D + d];
+                }
+            }
+        }
+        return CD_OK;
+    }
+    const std::vector<cd::AxisShape> sh = cd::axis_shapes(kind);
+    const int na = (int)sh.size();
+    *ncombo = t.ncombo[kind];
+    *len = t.len[kind];
+    if (!off) return CD_OK;
+    const size_t L = (size_t)t.len[kind];
+    for (int c = 0; c < t.ncombo[kind]; ++c) {
+        const cd::AxisShape* a[3] = {&sh[c % na], &sh[(c / na) % na], &sh[c / (na * na)]};
+        for (int k = 0; k < 3; ++k) {
+            if (ref) ref[3 * c + k] = a[k]->ref;
+            if (box) {
+                box[12 * c + 4 * k] = a[k]->ilo;
+                box[12 * c + 4 * k + 1] = a[k]->ihi;
+                box[12 * c + 4 * k + 2] = a[k]->olo;
+                box[12 * c + 4 * k + 3] = a[k]->ohi;
+            }
+        }
+        for (int d = 0; d < D; ++d) {
+            const size_t q = (size_t)c * D + d;
+            if (cnt) cnt[q] = t.cnt[kind][q];
+            for (size_t e = 0; e < L; ++e) {
+                const int32_t pk = t.off[kind][q * L + e];
+                off[3 * (q * L + e)] = (int8_t)(pk & 0xff);
+                off[3 * (q * L + e) + 1] = (int8_t)((pk >> 8) & 0xff);
+                off[3 * (q * L + e) + 2] = (int8_t)((pk >> 16) & 0xff);
+                if (w) w[q * L + e] = t.w[kind][q * L + e];
+            }
+        }
+    }
     return CD_OK;
 }
 

@@ -42,3 +42,30 @@ def test_rates_structure():
     _, uv3, _ = H.rates(np.full(3, 0.5), n, T, ne)
     assert np.all(uv3 > 0.5 * uv)                       # eps falls with G0_eff, so half the field gives more than half
 
+
+def test_efficiency_knee_of_the_first_term():
+    """Sect. 5 (efficiency of Wolfire et al. 1995): the first term halves at
+    x = G0_eff T^(1/2) / n_e = 1925.  At T = 1e-12 K the second term is below
+    1e-12 of it, so eps is 4.9e-2 / 2 there; a knee read as 5000 would give
+    3.27e-2."""
+    T = 1e-12
+    ne = np.array([1.0, 0.5, 2.0])
+    g0 = 1925.0 * ne / np.sqrt(T)
+    eps = H.efficiency(g0, np.full(3, T), ne)
+    np.testing.assert_allclose(eps, 0.5 * 4.9e-2, rtol=1e-9)
+    # a factor 10 on either side of the knee: the power law 0.73 of the first term
+    for f in (0.1, 10.0):
+        e = H.efficiency(f * g0[:1], np.array([T]), ne[:1])
+        np.testing.assert_allclose(e, 4.9e-2 / (1.0 + f ** 0.73), rtol=1e-9)
+
+
+def test_efficiency_knee_of_the_second_term():
+    """Sect. 5: the second term halves at x = 5000.  At a fixed x the first
+    term is the same at every temperature, so the difference between T = 1e4 K
+    and T = 1e-12 K (x kept at 5000 by the field) is the second term alone,
+    3.7e-2 (1 - 1e-11.2) / 2; a knee read as 1925 would give 1.03e-2."""
+    ne = 1.0
+    x = 5000.0
+    e_hot = H.efficiency(x * ne / np.sqrt(1e4), 1e4, ne)
+    e_cold = H.efficiency(x * ne / np.sqrt(1e-12), 1e-12, ne)
+    np.testing.assert_allclose(e_hot - e_cold, 0.5 * 3.7e-2 * (1.0 - (1e-16) ** 0.7), rtol=1e-9)

@@ -519,3 +519,73 @@ def test_internal_local_of_uniform_density_is_the_exit_distance_from_the_oct():
             dist = min(((hi[k] - c[k]) / u[k]) if u[k] > 0 else ((lo[k] - c[k]) / u[k])
                        for k in range(3) if u[k] != 0)
             assert abs(got[q, d] - n0 * box * dist) <= 1e-12 * n0 * box
+
+
+def test_raymarch_axis_rays_sum_distinct_densities():
+    """The brute-force reference along the six axes of a grid of distinct
+    densities: from a cell centre a ray along +x crosses half of its own cell
+    and then every later cell of its row, so the column is dx (n_own / 2 +
+    sum of the densities beyond); the other five axes likewise.  A lookup of
+    the wrong cell of a segment (its start instead of its middle) breaks the
+    negative directions."""
+    L = 3
+    n = 1 << L
+    rng = np.random.default_rng(21)
+    f = rng.permutation(n ** 3).reshape(n, n, n).astype(np.float64) + 1.0  # f[z, y, x], all distinct
+    box = 3.0
+    tin = synth.uniform_tree(f, box_cm=box)
+    tr = oracle.Tree(tin)
+    rays = oracle.dirs_axes6()
+    tg = np.arange(tin.n_leaf)
+    R = tr.raymarch(rays, tg)
+    dx = box / n
+    for q in tg:
+        i, j, k = q % n, (q // n) % n, q // (n * n)
+        own = 0.5 * f[k, j, i]
+        want = [own + f[k, j, i + 1:].sum(), own + f[k, j, :i].sum(),
+                own + f[k, j + 1:, i].sum(), own + f[k, :j, i].sum(),
+                own + f[k + 1:, j, i].sum(), own + f[:k, j, i].sum()]
+        np.testing.assert_allclose(R[q], dx * np.array(want), rtol=1e-13)
+
+
+def test_raymarch_single_dense_cell_gives_its_chord():
+    """Only one finest cell holds matter: every ray's column is that density
+    times the ray's chord through that one cell (the chord found by sorting
+    plane crossings here), for oblique rays of every sign pattern."""
+    L = 3
+    n = 1 << L
+    f = np.zeros((n, n, n))
+    c = np.array([5, 2, 3])  # x, y, z of the dense cell
+    f[c[2], c[1], c[0]] = 7.0
+    tin = synth.uniform_tree(f, box_cm=1.0)
+    tr = oracle.Tree(tin)
+    rays = oracle.dirs_healpix(4)
+    tg = np.arange(tin.n_leaf)
+    R = tr.raymarch(rays, tg)
+    lo, hi = c / n, (c + 1) / n
+    hits = 0
+    for q in tg:
+        T = np.array([q % n, (q // n) % n, q // (n * n)])
+        o = (T + 0.5) / n
+        for r, u in enumerate(rays):
+            want = 7.0 * chord_by_sorting(lo, hi, o, u)
+            hits += want > 0
+            assert abs(R[q, r] - want) <= 1e-13
+    assert hits > 500
+
+
+def test_mn_azimuths_step_two_pi_over_n():
+    """Sect. 3.2: the azimuths of a ring are phi_n = 2 pi (n - 1) / N, N equal
+    steps round the full circle starting at 0: each ring is closed under a
+    rotation by 2 pi / N about z, its unit vectors sum to zero (N >= 2), and
+    the first direction lies in the x-z half-plane x > 0."""
+    for M, N in [(3, 4), (5, 8), (7, 12), (2, 5), (3, 7)]:
+        u = oracle.dirs_mn(M, N)
+        rot = np.array([[np.cos(2 * np.pi / N), -np.sin(2 * np.pi / N), 0],
+                        [np.sin(2 * np.pi / N), np.cos(2 * np.pi / N), 0], [0, 0, 1]])
+        for m in range(M):
+            ring = u[m * N:(m + 1) * N]
+            assert abs(ring[0, 1]) == 0.0 and ring[0, 0] > 0
+            np.testing.assert_allclose(ring.sum(axis=0)[:2], 0.0, atol=1e-13)
+            # the ring rotated by one step is the next direction of the ring
+            np.testing.assert_allclose(ring @ rot.T, np.roll(ring, -1, axis=0), atol=1e-13)
