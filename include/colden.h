@@ -5,14 +5,14 @@
  * Method: Valdivia & Hennebelle (2014), "A fast tree-based method for
  * estimating column densities in Adaptive Mesh Refinement codes", A&A.
  * For every leaf (target) cell and every direction sector the column
- *   N(m,n) = sum_i n_i dx_i(m,n)                                 (Eq. 6)
+ *   N(m,n) = sum_i n_i dx_i(m,n)                                 (Eq. 8)
  * is split into the internal + local part (the target and its 7 siblings,
  * rays from the target centre) and the external part, a sum over concentric
  * cubic shells, one per coarser level, whose cells are weighted by
- * precalculated geometric factors K (Sect. 3.2 and 3.3, Eqs. 7-9):
+ * precalculated geometric factors K (Sect. 3.2 and 3.3, Eqs. 9-11):
  *   N_ext(m,n) = sum_l dx_l sum_{i in C_l} n_i K(r_i - r_target, m, n, dl).
  * The attenuation factor is chi = (1/D) sum_d exp(-gamma A_V,d) with
- * A_V = N av_per_nh (Eq. 5; gamma = 3.74 and av_per_nh = 1/1.87e21 cm^2
+ * A_V = N av_per_nh (Eq. 7; gamma = 3.74 and av_per_nh = 1/1.87e21 cm^2
  * reproduce the paper's sigma = 2e-21 cm^2).
  *
  * Conventions for every call:
@@ -55,7 +55,7 @@ enum {
 /* direction families */
 enum {
     CD_DIR_HEALPIX = 0,   /* HEALPix ring-scheme pixel centres, p1 = Nside: 12 Nside^2 sectors */
-    CD_DIR_PAPER_MN = 1,  /* the paper's M x N grid (Sect. 3.2, Eq. 3), p1 = M, p2 = N */
+    CD_DIR_PAPER_MN = 1,  /* the paper's M x N grid (Sect. 3.2, Eqs. 5-6), p1 = M, p2 = N */
     CD_DIR_AXES6 = 2      /* +x, -x, +y, -y, +z, -z (Sect. 4.4) */
 };
 
@@ -227,9 +227,9 @@ int cd_weights_split_steps(const cd_weights* w, int64_t* steps);
 void cd_weights_destroy(cd_weights* w);
 
 /*
- * Column densities of every leaf (Eqs. 6-9): writes N_dev[n_leaf][D]
+ * Column densities of every leaf (Eqs. 8-11): writes N_dev[n_leaf][D]
  * (float, cm^-2, row-major, direction fastest).  If chi_dev is not NULL the
- * screening factor (Eq. 5) is fused and written to chi_dev[n_leaf]
+ * screening factor (Eq. 7) is fused and written to chi_dev[n_leaf]
  * using av_per_nh and gamma (ignored otherwise).  The contraction runs in
  * the precision of the weights handle (see cd_precompute_weights); the
  * coarse shells (dl >= 4), the internal + local part, the level sums and chi
@@ -242,7 +242,7 @@ int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float*
                         double av_per_nh, double gamma, void* stream);
 
 /*
- * Screening factor (Eq. 5): A_V = N av_per_nh, chi = (1/D) sum_d
+ * Screening factor (Eq. 7): A_V = N av_per_nh, chi = (1/D) sum_d
  * exp(-gamma A_V,d).  N_dev [n_leaf][D]; writes chi_dev[n_leaf] and, if not
  * NULL, av_dev[n_leaf][D].  Asynchronous on `stream`.
  * Errors: CD_EINVAL (n_leaf < 0, D outside 1..CD_MAX_DIRS, NULL buffers).
@@ -269,7 +269,7 @@ int cd_heating_rates(const float* chi_dev, const float* n_dev, const float* T_de
                      void* stream);
 
 /*
- * Screening factor (Eq. 5) fused with the heating rates: reads each cell's
+ * Screening factor (Eq. 7) fused with the heating rates: reads each cell's
  * row of N_dev [n_cells][D] once, writes chi_dev (may be NULL) and the rates
  * as cd_heating_rates.  Errors: CD_EINVAL (as cd_heating_rates, D outside
  * 1..CD_MAX_DIRS, non-finite av_per_nh or gamma).
@@ -374,7 +374,7 @@ int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* tree, const cd_weigh
 
 /* Columns of every leaf of a uniform tree from the network plus the exact
  * internal + local parts (weights w): N_dev[n_leaf][D] (cm^-2) and, if
- * chi_dev is not NULL, chi (Eq. 5) with av_per_nh, gamma.  N_dev 16-byte
+ * chi_dev is not NULL, chi (Eq. 7) with av_per_nh, gamma.  N_dev 16-byte
  * and chi_dev 8-byte aligned.
  * Errors: CD_EINVAL, CD_ENOMEM. */
 int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,

@@ -13,13 +13,13 @@
  *
  * Sections of the paper followed:
  *   Sect. 3.1            column = sum of density x distance crossed.
- *   Sect. 3.2, Eq. (3)   representative directions theta_m, phi_n.
- *   Sect. 3.2, Eqs. (5)-(6)  discrete attenuation factor chi and column N(m,n).
+ *   Sect. 3.2, Eqs. (5)-(6) representative directions theta_m, phi_n.
+ *   Sect. 3.2, Eqs. (7)-(8)  discrete attenuation factor chi and column N(m,n).
  *   Sect. 3.2 (region split)  internal (target), local (its 7 siblings, rays
  *                        from the target centre), external (concentric cubic
  *                        shells, rays from the centre of the target's oct).
- *   Sect. 3.2, Eqs. (7)-(8)  external sum over shells C_l, cells of size dx_l.
- *   Sect. 3.3, Eq. (9)   precalculated form with the two-level approximation
+ *   Sect. 3.2, Eqs. (9)-(10) external sum over shells C_l, cells of size dx_l.
+ *   Sect. 3.3, Eq. (11)  precalculated form with the two-level approximation
  *                        of the reference point (1 + 8 + 64 = 73 configs).
  *   Sect. 3 (RAMSES tree)    coarse cells hold the mean of their children;
  *                        a missing cell is read from the coarser leaf.
@@ -376,7 +376,7 @@ static int orc_make_shells(int l0, const int64_t* T, int mode, orc_shell* sh) {
     return ns;
 }
 
-/* Internal + local + external column of one target, in cm^-2 (Eq. 6 split as
+/* Internal + local + external column of one target, in cm^-2 (Eq. 8 split as
  * in Sect. 3.2). */
 static void orc_target_column(const orc_tree* t, int l0, const int64_t* T,
                               const double* dirs, int D, int mode, double* out,
@@ -399,7 +399,7 @@ static void orc_target_column(const orc_tree* t, int l0, const int64_t* T,
 
 /* External column of the oct containing target T at level l0 (identical for
  * the 8 siblings): sum over shells of n x chord from the shell's reference
- * point (Eqs. 7-9). */
+ * point (Eqs. 9-11). */
 static void orc_external(const orc_tree* t, int l0, const int64_t* T, const double* dirs,
                          int D, int mode, double* ext) {
     orc_shell sh[32];
@@ -525,7 +525,7 @@ int orc_shells(const orc_tree* t, int64_t target, int mode, int64_t* out, double
     return ns;
 }
 
-/* Screening (Eq. 5 with A_V): chi = (1/D) sum_d exp(-gamma N_d av_per_nh). */
+/* Screening (Eq. 7 with A_V): chi = (1/D) sum_d exp(-gamma N_d av_per_nh). */
 void orc_screening(const double* N, int64_t n, int D, double av_per_nh, double gamma, double* chi) {
     for (int64_t q = 0; q < n; ++q) {
         double s = 0.0;

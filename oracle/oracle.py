@@ -69,7 +69,7 @@ def _p(a: np.ndarray):
 
 
 # --------------------------------------------------------------------------
-# directions (Sect. 3.2 Eq. 3; HEALPix centres; six axes)
+# directions (Sect. 3.2 Eqs. 5-6; HEALPix centres; six axes)
 # --------------------------------------------------------------------------
 
 def dirs_mn(M: int, N: int) -> np.ndarray:
@@ -177,7 +177,7 @@ class Tree:
 
 
 def screening(N: np.ndarray, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA) -> np.ndarray:
-    """chi = (1/D) sum_d exp(-gamma A_V,d), A_V = N av_per_nh (Eq. 5)."""
+    """chi = (1/D) sum_d exp(-gamma A_V,d), A_V = N av_per_nh (Eq. 7)."""
     N = np.ascontiguousarray(N, dtype=np.float64)
     n, D = N.shape
     chi = np.zeros(n)

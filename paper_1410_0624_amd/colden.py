@@ -233,7 +233,7 @@ def heating_rates(chi, n, T, ne, gamma_uv, g0eff=None, gamma_cr=None, G0: float 
 
 def screening_heating(N, n, T, ne, gamma_uv, chi=None, g0eff=None, gamma_cr=None, G0: float = G0_DRAINE,
                       av_per_nh: float = AV_PER_NH, gamma: float = GAMMA, stream=None):
-    """chi (Eq. 5) from N and the heating rates in one pass."""
+    """chi (Eq. 7) from N and the heating rates in one pass."""
     cells, D = N.shape
     _check(lib().cd_screening_heating(_dev_f32(N), cells, D, av_per_nh, gamma, _dev_f32(n), _dev_f32(T),
                                       _dev_f32(ne), G0, _opt(chi), _opt(g0eff), _dev_f32(gamma_uv),

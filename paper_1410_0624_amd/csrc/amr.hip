@@ -453,7 +453,7 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
         add_row(erow_p, true);
         if (qrow_p) add_row(qrow_p, false);
     }
-    // internal + local (Sect. 3.2) and the screening sum (Eq. 5)
+    // internal + local (Sect. 3.2) and the screening sum (Eq. 7)
     const float dxL = (float)(a.box * ldexp(1.0, -l0));
     const float b0 = (float)(c & 1), b1 = (float)((c >> 1) & 1), b2 = (float)(c >> 2);
     float chi = 0.f;

@@ -60,7 +60,7 @@ int make_directions(int scheme, int p1, int p2, std::vector<std::array<double, 3
         if (p1 < 1 || 12L * p1 * p1 > CD_MAX_DIRS * 64L) return CD_EINVAL;
         healpix(p1, out);
     } else if (scheme == CD_DIR_PAPER_MN) {
-        // Sect. 3.2, Eq. 3: theta_m = arccos(1 + (1 - 2m)/M), phi_n = 2 pi (n-1)/N
+        // Sect. 3.2, Eqs. 5-6: theta_m = arccos(1 + (1 - 2m)/M), phi_n = 2 pi (n-1)/N
         if (p1 < 1 || p2 < 1 || (long)p1 * p2 > CD_MAX_DIRS * 64L) return CD_EINVAL;
         for (int m = 1; m <= p1; ++m)
             for (int n = 1; n <= p2; ++n) {

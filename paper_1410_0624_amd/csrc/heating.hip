@@ -4,7 +4,7 @@
 // al. (1995) in x = G0_eff T^(1/2) / n_e,
 //   eps = 4.9e-2 / (1 + (x / 1925)^0.73) + 3.7e-2 (T / 1e4)^0.7 / (1 + x / 5000);
 // cosmic-ray heating Gamma_CR = 1e-27 n (erg cm^-3 s^-1).  One thread per
-// cell; chi either given or, fused, averaged from the cell's row of N (Eq. 5).
+// cell; chi either given or, fused, averaged from the cell's row of N (Eq. 7).
 #include <cmath>
 
 #include "cd_internal.h"

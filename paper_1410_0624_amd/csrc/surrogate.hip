@@ -445,7 +445,7 @@ __global__ void k_to_bf16(const float* __restrict__ P, int64_t n, uint16_t* __re
 }
 
 // N = internal + local + max(exp(y out_scale + out_shift) - floor, 0) and
-// chi (Eq. 5) for every leaf, y the row of its level-7 ancestor
+// chi (Eq. 7) for every leaf, y the row of its level-7 ancestor
 __global__ void k_output(const IlArgs il, const float* __restrict__ Y7, int64_t n_leaf, float out_shift,
                          float out_scale, float chi_scale, float* __restrict__ N, float* __restrict__ chi) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

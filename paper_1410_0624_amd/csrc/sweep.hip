@@ -1,5 +1,5 @@
-// FP32 column-density sweep on a uniform grid (Sect. 3.2-3.3, Eqs. 6-9) and
-// the screening epilogue (Eq. 5).
+// FP32 column-density sweep on a uniform grid (Sect. 3.2-3.3, Eqs. 8-11) and
+// the screening epilogue (Eq. 7).
 //
 // For a target at level L in the oct whose parent cell is A (level L-1):
 //   N = internal+local(target) + sum_{l < L} E_l(oct),

@@ -1,5 +1,5 @@
 // Target rows of a uniform grid: internal + local part (Sect. 3.2) added to
-// the oct's external columns, and the screening factor (Eq. 5).
+// the oct's external columns, and the screening factor (Eq. 7).
 //
 // A lane owns the x pair of targets of one oct in one row (y, z): the octant
 // bits oy, oz are wave-uniform, and so is, for each direction, whether the

@@ -62,7 +62,7 @@ def chord_by_sorting(lo, hi, o, u):
 # ------------------------------------------------------------ directions ---
 def test_theta_pin_from_precalc_caption():
     """Sect. 4.4 figure caption: theta = 0.841, 0.644, 0.541 rad at phi = 0 are
-    theta_1 = arccos(1 - 1/M) of Eq. 3 for M = 3, 5, 7, and phi_1 = 0."""
+    theta_1 = arccos(1 - 1/M) of Eqs. 5-6 for M = 3, 5, 7, and phi_1 = 0."""
     g = _gold("theta_caption.txt")
     for M, theta in g:
         M = int(M)
@@ -137,7 +137,7 @@ def test_chord_half_line_only():
 def _uniform_closed_form(L, T, u):
     """Uniform density, reference point fixed at the oct centre: the shells
     tile the box outside the oct, so their chords telescope to the exit
-    distance of the box minus that of the oct (Eqs. 7-8 with every cell of
+    distance of the box minus that of the oct (Eqs. 9-10 with every cell of
     density n0), plus the internal+local chord from the target centre."""
     dx = 0.5 ** L
     A = T // 2
@@ -449,7 +449,7 @@ def test_linearity_in_density():
 # -------------------------------------------------------------- screening ---
 def test_screening_factor_reading():
     """chi = (1/D) sum exp(-gamma A_V), A_V = N/1.87e21 with gamma = 3.74, is
-    the paper's chi = (1/MN) sum exp(-sigma N) with sigma = 2e-21 cm^2 (Eq. 5)."""
+    the paper's chi = (1/MN) sum exp(-sigma N) with sigma = 2e-21 cm^2 (Eq. 7)."""
     N = np.array([[0.0, 0.0, 0.0], [1e21, 1e21, 1e21], [0.0, 5e20, 3e21]])
     chi = oracle.screening(N)
     assert chi[0] == 1.0
@@ -463,7 +463,7 @@ def test_extinction_accuracy_against_cone_raymarching(mean, D):
     """Abstract and Sect. 6: the extinction of the tree method is accurate to
     better than 10 %.  Reference: 768 exact rays per target (HEALPix Nside=8
     centres) through every finest cell, chi_ref = mean exp(-sigma N_ray);
-    gate on the mean |chi_tree - chi_ref| (Eq. 11) over all targets of a 16^3
+    gate on the mean |chi_tree - chi_ref| (Eq. 13) over all targets of a 16^3
     turbulent log-normal cloud."""
     L = 4
     tin = synth.workload_uniform(L, sigma=1.5, mean=mean, seed=5)
