@@ -6,13 +6,14 @@ sweep with the fused screening epilogue (cd_column_densities: N_H[n_leaf][D]
 and chi[n_leaf]).  The weight tables are precalculated once, outside the
 timed region, as in the method (Sect. 3.3).
 
-Default workload: 256^3 uniform grid (16.8M leaves, 9-level pyramid),
-log-normal turbulent field sigma_ln n = 1.5, mean 10 cm^-3, box 10 pc, 12
-HEALPix sectors, FP32.  The same resident input is also timed with the
-split-precision forms (bf16 / fp16 hi + lo on the matrix cores), reported
+Default workload: the largest single-GPU configuration, a 512^3 uniform grid
+(134M leaves, 10-level pyramid), log-normal turbulent field sigma_ln n = 1.5,
+mean 10 cm^-3, box 10 pc, 48 HEALPix sectors (N_side = 2), FP32.  The same
+resident input is also timed with the split-precision forms (bf16 / fp16 hi +
+lo on the matrix cores), the in-situ reference points and 12 sectors, reported
 under "forms" with their speed-up and error against an oracle sample.
---workload amr: the adaptive tree (128^3 base + 2 levels, D = 48);
---level 9: the 512^3 grid.  Prints one JSON line.
+--level 8 --nside 1: the 256^3 grid with 12 sectors; --workload amr: the
+adaptive tree (128^3 base + 2 levels, D = 48).  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -43,19 +44,18 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def alg_bytes_sweep(n_leaf: int, D: int, L: int) -> float:
-    """Algorithmic HBM bytes of one column sweep: read every leaf density
-    once (4 B) and the coarse pyramid once (4 B x n_leaf/7 for all levels
-    below L), write N (4 B x D) and chi (4 B) per leaf."""
-    pyr_cells = sum(8 ** l for l in range(L))
-    return n_leaf * (4.0 + 4.0 * D + 4.0) + 4.0 * pyr_cells
-
-
-def alg_bytes_rows(n_leaf: int, D: int) -> float:
-    """Algorithmic HBM bytes of the target-row stage (the dominant kernel):
-    read the leaf density (4 B) and the oct's external columns (4 D B per 8
-    leaves), write the row of N (4 D B) and chi (4 B)."""
-    return n_leaf * (4.0 + 4.0 * D / 8.0 + 4.0 * D + 4.0)
+def alg_bytes_step(tin, D: int) -> float:
+    """Algorithmic HBM bytes of one step: read every leaf density once (4 B),
+    write and read back the coarse cells of the pyramid once (4 B each: every
+    level below the leaves of a uniform grid, the base levels below B and
+    every refined cell of an adaptive tree), write the row of N (4 D B) and
+    chi (4 B) of every leaf.  Intermediates of this implementation (external
+    rows, coarse tables) are not counted."""
+    if tin.base_level == tin.max_level:
+        coarse = sum(8 ** l for l in range(tin.max_level))
+    else:
+        coarse = sum(8 ** l for l in range(tin.base_level)) + sum(p.shape[0] for p in tin.oct_parents)
+    return tin.n_leaf * (4.0 + 4.0 * D + 4.0) + 4.0 * coarse
 
 
 def measured_traffic(key: str):
@@ -71,13 +71,6 @@ def measured_traffic(key: str):
 
 PREC = {"fp32": 0, "bf16x2": 1, "fp16x2": 2}
 MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
-
-
-def alg_bytes_amr_rows(n_leaf: int, n_tg: int, D: int) -> float:
-    """Algorithmic HBM bytes of the adaptive-tree target kernel: per leaf the
-    row of N (4 D B), chi (4 B) and its density (4 B); per target oct its row
-    of the coarse table and its row of E (shells dl = 1..3), 4 D B each."""
-    return n_leaf * (4.0 * D + 8.0) + n_tg * 4.0 * D * 2
 
 
 def hbm_ceiling(torch, n_floats):
@@ -117,13 +110,13 @@ def main():
     ap.add_argument("--train-fields", type=int, default=16, help="surrogate: seeded 256^3 training fields")
     ap.add_argument("--train-steps", type=int, default=6000, help="surrogate: Adam steps")
     ap.add_argument("--train-batch", type=int, default=8192, help="surrogate: leaves per step")
-    ap.add_argument("--level", type=int, default=8, help="uniform grid of 2^level cells per axis")
-    ap.add_argument("--nside", type=int, default=0, help="HEALPix Nside, D = 12 Nside^2 "
-                    "(default 1 for uniform grids, 2 for the adaptive tree)")
+    ap.add_argument("--level", type=int, default=9, help="uniform grid of 2^level cells per axis")
+    ap.add_argument("--nside", type=int, default=2, help="HEALPix Nside, D = 12 Nside^2")
     ap.add_argument("--precision", choices=list(PREC), default="fp32")
     ap.add_argument("--no-forms", action="store_true", help="skip timing the other precision forms")
-    ap.add_argument("--cpu-sample-octs", type=int, default=2097152,
-                    help="uniform grids: octs timed with the CPU oracle (bounded sample)")
+    ap.add_argument("--cpu-sample-octs", type=int, default=0,
+                    help="uniform grids: octs timed with the CPU oracle (bounded sample; default "
+                         "2e8 / (8 D) octs, about 10-30 s of oracle work)")
     ap.add_argument("--cpu-sample-leaves", type=int, default=400000,
                     help="adaptive tree: leaves timed with the CPU oracle (bounded sample)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -157,7 +150,7 @@ def main():
     dev = torch.device("cuda:0")
     sphere = args.workload == "sphere"
     amr = args.workload in ("amr", "sphere")
-    nside = args.nside or (2 if amr else 1)
+    nside = args.nside
     t0 = time.time()
     if sphere:
         tin = synth.workload_sphere()
@@ -191,16 +184,20 @@ def main():
     N = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
     chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
-    tree = colden.Tree(tin, leaf)
+    # the tree's workspace (a torch tensor) holds the sweep's buffers for up to
+    # max_dirs directions; its second stream is a torch stream
+    tree = colden.Tree(tin, leaf, max_dirs=max([D, 12] + [u.shape[0] for u in sets.values()]))
     rng = np.random.default_rng(0)
     check = rng.choice(tin.n_leaf, size=min(2000, tin.n_leaf), replace=False)
 
-    def measure(prec: str, mode: int = colden.CD_PRECALC73) -> dict:
-        w = colden.Weights(dirs, precision=PREC[prec], mode=mode)
+    def measure(prec: str, mode: int = colden.CD_PRECALC73, u=None, Nout=None) -> dict:
+        u = dirs if u is None else u
+        Nout = N if Nout is None else Nout
+        w = colden.Weights(u, precision=PREC[prec], mode=mode)
 
         def step():
             tree.update(leaf)
-            colden.column_densities(tree, w, N, chi)
+            colden.column_densities(tree, w, Nout, chi)
 
         for _ in range(args.warmup):
             step()
@@ -224,9 +221,9 @@ def main():
                 stages[k].append(v)
         tree.profile(False)
         torch.cuda.synchronize()
-        out = {"ms_per_step": ms_step, "value": tin.n_leaf * D / (ms_step * 1e-3),
+        out = {"ms_per_step": ms_step, "value": tin.n_leaf * u.shape[0] / (ms_step * 1e-3),
                "stages_ms": {k: float(np.mean(v)) for k, v in stages.items()},
-               "sample": N[torch.from_numpy(check).to(dev)].cpu().numpy().astype(np.float64),
+               "sample": Nout[torch.from_numpy(check).to(dev)].cpu().numpy().astype(np.float64),
                "split_steps": w.split_steps()}
         w.close()
         return out
@@ -263,30 +260,36 @@ def main():
                 continue
             forms[p] = measure(p)
             print(f"# form {p}: {forms[p]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    d12 = None
+    if not args.no_forms and not amr and D != 12:
+        # the same field with 12 sectors (HEALPix N_side = 1)
+        dirs12 = colden.directions(colden.CD_DIR_HEALPIX, 1)
+        N12 = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+        d12 = measure(args.precision, u=dirs12, Nout=N12)
+        del N12
+        torch.cuda.empty_cache()
+        print(f"# 12 sectors: {d12['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     stage_ms = main_form["stages_ms"]
     ms_step = main_form["ms_per_step"]
     value = main_form["value"]
 
+    # the dominant kernel is the one writing the rows of N and chi; its
+    # numerator is the algorithmic bytes of the whole step (leaf, pyramid, N,
+    # chi), its time the sum of its launches (one per z-slab)
     if amr:
-        # dominant kernel: the per-target-oct kernel (internal + local, rows of N and chi)
-        lv = tin.leaf_level
-        ijk = tin.leaf_ijk.astype(np.int64)
-        key = (lv.astype(np.int64) << 60) | ((ijk[:, 2] >> 1) << 40) | ((ijk[:, 1] >> 1) << 20) | (ijk[:, 0] >> 1)
-        n_tg = int(np.unique(key).shape[0])
-        rows_bytes = alg_bytes_amr_rows(tin.n_leaf, n_tg, D)
         kname = (f"k_target_leaves<{D}> (a lane per target: external row + coarse table, internal+local, N and chi rows)"
                  if D in (6, 12, 24, 40, 48) else
                  "k_target_octs (per target oct, a lane per direction: external row + coarse table, internal+local, "
                  "N and chi rows)")
     else:
-        rows_bytes = alg_bytes_rows(tin.n_leaf, D)
         kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"
-    achieved = rows_bytes / (stage_ms["rows"] * 1e-3) / 1e9
-    sweep_bytes = alg_bytes_sweep(tin.n_leaf, D, L)
+    step_bytes = alg_bytes_step(tin, D)
+    achieved = step_bytes / (stage_ms["rows"] * 1e-3) / 1e9
 
     cpu = None
     ref_check = None
     ref_check_insitu = None
+    ref_check12 = None
     e1 = None
     if not args.no_cpu:
         import oracle
@@ -297,7 +300,8 @@ def main():
             what = f"{tg.shape[0]} random leaves of the same tree"
         else:
             n1 = 1 << (L - 1)
-            octs = rng.choice(n1 ** 3, size=min(args.cpu_sample_octs, n1 ** 3), replace=False)
+            n_sample = args.cpu_sample_octs or int(2e8 / (8 * D))
+            octs = rng.choice(n1 ** 3, size=min(n_sample, n1 ** 3), replace=False)
             ax, ay, az = octs % n1, (octs // n1) % n1, octs // (n1 * n1)
             n = 1 << L
             tg = np.concatenate([((2 * az + (o >> 2)) * n + 2 * ay + ((o >> 1) & 1)) * n + 2 * ax + (o & 1)
@@ -312,6 +316,7 @@ def main():
                "sample": f"{what}, FP64 OpenMP oracle, {dt:.1f} s"}
         ref_check = tr.columns(dirs, check, nthreads=threads)
         ref_check_insitu = tr.columns(dirs, check, mode=oracle.INSITU, nthreads=threads) if insitu else None
+        ref_check12 = tr.columns(colden.directions(colden.CD_DIR_HEALPIX, 1), check, nthreads=threads) if d12 else None
         if sphere:
             # the paper's first test: midplane chi of the method against
             # exact rays (768 HEALPix N_side = 8 centres per target through
@@ -381,6 +386,13 @@ def main():
             o["max_rel_err_vs_oracle_insitu"] = float(np.max(np.abs(insitu["sample"] - ref_check_insitu)
                                                              / ref_check_insitu))
         forms_out["fp32_insitu"] = o
+    if d12 is not None:
+        o = {"ms_per_step": d12["ms_per_step"], "value": d12["value"], "n_dirs": 12,
+             "external_ms": d12["stages_ms"]["external"], "rows_ms": d12["stages_ms"]["rows"],
+             "step_frac": alg_bytes_step(tin, 12) / (d12["ms_per_step"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        if ref_check12 is not None:
+            o["max_rel_err_vs_oracle"] = float(np.max(np.abs(d12["sample"] - ref_check12) / ref_check12))
+        forms_out[f"{args.precision}_D12"] = o
     relerr, lnerr = errs(main_form)
 
     dtype = {"fp32": "f32", "bf16x2": "bf16x2 (f32 accumulate)", "fp16x2": "f16x2 (f32 accumulate)"}[args.precision]
@@ -405,11 +417,15 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic(f"k_target_leaves<{D}>|adaptive {tin.n_leaf} leaves D={D}" if amr
                                                  else f"k_target_rows<{D}>|uniform {1 << L}^3 D={D}"),
-                     "kernel": kname, "kernel_ms": stage_ms["rows"], "alg_bytes_per_launch": rows_bytes},
+                     "kernel": kname, "kernel_ms": stage_ms["rows"], "alg_bytes": step_bytes,
+                     "alg_bytes_what": "per step: leaf densities read (4 B), coarse pyramid cells written once "
+                                       "(4 B), rows of N (4 D B) and chi (4 B) written; the kernel's time is the "
+                                       "sum of its launches in one step",
+                     "step_frac": step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "hbm_ceiling": hbm_ceiling(torch, tin.n_leaf * D),
         "stages_ms": stage_ms,
-        "sweep": {"alg_bytes": sweep_bytes, "ms": stage_ms["sweep"],
-                  "GB_per_s": sweep_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},
+        "sweep": {"alg_bytes": step_bytes, "ms": stage_ms["sweep"],
+                  "GB_per_s": step_bytes / (stage_ms["sweep"] * 1e-3) / 1e9},
         "forms": forms_out,
         "cpu_baseline": cpu,
         **({"sphere_test": e1} if e1 is not None else {}),
@@ -437,7 +453,7 @@ def bench_surrogate(args):
     for sd in range(100, 100 + args.train_fields):
         tin = synth.workload_uniform(8, sigma=1.5, mean=10.0, seed=sd)
         leaf = torch.from_numpy(tin.leaf_n).to(dev)
-        tree = colden.Tree(tin, leaf)
+        tree = colden.Tree(tin, leaf, max_dirs=D)
         N = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
         colden.column_densities(tree, w, N)
         trees.append(tree)
@@ -461,7 +477,7 @@ def bench_surrogate(args):
     L = 9
     tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=999)
     leaf = torch.from_numpy(tin.leaf_n).to(dev)
-    tree = colden.Tree(tin, leaf)
+    tree = colden.Tree(tin, leaf, max_dirs=D)
     Np = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
     chip = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
     Ns_ = torch.empty_like(Np)

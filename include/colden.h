@@ -20,10 +20,18 @@
  *    returns a thread-local message for the last failure.  Nothing aborts,
  *    nothing throws across this boundary.
  *  - Pointers named *_dev are device pointers (HIP global memory); every
- *    other pointer is host memory.  The caller owns every buffer it passes;
- *    the library owns the opaque handles and the device memory behind them.
+ *    other pointer is host memory.  The caller owns every buffer it passes.
+ *    Device memory of the tree and weight handles is a workspace the caller
+ *    allocates (its size from cd_tree_workspace_bytes and
+ *    cd_weights_workspace_bytes) and keeps alive until the handle is
+ *    destroyed; the library owns only the host side of a handle.  Nothing on
+ *    the cd_tree_update / cd_column_densities / cd_screening_factor /
+ *    cd_check_densities path allocates device memory or creates a stream.
+ *    (The surrogate handle, not part of the paper's method, owns its own.)
  *  - `stream` is a hipStream_t (NULL = the default stream).  Device work is
  *    asynchronous on that stream; host arguments are consumed before return.
+ *    A second stream for stages that run side by side may be given to a
+ *    tree (cd_tree_set_aux_stream); the library creates none.
  *  - Leaf order (input densities, output rows): base-level cells in row-major
  *    order (x fastest) skipping refined ones, then for each finer level the
  *    octs in the order given, each oct's children c = i + 2j + 4k (i, j, k
@@ -93,6 +101,17 @@ int cd_version(void);
 int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D);
 
 /*
+ * Device bytes of the workspace a tree of this structure needs: the dense
+ * padded pyramid levels, the index maps and target lists of an adaptive tree,
+ * and the sweep's buffers for up to max_dirs directions (per-oct rows of the
+ * external shells dl = 1..3, the coarse tables of the shells dl >= 4, the
+ * in-situ rows, a check counter).  Host only: touches no device.  Arguments
+ * as cd_build_tree.  Errors: CD_EINVAL (malformed structure, NULL bytes).
+ */
+int cd_tree_workspace_bytes(int base_level, int max_level, const int64_t* n_octs,
+                            const int32_t* const* oct_parents, int64_t n_leaf, int max_dirs, size_t* bytes);
+
+/*
  * Build the tree of a fully threaded octree and its pyramid (Sect. 3: a
  * coarse cell holds the mean of its 8 children).
  *   box_cm           edge of the cubic box in cm; dx_l = 0.5^l box_cm.
@@ -109,27 +128,47 @@ int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D)
  *                    8-byte aligned, else CD_EINVAL).  An AMR tree copies
  *                    the leaves.
  *   n_leaf           number of leaves implied by the structure.
- * The structure is copied; the pyramid is built on `stream`.  Device
- * memory for the pyramid and the index maps is owned by the handle.  The
- * leaf densities are checked (finite, >= 0), which synchronises `stream`.
+ *   max_dirs         1 .. CD_MAX_DIRS: the largest direction count the tree
+ *                    will be swept with (cd_column_densities rejects more).
+ *   workspace_dev    device memory of at least cd_tree_workspace_bytes bytes,
+ *                    256-byte aligned, owned by the caller, alive and not
+ *                    used for anything else until cd_tree_destroy.
+ * The structure is copied; the pyramid is built on `stream`.  The leaf
+ * densities are checked (finite, >= 0), which synchronises `stream`.
  * Errors: CD_EINVAL (malformed structure, wrong n_leaf, a density that is
- * negative, NaN or infinite), CD_ENOMEM, CD_EDEVICE.
+ * negative, NaN or infinite, a workspace that is too small or misaligned),
+ * CD_EDEVICE.
  */
 int cd_build_tree(double box_cm, int base_level, int max_level,
                   const int64_t* n_octs, const int32_t* const* oct_parents,
-                  const float* leaf_n_dev, int64_t n_leaf, void* stream, cd_tree** out);
+                  const float* leaf_n_dev, int64_t n_leaf, int max_dirs,
+                  void* workspace_dev, size_t workspace_bytes, void* stream, cd_tree** out);
+
+/*
+ * Second stream of a tree's sweep: cd_column_densities then runs the coarse
+ * tables (and, on adaptive trees, the gathered targets) beside the external
+ * shells, and the rows of one z-slab beside the external shells of the next,
+ * joining `stream` of the call before it returns.  NULL (the default): every
+ * stage runs on the call's stream, one after the other.  The stream must
+ * outlive the tree's use; keep it at the default priority.
+ * Errors: CD_EINVAL (NULL tree).
+ */
+int cd_tree_set_aux_stream(cd_tree* tree, void* stream);
 
 /* Number of entries of leaf_n_dev[n_leaf] (device float) that are
  * negative, NaN or infinite, written to *n_invalid; -0.0 and subnormal
- * values are valid.  Synchronises `stream`.
- * Errors: CD_EINVAL (NULL n_invalid, n_leaf < 0, NULL buffer with n_leaf >
- * 0), CD_ENOMEM, CD_EDEVICE. */
-int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid, void* stream);
+ * values are valid.  scratch_dev: 8 bytes of device memory (8-byte aligned)
+ * the count is accumulated in.  Synchronises `stream`.
+ * Errors: CD_EINVAL (NULL n_invalid or scratch, n_leaf < 0, NULL buffer with
+ * n_leaf > 0), CD_EDEVICE. */
+int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, void* scratch_dev, int64_t* n_invalid,
+                       void* stream);
 
 /* New leaf densities for an existing structure (one hydro step later):
- * rebuilds the pyramid on `stream`.  Same layout and lifetime rules as
- * cd_build_tree. */
-int cd_tree_update(cd_tree* tree, const float* leaf_n_dev, void* stream);
+ * rebuilds the pyramid on `stream`.  n_leaf must be the tree's leaf count.
+ * Same layout and lifetime rules as cd_build_tree.
+ * Errors: CD_EINVAL (NULL arguments, wrong n_leaf, misaligned buffer). */
+int cd_tree_update(cd_tree* tree, const float* leaf_n_dev, int64_t n_leaf, void* stream);
 
 /* Number of leaves of the tree. */
 int cd_tree_n_leaf(const cd_tree* tree, int64_t* n_leaf);
@@ -138,8 +177,8 @@ int cd_tree_n_leaf(const cd_tree* tree, int64_t* n_leaf);
  * [n_leaf] and [n_leaf][3]. */
 int cd_tree_leaf_coords(const cd_tree* tree, int8_t* level, int32_t* ijk);
 
-/* Release the handle and its device memory (after the stream's work that
- * uses it has completed).  NULL is ignored. */
+/* Release the handle (after the stream's work that uses it has completed);
+ * its workspace then returns to the caller.  NULL is ignored. */
 void cd_tree_destroy(cd_tree* tree);
 
 /*
@@ -175,10 +214,21 @@ void cd_tree_destroy(cd_tree* tree);
  *              without tiles) are gathered in FP32 in every form, except
  *              that CD_BF16X2 for a D outside that set gathers every target
  *              on the matrix cores.
- * Errors: CD_EINVAL, CD_EUNSUPPORTED, CD_ENOMEM, CD_EDEVICE.
+ *   workspace_dev  device memory of at least cd_weights_workspace_bytes
+ *              bytes for the same arguments, 256-byte aligned, owned by the
+ *              caller and kept until cd_weights_destroy.
+ * The tables are copied into the workspace on `stream`, which is then
+ * synchronised.
+ * Errors: CD_EINVAL (bad arguments, a workspace that is too small or
+ * misaligned), CD_EUNSUPPORTED, CD_EDEVICE.
  */
 int cd_precompute_weights(const double* dirs, int D, int mode, int precision,
-                          void* stream, cd_weights** out);
+                          void* workspace_dev, size_t workspace_bytes, void* stream, cd_weights** out);
+
+/* Device bytes of the workspace cd_precompute_weights needs for these
+ * arguments (host only: the tables are computed, nothing is uploaded).
+ * Errors: as cd_precompute_weights. */
+int cd_weights_workspace_bytes(const double* dirs, int D, int mode, int precision, size_t* bytes);
 
 /*
  * The precalculated geometric factors K of Sect. 3.3 (Eqs. 10-11) as the
@@ -223,7 +273,8 @@ int cd_weights_n_dirs(const cd_weights* w, int* D);
  */
 int cd_weights_split_steps(const cd_weights* w, int64_t* steps);
 
-/* Release the handle (after the stream's work that uses it). */
+/* Release the handle (after the stream's work that uses it); its workspace
+ * then returns to the caller. */
 void cd_weights_destroy(cd_weights* w);
 
 /*
@@ -235,8 +286,10 @@ void cd_weights_destroy(cd_weights* w);
  * coarse shells (dl >= 4), the internal + local part, the level sums and chi
  * are FP32 in every form.  N_dev must be 16-byte aligned and chi_dev 8-byte
  * aligned (any device allocation is).  Asynchronous on `stream`.
- * Errors: CD_EINVAL (NULL handles or output, misaligned buffers), CD_EUNSUPPORTED (a split
- * form on a tree it is not offered for), CD_ENOMEM, CD_EDEVICE.
+ * Allocates nothing: its intermediates live in the tree's workspace.
+ * Errors: CD_EINVAL (NULL handles or output, misaligned buffers, more
+ * directions than the tree's max_dirs), CD_EUNSUPPORTED (a split form on a
+ * tree it is not offered for), CD_EDEVICE.
  */
 int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
                         double av_per_nh, double gamma, void* stream);

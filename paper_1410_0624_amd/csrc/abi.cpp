@@ -19,11 +19,23 @@ void set_error(const char* fmt, ...) {
 
 void clear_error() { g_err[0] = 0; }
 
+void* DevArena::take(size_t bytes, bool* ok) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    used = off + bytes;
+    if (!base) return nullptr;
+    if (used > cap) {
+        if (*ok) set_error("workspace of %zu bytes is too small (the workspace-size query gives what is needed)", cap);
+        *ok = false;
+        return nullptr;
+    }
+    return base + off;
+}
+
 }  // namespace cd
 
 extern "C" const char* cd_last_error(void) { return cd::g_err; }
 
-extern "C" int cd_version(void) { return 1; }
+extern "C" int cd_version(void) { return 2; }
 
 extern "C" int cd_directions(int scheme, int p1, int p2, double* out, int capacity, int* D) {
     cd::clear_error();
@@ -48,20 +60,8 @@ extern "C" int cd_directions(int scheme, int p1, int p2, double* out, int capaci
     return CD_OK;
 }
 
-template <class T>
-static int upload(const std::vector<T>& h, T** dptr, hipStream_t s) {
-    size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
-    if (hipMalloc((void**)dptr, bytes) != hipSuccess) {
-        cd::set_error("hipMalloc of %zu bytes failed", bytes);
-        return CD_ENOMEM;
-    }
-    if (!h.empty()) CD_HIP(hipMemcpyAsync(*dptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return CD_OK;
-}
-
 namespace cd {
 int upload_split_banks(cd_weights* w, hipStream_t s);  // split.hip
-void free_split_banks(cd_weights* w);
 }
 
 // Directions as unit vectors (finite, |u| = 1 within 1e-9).
@@ -85,51 +85,25 @@ static bool unit_dirs(const char* who, const double* dirs, int D, std::vector<st
     return true;
 }
 
-extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int precision, void* stream,
-                                     cd_weights** out) {
-    cd::clear_error();
-    if (!dirs || !out) {
-        cd::set_error("cd_precompute_weights: NULL argument");
-        return CD_EINVAL;
-    }
-    *out = nullptr;
-    if (D < 1 || D > CD_MAX_DIRS) {
-        cd::set_error("cd_precompute_weights: D = %d outside 1..%d", D, CD_MAX_DIRS);
-        return CD_EINVAL;
-    }
-    if (mode != CD_PRECALC73 && mode != CD_INSITU) {
-        cd::set_error("cd_precompute_weights: unknown mode %d", mode);
-        return CD_EINVAL;
-    }
-    if (precision != CD_FP32 && precision != CD_BF16X2 && precision != CD_FP16X2) {
-        cd::set_error("cd_precompute_weights: unknown precision %d", precision);
-        return CD_EINVAL;
-    }
-    std::vector<std::array<double, 3>> u;
-    if (!unit_dirs("cd_precompute_weights", dirs, D, u)) return CD_EINVAL;
-    cd_weights* w = new cd_weights();
-    w->D = D;
-    w->mode = mode;
-    w->precision = precision;
-    int brc = cd::build_tables(u, w->host);
-    if (brc == CD_OK) brc = cd::build_tile_tables(u, w->host);
-    if (brc == CD_OK) brc = cd::build_gather_tables(w->host);
-    if (brc != CD_OK) {
-        delete w;
-        return brc;
-    }
-    hipStream_t s = (hipStream_t)stream;
-    int rc = CD_OK;
-    // host staging buffers live until the stream is synchronised below
+// The weight tables of one direction set (FP64 on the host, Sect. 3.3) and
+// their copies in the workspace: FP32 lists, tile blobs, gather tables and
+// split banks.  With w->ws in a sizing pass only the bytes are counted.
+static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights* w, hipStream_t s) {
+    const int D = w->D;
+    int rc = cd::build_tables(u, w->host);
+    if (rc == CD_OK) rc = cd::build_tile_tables(u, w->host);
+    if (rc == CD_OK) rc = cd::build_gather_tables(w->host);
+    if (rc != CD_OK) return rc;
+    // host staging buffers live until the stream is synchronised by the caller
     std::vector<std::vector<float>> wf(cd::kKinds), wtf(cd::kKinds);
     std::vector<std::vector<int32_t>> otf(cd::kKinds);
     for (int k = 1; k < cd::kKinds && rc == CD_OK; ++k) {
         w->ncombo[k] = w->host.ncombo[k];
         w->len[k] = w->host.len[k];
         wf[k].assign(w->host.w[k].begin(), w->host.w[k].end());
-        rc = upload(w->host.off[k], &w->off[k], s);
-        if (rc == CD_OK) rc = upload(wf[k], &w->w[k], s);
-        if (rc == CD_OK) rc = upload(w->host.cnt[k], &w->cnt[k], s);
+        rc = cd::ws_upload(w->ws, w->host.off[k], &w->off[k], s);
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, wf[k], &w->w[k], s);
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.cnt[k], &w->cnt[k], s);
         // the same lists with the direction fastest, for kernels with a lane per direction
         const size_t nc = (size_t)w->ncombo[k], len = (size_t)w->len[k];
         otf[k].assign(nc * len * D, 0);
@@ -140,17 +114,17 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
                     otf[k][(c * len + e) * D + d] = w->host.off[k][(c * D + d) * len + e];
                     wtf[k][(c * len + e) * D + d] = (float)w->host.w[k][(c * D + d) * len + e];
                 }
-        if (rc == CD_OK) rc = upload(otf[k], &w->offT[k], s);
-        if (rc == CD_OK) rc = upload(wtf[k], &w->wT[k], s);
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, otf[k], &w->offT[k], s);
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, wtf[k], &w->wT[k], s);
     }
     std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
     std::vector<float> gf(w->host.gloc.begin(), w->host.gloc.end());
-    if (rc == CD_OK) rc = upload(kf, &w->kloc, s);
-    if (rc == CD_OK) rc = upload(w->host.blob, &w->blob, s);
-    if (rc == CD_OK) rc = upload(gf, &w->gloc, s);
-    if (rc == CD_OK) rc = upload(w->host.sgn, &w->sgn, s);
-    if (rc == CD_OK) rc = upload(w->host.ghdr, &w->ghdr, s);
-    if (rc == CD_OK) rc = upload(w->host.gent, &w->gent, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, kf, &w->kloc, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.blob, &w->blob, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, gf, &w->gloc, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.sgn, &w->sgn, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.ghdr, &w->ghdr, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.gent, &w->gent, s);
     // [D][6]: the unit vector (components below 1e-14 snapped to 0) and the
     // reciprocals of its components (0 where a component is 0)
     std::vector<double> du((size_t)D * 6);
@@ -160,14 +134,76 @@ extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int pr
             du[(size_t)d * 6 + k] = c;
             du[(size_t)d * 6 + 3 + k] = c != 0.0 ? 1.0 / c : 0.0;
         }
-    if (rc == CD_OK) rc = upload(du, &w->dirs, s);
-    if (rc == CD_OK && precision != CD_FP32) rc = cd::upload_split_banks(w, s);
-    if (rc == CD_OK && hipStreamSynchronize(s) != hipSuccess) {
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, du, &w->dirs, s);
+    if (rc == CD_OK && w->precision != CD_FP32) rc = cd::upload_split_banks(w, s);
+    if (rc == CD_OK && !w->ws.sizing() && hipStreamSynchronize(s) != hipSuccess) {
         cd::set_error("cd_precompute_weights: upload failed");
         rc = CD_EDEVICE;
     }
+    return rc;
+}
+
+static int weights_args(const char* who, const double* dirs, int D, int mode, int precision,
+                        std::vector<std::array<double, 3>>& u) {
+    if (D < 1 || D > CD_MAX_DIRS) {
+        cd::set_error("%s: D = %d outside 1..%d", who, D, CD_MAX_DIRS);
+        return CD_EINVAL;
+    }
+    if (mode != CD_PRECALC73 && mode != CD_INSITU) {
+        cd::set_error("%s: unknown mode %d", who, mode);
+        return CD_EINVAL;
+    }
+    if (precision != CD_FP32 && precision != CD_BF16X2 && precision != CD_FP16X2) {
+        cd::set_error("%s: unknown precision %d", who, precision);
+        return CD_EINVAL;
+    }
+    return unit_dirs(who, dirs, D, u) ? CD_OK : CD_EINVAL;
+}
+
+extern "C" int cd_weights_workspace_bytes(const double* dirs, int D, int mode, int precision, size_t* bytes) {
+    cd::clear_error();
+    if (!dirs || !bytes) {
+        cd::set_error("cd_weights_workspace_bytes: NULL argument");
+        return CD_EINVAL;
+    }
+    std::vector<std::array<double, 3>> u;
+    int rc = weights_args("cd_weights_workspace_bytes", dirs, D, mode, precision, u);
+    if (rc != CD_OK) return rc;
+    cd_weights w;
+    w.D = D;
+    w.mode = mode;
+    w.precision = precision;
+    rc = weights_build(u, &w, nullptr);  // sizing pass: no device access
+    if (rc == CD_OK) *bytes = w.ws.used;
+    return rc;
+}
+
+extern "C" int cd_precompute_weights(const double* dirs, int D, int mode, int precision, void* workspace_dev,
+                                     size_t workspace_bytes, void* stream, cd_weights** out) {
+    cd::clear_error();
+    if (!dirs || !out || !workspace_dev) {
+        cd::set_error("cd_precompute_weights: NULL argument");
+        return CD_EINVAL;
+    }
+    *out = nullptr;
+    if (!cd::is_aligned(workspace_dev, 256)) {
+        cd::set_error("cd_precompute_weights: the workspace must be 256-byte aligned");
+        return CD_EINVAL;
+    }
+    std::vector<std::array<double, 3>> u;
+    int rc = weights_args("cd_precompute_weights", dirs, D, mode, precision, u);
+    if (rc != CD_OK) return rc;
+    cd_weights* w = new cd_weights();
+    w->D = D;
+    w->mode = mode;
+    w->precision = precision;
+    w->ws.base = static_cast<char*>(workspace_dev);
+    w->ws.cap = workspace_bytes;
+    rc = weights_build(u, w, (hipStream_t)stream);
     if (rc != CD_OK) {
-        cd_weights_destroy(w);
+        // the copies already issued read host vectors that end here
+        (void)hipStreamSynchronize((hipStream_t)stream);
+        delete w;
         return rc;
     }
     *out = w;
@@ -260,21 +296,5 @@ extern "C" int cd_weights_split_steps(const cd_weights* w, int64_t* steps) {
 }
 
 extern "C" void cd_weights_destroy(cd_weights* w) {
-    if (!w) return;
-    for (int k = 0; k < cd::kKinds; ++k) {
-        if (w->off[k]) (void)hipFree(w->off[k]);
-        if (w->w[k]) (void)hipFree(w->w[k]);
-        if (w->cnt[k]) (void)hipFree(w->cnt[k]);
-        if (w->offT[k]) (void)hipFree(w->offT[k]);
-        if (w->wT[k]) (void)hipFree(w->wT[k]);
-    }
-    if (w->kloc) (void)hipFree(w->kloc);
-    if (w->blob) (void)hipFree(w->blob);
-    if (w->gloc) (void)hipFree(w->gloc);
-    if (w->sgn) (void)hipFree(w->sgn);
-    if (w->ghdr) (void)hipFree(w->ghdr);
-    if (w->gent) (void)hipFree(w->gent);
-    if (w->dirs) (void)hipFree(w->dirs);
-    cd::free_split_banks(w);
-    delete w;
+    delete w;  // its device memory is the caller's workspace
 }

@@ -76,9 +76,7 @@ struct AmrDev {
     int32_t* tile_all = nullptr;
     int32_t* tile_lvl = nullptr;
     float* x4 = nullptr;  // in-situ mode: shells dl >= 4 per target [n_tg][D]
-    size_t x4_bytes = 0;
     int64_t n_base_leaf = 0, n_oct_leaf = 0, n_tg = 0, n_grp = 0, n_sgrp = 0;
-    std::vector<void*> mem;
     AmrHost h;
 };
 
@@ -548,22 +546,14 @@ __global__ void k_inject(const int32_t* __restrict__ octidx, const float* __rest
 }
 
 // ------------------------------------------------------------------- host --
-template <class T>
-static int dev_copy(const std::vector<T>& h, T** d, hipStream_t s, std::vector<void*>& own) {
-    const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
-    if (hipMalloc((void**)d, bytes) != hipSuccess) {
-        set_error("hipMalloc of %zu bytes (adaptive tree) failed", bytes);
-        return CD_ENOMEM;
-    }
-    own.push_back(*d);
-    if (!h.empty()) CD_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return CD_OK;
-}
-
 constexpr int kAmrMaxLevel = 10;  // dense oct maps: 4 * 8^(Lmax-1) bytes at the finest level
 
-int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, const float* leaf_n_dev,
-              int64_t n_leaf, hipStream_t s) {
+// Structure of an adaptive tree (host planning) and its pieces of the tree's
+// workspace: dense levels, oct densities, index maps, target lists, groups,
+// tiles, listed coarse-table entries and the sweep buffers.  A sizing pass
+// (no workspace base) only counts them.
+int amr_layout(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, int64_t n_leaf,
+               hipStream_t s) {
     const int B = t->base, L = t->lmax;
     if (B < 1 || L > kAmrMaxLevel || !n_octs || !oct_parents) {
         set_error("cd_build_tree: adaptive trees need base level >= 1, max level <= %d and oct lists",
@@ -851,41 +841,39 @@ int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_paren
     int rc = alloc_dense_levels(t, L - 1, s);
     if (rc != CD_OK) return rc;
     {
-        const size_t bytes = (size_t)std::max<int64_t>(total_octs * 8, 1) * sizeof(float);
-        if (hipMalloc((void**)&A->octden, bytes) != hipSuccess) {
-            set_error("hipMalloc of %zu bytes (oct densities) failed", bytes);
-            return CD_ENOMEM;
-        }
-        A->mem.push_back(A->octden);
+        bool ok = true;
+        A->octden = static_cast<float*>(t->ws.take((size_t)std::max<int64_t>(total_octs * 8, 1) * sizeof(float), &ok));
+        if (!ok) return CD_EINVAL;
     }
-    std::vector<void*> maps;  // owned through t->d_octidx
-    for (int l = B + 1; l <= L; ++l) {
-        rc = dev_copy(octidx[l], &t->d_octidx[l], s, maps);
-        if (rc != CD_OK) return rc;
-    }
-    if ((rc = dev_copy(h.base_dst, &A->base_dst, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.oct_dst, &A->oct_dst, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.par_dst, &A->par_dst, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.tg_info, &A->tg_info, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.tg_src, &A->tg_src, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.tg_leaf, &A->tg_leaf, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.grp, &A->grp, s, A->mem)) != CD_OK) return rc;
-    if ((rc = dev_copy(h.grp_info, &A->grp_info, s, A->mem)) != CD_OK) return rc;
+    for (int l = B + 1; l <= L; ++l)
+        if ((rc = ws_upload(t->ws, octidx[l], &t->d_octidx[l], s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.base_dst, &A->base_dst, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.oct_dst, &A->oct_dst, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.par_dst, &A->par_dst, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.tg_info, &A->tg_info, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.tg_src, &A->tg_src, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.tg_leaf, &A->tg_leaf, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.grp, &A->grp, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.grp_info, &A->grp_info, s)) != CD_OK) return rc;
     if (!h.sgrp.empty()) {
-        if ((rc = dev_copy(h.sgrp, &A->sgrp, s, A->mem)) != CD_OK) return rc;
-        if ((rc = dev_copy(h.sgrp_info, &A->sgrp_info, s, A->mem)) != CD_OK) return rc;
+        if ((rc = ws_upload(t->ws, h.sgrp, &A->sgrp, s)) != CD_OK) return rc;
+        if ((rc = ws_upload(t->ws, h.sgrp_info, &A->sgrp_info, s)) != CD_OK) return rc;
     }
     for (int l = 2; l <= qtop; ++l) {
-        if ((rc = dev_copy(need[l], &A->need[l], s, A->mem)) != CD_OK) return rc;
+        if ((rc = ws_upload(t->ws, need[l], &A->need[l], s)) != CD_OK) return rc;
         A->n_need[l] = (int64_t)need[l].size();
     }
-    if ((rc = dev_copy(h.erow, &A->erow, s, A->mem)) != CD_OK) return rc;
+    if ((rc = ws_upload(t->ws, h.erow, &A->erow, s)) != CD_OK) return rc;
     if (!h.tile_all.empty()) {
-        if ((rc = dev_copy(h.tile_all, &A->tile_all, s, A->mem)) != CD_OK) return rc;
-        if ((rc = dev_copy(h.tile_lvl, &A->tile_lvl, s, A->mem)) != CD_OK) return rc;
+        if ((rc = ws_upload(t->ws, h.tile_all, &A->tile_all, s)) != CD_OK) return rc;
+        if ((rc = ws_upload(t->ws, h.tile_lvl, &A->tile_lvl, s)) != CD_OK) return rc;
     }
-    CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
-    return amr_update(t, leaf_n_dev, s);
+    // rows of external columns: those of the tiles and of the gathered
+    // targets, or one per target (direction counts without a tiled kernel)
+    rc = alloc_sweep_buffers(t, qtop, std::max<int64_t>(h.erows, A->n_tg), A->n_tg, &A->x4);
+    if (rc != CD_OK) return rc;
+    if (!t->ws.sizing()) CD_HIP(hipStreamSynchronize(s));  // the maps' host vectors end here
+    return CD_OK;
 }
 
 int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s) {
@@ -927,8 +915,6 @@ int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk) {
     return CD_OK;
 }
 
-int ensure_q(cd_tree* t, int D, int top, bool compact);                                     // sweep.hip
-int ensure_aux(cd_tree* t);                                                                 // sweep.hip
 bool tiled_weights_ok(const cd_weights* w);                                                 // sweep_tile.hip
 void launch_external_mfma_list(const float* const* levs, int nlev, double box, const cd_weights* w,
                                const int32_t* tiles, const int32_t* lvls, int64_t ntiles, float* E,
@@ -965,41 +951,14 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     }
     const bool compact = qtop == L - 4;
     int rc = CD_OK;
-    if (insitu) {
-        // the ray walks of the shells dl >= 4 take the place of the coarse tables
-        const size_t bytes = (size_t)std::max<int64_t>(A->n_tg, 1) * w->D * sizeof(float);
-        if (A->x4_bytes < bytes) {
-            if (A->x4) (void)hipFree(A->x4);
-            A->x4 = nullptr;
-            A->x4_bytes = 0;
-            if (hipMalloc((void**)&A->x4, bytes) != hipSuccess) {
-                set_error("hipMalloc of %zu bytes (in-situ columns) failed", bytes);
-                return CD_ENOMEM;
-            }
-            A->x4_bytes = bytes;
-        }
-    } else if ((rc = ensure_q(t, w->D, qtop, compact)) != CD_OK) {
-        return rc;
+    if (w->D > t->max_dirs) {
+        set_error("cd_column_densities: %d directions on a tree built for at most %d", w->D, t->max_dirs);
+        return CD_EINVAL;
     }
     const bool split = w->precision != CD_FP32;
     const bool tiled = split ? dset : tiled_weights_ok(w);
-    if ((rc = ensure_aux(t)) != CD_OK) return rc;
-    hipStream_t cs = t->aux;
+    hipStream_t cs = t->aux ? t->aux : s;  // the caller's second stream, or one stream
     const int64_t* erow = tiled ? A->erow : nullptr;
-    {
-        // rows of the tiles and of the gathered targets, or one per target
-        const size_t bytes = (size_t)std::max<int64_t>(tiled ? A->h.erows : A->n_tg, 1) * w->D * sizeof(float);
-        if (t->ext_bytes < bytes) {
-            if (t->ext) (void)hipFree(t->ext);
-            t->ext = nullptr;
-            t->ext_bytes = 0;
-            if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
-                set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
-                return CD_ENOMEM;
-            }
-            t->ext_bytes = bytes;
-        }
-    }
     if (t->prof) CD_HIP(hipEventRecord(t->pev[CD_STAGE_SWEEP][0], s));
     CD_HIP(hipEventRecord(t->ev[0], s));
     CD_HIP(hipStreamWaitEvent(cs, t->ev[0], 0));
@@ -1121,8 +1080,6 @@ void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
 
 void amr_free(cd_tree* t) {
     if (!t->amr) return;
-    for (void* p : t->amr->mem) (void)hipFree(p);
-    if (t->amr->x4) (void)hipFree(t->amr->x4);
     delete t->amr;
     t->amr = nullptr;
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <array>
 #include <cstdint>
 #include <string>
@@ -13,6 +14,38 @@
 namespace cd {
 
 struct AmrDev;
+
+// -------------------------------------------------------------- workspace --
+// Device memory of a handle comes from one caller-owned workspace, cut into
+// 256-byte aligned pieces in the order the handle asks for them.  With no
+// base (a sizing pass) nothing is handed out and `used` counts the bytes a
+// build would take; the workspace queries of the C ABI run that pass.
+struct DevArena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+    // The next `bytes` of the workspace (nullptr in a sizing pass, or when
+    // the workspace is too small: *ok is then cleared and an error set).
+    void* take(size_t bytes, bool* ok);
+    bool sizing() const { return base == nullptr; }
+};
+
+void set_error(const char* fmt, ...);
+
+// A host vector copied into the next piece of a workspace (asynchronously
+// on s: h must live until s has passed the copy); a sizing pass only counts.
+template <class T>
+int ws_upload(DevArena& a, const std::vector<T>& h, T** d, hipStream_t s) {
+    bool ok = true;
+    *d = static_cast<T*>(a.take(std::max<size_t>(h.size(), 1) * sizeof(T), &ok));
+    if (!ok) return CD_EINVAL;
+    if (!a.sizing() && !h.empty() && hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s) !=
+                                         hipSuccess) {
+        set_error("copy of %zu bytes into the workspace failed", h.size() * sizeof(T));
+        return CD_EDEVICE;
+    }
+    return CD_OK;
+}
 
 // ----------------------------------------------------------------- errors --
 // Device buffers are read and written with 8- and 16-byte vector accesses:
@@ -155,6 +188,7 @@ struct cd_weights {
     uint16_t* split_bank = nullptr;
     cd::HostTables host;
     cd::SplitHost split_host;
+    cd::DevArena ws;  // the caller's workspace
 };
 
 struct cd_tree {
@@ -176,12 +210,14 @@ struct cd_tree {
     int q_D = 0;
     float* ext = nullptr;  // per-oct external columns [n_oct][D]
     size_t ext_bytes = 0;
-    hipStream_t aux = nullptr;               // second stream of the sweep
+    int max_dirs = 0;                        // E rows, coarse tables and in-situ rows are sized for this D
+    cd::DevArena ws;                         // the caller's workspace
+    unsigned long long* counter = nullptr;   // density-check counter (workspace)
+    hipStream_t aux = nullptr;               // the caller's second stream (nullptr: one stream)
     bool prof = false;                       // stage timing enabled
     hipEvent_t pev[CD_NUM_STAGES][2] = {};   // start/stop events per stage
     bool pran[CD_NUM_STAGES] = {};           // stage ran in the last call
     hipEvent_t pslab[2][cd::kMaxSlabs][2] = {};  // per-slab launches: external, rows
     int pslabs = 0;                          // slabs of the last profiled uniform sweep
     hipEvent_t ev[cd::kMaxSlabs + 1] = {};  // slab hand-over and join events
-    std::vector<void*> scratch;  // other device allocations to free
 };

@@ -438,35 +438,16 @@ void launch_amr_external_mfma(const AmrLookupView& lk, const int32_t* tg_info, c
 }
 
 // ------------------------------------------------------------------- banks --
-template <class T>
-static int upload_vec(const std::vector<T>& h, T** d, hipStream_t s) {
-    const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
-    if (hipMalloc((void**)d, bytes) != hipSuccess) {
-        set_error("hipMalloc of %zu bytes (split banks) failed", bytes);
-        return CD_ENOMEM;
-    }
-    if (!h.empty()) CD_HIP(hipMemcpyAsync(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return CD_OK;
-}
-
+// Split banks into the weights' workspace (a sizing pass only counts them).
 int upload_split_banks(cd_weights* w, hipStream_t s) {
     SplitHost& sh = w->split_host;
     int rc = build_split_tables(w->host, w->precision, sh);
     if (rc != CD_OK) return rc;
     w->split_ntiles = sh.ntiles;
-    if ((rc = upload_vec(sh.hdr, &w->split_hdr, s)) != CD_OK) return rc;
-    if ((rc = upload_vec(sh.ent, &w->split_ent, s)) != CD_OK) return rc;
-    if ((rc = upload_vec(sh.eoff, &w->split_eoff, s)) != CD_OK) return rc;
-    return upload_vec(sh.bank, &w->split_bank, s);
-}
-
-void free_split_banks(cd_weights* w) {
-    if (w->split_hdr) (void)hipFree(w->split_hdr);
-    if (w->split_ent) (void)hipFree(w->split_ent);
-    if (w->split_eoff) (void)hipFree(w->split_eoff);
-    if (w->split_bank) (void)hipFree(w->split_bank);
-    w->split_hdr = w->split_ent = w->split_eoff = nullptr;
-    w->split_bank = nullptr;
+    if ((rc = ws_upload(w->ws, sh.hdr, &w->split_hdr, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(w->ws, sh.ent, &w->split_ent, s)) != CD_OK) return rc;
+    if ((rc = ws_upload(w->ws, sh.eoff, &w->split_eoff, s)) != CD_OK) return rc;
+    return ws_upload(w->ws, sh.bank, &w->split_bank, s);
 }
 
 }  // namespace cd

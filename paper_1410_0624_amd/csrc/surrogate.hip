@@ -1141,7 +1141,7 @@ extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_we
 }
 
 namespace cd {
-int ensure_q(cd_tree* t, int D, int top, bool compact);
+int ensure_sweep_buffers(const cd_tree* t, int D);  // sweep.hip
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);
 }
@@ -1252,7 +1252,6 @@ __global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__
 
 namespace cd {
 int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
-int ensure_ext(cd_tree* t, int D);                                                                          // sweep.hip
 bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
 bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
@@ -1296,13 +1295,12 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     // coarse tables of the method (shells dl >= 4) and, where the tiled
     // kernels take this direction set, the external columns E of every oct:
     // the samples and the fallback then read their shells dl = 1..3 from E
-    int rc = ensure_q(t, w->D, L - 4, true);
+    int rc = ensure_sweep_buffers(t, w->D);
     if (rc != CD_OK) return rc;
     launch_coarse(t, w, L - 4, true, st);
     const bool tiled = tiled_supported(t, w);
     const float* E = nullptr;
     if (tiled) {
-        if ((rc = ensure_ext(t, w->D)) != CD_OK) return rc;
         launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), st);
         E = t->ext;
     }

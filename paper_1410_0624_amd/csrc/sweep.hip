@@ -282,26 +282,13 @@ __global__ __launch_bounds__(256) void k_screening(const float* __restrict__ N, 
 }
 
 // --------------------------------------------------------------- drivers --
-// Coarse tables Q_l for levels 2 .. top; the last one holds only the 64
-// codes reachable at dl = 4 when `compact` (targets all at level top + 4).
-int ensure_q(cd_tree* t, int D, int top, bool compact) {
-    if (t->q_D == D) return CD_OK;
-    for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
-        if (t->q[l]) (void)hipFree(t->q[l]);
-        t->q[l] = nullptr;
-        t->q_bytes[l] = 0;
+// The tree's coarse tables and rows of external columns (carved from its
+// workspace at build time for up to max_dirs directions) serve D directions.
+int ensure_sweep_buffers(const cd_tree* t, int D) {
+    if (D > t->max_dirs) {
+        set_error("cd_column_densities: %d directions on a tree built for at most %d", D, t->max_dirs);
+        return CD_EINVAL;
     }
-    t->q_D = 0;
-    for (int l = 2; l <= top; ++l) {
-        const int ncodes = (compact && l == top) ? 64 : 216;
-        const size_t bytes = ((size_t)1 << (3 * l)) * ncodes * D * sizeof(float);
-        if (hipMalloc((void**)&t->q[l], bytes) != hipSuccess) {
-            set_error("hipMalloc of %zu bytes (coarse columns, level %d) failed", bytes, l);
-            return CD_ENOMEM;
-        }
-        t->q_bytes[l] = bytes;
-    }
-    t->q_D = D;
     return CD_OK;
 }
 
@@ -309,34 +296,10 @@ bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int 
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
                         float chi_scale, int64_t z0, int64_t nz, hipStream_t s);
 
-// Second stream and events of a tree: the target-row kernel of z-slab j runs
-// there while the external-column kernel of slab j+1 runs on the caller's
-// stream (both at the default priority).
-int ensure_aux(cd_tree* t) {
-    if (t->aux) return CD_OK;
-    CD_HIP(hipStreamCreateWithFlags(&t->aux, hipStreamNonBlocking));
-    for (int j = 0; j < kMaxSlabs + 1; ++j) CD_HIP(hipEventCreateWithFlags(&t->ev[j], hipEventDisableTiming));
-    return CD_OK;
-}
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
 bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
 void launch_insitu_coarse(const cd_tree* t, const cd_weights* w, float* E, bool accumulate,
                           hipStream_t s);  // insitu.hip
-
-// Per-oct external columns E[n_oct][D] owned by the tree.
-int ensure_ext(cd_tree* t, int D) {
-    const size_t bytes = ((size_t)1 << (3 * (t->lmax - 1))) * D * sizeof(float);
-    if (t->ext_bytes >= bytes) return CD_OK;
-    if (t->ext) (void)hipFree(t->ext);
-    t->ext = nullptr;
-    t->ext_bytes = 0;
-    if (hipMalloc((void**)&t->ext, bytes) != hipSuccess) {
-        set_error("hipMalloc of %zu bytes (external columns) failed", bytes);
-        return CD_ENOMEM;
-    }
-    t->ext_bytes = bytes;
-    return CD_OK;
-}
 
 template <int DC>
 static void launch_fine(const FineArgs& a, int64_t n_oct, hipStream_t s) {
@@ -418,11 +381,11 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         set_error("cd_column_densities: a single-cell tree has no oct");
         return CD_EINVAL;
     }
+    int rc = ensure_sweep_buffers(t, D);
+    if (rc != CD_OK) return rc;
     if (w->mode == CD_INSITU && !tiled_supported(t, w)) {
         // the per-oct kernel, with the walked shells dl >= 4 of each oct
         // written to a row per oct in place of the coarse tables
-        int rc = ensure_ext(t, D);
-        if (rc != CD_OK) return rc;
         launch_insitu_coarse(t, w, t->ext, false, s);
         launch_fine_path(t, w, nullptr, L >= 4 ? t->ext : nullptr, N, chi, chi_scale, s);
         CD_HIP(hipGetLastError());
@@ -431,8 +394,6 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
     if (w->mode == CD_INSITU) {
         // shells dl = 1..3 (the same in both schemes), then the in-situ
         // shells dl >= 4 added per oct, then the target rows
-        int rc = ensure_ext(t, D);
-        if (rc != CD_OK) return rc;
         auto mark = [t](int stage, int edge, hipStream_t st) -> hipError_t {
             if (!t->prof) return hipSuccess;
             t->pran[stage] = true;
@@ -454,14 +415,11 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         CD_HIP(hipGetLastError());
         return CD_OK;
     }
-    int rc = ensure_q(t, D, L - 4, true);
-    if (rc != CD_OK) return rc;
     if (L >= 1 && tiled_supported(t, w)) {
         // coarse tables (dl >= 4) on the second stream, concurrently with the
-        // tiled external kernel (dl = 1..3); the target rows need both
-        rc = ensure_ext(t, D);
-        if (rc == CD_OK) rc = ensure_aux(t);
-        if (rc != CD_OK) return rc;
+        // tiled external kernel (dl = 1..3); the target rows need both.
+        // Without a second stream from the caller every stage runs on s.
+        hipStream_t aux = t->aux ? t->aux : s;
         // stream s: the tiled kernel slab by slab (whole tile layers along z);
         // stream aux: the coarse tables, then the target rows of each slab
         // once its external columns are done, overlapping the next slab.
@@ -482,12 +440,12 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         };
         CD_HIP(mark(CD_STAGE_SWEEP, 0, s));
         CD_HIP(hipEventRecord(t->ev[kMaxSlabs], s));
-        CD_HIP(hipStreamWaitEvent(t->aux, t->ev[kMaxSlabs], 0));
-        CD_HIP(mark(CD_STAGE_COARSE, 0, t->aux));
-        launch_coarse(t, w, L - 4, true, t->aux, nullptr, nullptr);
-        CD_HIP(mark(CD_STAGE_COARSE, 1, t->aux));
+        CD_HIP(hipStreamWaitEvent(aux, t->ev[kMaxSlabs], 0));
+        CD_HIP(mark(CD_STAGE_COARSE, 0, aux));
+        launch_coarse(t, w, L - 4, true, aux, nullptr, nullptr);
+        CD_HIP(mark(CD_STAGE_COARSE, 1, aux));
         const bool rows_on_s = nslab == 1;
-        if (rows_on_s) CD_HIP(hipEventRecord(t->ev[kMaxSlabs - 1], t->aux));  // coarse tables done
+        if (rows_on_s) CD_HIP(hipEventRecord(t->ev[kMaxSlabs - 1], aux));  // coarse tables done
         CD_HIP(mark(CD_STAGE_EXTERNAL, 0, s));
         t->pslabs = t->prof ? nslab : 0;
         for (int j = 0; j < nslab; ++j) {
@@ -508,14 +466,14 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
             return CD_OK;
         }
         for (int j = 0; j < nslab; ++j) {
-            CD_HIP(hipStreamWaitEvent(t->aux, t->ev[j], 0));
-            if (j == 0) CD_HIP(mark(CD_STAGE_ROWS, 0, t->aux));
-            if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][0], t->aux));
-            launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, t->aux);
-            if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][1], t->aux));
+            CD_HIP(hipStreamWaitEvent(aux, t->ev[j], 0));
+            if (j == 0) CD_HIP(mark(CD_STAGE_ROWS, 0, aux));
+            if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][0], aux));
+            launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, aux);
+            if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][1], aux));
         }
-        CD_HIP(mark(CD_STAGE_ROWS, 1, t->aux));
-        CD_HIP(hipEventRecord(t->ev[kMaxSlabs], t->aux));
+        CD_HIP(mark(CD_STAGE_ROWS, 1, aux));
+        CD_HIP(hipEventRecord(t->ev[kMaxSlabs], aux));
         CD_HIP(hipStreamWaitEvent(s, t->ev[kMaxSlabs], 0));
         CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
         CD_HIP(hipGetLastError());

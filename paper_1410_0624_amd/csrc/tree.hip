@@ -1,6 +1,7 @@
 // Tree construction: the pyramid of coarse densities (Sect. 3: a refined cell
 // holds the mean of its 8 children) stored as zero-padded dense levels.
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 
 #include "cd_internal.h"
@@ -27,24 +28,20 @@ __global__ void k_count_invalid(const float* __restrict__ v, int64_t n, unsigned
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, (unsigned long long)c);
 }
 
-int count_invalid(const float* v, int64_t n, int64_t* out, hipStream_t s) {
+__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
+
+// Count with the 8-byte device counter `counter` (cleared here by a kernel,
+// read back, which synchronises s).
+int count_invalid(const float* v, int64_t n, unsigned long long* counter, int64_t* out, hipStream_t s) {
     *out = 0;
     if (n <= 0) return CD_OK;
-    unsigned long long* d = nullptr;
-    if (hipMalloc((void**)&d, sizeof(unsigned long long)) != hipSuccess) {
-        set_error("hipMalloc of the density-check counter failed");
-        return CD_ENOMEM;
-    }
     unsigned long long h = 0;
-    hipError_t e = hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) {
-        const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
-        k_count_invalid<<<(unsigned)blocks, 256, 0, s>>>(v, n, d);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s);
+    k_zero_counter<<<1, 1, 0, s>>>(counter);
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    k_count_invalid<<<(unsigned)blocks, 256, 0, s>>>(v, n, counter);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, counter, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    (void)hipFree(d);
     if (e != hipSuccess) {
         set_error("density check: %s", hipGetErrorString(e));
         return CD_EDEVICE;
@@ -162,36 +159,114 @@ int build_dense_below(cd_tree* t, int top, hipStream_t s) {
 
 int build_uniform_pyramid(cd_tree* t, hipStream_t s) { return build_dense_below(t, t->lmax, s); }
 
+// Zero-padded dense levels 0 .. top from the tree's workspace.
 int alloc_dense_levels(cd_tree* t, int top, hipStream_t s) {
     for (int l = 0; l <= top; ++l) {
         const size_t bytes = (size_t)padded_cells(l) * sizeof(float);
-        if (hipMalloc((void**)&t->lev[l], bytes) != hipSuccess) {
-            set_error("hipMalloc of %zu bytes (pyramid level %d) failed", bytes, l);
-            return CD_ENOMEM;
-        }
-        CD_HIP(hipMemsetAsync(t->lev[l], 0, bytes, s));
+        bool ok = true;
+        t->lev[l] = static_cast<float*>(t->ws.take(bytes, &ok));
+        if (!ok) return CD_EINVAL;
+        if (!t->ws.sizing()) CD_HIP(hipMemsetAsync(t->lev[l], 0, bytes, s));
     }
     return CD_OK;
 }
 
+// Buffers of the sweep for up to t->max_dirs directions: the coarse tables of
+// levels 2 .. top (216 inner-limit codes, the 64 codes of dl = 4 at top), the
+// rows of external columns, the in-situ rows of an adaptive tree, and the
+// density-check counter.
+int alloc_sweep_buffers(cd_tree* t, int top, int64_t ext_rows, int64_t insitu_rows, float** insitu) {
+    const size_t D = (size_t)t->max_dirs;
+    bool ok = true;
+    for (int l = 2; l <= top; ++l) {
+        const size_t ncodes = l == top ? 64 : 216;
+        t->q_bytes[l] = ((size_t)1 << (3 * l)) * ncodes * D * sizeof(float);
+        t->q[l] = static_cast<float*>(t->ws.take(t->q_bytes[l], &ok));
+    }
+    t->ext_bytes = (size_t)std::max<int64_t>(ext_rows, 1) * D * sizeof(float);
+    t->ext = static_cast<float*>(t->ws.take(t->ext_bytes, &ok));
+    if (insitu) *insitu = static_cast<float*>(t->ws.take((size_t)std::max<int64_t>(insitu_rows, 1) * D * 4, &ok));
+    t->counter = static_cast<unsigned long long*>(t->ws.take(sizeof(unsigned long long), &ok));
+    return ok ? CD_OK : CD_EINVAL;
+}
+
+// Validated structure and workspace layout of a tree (a sizing pass when
+// t->ws has no base: nothing on the device is touched).
+int tree_layout(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, int64_t n_leaf,
+                hipStream_t s) {
+    const int L = t->lmax;
+    if (t->base == L) {
+        if (n_leaf != ((int64_t)1 << (3 * L))) {
+            set_error("cd_build_tree: uniform 2^%d grid needs %lld leaves, got %lld", L,
+                      (long long)((int64_t)1 << (3 * L)), (long long)n_leaf);
+            return CD_EINVAL;
+        }
+        t->uniform = true;
+        t->n_leaf = n_leaf;
+        int rc = alloc_dense_levels(t, L - 1, s);
+        if (rc != CD_OK) return rc;
+        return alloc_sweep_buffers(t, L - 4, L >= 1 ? (int64_t)1 << (3 * (L - 1)) : 0, 0, nullptr);
+    }
+    t->uniform = false;
+    return amr_layout(t, n_octs, oct_parents, n_leaf, s);
+}
+
 }  // namespace cd
+
+static int tree_args(const char* who, int base_level, int max_level, int max_dirs) {
+    if (base_level < 0 || max_level < base_level || max_level > CD_MAX_LEVEL) {
+        cd::set_error("%s: bad levels (base %d, max %d)", who, base_level, max_level);
+        return CD_EINVAL;
+    }
+    if (max_dirs < 1 || max_dirs > CD_MAX_DIRS) {
+        cd::set_error("%s: max_dirs = %d outside 1..%d", who, max_dirs, CD_MAX_DIRS);
+        return CD_EINVAL;
+    }
+    return CD_OK;
+}
+
+extern "C" int cd_tree_workspace_bytes(int base_level, int max_level, const int64_t* n_octs,
+                                       const int32_t* const* oct_parents, int64_t n_leaf, int max_dirs,
+                                       size_t* bytes) {
+    cd::clear_error();
+    if (!bytes) {
+        cd::set_error("cd_tree_workspace_bytes: NULL argument");
+        return CD_EINVAL;
+    }
+    int rc = tree_args("cd_tree_workspace_bytes", base_level, max_level, max_dirs);
+    if (rc != CD_OK) return rc;
+    cd_tree t;
+    t.base = base_level;
+    t.lmax = max_level;
+    t.max_dirs = max_dirs;
+    rc = cd::tree_layout(&t, n_octs, oct_parents, n_leaf, nullptr);  // sizing pass
+    if (rc == CD_OK) *bytes = t.ws.used;
+    cd::amr_free(&t);
+    return rc;
+}
 
 extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const int64_t* n_octs,
                              const int32_t* const* oct_parents, const float* leaf_n_dev, int64_t n_leaf,
-                             void* stream, cd_tree** out) {
+                             int max_dirs, void* workspace_dev, size_t workspace_bytes, void* stream,
+                             cd_tree** out) {
     cd::clear_error();
-    if (!out || !leaf_n_dev) {
+    if (!out || !leaf_n_dev || !workspace_dev) {
         cd::set_error("cd_build_tree: NULL argument");
         return CD_EINVAL;
     }
     *out = nullptr;
-    if (!(box_cm > 0) || base_level < 0 || max_level < base_level || max_level > CD_MAX_LEVEL) {
-        cd::set_error("cd_build_tree: bad box or levels (box %g, base %d, max %d)", box_cm, base_level,
-                      max_level);
+    if (!(box_cm > 0) || !std::isfinite(box_cm)) {
+        cd::set_error("cd_build_tree: bad box size %g", box_cm);
         return CD_EINVAL;
     }
+    int rc = tree_args("cd_build_tree", base_level, max_level, max_dirs);
+    if (rc != CD_OK) return rc;
     if (base_level == max_level && !cd::is_aligned(leaf_n_dev, 8)) {
         cd::set_error("cd_build_tree: the leaf densities of a uniform grid must be 8-byte aligned");
+        return CD_EINVAL;
+    }
+    if (!cd::is_aligned(workspace_dev, 256)) {
+        cd::set_error("cd_build_tree: the workspace must be 256-byte aligned");
         return CD_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -199,34 +274,34 @@ extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const
     t->box_cm = box_cm;
     t->base = base_level;
     t->lmax = max_level;
-    int rc;
-    if (base_level == max_level) {
-        const int L = max_level;
-        if (n_leaf != ((int64_t)1 << (3 * L))) {
-            cd::set_error("cd_build_tree: uniform 2^%d grid needs %lld leaves, got %lld", L,
-                          (long long)((int64_t)1 << (3 * L)), (long long)n_leaf);
-            delete t;
-            return CD_EINVAL;
+    t->max_dirs = max_dirs;
+    t->ws.base = static_cast<char*>(workspace_dev);
+    t->ws.cap = workspace_bytes;
+    rc = cd::tree_layout(t, n_octs, oct_parents, n_leaf, s);
+    for (int j = 0; j < cd::kMaxSlabs + 1 && rc == CD_OK; ++j)
+        if (hipEventCreateWithFlags(&t->ev[j], hipEventDisableTiming) != hipSuccess) {
+            cd::set_error("cd_build_tree: hipEventCreateWithFlags failed");
+            rc = CD_EDEVICE;
         }
-        t->uniform = true;
-        t->n_leaf = n_leaf;
-        t->leaf = leaf_n_dev;
-        rc = cd::alloc_dense_levels(t, L - 1, s);
-        if (rc == CD_OK) rc = cd::build_uniform_pyramid(t, s);
-    } else {
-        t->uniform = false;
-        rc = cd::amr_build(t, n_octs, oct_parents, leaf_n_dev, n_leaf, s);
+    if (rc == CD_OK) {
+        if (t->uniform) {
+            t->leaf = leaf_n_dev;
+            rc = cd::build_uniform_pyramid(t, s);
+        } else {
+            rc = cd::amr_update(t, leaf_n_dev, s);
+        }
     }
     if (rc == CD_OK) {
         // densities must be finite and >= 0 (Sect. 3: n in cm^-3)
         int64_t bad = 0;
-        rc = cd::count_invalid(leaf_n_dev, n_leaf, &bad, s);
+        rc = cd::count_invalid(leaf_n_dev, n_leaf, t->counter, &bad, s);
         if (rc == CD_OK && bad > 0) {
             cd::set_error("cd_build_tree: %lld leaf densities are negative, NaN or infinite", (long long)bad);
             rc = CD_EINVAL;
         }
     }
     if (rc != CD_OK) {
+        (void)hipStreamSynchronize(s);  // copies from host vectors of the layout may still run
         cd_tree_destroy(t);
         return rc;
     }
@@ -234,19 +309,40 @@ extern "C" int cd_build_tree(double box_cm, int base_level, int max_level, const
     return CD_OK;
 }
 
-extern "C" int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid, void* stream) {
+extern "C" int cd_tree_set_aux_stream(cd_tree* t, void* stream) {
     cd::clear_error();
-    if (!n_invalid || n_leaf < 0 || (n_leaf > 0 && !leaf_n_dev)) {
+    if (!t) {
+        cd::set_error("cd_tree_set_aux_stream: NULL tree");
+        return CD_EINVAL;
+    }
+    t->aux = (hipStream_t)stream;
+    return CD_OK;
+}
+
+extern "C" int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, void* scratch_dev, int64_t* n_invalid,
+                                  void* stream) {
+    cd::clear_error();
+    if (!n_invalid || n_leaf < 0 || (n_leaf > 0 && !leaf_n_dev) || !scratch_dev) {
         cd::set_error("cd_check_densities: NULL argument or n_leaf %lld < 0", (long long)n_leaf);
         return CD_EINVAL;
     }
-    return cd::count_invalid(leaf_n_dev, n_leaf, n_invalid, (hipStream_t)stream);
+    if (!cd::is_aligned(scratch_dev, 8)) {
+        cd::set_error("cd_check_densities: the scratch must be 8-byte aligned");
+        return CD_EINVAL;
+    }
+    return cd::count_invalid(leaf_n_dev, n_leaf, static_cast<unsigned long long*>(scratch_dev), n_invalid,
+                             (hipStream_t)stream);
 }
 
-extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, void* stream) {
+extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, int64_t n_leaf, void* stream) {
     cd::clear_error();
     if (!t || !leaf_n_dev) {
         cd::set_error("cd_tree_update: NULL argument");
+        return CD_EINVAL;
+    }
+    if (n_leaf != t->n_leaf) {
+        cd::set_error("cd_tree_update: %lld leaf densities for a tree of %lld leaves", (long long)n_leaf,
+                      (long long)t->n_leaf);
         return CD_EINVAL;
     }
     if (t->uniform && !cd::is_aligned(leaf_n_dev, 8)) {
@@ -346,13 +442,7 @@ extern "C" int cd_tree_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk
 
 extern "C" void cd_tree_destroy(cd_tree* t) {
     if (!t) return;
-    for (int l = 0; l <= CD_MAX_LEVEL; ++l) {
-        if (t->lev[l]) (void)hipFree(t->lev[l]);
-        if (t->d_octidx[l]) (void)hipFree(t->d_octidx[l]);
-        if (t->q[l]) (void)hipFree(t->q[l]);
-    }
-    cd::amr_free(t);
-    if (t->ext) (void)hipFree(t->ext);
+    cd::amr_free(t);  // host side; the device memory is the caller's workspace
     for (auto& st : t->pev)
         for (auto& e : st)
             if (e) (void)hipEventDestroy(e);
@@ -360,12 +450,7 @@ extern "C" void cd_tree_destroy(cd_tree* t) {
         for (auto& sl : k)
             for (auto& e : sl)
                 if (e) (void)hipEventDestroy(e);
-    if (t->aux) {
-        (void)hipStreamSynchronize(t->aux);
-        for (auto& e : t->ev)
-            if (e) (void)hipEventDestroy(e);
-        (void)hipStreamDestroy(t->aux);
-    }
-    for (void* p : t->scratch) (void)hipFree(p);
+    for (auto& e : t->ev)
+        if (e) (void)hipEventDestroy(e);
     delete t;
 }

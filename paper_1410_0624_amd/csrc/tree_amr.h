@@ -76,12 +76,17 @@ void launch_amr_external_mfma(const AmrLookupView& lk, const int32_t* tg_info, c
                               const int32_t* grp_info, int64_t ngroups, const cd_weights* w, double box, float* E,
                               hipStream_t s);
 
-int amr_build(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, const float* leaf_n_dev,
-              int64_t n_leaf, hipStream_t s);
+int amr_layout(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, int64_t n_leaf,
+               hipStream_t s);
 int amr_update(cd_tree* t, const float* leaf_n_dev, hipStream_t s);
 int amr_leaf_coords(const cd_tree* t, int8_t* level, int32_t* ijk);
 int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);
 void amr_free(cd_tree* t);
 int build_dense_below(cd_tree* t, int top, hipStream_t s);
 int alloc_dense_levels(cd_tree* t, int top, hipStream_t s);
+int alloc_sweep_buffers(cd_tree* t, int top, int64_t ext_rows, int64_t insitu_rows, float** insitu);
+int tree_layout(cd_tree* t, const int64_t* n_octs, const int32_t* const* oct_parents, int64_t n_leaf,
+                hipStream_t s);
+int count_invalid(const float* v, int64_t n, unsigned long long* counter, int64_t* out, hipStream_t s);
+int build_uniform_pyramid(cd_tree* t, hipStream_t s);
 }  // namespace cd

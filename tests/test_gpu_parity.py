@@ -1,6 +1,8 @@
 """Parity of the HIP path with the FP64 CPU oracle (MI355X).  Every call goes
 through the C ABI; the oracle is the FP64 plain implementation in oracle/.
 Gate for the FP32 sweep: <= 1e-5 relative per output N_H(t, d)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -203,9 +205,82 @@ def test_error_paths(colden):
     dev = torch.device("cuda:0")
     tin = synth.workload_uniform(3, seed=1)
     leaf = torch.from_numpy(tin.leaf_n[:-1].copy()).to(dev)
-    with pytest.raises(colden.ColdenError) as e:
+    with pytest.raises(colden.ColdenError) as e:  # the structure needs one leaf more
         colden.Tree(tin, leaf)
     assert e.value.rc == colden.CD_EINVAL
+    # the library checks it too: cd_tree_update with a wrong leaf count
+    full = torch.from_numpy(tin.leaf_n).to(dev)
+    tree = colden.Tree(tin, full)
+    rc = colden.lib().cd_tree_update(tree.h, ctypes.c_void_p(full.data_ptr()), tin.n_leaf - 1,
+                                     ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert rc == colden.CD_EINVAL
+    with pytest.raises(ValueError):
+        tree.update(leaf)
+    w = colden.Weights(oracle.dirs_healpix(1))
+    with pytest.raises(ValueError):  # N of the wrong shape
+        colden.column_densities(tree, w, torch.empty((tin.n_leaf, 11), dtype=torch.float32, device=dev))
+    with pytest.raises(ValueError):  # chi of the wrong length
+        colden.column_densities(tree, w, torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev),
+                                torch.empty(tin.n_leaf - 1, dtype=torch.float32, device=dev))
+
+
+def _build_raw(colden, tin, leaf, max_dirs, ws):
+    """cd_build_tree through the ABI with a caller-chosen workspace tensor."""
+    par = [np.ascontiguousarray(p, dtype=np.int32) for p in tin.oct_parents]
+    n_octs = np.array([p.shape[0] for p in par] + [0], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * (len(par) + 1))(*[p.ctypes.data for p in par], None)
+    h = ctypes.c_void_p()
+    rc = colden.lib().cd_build_tree(float(tin.box_cm), int(tin.base_level), int(tin.max_level),
+                                    n_octs.ctypes.data_as(ctypes.c_void_p) if par else None,
+                                    ctypes.cast(ptrs, ctypes.c_void_p), ctypes.c_void_p(leaf.data_ptr()),
+                                    int(tin.n_leaf), max_dirs, ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("amr", [False, True])
+def test_sweep_runs_in_the_callers_workspace(colden, amr):
+    """Every device buffer of the sweep is the caller's: the tree in a torch
+    workspace of exactly the queried size (one byte less is refused), the
+    weights likewise; the sweep with and without the caller's second stream
+    gives the oracle's columns; more directions than max_dirs are refused."""
+    dev = torch.device("cuda:0")
+    if amr:
+        tin = synth.amr_tree(synth.lognormal_field(64, 2.0, 10.0, 7), 4, 14.0, 10 * synth.PC_CM)
+    else:
+        tin = synth.workload_uniform(6, seed=5)
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    dirs = oracle.dirs_healpix(1)
+    ref = oracle.Tree(tin).columns(dirs)
+    par = [np.ascontiguousarray(p, dtype=np.int32) for p in tin.oct_parents]
+    n_octs = np.array([p.shape[0] for p in par] + [0], dtype=np.int64)
+    ptrs = (ctypes.c_void_p * (len(par) + 1))(*[p.ctypes.data for p in par], None)
+    nb = ctypes.c_size_t(0)
+    assert colden.lib().cd_tree_workspace_bytes(int(tin.base_level), int(tin.max_level),
+                                                n_octs.ctypes.data_as(ctypes.c_void_p) if par else None,
+                                                ctypes.cast(ptrs, ctypes.c_void_p), int(tin.n_leaf), 12,
+                                                ctypes.byref(nb)) == 0
+    small = torch.empty(nb.value - 1, dtype=torch.uint8, device=dev)
+    rc, _ = _build_raw(colden, tin, leaf, 12, small)
+    assert rc == colden.CD_EINVAL and "too small" in colden.lib().cd_last_error().decode()
+    del small
+    for aux in (False, True):
+        tree = colden.Tree(tin, leaf, max_dirs=12, aux_stream=aux)
+        assert tree.workspace.numel() == nb.value
+        w = colden.Weights(dirs)
+        N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+        chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
+        colden.column_densities(tree, w, N, chi)
+        torch.cuda.synchronize()
+        got = N.cpu().numpy().astype(np.float64)
+        rel = np.abs(got - ref) / ref
+        print(f"{'amr' if amr else 'uniform'} aux={aux}: max rel {rel.max():.2e}")
+        assert rel.max() <= 1e-5
+        w48 = colden.Weights(oracle.dirs_healpix(2))
+        with pytest.raises(colden.ColdenError) as e:
+            colden.column_densities(tree, w48, torch.empty((tin.n_leaf, 48), dtype=torch.float32, device=dev))
+        assert e.value.rc == colden.CD_EINVAL
+        tree.close()
 
 
 def test_misaligned_buffers_are_rejected(colden):

@@ -111,35 +111,65 @@ def test_split_c3_amr_sampled(colden, pname):
     assert err.max() <= LN_GATE
 
 
-def test_c4_512_all_forms_sampled(colden):
-    """The 512^3 workload (134M leaves, D = 12) in the launch configuration
-    the benchmark times, all three forms against the oracle on 20k sampled
-    leaves (every tile layer of the grid represented)."""
+@pytest.fixture(scope="module")
+def c4(colden):
+    """The 512^3 workload (134M leaves, sigma_ln n = 1.5, mean 10, seed 4) on
+    the GPU, with leaves sampled in every z plane (so every z-slab boundary
+    of the sweep is covered, whatever the slab count) plus the 8 corners."""
     tin = synth.workload_uniform(9, sigma=1.5, mean=10.0, seed=4)
-    dirs = oracle.dirs_healpix(1)
+    n = 512
     rng = np.random.default_rng(9)
-    tg = np.concatenate([rng.choice(tin.n_leaf, 20000, replace=False), [0, tin.n_leaf - 1]])
-    ref = oracle.Tree(tin).columns(dirs, tg)
+    z = np.repeat(np.arange(n), 40)
+    tg = (z * n + rng.integers(0, n, z.size)) * n + rng.integers(0, n, z.size)
+    corners = [((k * n + j) * n + i) for k in (0, n - 1) for j in (0, n - 1) for i in (0, n - 1)]
+    tg = np.unique(np.concatenate([tg, corners])).astype(np.int64)
     dev = torch.device("cuda:0")
     leaf = torch.from_numpy(tin.leaf_n).to(dev)
-    tree = colden.Tree(tin, leaf)
-    N = torch.empty((tin.n_leaf, 12), dtype=torch.float32, device=dev)
+    tree = colden.Tree(tin, leaf, max_dirs=48)
+    yield tin, leaf, tree, tg
+    tree.close()
+
+
+@pytest.mark.parametrize("nside", [1, 2])
+def test_c4_512_all_forms_sampled(colden, c4, nside):
+    """The 512^3 workload with 12 and 48 sectors in the launch configuration
+    the benchmark times, all three forms against the oracle (Sect. 3.3, Eq. 11)
+    on 20k leaves sampled across every z plane and the box corners; chi from
+    the fused epilogue against the oracle's screening of its columns."""
+    tin, leaf, tree, tg = c4
+    dirs = oracle.dirs_healpix(nside)
+    D = dirs.shape[0]
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    chi_ref = oracle.screening(ref)
+    dev = torch.device("cuda:0")
+    N = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
+    chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
     idx = torch.from_numpy(tg).to(dev)
     for pname, prec, gate in [("fp32", 0, None), ("bf16x2", 1, LN_GATE), ("fp16x2", 2, LN_GATE)]:
         w = colden.Weights(dirs, precision=prec)
         N.fill_(float("nan"))
-        colden.column_densities(tree, w, N)
+        chi.fill_(float("nan"))
+        colden.column_densities(tree, w, N, chi)
         got = N[idx].cpu().numpy().astype(np.float64)
+        gchi = chi[idx].cpu().numpy().astype(np.float64)
         assert np.isfinite(got).all()
         err = _lnerr(got, ref)
         rel = np.abs(got - ref) / ref
-        print(f"512^3 {pname}: max rel {rel.max():.3e}, max |d ln N| {err.max():.3e}")
+        dchi = np.abs(gchi - chi_ref).max()
+        print(f"512^3 D={D} {pname}: max rel {rel.max():.3e}, max |d ln N| {err.max():.3e}, max |d chi| {dchi:.2e}",
+              flush=True)
         if gate is None:
             assert rel.max() <= 1e-5
+            assert dchi <= 1e-5
         else:
             assert err.max() <= gate
+            assert dchi <= 1e-3
         w.close()
-    assert torch.isfinite(N).all()
+        # every output written (the slabs tile the grid): no NaN left anywhere
+        assert not torch.isnan(N).any()
+        assert not torch.isnan(chi).any()
+    del N, chi
+    torch.cuda.empty_cache()
 
 
 def _rand_dirs(D, seed):
