@@ -86,7 +86,7 @@ static bool unit_dirs(const char* who, const double* dirs, int D, std::vector<st
 }
 
 // The weight tables of one direction set (FP64 on the host, Sect. 3.3) and
-// their copies in the workspace: FP32 lists, tile blobs, gather tables and
+// their copies in the workspace: FP32 lists, tile slots, gather tables and
 // split banks.  With w->ws in a sizing pass only the bytes are counted.
 static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights* w, hipStream_t s) {
     const int D = w->D;
@@ -120,7 +120,7 @@ static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights
     std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
     std::vector<float> gf(w->host.gloc.begin(), w->host.gloc.end());
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, kf, &w->kloc, s);
-    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.blob, &w->blob, s);
+    if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.slots, &w->slots, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, gf, &w->gloc, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.sgn, &w->sgn, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.ghdr, &w->ghdr, s);

@@ -479,8 +479,12 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
     }
     if (a.chi && leaf >= 0 && h == 0) __builtin_nontemporal_store(chi * (1.f / (float)D), a.chi + leaf);
 
-    // rows through LDS: lanes 32 p .. 32 p + 31 in pass p (both halves of a pair)
-    __shared__ __align__(16) float stage[NG][32 * D];
+    // rows through LDS: lanes 32 p .. 32 p + 31 in pass p (both halves of a
+    // pair).  Consecutive rows start RS words apart: D + 4 keeps them 16-byte
+    // aligned and 4 banks apart (at a stride of D words, lanes 2 or 4 apart
+    // would write the same bank)
+    constexpr int RS = D % 4 == 0 ? D + 4 : (D % 2 == 0 ? D + 2 : D + 1);  // keeps VS-float alignment
+    __shared__ __align__(16) float stage[NG][32 * RS];
     __shared__ int64_t rows[NG][32];
     float* st = stage[grp];
     auto sync = [&]() {
@@ -494,9 +498,15 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
 #pragma unroll 1
     for (int p = 0; p < 2; ++p) {
         if ((lane >> 5) == p) {
-            float* r = st + (lane & 31) * D + dh0;
+            float* r = st + (lane & 31) * RS + dh0;
+            if constexpr (D % 4 == 0 && DH % 4 == 0) {
 #pragma unroll
-            for (int d = 0; d < DH; ++d) r[d] = out[d];
+                for (int d = 0; d < DH; d += 4)
+                    *reinterpret_cast<v4f*>(r + d) = v4f{out[d], out[d + 1], out[d + 2], out[d + 3]};
+            } else {
+#pragma unroll
+                for (int d = 0; d < DH; ++d) r[d] = out[d];
+            }
             if (h == 0) rows[grp][lane & 31] = leaf;
         }
         sync();
@@ -507,10 +517,11 @@ __global__ __launch_bounds__(256) void k_target_leaves(const AmrSweepArgs a) {
             if (lf < 0) continue;
             float* dst = a.N + lf * D + col;
             // streaming stores: N is not read again by the sweep
+            const float* src = st + r * RS + col;
             if constexpr (VS == 4)
-                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(st + i * VS), reinterpret_cast<v4f*>(dst));
-            else if constexpr (VS == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(st + i * VS);
-            else *dst = st[i];
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(src), reinterpret_cast<v4f*>(dst));
+            else if constexpr (VS == 2) *reinterpret_cast<float2*>(dst) = *reinterpret_cast<const float2*>(src);
+            else *dst = *src;
         }
         sync();
     }

@@ -116,10 +116,9 @@ struct HostTables {
     std::vector<double> w[kKinds];         // [ncombo][D][len] chord in cell widths
     std::vector<int32_t> cnt[kKinds];      // [ncombo][D] true entry counts
     std::vector<double> kloc;              // [8 target octant][8 oct cell][D]
-    // tiled-sweep tables (see sweep_layout.h): one blob per (round, direction chunk)
-    int tile_dc = 0;                       // directions per chunk (0: no tiled sweep)
-    int blob_words = 0;                    // int32 words per blob
-    std::vector<int32_t> blob;             // [rounds][D / tile_dc][blob_words]
+    // tiled-sweep tables (see sweep_layout.h): one slot per (class, direction)
+    bool tile_ok = false;                  // every list fits its slot
+    std::vector<uint32_t> slots;           // [64][D][kSlotWords]
     std::vector<double> gloc;              // [D][8] internal+local chords by crossed-axis set m
     std::vector<int32_t> sgn;              // [D] sign bits of u (1 = negative component)
     // gather tables (any D): per configuration class c (A mod 4 per axis,
@@ -132,7 +131,6 @@ struct HostTables {
 int build_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
 int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t);
 int build_gather_tables(HostTables& t);
-int tile_chunk(int D);
 
 // Split-precision banks of the MFMA sweep (shells dl = 1, 2, 3).  For each
 // configuration class c (A mod 4 per axis), kind and tile of 16 directions:
@@ -174,7 +172,7 @@ struct cd_weights {
     int32_t* offT[cd::kKinds] = {nullptr};  // device, [ncombo][len][D]: the lists with the direction fastest
     float* wT[cd::kKinds] = {nullptr};      // device, same layout
     float* kloc = nullptr;                  // device [8][8][D]
-    int32_t* blob = nullptr;                // device tiled-sweep tables
+    uint32_t* slots = nullptr;              // device tiled-sweep tables
     float* gloc = nullptr;                  // device [D][8]
     int32_t* sgn = nullptr;                 // device [D]
     int32_t* ghdr = nullptr;                // device gather tables (cd::HostTables::ghdr, gent)

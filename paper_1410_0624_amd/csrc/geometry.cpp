@@ -244,29 +244,17 @@ static int32_t fbits(double w) {
 
 // Tables of the tiled sweep.  For each configuration class c (A mod 4 per
 // axis) and direction, the shell entries as (LDS offset relative to the
-// lane's base, weight): dl = 1, dl = 2, and for dl = 3 the union over the 8
-// parities of the level L-3 ancestor, split into entries common to all
-// parities and entries carrying a parity mask (bits 16..23 of the offset).
-// They are packed per (round, direction chunk) into blobs that the kernel
-// copies to LDS: a header of int4 (first entry, pairs of dl=1, pairs of dl=2,
-// pairs of common dl=3 | pairs of masked dl=3 << 16) per (class of the round,
-// direction of the chunk), then the entries, each list padded to an even
-// count with zero-weight entries.
-int tile_chunk(int D) {
-    if (D % 12 == 0 && D <= 24) return 12;
-    if (D % 16 == 0) return 16;
-    if (D % 8 == 0) return 8;
-    if (D <= 16) return D;
-    return 0;
-}
-
+// lane's base in its level's tile, weight): dl = 1, dl = 2, and for dl = 3
+// the union over the 8 parities of the level L-3 ancestor, split into entries
+// common to all parities and entries carrying a parity mask.  Each (class,
+// direction) gets one slot of tile::kSlotWords words (layout in
+// sweep_layout.h) that the kernel reads with scalar loads.  A list longer than
+// its slot part leaves the tiled sweep off for this direction set.
 int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables& t) {
     using namespace tile;
     const int D = (int)dirs.size();
-    const int DC = tile_chunk(D);
-    t.tile_dc = DC;
-    t.blob.clear();
-    t.blob_words = 0;
+    t.slots.clear();
+    t.tile_ok = false;
     // internal + local, for every direction count (the row kernels read
     // these whether or not the tiled sweep takes D): after mirroring u into
     // the positive octant, a target reaches the sibling across axis a only if
@@ -289,121 +277,100 @@ int build_tile_tables(const std::vector<std::array<double, 3>>& dirs, HostTables
             t.gloc[(size_t)d * 8 + m] = chord(lo, hi, org, au);
         }
     }
-    if (DC == 0) return CD_OK;  // no tiled sweep for this direction count
-    const int nchunks = D / DC;
-    std::vector<std::vector<int32_t>> blobs;
-    for (int r = 0; r < kRounds; ++r) {
-        for (int k = 0; k < nchunks; ++k) {
-            std::vector<int32_t> hdr((size_t)16 * DC * 4, 0), ent;
-            for (int w = 0; w < 16; ++w) {
-                const int ci = r * 16 + w;
-                const int c[3] = {ci & 3, (ci >> 2) & 3, ci >> 4};
-                for (int j = 0; j < DC; ++j) {
-                    const int d = k * DC + j;
-                    int32_t* h = &hdr[((size_t)w * DC + j) * 4];
-                    h[0] = (int32_t)(ent.size() / 2);
-                    auto pad_even = [&ent](size_t first) {
-                        if (((ent.size() - first) / 2) % 2) {
-                            ent.push_back(0);
-                            ent.push_back(0);
-                        }
-                    };
-                    // dl = 1: configuration = parity of A
-                    {
-                        const size_t first = ent.size();
-                        const int combo = (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1);
-                        const size_t row = ((size_t)combo * D + d);
-                        for (int e = 0; e < t.cnt[1][row]; ++e) {
-                            const int32_t pk = t.off[1][row * t.len[1] + e];
-                            const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
-                            int u[3];
-                            for (int a = 0; a < 3; ++a) {
-                                const int v = c[a] + 4 + o[a];
-                                u[a] = (v & 3) * 6 + (v >> 2);
-                            }
-                            ent.push_back(u[0] + k1Py * u[1] + k1Pz * u[2]);
-                            ent.push_back(fbits(t.w[1][row * t.len[1] + e]));
-                        }
-                        pad_even(first);
-                        h[1] = (int32_t)((ent.size() - first) / 4);
+    std::vector<uint32_t> slots((size_t)64 * D * kSlotWords, 0u);
+    // lanes l = lx + 4 ly + 16 lz of each parity p of A >> 2
+    uint64_t lanes_of[8] = {0};
+    for (int l = 0; l < 64; ++l) {
+        const int p = (l & 1) | (((l >> 2) & 1) << 1) | (((l >> 4) & 1) << 2);
+        lanes_of[p] |= 1ull << l;
+    }
+    for (int ci = 0; ci < 64; ++ci) {
+        const int c[3] = {ci & 3, (ci >> 2) & 3, ci >> 4};
+        for (int d = 0; d < D; ++d) {
+            uint32_t* sl = &slots[((size_t)ci * D + d) * kSlotWords];
+            // (offset, weight) of the unmasked entries, and the masked ones with
+            // their parity masks; weights carry dx_l / dx_{L-1}
+            std::vector<std::pair<uint32_t, double>> plain, masked;
+            std::vector<uint32_t> masks;
+            {  // dl = 1: configuration = parity of A
+                const int combo = (c[0] & 1) + 2 * (c[1] & 1) + 4 * (c[2] & 1);
+                const size_t row = ((size_t)combo * D + d);
+                for (int e = 0; e < t.cnt[1][row]; ++e) {
+                    const int32_t pk = t.off[1][row * t.len[1] + e];
+                    const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
+                    int u[3];
+                    for (int a = 0; a < 3; ++a) u[a] = slot1(c[a] + 4 + o[a]);
+                    plain.push_back({(uint32_t)(u[0] + kPy * u[1] + kPz * u[2]), t.w[1][row * t.len[1] + e]});
+                }
+            }
+            {  // dl = 2: configuration = A mod 4
+                const int combo = c[0] + 4 * c[1] + 16 * c[2];
+                const size_t row = ((size_t)combo * D + d);
+                for (int e = 0; e < t.cnt[2][row]; ++e) {
+                    const int32_t pk = t.off[2][row * t.len[2] + e];
+                    const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
+                    int u[3];
+                    for (int a = 0; a < 3; ++a) u[a] = slot2((c[a] >> 1) + 4 + o[a]);
+                    plain.push_back({(uint32_t)(kL2 + u[0] + kPy * u[1] + kPz * u[2]), 2.0 * t.w[2][row * t.len[2] + e]});
+                }
+            }
+            {  // dl = 3: reference fixed by A mod 4; union over the parity of A >> 2
+                std::map<int32_t, std::pair<double, int>> uni;  // packed offset -> (w, mask)
+                for (int p3 = 0; p3 < 8; ++p3) {
+                    int combo = 0, mul = 1;
+                    for (int a = 0; a < 3; ++a) {
+                        combo += (4 * ((p3 >> a) & 1) + c[a]) * mul;
+                        mul *= 8;
                     }
-                    // dl = 2: configuration = A mod 4
-                    {
-                        const size_t first = ent.size();
-                        const int combo = c[0] + 4 * c[1] + 16 * c[2];
-                        const size_t row = ((size_t)combo * D + d);
-                        for (int e = 0; e < t.cnt[2][row]; ++e) {
-                            const int32_t pk = t.off[2][row * t.len[2] + e];
-                            const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
-                            int u[3];
-                            for (int a = 0; a < 3; ++a) {
-                                const int v = (c[a] >> 1) + 4 + o[a];
-                                u[a] = (v & 1) * 8 + (v >> 1);
+                    const size_t row = ((size_t)combo * D + d);
+                    for (int e = 0; e < t.cnt[3][row]; ++e) {
+                        const int32_t pk = t.off[3][row * t.len[3] + e];
+                        const double wv = t.w[3][row * t.len[3] + e];
+                        auto it = uni.find(pk);
+                        if (it == uni.end()) {
+                            uni[pk] = {wv, 1 << p3};
+                        } else {
+                            if (std::fabs(it->second.first - wv) > 1e-12) {
+                                set_error("internal: dl=3 weights differ across parities");
+                                return CD_EINVAL;
                             }
-                            ent.push_back(u[0] + k2Py * u[1] + k2Pz * u[2]);
-                            ent.push_back(fbits(t.w[2][row * t.len[2] + e]));
-                        }
-                        pad_even(first);
-                        h[2] = (int32_t)((ent.size() - first) / 4);
-                    }
-                    // dl = 3: reference fixed by A mod 4; union over the parity of A >> 2
-                    {
-                        std::map<int32_t, std::pair<double, int>> uni;  // packed offset -> (w, mask)
-                        for (int p3 = 0; p3 < 8; ++p3) {
-                            int combo = 0, mul = 1;
-                            for (int a = 0; a < 3; ++a) {
-                                combo += (4 * ((p3 >> a) & 1) + c[a]) * mul;
-                                mul *= 8;
-                            }
-                            const size_t row = ((size_t)combo * D + d);
-                            for (int e = 0; e < t.cnt[3][row]; ++e) {
-                                const int32_t pk = t.off[3][row * t.len[3] + e];
-                                const double wv = t.w[3][row * t.len[3] + e];
-                                auto it = uni.find(pk);
-                                if (it == uni.end()) {
-                                    uni[pk] = {wv, 1 << p3};
-                                } else {
-                                    if (std::fabs(it->second.first - wv) > 1e-12) {
-                                        set_error("internal: dl=3 weights differ across parities");
-                                        return CD_EINVAL;
-                                    }
-                                    it->second.second |= 1 << p3;
-                                }
-                            }
-                        }
-                        for (int pass = 0; pass < 2; ++pass) {  // common entries, then masked ones
-                            const size_t first = ent.size();
-                            for (auto& kv : uni) {
-                                const bool common = kv.second.second == 0xff;
-                                if (common != (pass == 0)) continue;
-                                const int32_t pk = kv.first;
-                                const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
-                                int32_t off = (5 + o[0]) + k3Py * (5 + o[1]) + k3Pz * (5 + o[2]);
-                                if (!common) off |= kv.second.second << 16;
-                                ent.push_back(off);
-                                ent.push_back(fbits(kv.second.first));
-                            }
-                            pad_even(first);
-                            const int32_t pairs = (int32_t)((ent.size() - first) / 4);
-                            if (pass == 0) h[3] = pairs;
-                            else h[3] |= pairs << 16;
+                            it->second.second |= 1 << p3;
                         }
                     }
                 }
+                for (auto& kv : uni) {
+                    const int32_t pk = kv.first;
+                    const int o[3] = {(int8_t)(pk & 0xff), (int8_t)((pk >> 8) & 0xff), (int8_t)((pk >> 16) & 0xff)};
+                    const uint32_t off = (uint32_t)(kL3 + (5 + o[0]) + kPy * (5 + o[1]) + kPz * (5 + o[2]));
+                    if (kv.second.second == 0xff) {
+                        plain.push_back({off, 4.0 * kv.second.first});
+                    } else {
+                        masked.push_back({off, 4.0 * kv.second.first});
+                        masks.push_back((uint32_t)kv.second.second);
+                    }
+                }
             }
-            // entry indices are relative to the end of the header
-            std::vector<int32_t> blob(hdr);
-            blob.insert(blob.end(), ent.begin(), ent.end());
-            while (blob.size() % 4) blob.push_back(0);
-            blobs.push_back(std::move(blob));
+            if ((int)plain.size() > kSlotMain + kSlotExtra || (int)masked.size() > kSlotMasked) return CD_OK;
+            sl[0] = (uint32_t)plain.size();
+            for (size_t e = 0; e < plain.size(); ++e) {
+                const bool main = (int)e < kSlotMain;
+                const int k = main ? (int)e : (int)e - kSlotMain;
+                sl[(main ? kSlotOff : kSlotXOff) + k] = plain[e].first;
+                sl[(main ? kSlotW : kSlotXW) + k] = (uint32_t)fbits(plain[e].second);
+            }
+            for (size_t e = 0; e < masked.size(); ++e) {
+                uint64_t lm = 0;
+                for (int p = 0; p < 8; ++p)
+                    if ((masks[e] >> p) & 1) lm |= lanes_of[p];
+                sl[kSlotMOff + e] = masked[e].first;
+                sl[kSlotMW + e] = (uint32_t)fbits(masked[e].second);
+                sl[kSlotMMask + 2 * e] = (uint32_t)(lm & 0xffffffffu);
+                sl[kSlotMMask + 2 * e + 1] = (uint32_t)(lm >> 32);
+            }
         }
     }
-    size_t words = 0;
-    for (auto& b : blobs) words = std::max(words, b.size());
-    t.blob_words = (int)words;
-    t.blob.assign(words * blobs.size(), 0);
-    for (size_t i = 0; i < blobs.size(); ++i) std::copy(blobs[i].begin(), blobs[i].end(), t.blob.begin() + i * words);
-
+    t.slots.swap(slots);
+    t.tile_ok = true;
     return CD_OK;
 }
 

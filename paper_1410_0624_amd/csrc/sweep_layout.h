@@ -32,8 +32,34 @@ constexpr int k2Size = k2Side * k2Pz;
 constexpr int k3Side = 14, k3Py = 14, k3Pz = 196;
 constexpr int k3Size = k3Side * k3Pz;
 
-// LDS words for one blob of weight lists (one round, one direction chunk)
-constexpr int kTabWords = 10752;
+// The FP32 tiled kernel keeps the three levels in one LDS array with a
+// common row and plane pitch (level L-1 at 0, L-2 at kL2, L-3 at kL3, each in
+// the per-level slot order above), so that one lane base lx + kPy ly + kPz lz
+// serves every level and an entry is one offset from it.
+constexpr int kPy = 24, kPz = 580;
+constexpr int kL2 = k1Side * kPz, kL3 = kL2 + k2Side * kPz;
+constexpr int kLdsWords = kL3 + k3Side * kPz;  // 31320 words, 125 KB
+
+// Weight-list slots of the FP32 tiled kernel, one per (configuration class,
+// direction), read with scalar loads (kSlotWords 32-bit words):
+//   [0]            number of unmasked entries (at most kSlotMain + kSlotExtra)
+//   [1, 17)        kSlotMain unmasked entries: LDS word offsets from the lane base
+//   [17, 33)       their weights (FP32): the chord in cell widths times
+//                  dx_l / dx_{L-1} = 1, 2, 4, so that one sum times dx_{L-1} is E
+//   [33, 36)       kSlotMasked dl = 3 entries that only some parities of
+//                  A >> 2 have: offsets
+//   [36, 39)       their weights
+//   [39, 45)       their 64-bit lane masks (low word first): the lanes whose
+//                  parity has the entry
+//   [45, 53)       unmasked entries kSlotMain .. kSlotMain + kSlotExtra - 1:
+//                  offsets (read only when the count exceeds kSlotMain)
+//   [53, 61)       their weights
+// Unused entries have offset 0 and weight 0 (a lane's own cell).
+constexpr int kSlotWords = 64;
+constexpr int kSlotMain = 16, kSlotMasked = 3, kSlotExtra = 8;
+constexpr int kSlotOff = 1, kSlotW = 17, kSlotMOff = 33, kSlotMW = 36, kSlotMMask = 39, kSlotXOff = 45, kSlotXW = 53;
+constexpr int kSlotHead = 45;  // words read for every direction
+
 // screening factors of one round: 8 target z-planes of 32 x 32
 constexpr int kChiStage = 8 * 32 * 32;
 

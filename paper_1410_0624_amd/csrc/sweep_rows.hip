@@ -66,6 +66,11 @@ __device__ __forceinline__ void il_pair(const float (&c0)[4], const float (&c1)[
     r1 = fx0 ? a1 : a1 + b1;
 }
 
+// LDS row pitch of the external columns shared by a workgroup (a multiple of
+// 4 floats, off the 32-bank period for the lanes' row reads).
+template <int D>
+constexpr int kRowPitch = D % 4 == 0 ? D + 4 : D + 1;
+
 template <int D>
 __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
     const int L = a.L;
@@ -112,7 +117,9 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
         const float* yr = a.y7 + r7 * D;
 #pragma unroll
         for (int d = 0; d < D; ++d) e0[d] = fmaxf(__expf(fmaf(yr[d], a.y_scale, a.y_shift)) - a.y_floor, 0.f);
-    } else {
+    } else if constexpr (D <= 12) {
+        // short rows: each lane loads its oct's rows of E and of the coarse
+        // table itself (their lines are few and the LDS is kept for staging)
         const float* er = a.E + oct * D;
         if constexpr (D % 4 == 0) {
 #pragma unroll
@@ -130,10 +137,10 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
         if (a.q4) {
             // shells dl >= 4: the level L-4 ancestor and the inner-limit state
             // fixed by bits 1 and 2 of the oct's coordinates
-            const int64_t Ay = y >> 1, Az = z >> 1;
+            const int64_t Az = z >> 1;
             const int64_t n4 = n1 >> 3;
-            const int64_t cell = ((Az >> 3) * n4 + (Ay >> 3)) * n4 + (ax >> 3);
-            const int code = (int)(((ax >> 1) & 3) + 4 * ((Ay >> 1) & 3) + 16 * ((Az >> 1) & 3));
+            const int64_t cell = ((Az >> 3) * n4 + (Y >> 3)) * n4 + (ax >> 3);
+            const int code = (int)(((ax >> 1) & 3) + 4 * ((Y >> 1) & 3) + 16 * ((Az >> 1) & 3));
             const float* qr = a.q4 + (cell * 64 + code) * D;
             if constexpr (D % 4 == 0) {
 #pragma unroll
@@ -149,6 +156,47 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
                 for (int d = 0; d < D; ++d) e0[d] += qr[d];
             }
         }
+    } else {
+        // The 4 waves read the same seg octs: their rows of E (contiguous)
+        // and of the coarse table are loaded once per workgroup, coalesced,
+        // summed and shared through LDS (a lane loading its own oct's 4 D-byte
+        // rows touches a cache line per lane and load, four times over)
+        __shared__ float ext[64 * kRowPitch<D>];
+        const int64_t Az = z >> 1, ax0 = seg_i * seg;
+        const int64_t oct0 = (Az << (2 * L1)) + (Y << L1) + ax0;
+        const int64_t n4 = n1 >> 3;
+        constexpr int V = D % 4 == 0 ? 4 : 1;  // floats per load
+        constexpr int DV = D / V;
+        for (int t = threadIdx.x; t < seg * DV; t += 256) {
+            const int o = t / DV, c = t - o * DV;
+            float v[V];
+            if constexpr (V == 4) {
+                const float4 q = reinterpret_cast<const float4*>(a.E + (oct0 + o) * D)[c];
+                v[0] = q.x, v[1] = q.y, v[2] = q.z, v[3] = q.w;
+            } else {
+                v[0] = a.E[(oct0 + o) * D + c];
+            }
+            if (a.q4) {
+                // shells dl >= 4: the level L-4 ancestor and the inner-limit
+                // state fixed by bits 1 and 2 of the oct's coordinates
+                const int64_t xo = ax0 + o;
+                const int64_t cell = ((Az >> 3) * n4 + (Y >> 3)) * n4 + (xo >> 3);
+                const int code = (int)(((xo >> 1) & 3) + 4 * ((Y >> 1) & 3) + 16 * ((Az >> 1) & 3));
+                const float* qr = a.q4 + (cell * 64 + code) * D;
+                if constexpr (V == 4) {
+                    const float4 q = reinterpret_cast<const float4*>(qr)[c];
+                    v[0] += q.x, v[1] += q.y, v[2] += q.z, v[3] += q.w;
+                } else {
+                    v[0] += qr[c];
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < V; ++k) ext[o * kRowPitch<D> + c * V + k] = v[k];
+        }
+        __syncthreads();
+        const float* er = ext + lane * kRowPitch<D>;
+#pragma unroll
+        for (int d = 0; d < D; ++d) e0[d] = er[d];
     }
     float chi0 = 0.f, chi1 = 0.f;
 #pragma unroll
@@ -180,19 +228,31 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
                                     reinterpret_cast<v2f*>(a.chi + T));
 
     // rows of the wave's targets through LDS, P lanes (2 P targets) at a time:
-    // the whole wave at once up to 12 directions (24 KB per workgroup)
+    // the whole wave at once up to 12 directions.  A lane's two rows start
+    // RS = 2 D + 4 words after the previous lane's (16-byte aligned, and 4
+    // banks further: at a stride of 2 D words every lane would write the same
+    // bank), and are read back as the contiguous rows they are in N.
     constexpr int P = D <= 12 ? 64 : 16;
-    __shared__ float stage[4][2 * P * D];
+    constexpr int RS = D % 4 == 0 ? 2 * D + 4 : 2 * D + 1;
+    __shared__ float stage[4][P * RS];
     float* st = stage[w];
     const int64_t T0 = (z * n + y) * n + 2 * seg_i * seg;  // first target of the wave
     const int nl = seg < 64 ? seg : 64;
     for (int p = 0; p * P < nl; ++p) {
         if (lane / P == p) {
-            float* r = st + (lane % P) * 2 * D;
+            float* r = st + (lane % P) * RS;
+            if constexpr (D % 4 == 0) {
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                r[d] = e0[d];
-                r[D + d] = e1[d];
+                for (int d = 0; d < D; d += 4) {
+                    *reinterpret_cast<v4f*>(r + d) = v4f{e0[d], e0[d + 1], e0[d + 2], e0[d + 3]};
+                    *reinterpret_cast<v4f*>(r + D + d) = v4f{e1[d], e1[d + 1], e1[d + 2], e1[d + 3]};
+                }
+            } else {
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    r[d] = e0[d];
+                    r[D + d] = e1[d];
+                }
             }
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
@@ -200,12 +260,16 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
         const int ntg = (nl - P * p) >= P ? 2 * P : 2 * (nl - P * p);  // targets in this piece
         float* dst = a.N + (T0 + 2 * P * p) * D;
         if constexpr (D % 4 == 0) {
+            constexpr int Q = D / 2;  // float4 pieces per lane's pair of rows
             const int nf4 = ntg * D / 4;
-            for (int i = lane; i < nf4; i += 64)
-                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(st + 4 * i), reinterpret_cast<v4f*>(dst + 4 * i));
+            for (int i = lane; i < nf4; i += 64) {
+                const int pr = i / Q;  // the staging lane it comes from
+                __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(st + pr * RS + 4 * (i - pr * Q)),
+                                            reinterpret_cast<v4f*>(dst + 4 * i));
+            }
         } else {
             const int nf = ntg * D;
-            for (int i = lane; i < nf; i += 64) dst[i] = st[i];
+            for (int i = lane; i < nf; i += 64) dst[i] = st[(i / (2 * D)) * RS + i % (2 * D)];
         }
         __builtin_amdgcn_s_waitcnt(0xc07f);
         __builtin_amdgcn_wave_barrier();
