@@ -164,6 +164,17 @@ int cd_tree_set_aux_stream(cd_tree* tree, void* stream);
 int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, void* scratch_dev, int64_t* n_invalid,
                        void* stream);
 
+/* cd_check_densities for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops): the same count, accumulated
+ * in a 256-byte scratch array the library holds per GPU (in device memory
+ * from load until the process ends) instead of a caller scratch.  n_leaf is
+ * not limited by it (the count is 64-bit).  Calls that overlap on one GPU
+ * share that array and race: run them one after another.  Allocates nothing;
+ * synchronises `stream`.
+ * Errors: CD_EINVAL (NULL n_invalid, n_leaf < 0, NULL buffer with n_leaf >
+ * 0), CD_EDEVICE. */
+int cd_check_densities_noalloc(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid, void* stream);
+
 /* New leaf densities for an existing structure (one hydro step later):
  * rebuilds the pyramid on `stream`.  n_leaf must be the tree's leaf count.
  * Same layout and lifetime rules as cd_build_tree.

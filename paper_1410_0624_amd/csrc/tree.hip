@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "cd_internal.h"
 #include "tree_amr.h"
@@ -332,6 +333,54 @@ extern "C" int cd_check_densities(const float* leaf_n_dev, int64_t n_leaf, void*
     }
     return cd::count_invalid(leaf_n_dev, n_leaf, static_cast<unsigned long long*>(scratch_dev), n_invalid,
                              (hipStream_t)stream);
+}
+
+// ------------------------------------------------ density check, no alloc --
+// Scratch of cd_check_densities_noalloc: 256 bytes per GPU, of which the
+// first 8 hold the 64-bit count.  In host code `scratch` names a host-side
+// stand-in, not device memory: kernels and copies get the device address
+// that hipGetSymbolAddress returns for the current device, taken once per
+// device on the first call there.
+static __device__ __align__(256) unsigned long long scratch[32];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+unsigned long long* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of this device's scratch (set up on the first call).
+int scratch_address(unsigned long long** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxScratchDevices) {
+        cd::set_error("cd_check_densities_noalloc: no usable current device");
+        return CD_EDEVICE;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            cd::set_error("cd_check_densities_noalloc: hipGetSymbolAddress failed: %s", hipGetErrorString(e));
+            return CD_EDEVICE;
+        }
+        g_scratch_dev[dev] = static_cast<unsigned long long*>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return CD_OK;
+}
+}  // namespace
+
+extern "C" int cd_check_densities_noalloc(const float* leaf_n_dev, int64_t n_leaf, int64_t* n_invalid,
+                                          void* stream) {
+    cd::clear_error();
+    if (!n_invalid || n_leaf < 0 || (n_leaf > 0 && !leaf_n_dev)) {
+        cd::set_error("cd_check_densities_noalloc: NULL argument or n_leaf %lld < 0", (long long)n_leaf);
+        return CD_EINVAL;
+    }
+    unsigned long long* counter = nullptr;
+    int rc = scratch_address(&counter);
+    if (rc != CD_OK) return rc;
+    return cd::count_invalid(leaf_n_dev, n_leaf, counter, n_invalid, (hipStream_t)stream);
 }
 
 extern "C" int cd_tree_update(cd_tree* t, const float* leaf_n_dev, int64_t n_leaf, void* stream) {
