@@ -109,7 +109,7 @@ def main():
                     help="adaptive tree: refine cells with averaged n above this (cm^-3)")
     ap.add_argument("--train-fields", type=int, default=16, help="surrogate: seeded 256^3 training fields")
     ap.add_argument("--train-steps", type=int, default=6000, help="surrogate: Adam steps")
-    ap.add_argument("--train-batch", type=int, default=8192, help="surrogate: leaves per step")
+    ap.add_argument("--train-batch", type=int, default=8192, help="surrogate: level-7 cells per step")
     ap.add_argument("--level", type=int, default=9, help="uniform grid of 2^level cells per axis")
     ap.add_argument("--nside", type=int, default=2, help="HEALPix Nside, D = 12 Nside^2")
     ap.add_argument("--precision", choices=list(PREC), default="fp32")
@@ -436,10 +436,12 @@ def main():
 
 
 def bench_surrogate(args):
-    """Learned surrogate: trained on seeded 256^3 fields (labels from the
-    FP32 sweep), run on an unseen 512^3 field; the timed path is inference +
-    the 1 % sampled check + fallback of the failing 8^3 tiles, beside the
-    plain FP32 sweep of the same field."""
+    """Learned surrogate: a network for 512^3 grids trained on seeded 256^3
+    fields (each refined into 2^9 equal leaves; labels: the method's near
+    shells dl = 1..3), run on an unseen 512^3 field; the timed path is the
+    pyramid, inference (network near shells + the method's internal + local
+    part and coarse shells) + the 1 % sampled check + fallback of the failing
+    8^3 tiles, beside the plain FP32 sweep of the same field."""
     import torch
 
     from paper_1410_0624_amd import colden, surrogate_train, synth
@@ -448,33 +450,26 @@ def bench_surrogate(args):
     D = 12
     dirs = colden.directions(colden.CD_DIR_HEALPIX, 1)
     w = colden.Weights(dirs)
+    L = 9
     t0 = time.time()
-    trees, Ns, leaves = [], [], []
-    for sd in range(100, 100 + args.train_fields):
-        tin = synth.workload_uniform(8, sigma=1.5, mean=10.0, seed=sd)
-        leaf = torch.from_numpy(tin.leaf_n).to(dev)
-        tree = colden.Tree(tin, leaf, max_dirs=D)
-        N = torch.empty((tin.n_leaf, D), dtype=torch.float32, device=dev)
-        colden.column_densities(tree, w, N)
-        trees.append(tree)
-        Ns.append(N)
-        leaves.append(leaf)
+    tins = synth.workloads_uniform(8, list(range(100, 100 + args.train_fields)), sigma=1.5, mean=10.0)
+    fields = [surrogate_train.label_field(t, w, L, dev) for t in tins]
+    del tins
     torch.cuda.synchronize()
     t_data = time.time() - t0
     print(f"# {args.train_fields} training fields with labels in {t_data:.1f}s", file=sys.stderr, flush=True)
-    nrm = surrogate_train.norms(trees, w, Ns)
-    surr = colden.Surrogate(D, 256, colden.CD_SURR_BF16, 1, norm=nrm)
+    nrm = surrogate_train.norms(fields)
+    surr = colden.Surrogate(D, 256, colden.CD_SURR_BF16, 1, norm=nrm, leaf_level=L)
     t0 = time.time()
-    log = surrogate_train.fit(surr, trees, w, Ns, steps=args.train_steps, batch=args.train_batch, lr=2e-3,
+    log = surrogate_train.fit(surr, fields, steps=args.train_steps, batch=args.train_batch, lr=2e-3,
                               lr_final=5e-5, seed=2, log_every=max(args.train_steps // 10, 1))
     torch.cuda.synchronize()
     t_train = time.time() - t0
     print(f"# trained {args.train_steps} steps in {t_train:.1f}s, loss {log[0][1]:.4f} -> {log[-1][1]:.4f}",
           file=sys.stderr, flush=True)
-    del trees, Ns, leaves
+    del fields
     torch.cuda.empty_cache()
 
-    L = 9
     tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=999)
     leaf = torch.from_numpy(tin.leaf_n).to(dev)
     tree = colden.Tree(tin, leaf, max_dirs=D)
@@ -519,9 +514,10 @@ def bench_surrogate(args):
     e_net = np.abs(chi_net - ref) / ref
     e_fin = np.abs(chis.cpu().numpy().astype(np.float64) - ref) / ref
     q = lambda e: {"mean": float(e.mean()), "p99": float(np.percentile(e, 99)), "max": float(e.max())}
-    # the network runs once per level-7 cell (its leaves share the features)
+    # the network runs once per level-7 cell (its leaves share the features),
+    # with a block of D outputs for each of its 8 octs
     net_rows = 1 << 21
-    flops = 2.0 * net_rows * (576 * 256 + 256 * 256 + 256 * D)
+    flops = 2.0 * net_rows * (576 * 256 + 256 * 256 + 256 * surr.Dout)
     achieved = flops / (ms_infer * 1e-3) / 1e12
 
     cpu = None
@@ -561,14 +557,16 @@ def bench_surrogate(args):
         "vs_baseline": None,
         "dtype": "bf16 (f32 accumulate)",
         "data": "synthetic",
-        "config": {"workload": f"learned surrogate (MLP 576-256-256-12, bf16 on the matrix cores) trained on "
-                               f"{args.train_fields} seeded 256^3 log-normal fields (sigma_ln n=1.5, mean 10 cm^-3, "
-                               f"box 10 pc), run on an unseen 512^3 field (seed 999), 12 HEALPix sectors; step = "
-                               f"pyramid + inference + 1% sampled check per 8^3 tile + fallback (tol 3% in chi)",
+        "config": {"workload": f"learned surrogate (MLP 576-256-256-96: near shells dl=1..3 of the 8 octs of a "
+                               f"level-7 cell, bf16 on the matrix cores) trained on {args.train_fields} seeded 256^3 "
+                               f"log-normal fields (sigma_ln n=1.5, mean 10 cm^-3, box 10 pc) refined to 512^3, run "
+                               f"on an unseen 512^3 field (seed 999), 12 HEALPix sectors; step = pyramid + inference "
+                               f"(+ the method's internal/local and dl>=4 parts) + 1% sampled check per 8^3 tile + "
+                               f"fallback (tol 3% in chi)",
                    "n_leaf": tin.n_leaf, "n_dirs": D},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": 2500.0, "unit": "TFLOP/s",
                      "frac": achieved / 2500.0, "traffic": None,
-                     "kernel": "inference (features + network on 2^21 level-7 rows + per-leaf output)",
+                     "kernel": "inference (features + network on 2^21 level-7 rows + coarse tables + row kernel)",
                      "kernel_ms": ms_infer, "flops_per_launch": flops, "network_rows": net_rows},
         "forms": {"plain_fp32": {"ms_per_step": ms_plain, "value": tin.n_leaf * D / (ms_plain * 1e-3)},
                   "surrogate_infer_only": {"ms": ms_infer, "chi_rel_err_vs_plain": q(e_net)},

@@ -363,37 +363,54 @@ int cd_profile_read(cd_tree* tree, float* ms /* [CD_NUM_STAGES] */);
 /*
  * Learned surrogate of the column sweep.  Not part of the paper's method: a
  * network trained on the columns the method computes, with the method as
- * fallback.  Uniform grids of 2^L >= 256 cells per axis.
+ * fallback.  Uniform grids; a network serves one leaf level L, 8 or 9
+ * (2^L = 256 or 512 cells per axis).
  *
  * Features of a leaf (576): for each absolute level l = 0 .. 8 of the
  * pyramid (Sect. 3: a coarse cell holds the mean of its children), the 4^3
  * level-l cells centred on the centre of the leaf's level-(l-1) ancestor A
  * (indices 2A-1 .. 2A+2 per axis; A = 0 at l = 0), feature
  * l*64 + sx + 4 sy + 16 sz = (ln max(n, 1e-10) - in_shift) / in_scale, with
- * n = 0 outside the box.  The features are those of the leaf's oct, shared
- * by its 8 leaves, and so is what the network predicts: the external part
- * of the column (shells dl >= 1), y = (ln(N - N_il + 1e17) - out_shift) /
- * out_scale per direction, N_il the leaf's internal + local part (Sect.
- * 3.2), which is added back exactly: N = N_il + max(exp(y out_scale +
- * out_shift) - 1e17, 0).  Network: 576 -> width -> width -> D, ReLU.  Loss:
- * mean squared error over all outputs.  Optimiser: Adam (beta1 0.9, beta2
- * 0.999, eps 1e-8).
+ * n = 0 outside the box.  They depend on the leaf's level-7 ancestor only,
+ * so the network runs once per level-7 cell (a "row").  It predicts the
+ * near shells dl = 1..3 of the external sum (Sect. 3.2, Eqs. 9-10; shared by
+ * the 8 leaves of an oct) of each of the 8^(L-8) octs inside that cell:
+ * Dout = 8^(L-8) D outputs, block j = jx + 2^(L-8) (jy + 2^(L-8) jz) of D
+ * values for the oct at offset (jx, jy, jz) inside the cell,
+ * y = (ln(E + 1e17) - out_shift) / out_scale per direction, E the method's
+ * near-shell column.  The method supplies the rest exactly: the internal +
+ * local part and the shells dl >= 4 (its coarse tables, Eq. 11), so
+ * N = N_il + N_dl>=4 + max(exp(y out_scale + out_shift) - 1e17, 0).
+ * The near shells are what the method spends its gather on, and they carry
+ * less of the column than the coarse shells, which the 4^3 stencils resolve
+ * worst.  Network: 576 -> width -> width -> Dout, ReLU.
+ * Loss: mean squared error over all outputs.  Optimiser: Adam (beta1 0.9,
+ * beta2 0.999, eps 1e-8).
  * Parameters in the order W1 [576][width], b1, W2 [width][width], b2,
- * W3 [width][D], b3 (row-major, y = x W + b), FP32 master copies.
+ * W3 [width][Dout], b3 (row-major, y = x W + b), FP32 master copies.
  *
- * CD_SURR_BF16: weights and activations rounded to bfloat16 for the matrix
- * cores, FP32 accumulation.  CD_SURR_FP32: every product in FP32 (a checking
- * path).  A handle holds scratch for its largest batch; calls on one handle
- * must not overlap.
+ * CD_SURR_BF16: inference (cd_surrogate_infer, cd_surrogate_forward) with
+ * weights and activations rounded to bfloat16 on the matrix cores, FP32
+ * accumulation; training (train steps, cd_surrogate_gradients) on the
+ * matrix cores too, with every FP32 operand split into bfloat16 hi + lo
+ * and three products per pair (about 16 significant bits), so gradients
+ * match FP32 arithmetic.  CD_SURR_FP32: every product in FP32 on the vector
+ * units (a checking path).  A handle holds scratch for its largest batch;
+ * calls on one handle must not overlap.
  */
 enum { CD_SURR_FP32 = 0, CD_SURR_BF16 = 1 };
 typedef struct cd_surrogate cd_surrogate;
 
-/* New network for D directions, hidden width (multiple of 16, 16 .. 1024),
- * precision CD_SURR_*, He-uniform weights from `seed`, zero biases.
+/* New network for D directions on grids of leaf level leaf_level (8 or 9),
+ * hidden width (multiple of 16, 16 .. 1024), precision CD_SURR_*,
+ * He-uniform weights from `seed`, zero biases.
  * norm = {in_shift, in_scale, out_shift, out_scale} (scales > 0).
  * Errors: CD_EINVAL, CD_ENOMEM. */
-int cd_surrogate_create(int D, int width, int precision, uint64_t seed, const float* norm, cd_surrogate** out);
+int cd_surrogate_create(int D, int leaf_level, int width, int precision, uint64_t seed, const float* norm,
+                        cd_surrogate** out);
+
+/* info[5] = {D, leaf level, width, precision, Dout}. */
+int cd_surrogate_info(const cd_surrogate* s, int32_t* info);
 
 /* Release the handle (after the stream's work that uses it).  NULL is ignored. */
 void cd_surrogate_destroy(cd_surrogate* s);
@@ -411,37 +428,57 @@ int cd_surrogate_set_params(cd_surrogate* s, const float* params);
 int cd_surrogate_features(const cd_surrogate* s, const cd_tree* tree, const int64_t* cells_dev, int64_t n,
                           float* X_dev, void* stream);
 
-/* Training targets of n leaves (cells_dev[n]): T_dev[n][D] = scaled
- * ln(N - N_il + 1e17) from the method's columns N_dev[n_leaf][D] and the
- * internal + local parts (weights w).  An index outside [0, n_leaf) gives
- * NaN.  Errors: CD_EINVAL. */
-int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const float* N_dev,
-                         const int64_t* cells_dev, int64_t n, float* T_dev, void* stream);
+/* Training targets of n leaves (cells_dev[n]) of a tree of the network's
+ * leaf level: T_dev[n][Dout], block j = scaled ln(E + 1e17) of oct j of the
+ * listed leaf's level-7 cell, E the method's near shells dl = 1..3 computed
+ * here with weights w (FP32, precalculated, the network's D, a direction
+ * set the tiled near-shell kernel takes: D in {6, 12, 24, 40, 48}).  An
+ * index outside [0, n_leaf) gives NaN.
+ * Errors: CD_EINVAL, CD_EUNSUPPORTED. */
+int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const int64_t* cells_dev,
+                         int64_t n, float* T_dev, void* stream);
 
-/* Network outputs Y_dev[n][D] (scaled log columns) of inputs X_dev[n][576]. */
+/* Unscaled targets of every level-7 cell of a tree of the network's leaf
+ * level: T_rows_dev[2^21][Dout] = ln(E + 1e17) (the table
+ * cd_surrogate_train_step_rows reads).  Weights as cd_surrogate_targets.
+ * Errors: CD_EINVAL, CD_EUNSUPPORTED. */
+int cd_surrogate_row_targets(const cd_surrogate* s, const cd_tree* tree, const cd_weights* w, float* T_rows_dev,
+                             void* stream);
+
+/* Network outputs Y_dev[n][Dout] (scaled log columns) of inputs X_dev[n][576]. */
 int cd_surrogate_forward(cd_surrogate* s, const float* X_dev, int64_t n, float* Y_dev, void* stream);
 
 /* Loss and gradient of the loss for inputs X_dev[n][576] and targets
- * T_dev[n][D] (scaled log columns), without an update: grad[n_params] and
+ * T_dev[n][Dout] (scaled log columns), without an update: grad[n_params] and
  * *loss in host memory (synchronises the stream). */
 int cd_surrogate_gradients(cd_surrogate* s, const float* X_dev, const float* T_dev, int64_t n, float* grad,
                            float* loss, void* stream);
 
 /* One Adam step of learning rate lr on a batch of leaves cells_dev[batch] of
- * a uniform tree, with targets from the method's columns N_dev[n_leaf][D]
- * (cm^-2, from cd_column_densities on the same tree) minus the internal +
- * local parts (weights w of the same D supply them).  If loss is not NULL
- * the batch loss before the step is written there (synchronises the stream).
- * Errors: CD_EINVAL. */
-int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const float* N_dev,
-                            const int64_t* cells_dev, int64_t batch, float lr, float* loss, void* stream);
+ * a uniform tree of the network's leaf level, with targets as
+ * cd_surrogate_targets (the near shells are recomputed on every call).  If
+ * loss is not NULL the batch loss before the step is written there
+ * (synchronises the stream).  Errors: CD_EINVAL, CD_EUNSUPPORTED. */
+int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, const int64_t* cells_dev,
+                            int64_t batch, float lr, float* loss, void* stream);
 
-/* Columns of every leaf of a uniform tree from the network plus the exact
- * internal + local parts (weights w): N_dev[n_leaf][D] (cm^-2) and, if
- * chi_dev is not NULL, chi (Eq. 7) with av_per_nh, gamma.  N_dev 16-byte
- * and chi_dev 8-byte aligned.
- * Errors: CD_EINVAL, CD_ENOMEM. */
-int cd_surrogate_infer(cd_surrogate* s, const cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
+/* The same step on level-7 cells rows_dev[batch] (row-major, x fastest; an
+ * index outside [0, 2^21) gives NaN): features from `tree`, a uniform tree
+ * of any leaf level >= 8 (they read pyramid levels 0 .. 8 only), targets
+ * from a table of cd_surrogate_row_targets scaled by the handle's norm.
+ * A 2^8 field refined into 2^9 equal leaves has the same levels 0 .. 8, so
+ * its 2^8 tree supplies the features of rows labelled on the 2^9 tree.
+ * Errors: CD_EINVAL. */
+int cd_surrogate_train_step_rows(cd_surrogate* s, const cd_tree* tree, const float* T_rows_dev,
+                                 const int64_t* rows_dev, int64_t batch, float lr, float* loss, void* stream);
+
+/* Columns of every leaf of a uniform tree of the network's leaf level: the
+ * network's near shells plus the method's internal + local parts and coarse
+ * shells dl >= 4 (weights as cd_surrogate_targets): N_dev[n_leaf][D]
+ * (cm^-2) and, if chi_dev is not NULL, chi (Eq. 7) with av_per_nh, gamma.
+ * N_dev 16-byte and chi_dev 8-byte aligned.
+ * Errors: CD_EINVAL, CD_ENOMEM, CD_EUNSUPPORTED. */
+int cd_surrogate_infer(cd_surrogate* s, cd_tree* tree, const cd_weights* w, float* N_dev, float* chi_dev,
                        double av_per_nh, double gamma, void* stream);
 
 /* Sampled check and fallback after cd_surrogate_infer: the grid is cut into

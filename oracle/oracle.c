@@ -399,15 +399,17 @@ static void orc_target_column(const orc_tree* t, int l0, const int64_t* T,
 
 /* External column of the oct containing target T at level l0 (identical for
  * the 8 siblings): sum over shells of n x chord from the shell's reference
- * point (Eqs. 9-11). */
+ * point (Eqs. 9-11), restricted to the shells dl_lo <= dl <= dl_hi. */
 static void orc_external(const orc_tree* t, int l0, const int64_t* T, const double* dirs,
-                         int D, int mode, double* ext) {
+                         int D, int mode, int dl_lo, int dl_hi, double* ext) {
     orc_shell sh[32];
     int ns = orc_make_shells(l0, T, mode, sh);
     for (int d = 0; d < D; ++d) ext[d] = 0.0;
     for (int q = 0; q < ns; ++q) {
         const orc_shell* s = &sh[q];
         int l = s->level;
+        int dl = l0 - l;
+        if (dl < dl_lo || dl > dl_hi) continue;
         int64_t n = (int64_t)1 << l;
         double dx = ldexp(1.0, -l);
         int64_t a0[3], a1[3];
@@ -474,7 +476,7 @@ int orc_columns(const orc_tree* t, const double* dirs, int D, int mode,
             int64_t li = targets[first];
             int l0 = t->leaf_level[li];
             int64_t T[3] = {t->leaf_ijk[3 * li], t->leaf_ijk[3 * li + 1], t->leaf_ijk[3 * li + 2]};
-            orc_external(t, l0, T, dirs, D, mode, ext);
+            orc_external(t, l0, T, dirs, D, mode, 1, l0, ext);
             for (int64_t q = gs[g]; q < gs[g + 1]; ++q) {
                 int64_t lj = targets[kv[q].idx];
                 int64_t Tq[3] = {t->leaf_ijk[3 * lj], t->leaf_ijk[3 * lj + 1], t->leaf_ijk[3 * lj + 2]};
@@ -485,6 +487,26 @@ int orc_columns(const orc_tree* t, const double* dirs, int D, int mode,
     }
     free(gs);
     free(kv);
+    return 0;
+}
+
+/* External sum of the listed leaves' octs over the shells dl_lo <= dl <=
+ * dl_hi alone (the terms of Eqs. 9-10 one shell at a time), ext[n][D] in
+ * cm^-2.  Returns 0, or -1 on bad arguments. */
+int orc_external_shells(const orc_tree* t, const double* dirs, int D, int mode, const int64_t* targets, int64_t n,
+                        int dl_lo, int dl_hi, double* out, int nthreads) {
+    if (D < 1 || n < 0 || dl_lo < 1 || dl_hi < dl_lo) return -1;
+    for (int64_t q = 0; q < n; ++q)
+        if (targets[q] < 0 || targets[q] >= t->n_leaf) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < n; ++q) {
+        int64_t li = targets[q];
+        int64_t T[3] = {t->leaf_ijk[3 * li], t->leaf_ijk[3 * li + 1], t->leaf_ijk[3 * li + 2]};
+        orc_external(t, t->leaf_level[li], T, dirs, D, mode, dl_lo, dl_hi, out + q * D);
+    }
     return 0;
 }
 

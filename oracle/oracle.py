@@ -58,6 +58,7 @@ def lib():
         L.orc_columns.argtypes = [P, P, C.c_int, C.c_int, P, C.c_int64, P, C.c_int]
         L.orc_shells.argtypes = [P, C.c_int64, C.c_int, P, P]
         L.orc_internal_local.argtypes = [P, P, C.c_int, P, C.c_int64, P]
+        L.orc_external_shells.argtypes = [P, P, C.c_int, C.c_int, P, C.c_int64, C.c_int, C.c_int, P, C.c_int]
         L.orc_screening.argtypes = [P, C.c_int64, C.c_int, C.c_double, C.c_double, P]
         L.orc_raymarch.argtypes = [P, P, C.c_int, P, C.c_int64, P, C.c_int]
         _lib = L
@@ -157,6 +158,18 @@ class Tree:
         targets = np.ascontiguousarray(targets, dtype=np.int64)
         out = np.zeros((targets.shape[0], dirs.shape[0]))
         if lib().orc_internal_local(self.h, _p(dirs), dirs.shape[0], _p(targets), targets.shape[0], _p(out)) != 0:
+            raise ValueError("oracle: bad arguments")
+        return out
+
+    def external(self, dirs: np.ndarray, targets, dl_lo: int = 1, dl_hi: int = 1 << 20, mode: int = PRECALC73,
+                 nthreads: int = 0) -> np.ndarray:
+        """External sum of the targets' octs over the shells dl_lo <= dl <=
+        dl_hi only (Sect. 3.2, Eqs. 9-10), [n_targets, D] cm^-2."""
+        dirs = np.ascontiguousarray(dirs, dtype=np.float64)
+        targets = np.ascontiguousarray(targets, dtype=np.int64)
+        out = np.zeros((targets.shape[0], dirs.shape[0]))
+        if lib().orc_external_shells(self.h, _p(dirs), dirs.shape[0], mode, _p(targets), targets.shape[0],
+                                     int(dl_lo), int(min(dl_hi, 1 << 30)), _p(out), nthreads) != 0:
             raise ValueError("oracle: bad arguments")
         return out
 

@@ -14,12 +14,15 @@ coarse data to the columns the method computes.  What it is built from:
   the root lies inside the box).  Feature l * 64 + sx + 4 sy + 16 sz is
   ln max(n, 1e-10) at offset (sx, sy, sz), zero density outside the box;
   features are then shifted and scaled, f' = (f - in_shift) / in_scale;
-* a multilayer perceptron 576 -> W -> W -> D with ReLU activations, outputs
-  the scaled log external columns y = (ln(N - N_il + EXT_FLOOR) - out_shift)
-  / out_scale, N_il the target's internal + local part (Sect. 3.2).  The
-  features are those of the target's oct (its 8 leaves share them), and so
-  is the external part (the shells are per oct); N_il is added back exactly:
-  N = N_il + max(exp(y out_scale + out_shift) - EXT_FLOOR, 0);
+* a multilayer perceptron 576 -> W -> W -> Dout with ReLU activations.  The
+  features depend on the target's level-7 ancestor only; for a network
+  serving leaf level L (8 or 9) a row of outputs holds a block of D for each
+  of the 8^(L-8) octs inside that cell, the scaled log near-shell columns
+  y = (ln(E + EXT_FLOOR) - out_shift) / out_scale, E the external sum over
+  the shells dl = 1..3 (Sect. 3.2, Eqs. 9-10; shared by the 8 leaves of an
+  oct).  The rest of the column is the method's, added back exactly:
+  N = N_il + N_far + max(exp(y out_scale + out_shift) - EXT_FLOOR, 0), N_il
+  the internal + local part, N_far the shells dl >= 4;
 * mean squared error over all outputs and Adam (Kingma & Ba 2015,
   Algorithm 1: beta1 = 0.9, beta2 = 0.999, eps = 1e-8, bias-corrected).
 
@@ -138,15 +141,27 @@ def adam_step(p: np.ndarray, g: np.ndarray, m: np.ndarray, v: np.ndarray, t: int
     return p - lr * mhat / (np.sqrt(vhat) + ADAM_EPS), m, v
 
 
-def targets(N: np.ndarray, N_il: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
-    """Scaled log external columns from the method's columns and the
-    internal + local parts."""
-    return (np.log(np.maximum(N - N_il, 0.0) + EXT_FLOOR) - out_shift) / out_scale
+def targets(E_near: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
+    """Scaled log near-shell columns (shells dl = 1..3, cm^-2)."""
+    return (np.log(E_near + EXT_FLOOR) - out_shift) / out_scale
 
 
-def columns_from_output(Y: np.ndarray, N_il: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
-    """N (cm^-2) from the network outputs and the internal + local parts."""
-    return N_il + np.maximum(np.exp(Y * out_scale + out_shift) - EXT_FLOOR, 0.0)
+def columns_from_output(Y: np.ndarray, N_exact: np.ndarray, out_shift: float, out_scale: float) -> np.ndarray:
+    """N (cm^-2) from the network outputs (one block of D) and the parts the
+    method supplies exactly (internal + local and shells dl >= 4)."""
+    return N_exact + np.maximum(np.exp(Y * out_scale + out_shift) - EXT_FLOOR, 0.0)
+
+
+def block_of(cells: np.ndarray, L: int) -> np.ndarray:
+    """Output block of each leaf's oct inside its level-7 ancestor for a
+    network of leaf level L: j = jx + s (jy + s jz), s = 2^(L-8), (jx, jy,
+    jz) the oct's offset inside the level-7 cell."""
+    n = 1 << L
+    cells = np.asarray(cells, dtype=np.int64)
+    sb = L - 8
+    m = (1 << sb) - 1
+    ox, oy, oz = (cells % n) >> 1, ((cells // n) % n) >> 1, (cells // (n * n)) >> 1
+    return (ox & m) + ((oy & m) << sb) + ((oz & m) << (2 * sb))
 
 
 def bf16_round(a: np.ndarray) -> np.ndarray:

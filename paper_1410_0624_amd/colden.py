@@ -189,6 +189,7 @@ class Tree:
                                    self.workspace.numel(), _stream(stream), C.byref(h)))
         self.h = h
         self.n_leaf = n_leaf
+        self.max_level = int(tin.max_level)
         self.max_dirs = int(max_dirs)
         self.aux = None
         if aux_stream:
@@ -334,7 +335,7 @@ SURROGATE_EXPORTS = [
     "cd_surrogate_create", "cd_surrogate_destroy", "cd_surrogate_n_params", "cd_surrogate_get_params",
     "cd_surrogate_set_params", "cd_surrogate_features", "cd_surrogate_targets", "cd_surrogate_forward", "cd_surrogate_gradients",
     "cd_surrogate_train_step", "cd_surrogate_infer", "cd_surrogate_check_fallback", "cd_surrogate_save",
-    "cd_surrogate_load",
+    "cd_surrogate_load", "cd_surrogate_info", "cd_surrogate_row_targets", "cd_surrogate_train_step_rows",
 ]
 EXPORTS += SURROGATE_EXPORTS
 N_FEAT = 576
@@ -345,17 +346,20 @@ def _surr_types():
     if getattr(L, "_surr_typed", False):
         return L
     P, I, I64, D, F = C.c_void_p, C.c_int, C.c_int64, C.c_double, C.c_float
-    L.cd_surrogate_create.argtypes = [I, I, I, C.c_uint64, P, P]
+    L.cd_surrogate_create.argtypes = [I, I, I, I, C.c_uint64, P, P]
+    L.cd_surrogate_info.argtypes = [P, P]
+    L.cd_surrogate_row_targets.argtypes = [P, P, P, P, P]
+    L.cd_surrogate_train_step_rows.argtypes = [P, P, P, P, I64, F, P, P]
     L.cd_surrogate_destroy.argtypes = [P]
     L.cd_surrogate_destroy.restype = None
     L.cd_surrogate_n_params.argtypes = [P, P]
     L.cd_surrogate_get_params.argtypes = [P, P]
     L.cd_surrogate_set_params.argtypes = [P, P]
     L.cd_surrogate_features.argtypes = [P, P, P, I64, P, P]
-    L.cd_surrogate_targets.argtypes = [P, P, P, P, P, I64, P, P]
+    L.cd_surrogate_targets.argtypes = [P, P, P, P, I64, P, P]
     L.cd_surrogate_forward.argtypes = [P, P, I64, P, P]
     L.cd_surrogate_gradients.argtypes = [P, P, P, I64, P, P, P]
-    L.cd_surrogate_train_step.argtypes = [P, P, P, P, P, I64, F, P, P]
+    L.cd_surrogate_train_step.argtypes = [P, P, P, P, I64, F, P, P]
     L.cd_surrogate_infer.argtypes = [P, P, P, P, P, D, D, P]
     L.cd_surrogate_check_fallback.argtypes = [P, P, P, D, D, C.c_uint64, P, P, D, D, P, P, P, P]
     L.cd_surrogate_save.argtypes = [P, C.c_char_p]
@@ -372,28 +376,32 @@ def _dev_i64(t, name: str = "cells", numel=None):
 
 
 class Surrogate:
-    """cd_surrogate handle: ReLU MLP 576 -> width -> width -> D on the
-    pyramid features, trained and run by the library's kernels."""
+    """cd_surrogate handle: ReLU MLP 576 -> width -> width -> Dout on the
+    pyramid features of a level-7 cell, Dout = D for each of the
+    8^(leaf_level - 8) octs inside it; trained and run by the library's
+    kernels."""
+
+    ROWS = 1 << 21  # level-7 cells
 
     def __init__(self, D: int = 12, width: int = 256, precision: int = CD_SURR_BF16, seed: int = 0,
-                 norm=(0.0, 1.0, 0.0, 1.0), _handle=None):
+                 norm=(0.0, 1.0, 0.0, 1.0), leaf_level: int = 8, _handle=None):
         L = _surr_types()
         if _handle is None:
             nrm = np.asarray(norm, dtype=np.float32)
             h = C.c_void_p()
-            _check(L.cd_surrogate_create(D, width, precision, seed, _np(nrm), C.byref(h)))
+            _check(L.cd_surrogate_create(D, leaf_level, width, precision, seed, _np(nrm), C.byref(h)))
             _handle = h
         self.h = _handle
-        self.D, self.width, self.precision = D, width, precision
+        info = np.zeros(5, np.int32)
+        _check(L.cd_surrogate_info(self.h, _np(info)))
+        self.D, self.leaf_level, self.width, self.precision, self.Dout = (int(v) for v in info)
 
     @classmethod
     def load(cls, path: str) -> "Surrogate":
         L = _surr_types()
         h = C.c_void_p()
         _check(L.cd_surrogate_load(path.encode(), C.byref(h)))
-        s = cls(_handle=h)
-        s.D = s.width = None  # as stored in the file
-        return s
+        return cls(_handle=h)
 
     def save(self, path: str):
         _check(_surr_types().cd_surrogate_save(self.h, path.encode()))
@@ -425,17 +433,24 @@ class Surrogate:
                                                    self._rows(X, "X", n, N_FEAT), _stream(stream)))
         return X
 
-    def targets(self, tree: Tree, w: Weights, N, cells, T, stream=None):
+    def targets(self, tree: Tree, w: Weights, cells, T, stream=None):
+        """Scaled near-shell targets of the level-7 cells of `cells` into T [n, Dout]."""
         n = int(cells.numel())
-        _check(_surr_types().cd_surrogate_targets(self.h, tree.h, w.h, _dev_f32(N, "N", shape=(tree.n_leaf, w.D)),
-                                                  _dev_i64(cells), n, self._rows(T, "T", n, self.D),
-                                                  _stream(stream)))
+        _check(_surr_types().cd_surrogate_targets(self.h, tree.h, w.h, _dev_i64(cells), n,
+                                                  self._rows(T, "T", n, self.Dout), _stream(stream)))
         return T
+
+    def row_targets(self, tree: Tree, w: Weights, T_rows, stream=None):
+        """Unscaled near-shell targets of every level-7 cell into T_rows [2^21, Dout]."""
+        _check(_surr_types().cd_surrogate_row_targets(self.h, tree.h, w.h,
+                                                      self._rows(T_rows, "T_rows", self.ROWS, self.Dout),
+                                                      _stream(stream)))
+        return T_rows
 
     def forward(self, X, Y, stream=None):
         n = int(X.shape[0]) if X.dim() == 2 else -1
         _check(_surr_types().cd_surrogate_forward(self.h, self._rows(X, "X", n, N_FEAT), n,
-                                                  self._rows(Y, "Y", n, self.D), _stream(stream)))
+                                                  self._rows(Y, "Y", n, self.Dout), _stream(stream)))
         return Y
 
     def gradients(self, X, T, stream=None):
@@ -443,16 +458,25 @@ class Surrogate:
         loss = C.c_float(0)
         n = int(X.shape[0]) if X.dim() == 2 else -1
         _check(_surr_types().cd_surrogate_gradients(self.h, self._rows(X, "X", n, N_FEAT),
-                                                    self._rows(T, "T", n, self.D), n, _np(g),
+                                                    self._rows(T, "T", n, self.Dout), n, _np(g),
                                                     C.byref(loss), _stream(stream)))
         return g, loss.value
 
-    def train_step(self, tree: Tree, w: Weights, N, cells, lr: float, want_loss: bool = False, stream=None):
+    def train_step(self, tree: Tree, w: Weights, cells, lr: float, want_loss: bool = False, stream=None):
         loss = C.c_float(0)
-        _check(_surr_types().cd_surrogate_train_step(self.h, tree.h, w.h,
-                                                     _dev_f32(N, "N", shape=(tree.n_leaf, w.D)), _dev_i64(cells),
+        _check(_surr_types().cd_surrogate_train_step(self.h, tree.h, w.h, _dev_i64(cells),
                                                      int(cells.numel()), float(lr),
                                                      C.byref(loss) if want_loss else None, _stream(stream)))
+        return loss.value if want_loss else None
+
+    def train_step_rows(self, tree: Tree, T_rows, rows, lr: float, want_loss: bool = False, stream=None):
+        """Adam step on level-7 cells `rows` (int64), features from `tree`,
+        targets from a row_targets table."""
+        loss = C.c_float(0)
+        _check(_surr_types().cd_surrogate_train_step_rows(self.h, tree.h,
+                                                          self._rows(T_rows, "T_rows", self.ROWS, self.Dout),
+                                                          _dev_i64(rows), int(rows.numel()), float(lr),
+                                                          C.byref(loss) if want_loss else None, _stream(stream)))
         return loss.value if want_loss else None
 
     def infer(self, tree: Tree, w: Weights, N, chi=None, av_per_nh: float = AV_PER_NH, gamma: float = GAMMA,

@@ -1,9 +1,11 @@
-// Learned surrogate of the column sweep: features from the pyramid, a ReLU
-// MLP 576 -> W -> W -> D trained with Adam, batched inference, and a sampled
-// check with the method itself as fallback.  Every step runs in the kernels
-// below: feature gather, a strided GEMM (bfloat16 on the matrix cores or
-// FP32 on the vector units) with bias / ReLU / mask epilogues, the loss and
-// its gradient, column sums, the Adam update and the output transform.
+// Learned surrogate of the method's near shells: features from the pyramid,
+// a ReLU MLP 576 -> W -> W -> Dout trained with Adam, batched inference, and
+// a sampled check with the method itself as fallback.  Every step runs in
+// the kernels below: feature gather, targets from the method's near-shell
+// rows, a strided GEMM (bfloat16, or FP32 split into bfloat16 hi + lo, on
+// the matrix cores; FP32 on the vector units) with bias / ReLU / mask
+// epilogues, the loss and its gradient, column sums, the Adam update, and a
+// tiled bfloat16 GEMM for inference whose rows feed the method's row kernel.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,38 +21,9 @@ constexpr int kFeat = kFeatLevels * 64;  // 576
 constexpr float kFloor = 1e-10f;
 constexpr float kExtFloor = 1e17f;  // cm^-2 added to the external column before the logarithm
 
-// The network predicts the external part of the column (shells dl >= 1,
-// shared by the 8 leaves of an oct, like the features); the internal + local
-// part (Sect. 3.2) is computed exactly from the oct's densities.
-struct IlArgs {
-    const float* leaf;  // [n^3] row-major
-    const float* kloc;  // [8 target octant][8 oct cell][D]
-    int L, D;
-    float dxL;
-};
-
-// the oct densities of leaf q and its octant in the oct
-struct OctCells {
-    float n[8];
-    int o;
-};
-__device__ __forceinline__ OctCells oct_cells(const IlArgs& a, int64_t q) {
-    const int64_t n = (int64_t)1 << a.L;
-    const int64_t x = q & (n - 1), y = (q >> a.L) & (n - 1), z = q >> (2 * a.L);
-    OctCells c;
-    c.o = (int)((x & 1) | ((y & 1) << 1) | ((z & 1) << 2));
-#pragma unroll
-    for (int s = 0; s < 8; ++s)
-        c.n[s] = a.leaf[(((z & ~1LL) + (s >> 2)) * n + (y & ~1LL) + ((s >> 1) & 1)) * n + (x & ~1LL) + (s & 1)];
-    return c;
-}
-// internal + local part of that leaf for direction d
-__device__ __forceinline__ float internal_local(const IlArgs& a, const OctCells& c, int d) {
-    float acc = 0.f;
-#pragma unroll
-    for (int s = 0; s < 8; ++s) acc = fmaf(c.n[s], a.kloc[(c.o * 8 + s) * a.D + d], acc);
-    return a.dxL * acc;
-}
+// The network predicts the near shells dl = 1..3 of the external sum
+// (Sect. 3.2, Eqs. 9-10) per oct; the method supplies the rest exactly: the
+// internal + local part and the shells dl >= 4 (its coarse tables).
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
@@ -72,17 +45,31 @@ __device__ __forceinline__ uint16_t from_f<uint16_t>(float x) { return f2bf(x); 
 struct FeatArgs {
     const float* lev[kFeatLevels];  // level l < L: padded pyramid level; l == L: the leaves
     int L;
-    const int64_t* cells;  // leaf indices, or nullptr: c0 + i
+    const int64_t* cells;  // leaf indices (l7rows: level-7 cell indices), or nullptr: c0 + i
     int64_t c0, n;
-    int l7rows;            // rows are level-7 cells c0 + i (x fastest), read through their first leaf
+    int l7rows;            // rows are level-7 cells (x fastest), read through their first leaf
     int logged;            // lev[l] (every l) are padded arrays of the finished scaled feature values
     float shift, inv_scale;
 };
 
 // The features of a leaf depend only on its level-7 ancestor (the finest
 // stencil, level 8, is centred on it), so the network runs once per level-7
-// cell and its leaves share the row.
+// cell.  A network serves grids of one leaf level L (8 or 9): its output row
+// holds the external columns of every oct (level L-1 cell) inside the
+// level-7 cell, 8^(L-8) blocks of D (block index x fastest), so at 2^9 each
+// of the 8 octs of a row gets its own shells.
 constexpr int kRowLevel = 7;
+
+// the sub-oct block of oct (ox, oy, oz) (level L-1 indices) inside its
+// level-7 ancestor, sb = L - 8 bits per axis
+__device__ __forceinline__ int64_t sub_block(int64_t ox, int64_t oy, int64_t oz, int sb) {
+    const int64_t m = ((int64_t)1 << sb) - 1;
+    return (ox & m) + ((oy & m) << sb) + ((oz & m) << (2 * sb));
+}
+// row-major index of the level-7 ancestor of oct (ox, oy, oz) at level L-1
+__device__ __forceinline__ int64_t row7_of_oct(int64_t ox, int64_t oy, int64_t oz, int sb) {
+    return (((oz >> sb) << kRowLevel) + (oy >> sb)) * ((int64_t)1 << kRowLevel) + (ox >> sb);
+}
 
 // One thread per feature value (row, level, stencil cell): a wave writes the
 // 64 values of one (row, level) contiguously and reads one 4^3 stencil.
@@ -97,8 +84,11 @@ __global__ __launch_bounds__(256) void k_features(const FeatArgs a, T* __restric
     const int64_t nL = (int64_t)1 << L;
     int64_t q;
     if (a.l7rows) {
-        const int64_t r = a.c0 + i, sh7 = L - kRowLevel, m = (int64_t)1 << kRowLevel;
-        q = (((r >> (2 * kRowLevel)) << sh7) * nL + (((r >> kRowLevel) & (m - 1)) << sh7)) * nL + ((r & (m - 1)) << sh7);
+        const int64_t r = a.cells ? a.cells[i] : a.c0 + i, sh7 = L - kRowLevel, m = (int64_t)1 << kRowLevel;
+        q = (r < 0 || r >= m * m * m)
+                ? -1
+                : (((r >> (2 * kRowLevel)) << sh7) * nL + (((r >> kRowLevel) & (m - 1)) << sh7)) * nL +
+                      ((r & (m - 1)) << sh7);
     } else {
         q = a.cells ? a.cells[i] : a.c0 + i;
     }
@@ -199,21 +189,51 @@ __global__ void k_convert(const float* __restrict__ in, int64_t n, T* __restrict
     if (i < n) out[i] = from_f<T>(in[i]);
 }
 
-// targets: scaled ln of the external part of the method's columns for the
-// listed leaves (one thread per leaf)
-__global__ void k_targets(const IlArgs il, const float* __restrict__ N, const int64_t* __restrict__ cells,
-                          int64_t n, int64_t n_leaf, float shift, float inv_scale, float* __restrict__ T) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    const int D = il.D;
-    const int64_t q = cells[r];
-    if (q < 0 || q >= n_leaf) {
-        for (int d = 0; d < D; ++d) T[r * D + d] = __builtin_nanf("");
-        return;
+// Targets: scaled ln of the method's near shells dl = 1..3, E[oct][D] (the
+// tiled external kernel's rows, oct index row-major at level L-1).  Listed
+// leaf q (cells) stands for the row of its level-7 ancestor, cells ==
+// nullptr: row r is level-7 cell r.  T[r][j D + d] holds oct j of the row
+// (j = jx + 2^sb (jy + 2^sb jz), sb = L - 8).  One thread per row and oct.
+__global__ void k_targets(const float* __restrict__ E, int L, int D, const int64_t* __restrict__ cells, int64_t n,
+                          int64_t n_leaf, float shift, float inv_scale, float* __restrict__ T) {
+    const int sb = L - 8, per = 1 << (3 * sb);
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * per) return;
+    const int64_t r = idx / per;
+    const int j = (int)(idx % per);
+    float* out = T + r * ((int64_t)per * D) + (int64_t)j * D;
+    const int64_t nL = (int64_t)1 << L, m = (int64_t)1 << kRowLevel;
+    int64_t r7 = r;
+    if (cells) {
+        const int64_t q = cells[r];
+        if (q < 0 || q >= n_leaf) {
+            for (int d = 0; d < D; ++d) out[d] = __builtin_nanf("");
+            return;
+        }
+        const int sh = L - kRowLevel;
+        const int64_t x = q & (nL - 1), y = (q >> L) & (nL - 1), z = q >> (2 * L);
+        r7 = ((z >> sh) * m + (y >> sh)) * m + (x >> sh);
     }
-    const OctCells oc = oct_cells(il, q);
-    for (int d = 0; d < D; ++d)
-        T[r * D + d] = (logf(fmaxf(N[q * D + d] - internal_local(il, oc, d), 0.f) + kExtFloor) - shift) * inv_scale;
+    const int64_t msk = ((int64_t)1 << sb) - 1;
+    const int64_t ox = ((r7 & (m - 1)) << sb) + (j & msk);
+    const int64_t oy = (((r7 >> kRowLevel) & (m - 1)) << sb) + ((j >> sb) & msk);
+    const int64_t oz = ((r7 >> (2 * kRowLevel)) << sb) + (j >> (2 * sb));
+    const int L1 = L - 1;
+    const float* e = E + (((oz << L1) + oy) << L1) * D + ox * D;
+    for (int d = 0; d < D; ++d) out[d] = (logf(e[d] + kExtFloor) - shift) * inv_scale;
+}
+
+// Scaled targets of listed level-7 rows from a table of unscaled rows
+// (T_rows[2^21][dout] = ln(N_ext + 1e17)); a row outside the grid gives NaN.
+__global__ void k_gather_targets(const float* __restrict__ Trows, const int64_t* __restrict__ rows, int64_t n,
+                                 int dout, float shift, float inv_scale, float* __restrict__ T) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * dout) return;
+    const int64_t i = idx / dout;
+    const int k = (int)(idx % dout);
+    const int64_t r = rows[i];
+    const int64_t nr = (int64_t)1 << (3 * kRowLevel);
+    T[idx] = (r < 0 || r >= nr) ? __builtin_nanf("") : (Trows[r * dout + k] - shift) * inv_scale;
 }
 
 // -------------------------------------------------------------------- GEMM --
@@ -351,10 +371,77 @@ __global__ __launch_bounds__(256) void k_gemm_f32(const GemmArgs<float> g) {
         for (int j = 0; j < 4; ++j) gemm_store<float>(g, m0 + 4 * tm + i, n0 + 4 * tn + j, acc[i][j]);
 }
 
+// FP32 operands on the matrix cores: each operand x split into bfloat16
+// hi = bf16(x) and lo = bf16(x - hi) (x - hi is exact in FP32), and
+// A B = Ahi Bhi + Ahi Blo + Alo Bhi with FP32 accumulation (Alo Blo is
+// below 2^-16 of a product): about 16 significant bits per operand, the
+// training path of the bfloat16 network.  Layout as k_gemm_bf16.
+__global__ __launch_bounds__(256) void k_gemm_split(const GemmArgs<float> g) {
+    __shared__ __attribute__((aligned(16))) uint16_t Ah[kGT][kGP];
+    __shared__ __attribute__((aligned(16))) uint16_t Al[kGT][kGP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bh[kGT][kGP];
+    __shared__ __attribute__((aligned(16))) uint16_t Bl[kGT][kGP];
+    const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int r = lane & 15, grp = lane >> 4;
+    const bool a_kfast = g.sak == 1, b_nfast = g.sbn == 1;
+    f32x4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < (kGT * kGK) / 256; ++rr) {
+            const int e = tid + 256 * rr;
+            const int m = a_kfast ? e / kGK : e % kGT, k = a_kfast ? e % kGK : e / kGT;
+            const int64_t gm = m0 + m, gk = k0 + k;
+            const float av = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : 0.f;
+            const uint16_t ah = f2bf(av);
+            Ah[m][k] = ah;
+            Al[m][k] = f2bf(av - bf2f(ah));
+            const int n = b_nfast ? e % kGT : e / kGK, kb = b_nfast ? e / kGT : e % kGK;
+            const int64_t gn = n0 + n, gkb = k0 + kb;
+            const float bv = (gn < g.N && gkb < g.K) ? g.B[gkb * g.sbk + gn * g.sbn] : 0.f;
+            const uint16_t bh = f2bf(bv);
+            Bh[n][kb] = bh;
+            Bl[n][kb] = f2bf(bv - bf2f(bh));
+        }
+        __syncthreads();
+        bf16x8 ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+            ah[i] = *reinterpret_cast<const bf16x8*>(&Ah[wm + 16 * i + r][8 * grp]);
+            al[i] = *reinterpret_cast<const bf16x8*>(&Al[wm + 16 * i + r][8 * grp]);
+            bh[i] = *reinterpret_cast<const bf16x8*>(&Bh[wn + 16 * i + r][8 * grp]);
+            bl[i] = *reinterpret_cast<const bf16x8*>(&Bl[wn + 16 * i + r][8 * grp]);
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+            }
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                gemm_store<float>(g, m0 + wm + 16 * i + 4 * grp + e, n0 + wn + 16 * j + r, acc[i][j][e]);
+}
+
+// split: FP32 operands through k_gemm_split instead of the vector units
 template <typename T>
-static void gemm(const GemmArgs<T>& g, hipStream_t s) {
+static void gemm(const GemmArgs<T>& g, hipStream_t s, bool split = false) {
     dim3 grid((unsigned)((g.M + kGT - 1) / kGT), (unsigned)((g.N + kGT - 1) / kGT));
     if constexpr (sizeof(T) == 2) k_gemm_bf16<<<grid, 256, 0, s>>>(g);
+    else if (split) k_gemm_split<<<grid, 256, 0, s>>>(g);
     else k_gemm_f32<<<grid, 256, 0, s>>>(g);
 }
 
@@ -442,64 +529,6 @@ __global__ void k_adam(float* __restrict__ P, const float* __restrict__ G, float
 __global__ void k_to_bf16(const float* __restrict__ P, int64_t n, uint16_t* __restrict__ Pb) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) Pb[i] = f2bf(P[i]);
-}
-
-// N = internal + local + max(exp(y out_scale + out_shift) - floor, 0) and
-// chi (Eq. 7) for every leaf, y the row of its level-7 ancestor
-__global__ void k_output(const IlArgs il, const float* __restrict__ Y7, int64_t n_leaf, float out_shift,
-                         float out_scale, float chi_scale, float* __restrict__ N, float* __restrict__ chi) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_leaf) return;
-    const int D = il.D, L = il.L, sh = L - kRowLevel;
-    const int64_t n = (int64_t)1 << L;
-    const int64_t x = i & (n - 1), y = (i >> L) & (n - 1), z = i >> (2 * L);
-    const int64_t r = (((z >> sh) << kRowLevel) + (y >> sh)) * ((int64_t)1 << kRowLevel) + (x >> sh);
-    const float* yr = Y7 + r * D;
-    const OctCells oc = oct_cells(il, i);
-    float c = 0.f;
-    for (int d = 0; d < D; ++d) {
-        const float v = internal_local(il, oc, d) + fmaxf(__expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
-        N[i * D + d] = v;
-        c += __expf(-chi_scale * v);
-    }
-    if (chi) chi[i] = c / (float)D;
-}
-
-// The same for 256 consecutive leaves per workgroup (row-major, so their rows
-// of N are contiguous): kloc in LDS, rows staged in LDS and written as
-// 16-byte stores.  D <= kOutMaxD; n_leaf a multiple of 256.
-constexpr int kOutMaxD = 48;
-__global__ __launch_bounds__(256) void k_output_tiled(const IlArgs il, const float* __restrict__ Y7, float out_shift,
-                                                      float out_scale, float chi_scale, float* __restrict__ N,
-                                                      float* __restrict__ chi) {
-    extern __shared__ float sm[];  // kloc [64 D], then rows [256 D]
-    const int D = il.D, L = il.L, sh = L - kRowLevel;
-    float* kl = sm;
-    float* st = sm + 64 * D;
-    for (int i = threadIdx.x; i < 64 * D; i += 256) kl[i] = il.kloc[i];
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * 256;
-    const int64_t i = base + threadIdx.x;
-    const int64_t n = (int64_t)1 << L;
-    const int64_t x = i & (n - 1), y = (i >> L) & (n - 1), z = i >> (2 * L);
-    const int64_t r = (((z >> sh) << kRowLevel) + (y >> sh)) * ((int64_t)1 << kRowLevel) + (x >> sh);
-    const float* yr = Y7 + r * D;
-    const OctCells oc = oct_cells(il, i);
-    const float* ko = kl + oc.o * 8 * D;
-    float c = 0.f;
-    for (int d = 0; d < D; ++d) {
-        float acc = 0.f;
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) acc = fmaf(oc.n[s2], ko[s2 * D + d], acc);
-        const float v = il.dxL * acc + fmaxf(__expf(fmaf(yr[d], out_scale, out_shift)) - kExtFloor, 0.f);
-        st[threadIdx.x * D + d] = v;
-        c += __expf(-chi_scale * v);
-    }
-    if (chi) chi[i] = c / (float)D;
-    __syncthreads();
-    float4* dst = reinterpret_cast<float4*>(N + base * D);
-    const float4* src = reinterpret_cast<const float4*>(st);
-    for (int k = threadIdx.x; k < 64 * D; k += 256) dst[k] = src[k];  // 256 D floats = 64 D float4
 }
 
 // ------------------------------------------------------- inference GEMM --
@@ -631,6 +660,8 @@ static void colsum(const float* a, int64_t rows, int cols, float* part, float* o
 // ------------------------------------------------------------------ handle --
 struct cd_surrogate {
     int D = 0, W = 0, prec = CD_SURR_BF16;
+    int L = 8;     // leaf level of the grids served
+    int Dout = 0;  // outputs per row: D for each of the 8^(L-8) octs of a level-7 cell
     float norm[4] = {0.f, 1.f, 0.f, 1.f};  // in_shift, in_scale, out_shift, out_scale
     int64_t off[7] = {0};                  // W1 b1 W2 b2 W3 b3 end
     int64_t n_params = 0;
@@ -658,13 +689,15 @@ struct cd_surrogate {
     float* loss = nullptr;
     int64_t* cells = nullptr;  // [cap] scratch index list
     float* colpart = nullptr;  // [kColChunks][max(W, D)] column-sum partials
-    float* Y7 = nullptr;       // [2^21][D] network rows of the level-7 cells (inference)
+    float* Y7 = nullptr;       // [2^21][Dout] network rows of the level-7 cells (inference)
     uint16_t* Wt = nullptr;    // transposed bfloat16 weights for the inference GEMM
 };
 
 namespace cd {
 
-static size_t esize(const cd_surrogate* s) { return s->prec == CD_SURR_BF16 ? 2 : 4; }
+// storage of the batch activations: FP32 (training runs on FP32 operands,
+// bfloat16 inference uses the first half of each buffer)
+static size_t esize(const cd_surrogate*) { return 4; }
 
 static void free_scratch(cd_surrogate* s) {
     void* bufs[] = {s->X, s->A1, s->A2, s->A1l, s->A2l, s->Y, s->Tg, s->dY, s->dYl, s->dZ2, s->dZ2l, s->dZ1,
@@ -681,7 +714,7 @@ static void free_scratch(cd_surrogate* s) {
 static int ensure_cap(cd_surrogate* s, int64_t n) {
     if (n <= s->cap) return CD_OK;
     free_scratch(s);
-    const size_t es = esize(s), W = s->W, D = s->D, nr = (size_t)n;
+    const size_t es = esize(s), W = s->W, D = s->Dout, nr = (size_t)n;
     struct {
         void** p;
         size_t bytes;
@@ -707,14 +740,22 @@ static int ensure_cap(cd_surrogate* s, int64_t n) {
 
 static bool surrogate_tree_ok(const cd_tree* t) { return t && t->uniform && t->lmax >= 8 && t->lmax <= CD_MAX_LEVEL; }
 
-static IlArgs il_args(const cd_tree* t, const cd_weights* w) {
-    IlArgs a{};
-    a.leaf = t->leaf;
-    a.kloc = w->kloc;
-    a.L = t->lmax;
-    a.D = w->D;
-    a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));
-    return a;
+int ensure_sweep_buffers(const cd_tree* t, int D);                                                        // sweep.hip
+void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
+                   const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);              // sweep.hip
+bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
+bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
+
+// The method's near shells dl = 1..3 of every oct into the tree's rows E
+static int near_shells(const cd_tree* t, const cd_weights* w, hipStream_t st, const float** E) {
+    int rc = ensure_sweep_buffers(t, w->D);
+    if (rc != CD_OK) return rc;
+    if (!launch_external_tiled(t, w, t->ext, 0, 1 << (t->lmax - 5), st)) {
+        set_error("the near-shell kernel does not take these %d directions", w->D);
+        return CD_EUNSUPPORTED;
+    }
+    *E = t->ext;
+    return CD_OK;
 }
 
 static FeatArgs feat_args(const cd_surrogate* s, const cd_tree* t) {
@@ -735,8 +776,11 @@ static void launch_features(const FeatArgs& a, T* X, hipStream_t st) {
 // for the backward pass.
 template <typename T>
 static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st, float* Yout = nullptr) {
-    const int W = s->W, D = s->D;
-    const T* Wt = s->prec == CD_SURR_BF16 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    const int W = s->W, D = s->Dout;
+    // bfloat16 operands: the rounded weights; FP32 operands: the master
+    // weights, on the matrix cores as hi + lo pairs for a bfloat16 network
+    const T* Wt = sizeof(T) == 2 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    const bool split = sizeof(T) == 4 && s->prec == CD_SURR_BF16;
     GemmArgs<T> g{};
     // layer 1: X [n][576] W1 [576][W]
     g.A = (const T*)s->X; g.sam = kFeat; g.sak = 1;
@@ -744,27 +788,28 @@ static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st, 
     g.M = n; g.N = W; g.K = kFeat;
     g.C = keep ? s->A1 : nullptr; g.Cl = (T*)s->A1l; g.ldc = W;
     g.bias = s->P + s->off[1]; g.mask = nullptr; g.relu = 1;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     // layer 2
     g.A = (const T*)s->A1l; g.sam = W;
     g.B = Wt + s->off[2];
     g.K = W;
     g.C = keep ? s->A2 : nullptr; g.Cl = (T*)s->A2l;
     g.bias = s->P + s->off[3];
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     // layer 3
     g.A = (const T*)s->A2l;
     g.B = Wt + s->off[4]; g.sbk = D;
     g.N = D;
     g.C = Yout ? Yout : s->Y; g.Cl = nullptr; g.ldc = D;
     g.bias = s->P + s->off[5]; g.relu = 0;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
 }
 
 // bfloat16 inference of n rows (n % 128 == 0, width % 128 == 0) on the tiled
-// GEMM, weights transposed into s->Wt first; rows into Yout [n][D].
+// GEMM, weights transposed into s->Wt first; rows into Yout [n][Dout].
+static int out_pad(const cd_surrogate* s) { return (s->Dout + kFT - 1) / kFT * kFT; }
 static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float* Yout) {
-    const int W = s->W, D = s->D, npad3 = 128;
+    const int W = s->W, D = s->Dout, ntn3 = out_pad(s) / kFT;
     const uint16_t* X = (const uint16_t*)s->X;
     uint16_t* W1t = s->Wt;
     uint16_t* W2t = W1t + (int64_t)W * kFeat;
@@ -774,15 +819,19 @@ static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float*
     k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat, ntn);
     k_gemm_bf16_nt<<<g1, 256, 0, st>>>((const uint16_t*)s->A1l, W2t, s->P + s->off[3], 1, (uint16_t*)s->A2l, nullptr,
                                        W, W, W, ntn);
-    const unsigned g3 = (unsigned)(n / kFT);
-    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W, 1);
+    const unsigned g3 = (unsigned)(n / kFT * ntn3);
+    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W,
+                                       ntn3);
 }
 
 // Loss, gradient into s->G (targets in s->Tg, activations kept).
 template <typename T>
 static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
-    const int W = s->W, D = s->D;
-    const T* Wt = s->prec == CD_SURR_BF16 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    const int W = s->W, D = s->Dout;
+    // bfloat16 operands: the rounded weights; FP32 operands: the master
+    // weights, on the matrix cores as hi + lo pairs for a bfloat16 network
+    const T* Wt = sizeof(T) == 2 ? (const T*)(const void*)s->Pb : (const T*)(const void*)s->P;
+    const bool split = sizeof(T) == 4 && s->prec == CD_SURR_BF16;
     const int64_t nd = n * D;
     const unsigned nb = nblk(nd);
     k_mse<T><<<nb, 256, 0, st>>>(s->Y, s->Tg, nd, s->dY, (T*)s->dYl, s->part);
@@ -793,33 +842,33 @@ static void backward_rows(cd_surrogate* s, int64_t n, hipStream_t st) {
     g.B = (const T*)s->dYl; g.sbk = D; g.sbn = 1;
     g.M = W; g.N = D; g.K = n;
     g.C = s->G + s->off[4]; g.Cl = nullptr; g.ldc = D;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     colsum(s->dY, n, D, s->colpart, s->G + s->off[5], st);
     // dZ2 = (dY W3^T) * (A2 > 0): [n][W]
     g.A = (const T*)s->dYl; g.sam = D; g.sak = 1;
     g.B = Wt + s->off[4]; g.sbk = 1; g.sbn = D;
     g.M = n; g.N = W; g.K = D;
     g.C = s->dZ2; g.Cl = (T*)s->dZ2l; g.ldc = W; g.mask = s->A2;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     // dW2 = A1^T dZ2
     g.A = (const T*)s->A1l; g.sam = 1; g.sak = W;
     g.B = (const T*)s->dZ2l; g.sbk = W; g.sbn = 1;
     g.M = W; g.N = W; g.K = n;
     g.C = s->G + s->off[2]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     colsum(s->dZ2, n, W, s->colpart, s->G + s->off[3], st);
     // dZ1 = (dZ2 W2^T) * (A1 > 0)
     g.A = (const T*)s->dZ2l; g.sam = W; g.sak = 1;
     g.B = Wt + s->off[2]; g.sbk = 1; g.sbn = W;
     g.M = n; g.N = W; g.K = W;
     g.C = s->dZ1; g.Cl = (T*)s->dZ1l; g.ldc = W; g.mask = s->A1;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     // dW1 = X^T dZ1: [576][W]
     g.A = (const T*)s->X; g.sam = 1; g.sak = kFeat;
     g.B = (const T*)s->dZ1l; g.sbk = W; g.sbn = 1;
     g.M = kFeat; g.N = W; g.K = n;
     g.C = s->G + s->off[0]; g.Cl = nullptr; g.ldc = W; g.mask = nullptr;
-    gemm<T>(g, st);
+    gemm<T>(g, st, split);
     colsum(s->dZ1, n, W, s->colpart, s->G + s->off[1], st);
 }
 
@@ -849,12 +898,13 @@ using namespace cd;
         }                             \
     } while (0)
 
-extern "C" int cd_surrogate_create(int D, int width, int precision, uint64_t seed, const float* norm,
+extern "C" int cd_surrogate_create(int D, int leaf_level, int width, int precision, uint64_t seed, const float* norm,
                                    cd_surrogate** out) {
     clear_error();
     SURR_CHECK(out, "cd_surrogate_create: NULL output");
     *out = nullptr;
     SURR_CHECK(D >= 1 && D <= CD_MAX_DIRS, "cd_surrogate_create: D = %d outside 1..%d", D, CD_MAX_DIRS);
+    SURR_CHECK(leaf_level == 8 || leaf_level == 9, "cd_surrogate_create: leaf level %d (8 or 9)", leaf_level);
     SURR_CHECK(width >= 16 && width <= 1024 && width % 16 == 0, "cd_surrogate_create: width %d", width);
     SURR_CHECK(precision == CD_SURR_FP32 || precision == CD_SURR_BF16, "cd_surrogate_create: precision %d",
                precision);
@@ -862,17 +912,20 @@ extern "C" int cd_surrogate_create(int D, int width, int precision, uint64_t see
                "cd_surrogate_create: bad normalisation");
     cd_surrogate* s = new cd_surrogate();
     s->D = D;
+    s->L = leaf_level;
+    s->Dout = D << (3 * (leaf_level - 8));
     s->W = width;
     s->prec = precision;
     if (norm) std::memcpy(s->norm, norm, sizeof(s->norm));
-    const int64_t sizes[6] = {(int64_t)kFeat * width, width, (int64_t)width * width, width, (int64_t)width * D, D};
+    const int64_t sizes[6] = {(int64_t)kFeat * width, width, (int64_t)width * width, width, (int64_t)width * s->Dout,
+                              s->Dout};
     for (int i = 0; i < 6; ++i) s->off[i + 1] = s->off[i] + sizes[i];
     s->n_params = s->off[6];
     // He-uniform weights (ReLU fan-in), Glorot-uniform output layer, zero biases
     std::vector<float> h((size_t)s->n_params, 0.f);
     uint64_t c = seed;
     auto uni = [&c]() { return (double)(splitmix64(c++) >> 11) * 0x1.0p-53; };
-    const double lim[3] = {std::sqrt(6.0 / kFeat), std::sqrt(6.0 / width), std::sqrt(6.0 / (width + D))};
+    const double lim[3] = {std::sqrt(6.0 / kFeat), std::sqrt(6.0 / width), std::sqrt(6.0 / (width + s->Dout))};
     for (int layer = 0; layer < 3; ++layer)
         for (int64_t i = s->off[2 * layer]; i < s->off[2 * layer + 1]; ++i)
             h[(size_t)i] = (float)((2.0 * uni() - 1.0) * lim[layer]);
@@ -954,7 +1007,7 @@ static int forward_impl(cd_surrogate* s, const float* X, int64_t n, float* Y, hi
     if (rc != CD_OK) return rc;
     k_convert<T><<<nblk(n * kFeat), 256, 0, st>>>(X, n * kFeat, (T*)s->X);
     forward_rows<T>(s, n, false, st);
-    CD_HIP(hipMemcpyAsync(Y, s->Y, (size_t)n * s->D * 4, hipMemcpyDeviceToDevice, st));
+    CD_HIP(hipMemcpyAsync(Y, s->Y, (size_t)n * s->Dout * 4, hipMemcpyDeviceToDevice, st));
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
@@ -973,7 +1026,7 @@ static int grad_impl(cd_surrogate* s, const float* X, const float* Tg, int64_t n
     int rc = ensure_cap(s, n);
     if (rc != CD_OK) return rc;
     k_convert<T><<<nblk(n * kFeat), 256, 0, st>>>(X, n * kFeat, (T*)s->X);
-    CD_HIP(hipMemcpyAsync(s->Tg, Tg, (size_t)n * s->D * 4, hipMemcpyDeviceToDevice, st));
+    CD_HIP(hipMemcpyAsync(s->Tg, Tg, (size_t)n * s->Dout * 4, hipMemcpyDeviceToDevice, st));
     forward_rows<T>(s, n, true, st);
     backward_rows<T>(s, n, st);
     CD_HIP(hipGetLastError());
@@ -985,8 +1038,7 @@ extern "C" int cd_surrogate_gradients(cd_surrogate* s, const float* X_dev, const
     clear_error();
     SURR_CHECK(s && X_dev && T_dev && grad && n > 0, "cd_surrogate_gradients: bad arguments");
     hipStream_t st = (hipStream_t)stream;
-    int rc = s->prec == CD_SURR_BF16 ? grad_impl<uint16_t>(s, X_dev, T_dev, n, st)
-                                     : grad_impl<float>(s, X_dev, T_dev, n, st);
+    int rc = grad_impl<float>(s, X_dev, T_dev, n, st);
     if (rc != CD_OK) return rc;
     CD_HIP(hipStreamSynchronize(st));
     CD_HIP(hipMemcpy(grad, s->G, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
@@ -994,29 +1046,75 @@ extern "C" int cd_surrogate_gradients(cd_surrogate* s, const float* X_dev, const
     return CD_OK;
 }
 
-extern "C" int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N_dev,
+static int leaf_level_ok(const cd_surrogate* s, const cd_tree* t, const char* fn) {
+    SURR_CHECK(surrogate_tree_ok(t), "%s: the surrogate needs a uniform grid with 2^L >= 256", fn);
+    SURR_CHECK(t->lmax == s->L, "%s: a network for 2^%d grids on a 2^%d grid", fn, s->L, t->lmax);
+    return CD_OK;
+}
+
+// weights the method's parts need: FP32, precalculated, the network's D
+static int weights_ok(const cd_surrogate* s, const cd_tree* t, const cd_weights* w, const char* fn) {
+    SURR_CHECK(w->precision == CD_FP32 && w->mode == CD_PRECALC73 && w->D == s->D,
+               "%s: needs FP32 precalculated weights of D = %d", fn, s->D);
+    if (!tiled_supported(t, w)) {
+        set_error("%s: the near-shell kernel does not take these %d directions", fn, w->D);
+        return CD_EUNSUPPORTED;
+    }
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_targets(const cd_surrogate* s, const cd_tree* t, const cd_weights* w,
                                     const int64_t* cells_dev, int64_t n, float* T_dev, void* stream) {
     clear_error();
-    SURR_CHECK(s && t && w && N_dev && T_dev && (cells_dev || n == 0) && n >= 0, "cd_surrogate_targets: bad arguments");
-    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_targets: the surrogate needs a uniform grid with 2^L >= 256");
-    SURR_CHECK(w->D == s->D, "cd_surrogate_targets: weights of D = %d for a network of D = %d", w->D, s->D);
-    if (n == 0) return CD_OK;
-    k_targets<<<nblk(n), 256, 0, (hipStream_t)stream>>>(il_args(t, w), N_dev, cells_dev, n, t->n_leaf, s->norm[2],
-                                                        1.f / s->norm[3], T_dev);
+    SURR_CHECK(s && t && w && T_dev && (cells_dev || n == 0) && n >= 0, "cd_surrogate_targets: bad arguments");
+    int rc = leaf_level_ok(s, t, "cd_surrogate_targets");
+    if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_targets");
+    if (rc != CD_OK || n == 0) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const float* E = nullptr;
+    if ((rc = near_shells(t, w, st, &E)) != CD_OK) return rc;
+    const int64_t per = s->Dout / s->D;
+    k_targets<<<nblk(n * per), 256, 0, st>>>(E, t->lmax, s->D, cells_dev, n, t->n_leaf, s->norm[2],
+                                             1.f / s->norm[3], T_dev);
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
 
+extern "C" int cd_surrogate_row_targets(const cd_surrogate* s, const cd_tree* t, const cd_weights* w,
+                                        float* T_rows_dev, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && T_rows_dev, "cd_surrogate_row_targets: NULL argument");
+    int rc = leaf_level_ok(s, t, "cd_surrogate_row_targets");
+    if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_row_targets");
+    if (rc != CD_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const float* E = nullptr;
+    if ((rc = near_shells(t, w, st, &E)) != CD_OK) return rc;
+    const int64_t rows = (int64_t)1 << (3 * kRowLevel), per = s->Dout / s->D;
+    k_targets<<<nblk(rows * per), 256, 0, st>>>(E, t->lmax, s->D, nullptr, rows, t->n_leaf, 0.f, 1.f, T_rows_dev);
+    CD_HIP(hipGetLastError());
+    return CD_OK;
+}
+
+// one step: targets from the near-shell rows E (cells are leaves) or from a
+// table of unscaled row targets Trows (cells are level-7 cells)
 template <typename T>
-static int train_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N, const int64_t* cells,
+static int train_impl(cd_surrogate* s, const cd_tree* t, const float* E, const int64_t* cells, const float* Trows,
                       int64_t n, float lr, hipStream_t st) {
     int rc = ensure_cap(s, n);
     if (rc != CD_OK) return rc;
     FeatArgs a = feat_args(s, t);
     a.cells = cells;
     a.n = n;
+    if (Trows) {
+        a.l7rows = 1;
+        k_gather_targets<<<nblk(n * s->Dout), 256, 0, st>>>(Trows, cells, n, s->Dout, s->norm[2], 1.f / s->norm[3],
+                                                           s->Tg);
+    } else {
+        k_targets<<<nblk(n * (s->Dout / s->D)), 256, 0, st>>>(E, t->lmax, s->D, cells, n, t->n_leaf, s->norm[2],
+                                                              1.f / s->norm[3], s->Tg);
+    }
     launch_features<T>(a, (T*)s->X, st);
-    k_targets<<<nblk(n), 256, 0, st>>>(il_args(t, w), N, cells, n, t->n_leaf, s->norm[2], 1.f / s->norm[3], s->Tg);
     forward_rows<T>(s, n, true, st);
     backward_rows<T>(s, n, st);
     adam(s, lr, st);
@@ -1024,20 +1122,47 @@ static int train_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, co
     return CD_OK;
 }
 
-extern "C" int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* t, const cd_weights* w, const float* N_dev,
-                                       const int64_t* cells_dev, int64_t batch, float lr, float* loss, void* stream) {
-    clear_error();
-    SURR_CHECK(s && t && w && N_dev && cells_dev && batch > 0 && lr > 0, "cd_surrogate_train_step: bad arguments");
-    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_train_step: the surrogate needs a uniform grid with 2^L >= 256");
-    SURR_CHECK(w->D == s->D, "cd_surrogate_train_step: weights of D = %d for a network of D = %d", w->D, s->D);
-    hipStream_t st = (hipStream_t)stream;
-    int rc = s->prec == CD_SURR_BF16 ? train_impl<uint16_t>(s, t, w, N_dev, cells_dev, batch, lr, st)
-                                     : train_impl<float>(s, t, w, N_dev, cells_dev, batch, lr, st);
-    if (rc != CD_OK) return rc;
+static int finish_step(cd_surrogate* s, float* loss, hipStream_t st) {
     if (loss) {
         CD_HIP(hipMemcpyAsync(loss, s->loss, 4, hipMemcpyDeviceToHost, st));
         CD_HIP(hipStreamSynchronize(st));
     }
+    return CD_OK;
+}
+
+extern "C" int cd_surrogate_train_step(cd_surrogate* s, const cd_tree* t, const cd_weights* w,
+                                       const int64_t* cells_dev, int64_t batch, float lr, float* loss, void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && w && cells_dev && batch > 0 && lr > 0, "cd_surrogate_train_step: bad arguments");
+    int rc = leaf_level_ok(s, t, "cd_surrogate_train_step");
+    if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_train_step");
+    if (rc != CD_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const float* E = nullptr;
+    if ((rc = near_shells(t, w, st, &E)) != CD_OK) return rc;
+    rc = train_impl<float>(s, t, E, cells_dev, nullptr, batch, lr, st);
+    return rc != CD_OK ? rc : finish_step(s, loss, st);
+}
+
+extern "C" int cd_surrogate_train_step_rows(cd_surrogate* s, const cd_tree* t, const float* T_rows_dev,
+                                            const int64_t* rows_dev, int64_t batch, float lr, float* loss,
+                                            void* stream) {
+    clear_error();
+    SURR_CHECK(s && t && T_rows_dev && rows_dev && batch > 0 && lr > 0, "cd_surrogate_train_step_rows: bad arguments");
+    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_train_step_rows: the features need a uniform grid with 2^L >= 256");
+    hipStream_t st = (hipStream_t)stream;
+    int rc = train_impl<float>(s, t, nullptr, rows_dev, T_rows_dev, batch, lr, st);
+    return rc != CD_OK ? rc : finish_step(s, loss, st);
+}
+
+extern "C" int cd_surrogate_info(const cd_surrogate* s, int32_t* info) {
+    clear_error();
+    SURR_CHECK(s && info, "cd_surrogate_info: NULL argument");
+    info[0] = s->D;
+    info[1] = s->L;
+    info[2] = s->W;
+    info[3] = s->prec;
+    info[4] = s->Dout;
     return CD_OK;
 }
 
@@ -1047,27 +1172,28 @@ bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y
 }
 
 template <typename T>
-static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
+static int infer_impl(cd_surrogate* s, cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
                       hipStream_t st) {
     const int64_t rows = (int64_t)1 << (3 * kRowLevel);  // level-7 cells
     const int64_t batch = (int64_t)1 << 20;
     int rc = ensure_cap(s, batch);
+    if (rc == CD_OK) rc = ensure_sweep_buffers(t, w->D);
     if (rc != CD_OK) return rc;
-    if (!s->Y7 && hipMalloc((void**)&s->Y7, (size_t)rows * s->D * 4) != hipSuccess) {
+    if (!s->Y7 && hipMalloc((void**)&s->Y7, (size_t)rows * s->Dout * 4) != hipSuccess) {
         set_error("hipMalloc of the network rows failed");
         return CD_ENOMEM;
     }
     const bool fast = sizeof(T) == 2 && s->W % kFT == 0;
     if (fast) {
-        const int W = s->W;
-        const int64_t wt = (int64_t)W * kFeat + (int64_t)W * W + (int64_t)128 * W;
+        const int W = s->W, np3 = out_pad(s);
+        const int64_t wt = (int64_t)W * kFeat + (int64_t)W * W + (int64_t)np3 * W;
         if (!s->Wt && hipMalloc((void**)&s->Wt, (size_t)wt * 2) != hipSuccess) {
             set_error("hipMalloc of the transposed weights failed");
             return CD_ENOMEM;
         }
         k_transpose_pad<<<nblk((int64_t)W * kFeat), 256, 0, st>>>(s->Pb + s->off[0], kFeat, W, W, s->Wt);
         k_transpose_pad<<<nblk((int64_t)W * W), 256, 0, st>>>(s->Pb + s->off[2], W, W, W, s->Wt + (int64_t)W * kFeat);
-        k_transpose_pad<<<nblk((int64_t)128 * W), 256, 0, st>>>(s->Pb + s->off[4], W, s->D, 128,
+        k_transpose_pad<<<nblk((int64_t)np3 * W), 256, 0, st>>>(s->Pb + s->off[4], W, s->Dout, np3,
                                                                s->Wt + (int64_t)W * kFeat + (int64_t)W * W);
     }
     FeatArgs a = feat_args(s, t);
@@ -1105,32 +1231,29 @@ static int infer_impl(cd_surrogate* s, const cd_tree* t, const cd_weights* w, fl
         a.c0 = c0;
         a.n = batch;
         k_features_rows<T><<<(unsigned)(batch / kFeatBlockRows), 256, 0, st>>>(a, (T*)s->X);
-        if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->D);
-        else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->D);
+        if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->Dout);
+        else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->Dout);
     }
-    // per leaf N = N_il + max(exp(y out_scale + out_shift) - floor, 0) and chi:
-    // the method's row kernel with the network rows as the external part
-    if ((reinterpret_cast<uintptr_t>(N) & 15) == 0 &&
-        launch_surrogate_rows(t, w, s->Y7, s->norm[3], s->norm[2], kExtFloor, N, chi, chi_scale, st)) {
-        // done
-    } else if (s->D <= kOutMaxD && t->n_leaf % 256 == 0) {
-        const size_t lds = (size_t)(64 + 256) * s->D * 4;
-        k_output_tiled<<<(unsigned)(t->n_leaf / 256), 256, lds, st>>>(il_args(t, w), s->Y7, s->norm[2], s->norm[3],
-                                                                      chi_scale, N, chi);
-    } else {
-        k_output<<<nblk(t->n_leaf), 256, 0, st>>>(il_args(t, w), s->Y7, t->n_leaf, s->norm[2], s->norm[3], chi_scale,
-                                                  N, chi);
+    // per leaf N = N_il + Q + max(exp(y out_scale + out_shift) - floor, 0) and
+    // chi: the method's row kernel with the network rows as the shells
+    // dl = 1..3 and the method's coarse table for dl >= 4
+    launch_coarse(t, w, t->lmax - 4, true, st);
+    if (!launch_surrogate_rows(t, w, s->Y7, s->norm[3], s->norm[2], kExtFloor, N, chi, chi_scale, st)) {
+        set_error("cd_surrogate_infer: the row kernel does not take D = %d", w->D);
+        return CD_EUNSUPPORTED;
     }
     CD_HIP(hipGetLastError());
     return CD_OK;
 }
 
-extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_weights* w, float* N_dev,
+extern "C" int cd_surrogate_infer(cd_surrogate* s, cd_tree* t, const cd_weights* w, float* N_dev,
                                   float* chi_dev, double av_per_nh, double gamma, void* stream) {
     clear_error();
     SURR_CHECK(s && t && w && N_dev, "cd_surrogate_infer: NULL argument");
     SURR_CHECK(w->D == s->D, "cd_surrogate_infer: weights of D = %d for a network of D = %d", w->D, s->D);
-    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_infer: the surrogate needs a uniform grid with 2^L >= 256");
+    int rc = leaf_level_ok(s, t, "cd_surrogate_infer");
+    if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_infer");
+    if (rc != CD_OK) return rc;
     SURR_CHECK(!chi_dev || (std::isfinite(av_per_nh) && std::isfinite(gamma)), "cd_surrogate_infer: bad chi parameters");
     SURR_CHECK(is_aligned(N_dev, 16) && (!chi_dev || is_aligned(chi_dev, 8)),
                "cd_surrogate_infer: N must be 16-byte aligned and chi 8-byte aligned");
@@ -1140,11 +1263,6 @@ extern "C" int cd_surrogate_infer(cd_surrogate* s, const cd_tree* t, const cd_we
                                    : infer_impl<float>(s, t, w, N_dev, chi_dev, cs, st);
 }
 
-namespace cd {
-int ensure_sweep_buffers(const cd_tree* t, int D);  // sweep.hip
-void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
-                   const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);
-}
 
 // Generic per-oct arguments for target octs of a uniform tree (children at
 // level L read from the leaf array, shells from the dense levels).
@@ -1252,8 +1370,6 @@ __global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__
 
 namespace cd {
 int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
-bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
-bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
                         float chi_scale, int64_t z0, int64_t nz, hipStream_t s);                            // sweep_rows.hip
 }
@@ -1286,16 +1402,17 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     SURR_CHECK(frac > 0 && frac <= 1 && tol_chi >= 0, "cd_surrogate_check_fallback: frac %g, tol %g", frac, tol_chi);
     SURR_CHECK(is_aligned(N_dev, 16) && is_aligned(chi_dev, 8),
                "cd_surrogate_check_fallback: N must be 16-byte aligned and chi 8-byte aligned");
-    SURR_CHECK(surrogate_tree_ok(t), "cd_surrogate_check_fallback: the surrogate needs a uniform grid with 2^L >= 256");
-    SURR_CHECK(w->precision == CD_FP32 && w->mode == CD_PRECALC73 && w->D == s->D, "cd_surrogate_check_fallback: needs FP32 precalculated weights of D = %d",
-               s->D);
+    int rc = leaf_level_ok(s, t, "cd_surrogate_check_fallback");
+    if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_check_fallback");
+    if (rc != CD_OK) return rc;
+
     hipStream_t st = (hipStream_t)stream;
     const float cs = (float)(gamma * av_per_nh);
     const int L = t->lmax;
     // coarse tables of the method (shells dl >= 4) and, where the tiled
     // kernels take this direction set, the external columns E of every oct:
     // the samples and the fallback then read their shells dl = 1..3 from E
-    int rc = ensure_sweep_buffers(t, w->D);
+    rc = ensure_sweep_buffers(t, w->D);
     if (rc != CD_OK) return rc;
     launch_coarse(t, w, L - 4, true, st);
     const bool tiled = tiled_supported(t, w);
@@ -1394,8 +1511,8 @@ extern "C" int cd_surrogate_save(const cd_surrogate* s, const char* path) {
     CD_HIP(hipMemcpy(buf.data() + 2 * s->n_params, s->V, (size_t)s->n_params * 4, hipMemcpyDeviceToHost));
     FILE* f = std::fopen(path, "wb");
     SURR_CHECK(f, "cd_surrogate_save: cannot open %s", path);
-    const char magic[8] = {'C', 'D', 'S', 'U', 'R', 'R', '0', '1'};
-    const int32_t hdr[4] = {s->D, s->W, s->prec, 0};
+    const char magic[8] = {'C', 'D', 'S', 'U', 'R', 'R', '0', '2'};
+    const int32_t hdr[4] = {s->D, s->W, s->prec, s->L};
     const int64_t nt[2] = {s->n_params, s->t};
     bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, 4, 4, f) == 4 &&
               std::fwrite(s->norm, 4, 4, f) == 4 && std::fwrite(nt, 8, 2, f) == 2 &&
@@ -1415,7 +1532,7 @@ extern "C" int cd_surrogate_load(const char* path, cd_surrogate** out) {
     int32_t hdr[4];
     float norm[4];
     int64_t nt[2];
-    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CDSURR01", 8) == 0 &&
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, "CDSURR02", 8) == 0 &&
               std::fread(hdr, 4, 4, f) == 4 && std::fread(norm, 4, 4, f) == 4 && std::fread(nt, 8, 2, f) == 2;
     if (!ok) {
         std::fclose(f);
@@ -1423,7 +1540,7 @@ extern "C" int cd_surrogate_load(const char* path, cd_surrogate** out) {
         return CD_EINVAL;
     }
     cd_surrogate* s = nullptr;
-    int rc = cd_surrogate_create(hdr[0], hdr[1], hdr[2], 0, norm, &s);
+    int rc = cd_surrogate_create(hdr[0], hdr[3], hdr[1], hdr[2], 0, norm, &s);
     if (rc != CD_OK) {
         std::fclose(f);
         return rc;

@@ -33,9 +33,10 @@ struct RowArgs {
     float chi_scale;
     int64_t z0;         // first target plane of this launch
     int64_t nz;         // number of target planes of this launch
-    // learned surrogate: instead of E and q4, the external part of every
-    // target is max(exp(y s + m) - floor, 0) from the network's row y of
-    // the oct's level-7 ancestor (rows x fastest)
+    // learned surrogate: instead of E, the shells dl = 1..3 of every target
+    // are max(exp(y s + m) - floor, 0) from the network's row of the oct's
+    // level-7 ancestor (rows x fastest; a row holds one block of D per oct
+    // inside the level-7 cell, blocks x fastest); q4 adds dl >= 4 as usual
     const float* y7;
     float y_scale, y_shift, y_floor;
 };
@@ -70,6 +71,31 @@ __device__ __forceinline__ void il_pair(const float (&c0)[4], const float (&c1)[
 // 4 floats, off the 32-bank period for the lanes' row reads).
 template <int D>
 constexpr int kRowPitch = D % 4 == 0 ? D + 4 : D + 1;
+
+// shells dl >= 4 of oct (ax, Y, Az) added to e: the level L-4 ancestor's row
+// of the coarse table, at the inner-limit state fixed by bits 1 and 2 of the
+// oct's coordinates
+template <int D>
+__device__ __forceinline__ void add_coarse(const RowArgs& a, int64_t ax, int64_t Y, int64_t Az, int64_t n1,
+                                           float (&e)[D]) {
+    const int64_t n4 = n1 >> 3;
+    const int64_t cell = ((Az >> 3) * n4 + (Y >> 3)) * n4 + (ax >> 3);
+    const int code = (int)(((ax >> 1) & 3) + 4 * ((Y >> 1) & 3) + 16 * ((Az >> 1) & 3));
+    const float* qr = a.q4 + (cell * 64 + code) * D;
+    if constexpr (D % 4 == 0) {
+#pragma unroll
+        for (int d = 0; d < D; d += 4) {
+            const float4 v = *reinterpret_cast<const float4*>(qr + d);
+            e[d] += v.x;
+            e[d + 1] += v.y;
+            e[d + 2] += v.z;
+            e[d + 3] += v.w;
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) e[d] += qr[d];
+    }
+}
 
 template <int D>
 __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
@@ -112,11 +138,15 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
     }
     float e0[D], e1[D];
     if (a.y7) {
-        const int sh7 = L - 8;  // level L-1 oct -> level-7 cell
-        const int64_t r7 = ((((z >> 1) >> sh7) << 7) + ((y >> 1) >> sh7)) * 128 + (ax >> sh7);
-        const float* yr = a.y7 + r7 * D;
+        // level L-1 oct -> its level-7 cell's row and its block in that row
+        const int sb = L - 8;
+        const int64_t oy = y >> 1, oz = z >> 1, m = ((int64_t)1 << sb) - 1;
+        const int64_t r7 = (((oz >> sb) << 7) + (oy >> sb)) * 128 + (ax >> sb);
+        const int64_t jb = (ax & m) + ((oy & m) << sb) + ((oz & m) << (2 * sb));
+        const float* yr = a.y7 + ((r7 << (3 * sb)) + jb) * D;
 #pragma unroll
         for (int d = 0; d < D; ++d) e0[d] = fmaxf(__expf(fmaf(yr[d], a.y_scale, a.y_shift)) - a.y_floor, 0.f);
+        if (a.q4) add_coarse<D>(a, ax, Y, z >> 1, n1, e0);
     } else if constexpr (D <= 12) {
         // short rows: each lane loads its oct's rows of E and of the coarse
         // table itself (their lines are few and the LDS is kept for staging)
@@ -134,28 +164,7 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
 #pragma unroll
             for (int d = 0; d < D; ++d) e0[d] = er[d];
         }
-        if (a.q4) {
-            // shells dl >= 4: the level L-4 ancestor and the inner-limit state
-            // fixed by bits 1 and 2 of the oct's coordinates
-            const int64_t Az = z >> 1;
-            const int64_t n4 = n1 >> 3;
-            const int64_t cell = ((Az >> 3) * n4 + (Y >> 3)) * n4 + (ax >> 3);
-            const int code = (int)(((ax >> 1) & 3) + 4 * ((Y >> 1) & 3) + 16 * ((Az >> 1) & 3));
-            const float* qr = a.q4 + (cell * 64 + code) * D;
-            if constexpr (D % 4 == 0) {
-#pragma unroll
-                for (int d = 0; d < D; d += 4) {
-                    const float4 v = *reinterpret_cast<const float4*>(qr + d);
-                    e0[d] += v.x;
-                    e0[d + 1] += v.y;
-                    e0[d + 2] += v.z;
-                    e0[d + 3] += v.w;
-                }
-            } else {
-#pragma unroll
-                for (int d = 0; d < D; ++d) e0[d] += qr[d];
-            }
-        }
+        if (a.q4) add_coarse<D>(a, ax, Y, z >> 1, n1, e0);
     } else {
         // The 4 waves read the same seg octs: their rows of E (contiguous)
         // and of the coarse table are loaded once per workgroup, coalesced,
@@ -284,8 +293,10 @@ static void launch_rows(const RowArgs& a, int64_t nz, hipStream_t s) {
     k_target_rows<D><<<(unsigned)blocks, 256, 0, s>>>(a);
 }
 
-// The learned surrogate's rows (every target plane): external part from the
-// network rows y7 of the level-7 cells (needs 2^L >= 256).
+// The learned surrogate's rows (every target plane): shells dl = 1..3 from
+// the network rows y7 of the level-7 cells (needs 2^L >= 256; rows of
+// 8^(L-8) D values), dl >= 4 from the coarse table of level L-4 (built by
+// the coarse chain beforehand).
 bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y7, float y_scale, float y_shift,
                            float y_floor, float* N, float* chi, float chi_scale, hipStream_t s) {
     const int D = w->D;
@@ -293,6 +304,7 @@ bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y
     RowArgs a{};
     a.leaf = t->leaf;
     a.L = t->lmax;
+    a.q4 = t->q[t->lmax - 4];
     a.gloc = w->gloc;
     a.sgn = w->sgn;
     a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));

@@ -109,6 +109,17 @@ def uniform_tree(density_zyx: np.ndarray, box_cm: float) -> TreeInput:
     return t
 
 
+def refine_uniform(tin: TreeInput) -> TreeInput:
+    """The same uniform field one level finer: every leaf split into 8
+    equal children (2^(L+1) per axis, same box).  Levels 0 .. L of its
+    pyramid are the original field's."""
+    assert tin.is_uniform
+    n = 1 << tin.max_level
+    a = tin.leaf_n.reshape(n, n, n)
+    a = np.repeat(np.repeat(np.repeat(a, 2, axis=0), 2, axis=1), 2, axis=2)
+    return uniform_tree(a, tin.box_cm)
+
+
 def amr_tree(fine_zyx: np.ndarray, base_level: int, threshold: float,
              box_cm: float) -> TreeInput:
     """AMR tree on a field sampled at the finest level: a full 2^base grid,
@@ -170,6 +181,16 @@ def amr_tree(fine_zyx: np.ndarray, base_level: int, threshold: float,
 def workload_uniform(L: int, sigma: float = 1.5, mean: float = 10.0, seed: int = 1,
                      box_pc: float = 10.0) -> TreeInput:
     return uniform_tree(lognormal_field(1 << L, sigma, mean, seed), box_pc * PC_CM)
+
+
+def workloads_uniform(L: int, seeds, sigma: float = 1.5, mean: float = 10.0, box_pc: float = 10.0,
+                      threads: int = 8) -> List[TreeInput]:
+    """workload_uniform for several seeds, generated side by side in threads
+    (each field depends on its own seed only)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max(1, min(threads, len(seeds)))) as ex:
+        return list(ex.map(lambda sd: workload_uniform(L, sigma, mean, sd, box_pc), seeds))
 
 
 def workload_amr(base_level: int = 7, max_level: int = 9, sigma: float = 2.0,

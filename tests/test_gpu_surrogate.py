@@ -1,11 +1,12 @@
 """The learned surrogate on the GPU, through the C ABI, against the FP64
-reference in oracle/surrogate.py and against the method itself.
+reference in oracle/surrogate.py, the oracle's shell sums and the method
+itself (networks for 256^3 grids; the 512^3 case is in
+test_gpu_surrogate_512.py).
 
 Gates: features and targets to 2e-5 (ln units); forward and gradients of
-the FP32 checking path to 1e-5 against the FP64 reference, of the bfloat16
-path to 1e-2 against the reference rounded where the bfloat16 path rounds
-(relative, per parameter block); after the sampled check and fallback, the
-99th percentile of the relative chi error <= 3 %."""
+the FP32 checking path to 1e-5 against the FP64 reference; after the
+sampled check and fallback, the 99th percentile of the relative chi error
+<= 3 %."""
 import os
 import tempfile
 
@@ -73,8 +74,17 @@ def test_features_match_reference(colden):
     assert torch.isnan(Xb).all()
 
 
-@pytest.mark.parametrize("prec,tol", [(0, 1e-5), (1, 1e-2)])
-def test_forward_and_gradients_match_reference(colden, prec, tol):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_forward_and_gradients_match_reference(colden, prec):
+    """Forward: the FP32 path against the FP64 reference to 1e-5; the
+    bfloat16 inference path against the reference rounded where it rounds
+    to 1e-2.  Gradients (both precisions: the bfloat16 network trains on
+    hi + lo operand pairs) against the exact FP64 backward, element by
+    element: |g - g_ref| <= tol (|g_ref| + 1e-3 max |g_ref| of the block).
+    FP32: sums of up to 576 terms carry up to 576 * 2^-24 = 3.4e-5 of the
+    sum of their magnitudes, which near the floor is up to ~10 times the
+    element, three layers deep: tol = 1e-3.  bfloat16 pairs: about 2^-15
+    per product before accumulation: tol = 1e-2."""
     W, D, n = 64, 12, 300
     s = colden.Surrogate(D, W, prec, 7)
     p = _blocks(s.get_params(), W, D)
@@ -95,20 +105,26 @@ def test_forward_and_gradients_match_reference(colden, prec, tol):
     g, loss = s.gradients(Xd, Td)
     Tr = T.astype(np.float32).astype(np.float64)
     gexact = S.backward(p, cache, Yref, Tr)
-    gref = S.backward_bf16(p, Xr, Tr) if prec == 1 else gexact
     lref = S.mse(Yref, Tr)
-    rel = lambda gs, rs: [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(gs, rs)]
-    gerr = rel(_blocks(g, W, D), gref)
-    print(f"prec {prec}: forward {yerr:.2e}, loss {loss:.6f} vs {lref:.6f}, gradient blocks {np.round(gerr, 6)}; "
-          f"vs the exact FP64 gradient {np.round(rel(_blocks(g, W, D), gexact), 4)}")
-    assert yerr <= tol
-    assert abs(loss - lref) <= (tol if prec == 0 else 2e-2) * lref
-    assert max(gerr) <= tol
+    got = _blocks(g, W, D)
+    tol = 1e-3 if prec == 0 else 1e-2
+    elem = [float((np.abs(a - b) / (np.abs(b) + 1e-3 * np.abs(b).max())).max()) for a, b in zip(got, gexact)]
+    norm = [float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(got, gexact)]
+    diag = ""
+    if prec == 1:  # what single bfloat16 operands would give (not a gate)
+        gb = S.backward_bf16(p, Xr, Tr)
+        diag = f"; single-bf16 reference vs exact {np.round([float(np.linalg.norm(a - b) / np.linalg.norm(b)) for a, b in zip(gb, gexact)], 4)}"
+    print(f"prec {prec}: forward {yerr:.2e}, loss {loss:.7f} vs {lref:.7f}, gradient vs exact FP64 per element "
+          f"{np.round(elem, 6)}, per block norm {np.round(norm, 7)}{diag}")
+    assert yerr <= (1e-5 if prec == 0 else 1e-2)
+    assert abs(loss - lref) <= 1e-5 * lref
+    assert max(elem) <= tol
 
 
 def test_adam_step_matches_reference(colden):
-    """One training step of the FP32 path: features, targets from the
-    method's columns, gradient and the Adam update against the reference."""
+    """One training step of the FP32 path: features, targets (the method's
+    near shells dl = 1..3 against the oracle's), gradient and the Adam
+    update against the reference."""
     tin = _field(101)
     w = colden.Weights(oracle.dirs_healpix(1))
     tree, leaf, N, _ = _plain(colden, tin, w)
@@ -119,14 +135,13 @@ def test_adam_step_matches_reference(colden):
     cells = np.random.default_rng(3).choice(tin.n_leaf, 512, replace=False)
     dcells = torch.from_numpy(cells).to(DEV)
     Tg = torch.empty((cells.size, D), dtype=torch.float32, device=DEV)
-    s.targets(tree, w, N, dcells, Tg)
-    s.train_step(tree, w, N, dcells, lr)
+    s.targets(tree, w, dcells, Tg)
+    s.train_step(tree, w, dcells, lr)
     p1 = s.get_params().astype(np.float64)
     n = 256
     lv = S.pyramid(tin.leaf_n.reshape(n, n, n).astype(np.float64))
     X = S.features(lv, cells, norm[0], norm[1])
-    nil = oracle.Tree(tin).internal_local(oracle.dirs_healpix(1), cells)
-    T = S.targets(N.cpu().numpy()[cells].astype(np.float64), nil, norm[2], norm[3])
+    T = S.targets(oracle.Tree(tin).external(oracle.dirs_healpix(1), cells, 1, 3), norm[2], norm[3])
     terr = np.abs(Tg.cpu().numpy() - T).max()
     print(f"targets: max abs diff {terr:.2e}")
     assert terr <= 2e-5
@@ -144,17 +159,16 @@ def test_adam_step_matches_reference(colden):
 
 @pytest.fixture(scope="module")
 def trained(colden):
-    """A bfloat16 network trained on two seeded 256^3 fields."""
+    """A bfloat16 network for 256^3 grids trained on two seeded 256^3 fields."""
     from paper_1410_0624_amd import surrogate_train
     w = colden.Weights(oracle.dirs_healpix(1))
     runs = [_plain(colden, _field(sd), w) for sd in (110, 111)]
-    trees = [r[0] for r in runs]
-    Ns = [r[2] for r in runs]
-    nrm = surrogate_train.norms(trees, w, Ns)
+    fields = [surrogate_train.label_field(_field(sd), w, 8, DEV) for sd in (110, 111)]
+    nrm = surrogate_train.norms(fields)
     s = colden.Surrogate(12, 256, colden.CD_SURR_BF16, 11, norm=nrm)
     untrained = s.get_params()
-    log = surrogate_train.fit(s, trees, w, Ns, steps=2000, batch=4096, lr=2e-3, lr_final=1e-4, seed=5,
-                              log_every=250)
+    log = surrogate_train.fit(s, fields, steps=2000, batch=4096, lr=2e-3, lr_final=1e-4, seed=5, log_every=250)
+    del fields
     print("training log:", [(k, round(l, 4)) for k, l in log])
     return s, w, nrm, untrained, log, runs
 
@@ -181,8 +195,9 @@ def test_training_lowers_the_loss_and_beats_baselines(colden, trained):
     s.infer(tree, w, Ns, chis)
     torch.cuda.synchronize()
     e_un = _chi_err(chis.cpu().numpy(), ref)
-    # best constant external column: every direction at exp(out_shift), plus
-    # the exact internal + local part (the same split as the network's)
+    # best constant near-shell column: every direction at exp(out_shift),
+    # plus the method's internal + local part and shells dl >= 4 (the same
+    # split as the network's)
     s.set_params(np.concatenate([np.zeros(s.n_params() - 12, np.float32), np.zeros(12, np.float32)]))
     s.infer(tree, w, Ns, chis)
     torch.cuda.synchronize()
@@ -198,7 +213,7 @@ def test_infer_matches_features_and_forward(colden, trained):
     """Inference (network once per level-7 cell on the logarithms taken once
     per pyramid cell, then each leaf's output) equals, at sampled leaves,
     the same network run row by row on cd_surrogate_features, plus the
-    oracle's internal + local part (Sect. 3.2)."""
+    oracle's internal + local part and shells dl >= 4 (Sect. 3.2)."""
     s, w, nrm, _, _, _ = trained
     tin = _field(122)
     tree, leaf, N, chi = _plain(colden, tin, w)
@@ -211,8 +226,9 @@ def test_infer_matches_features_and_forward(colden, trained):
     Y = torch.empty((tg.size, w.D), dtype=torch.float32, device=DEV)
     s.forward(X, Y)
     torch.cuda.synchronize()
-    nil = oracle.Tree(tin).internal_local(oracle.dirs_healpix(1), tg)
-    ref = S.columns_from_output(Y.cpu().numpy().astype(np.float64), nil, nrm[2], nrm[3])
+    tr = oracle.Tree(tin)
+    exact = tr.internal_local(oracle.dirs_healpix(1), tg) + tr.external(oracle.dirs_healpix(1), tg, 4)
+    ref = S.columns_from_output(Y.cpu().numpy().astype(np.float64), exact, nrm[2], nrm[3])
     got = Ns.cpu().numpy().astype(np.float64)[tg]
     err = np.abs(np.log(got) - np.log(ref))
     print(f"infer vs features + forward: max |d ln N| {err.max():.3e} mean {err.mean():.3e}")
@@ -282,7 +298,7 @@ def test_few_failing_tiles_take_the_per_tile_route(colden, trained):
     Ns0 = torch.empty_like(N)
     chis0 = torch.empty_like(chi)
     s.infer(tree, w, Ns0, chis0)
-    for tol in (0.3, 0.5, 1.0, 2.0, 5.0):
+    for tol in (0.01, 0.02, 0.03, 0.05, 0.1, 0.3, 0.5, 1.0, 2.0, 5.0):
         Ns, chis = Ns0.clone(), chis0.clone()
         nf, nt, _ = s.check_fallback(tree, w, Ns, chis, frac=0.01, tol_chi=tol, seed=4)
         if 0 < 4 * nf <= nt:
@@ -324,6 +340,21 @@ def test_save_load_round_trip(colden, trained):
 def test_surrogate_errors(colden):
     with pytest.raises(colden.ColdenError):
         colden.Surrogate(12, 100)  # width not a multiple of 16
+    with pytest.raises(colden.ColdenError):
+        colden.Surrogate(12, 32, leaf_level=10)
+    # a network for 512^3 grids on a 256^3 tree, and weights of another D
+    tin8 = _field(100)
+    leaf8 = torch.from_numpy(tin8.leaf_n).to(DEV)
+    tree8 = colden.Tree(tin8, leaf8)
+    N8 = torch.empty((tin8.n_leaf, 12), device=DEV)
+    s9 = colden.Surrogate(12, 32, leaf_level=9)
+    assert s9.Dout == 96
+    with pytest.raises(colden.ColdenError) as e:
+        s9.infer(tree8, colden.Weights(oracle.dirs_healpix(1)), N8)
+    assert e.value.rc == colden.CD_EINVAL
+    N6 = torch.empty((tin8.n_leaf, 6), device=DEV)
+    with pytest.raises(colden.ColdenError):
+        colden.Surrogate(12, 32).infer(tree8, colden.Weights(oracle.dirs_axes6()), N6)
     tin = synth.workload_uniform(5, seed=1)
     leaf = torch.from_numpy(tin.leaf_n).to(DEV)
     tree = colden.Tree(tin, leaf)

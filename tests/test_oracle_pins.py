@@ -589,3 +589,73 @@ def test_mn_azimuths_step_two_pi_over_n():
             np.testing.assert_allclose(ring.sum(axis=0)[:2], 0.0, atol=1e-13)
             # the ring rotated by one step is the next direction of the ring
             np.testing.assert_allclose(ring @ rot.T, np.roll(ring, -1, axis=0), atol=1e-13)
+
+
+def _slab_chords(lo, hi, o, u):
+    """Length of the half-line o + t u (t >= 0) inside each box [lo, hi]
+    (rows), by the slab method: a second chord routine, independent of the
+    oracle's."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (lo - o) / u
+        t2 = (hi - o) / u
+    inside = (o >= lo) & (o <= hi)
+    tmin = np.where(u == 0, np.where(inside, -np.inf, np.inf), np.minimum(t1, t2))
+    tmax = np.where(u == 0, np.where(inside, np.inf, -np.inf), np.maximum(t1, t2))
+    return np.maximum(tmax.min(-1) - np.maximum(tmin.max(-1), 0.0), 0.0)
+
+
+@pytest.mark.parametrize("lo,hi", [(1, 1), (2, 3), (1, 3), (4, 6)])
+def test_external_shell_ranges_against_a_direct_sum(lo, hi):
+    """Eqs. 9-10 shell by shell: the oracle's external sum restricted to
+    dl = lo..hi equals a direct numpy sum over the same shells (cells of the
+    outer box minus the inner box, inside the grid, density from the
+    pyramid, chord from the shell's reference point by a second chord
+    routine)."""
+    L = 6
+    n = 1 << L
+    tin = synth.workload_uniform(L, seed=11)
+    tr = oracle.Tree(tin)
+    dirs = oracle.dirs_healpix(1)
+    f = tin.leaf_n.reshape(n, n, n).astype(np.float64)
+    lv = [f]
+    while lv[0].shape[0] > 1:
+        a = lv[0]
+        m = a.shape[0] // 2
+        lv.insert(0, a.reshape(m, 2, m, 2, m, 2).mean(axis=(1, 3, 5)))
+    tg = np.random.default_rng(5).choice(tin.n_leaf, 12, replace=False)
+    got = tr.external(dirs, tg, lo, hi)
+    for i, q in enumerate(tg):
+        sh, ref = tr.shells(int(q))
+        want = np.zeros(dirs.shape[0])
+        for s, r in zip(sh, ref):
+            l = int(s[0])
+            if not lo <= L - l <= hi:
+                continue
+            olo, ohi, ilo, ihi = s[1:4], s[4:7], s[7:10], s[10:13]
+            g = np.stack(np.meshgrid(*[np.arange(olo[a], ohi[a] + 1) for a in range(3)], indexing="ij"), -1)
+            g = g.reshape(-1, 3)
+            keep = ~np.all((g >= ilo) & (g <= ihi), 1) & np.all((g >= 0) & (g < (1 << l)), 1)
+            g = g[keep]
+            dn = lv[l][g[:, 2], g[:, 1], g[:, 0]]
+            dx = 1.0 / (1 << l)
+            for d in range(dirs.shape[0]):
+                want[d] += (dn * _slab_chords(g * dx, (g + 1) * dx, r, dirs[d])).sum()
+        want *= tin.box_cm
+        assert np.allclose(got[i], want, rtol=1e-12, atol=1e-9 * want.max())
+
+
+def test_external_shell_ranges_partition_the_column():
+    """Internal + local plus the external sums over dl = 1, 2, 3 and >= 4
+    give the method's column exactly, on a uniform grid and an AMR tree."""
+    dirs = oracle.dirs_healpix(1)
+    for tin in (synth.workload_uniform(6, seed=2), synth.workload_amr(4, 6, seed=3, threshold=30.0)):
+        tr = oracle.Tree(tin)
+        tg = np.random.default_rng(1).choice(tin.n_leaf, 200, replace=False)
+        parts = tr.internal_local(dirs, tg) + sum(tr.external(dirs, tg, k, k) for k in (1, 2, 3)) + \
+            tr.external(dirs, tg, 4)
+        full = tr.columns(dirs, tg)
+        assert np.allclose(parts, full, rtol=1e-13, atol=0)
+        with pytest.raises(ValueError):
+            tr.external(dirs, tg, 0, 3)
+        with pytest.raises(ValueError):
+            tr.external(dirs, tg, 3, 2)
