@@ -489,8 +489,10 @@ int cd_surrogate_infer(cd_surrogate* s, cd_tree* tree, const cd_weights* w, floa
  * of all tiles, and the largest sampled relative chi error (may be NULL).
  * When more than a quarter of the tiles fail, the method runs once over the
  * whole grid straight into N_dev and chi_dev instead, so every tile then holds
- * the method's values.  Synchronises the stream (the host picks the tiles).
- * N_dev 16-byte and chi_dev 8-byte aligned.
+ * the method's values.  The tiles are judged on the device; the stream is
+ * synchronised once, for the count of failing tiles, and the recomputation
+ * is left queued on it.  The sample and tile lists live in the handle
+ * (grown on first use).  N_dev 16-byte and chi_dev 8-byte aligned.
  * Errors: CD_EINVAL (frac outside (0, 1], tree not uniform, w not FP32,
  * misaligned buffers), CD_ENOMEM, CD_EDEVICE. */
 int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* tree, const cd_weights* w, double frac, double tol_chi,

@@ -66,9 +66,26 @@ __device__ __forceinline__ int64_t sub_block(int64_t ox, int64_t oy, int64_t oz,
     const int64_t m = ((int64_t)1 << sb) - 1;
     return (ox & m) + ((oy & m) << sb) + ((oz & m) << (2 * sb));
 }
-// row-major index of the level-7 ancestor of oct (ox, oy, oz) at level L-1
-__device__ __forceinline__ int64_t row7_of_oct(int64_t ox, int64_t oy, int64_t oz, int sb) {
-    return (((oz >> sb) << kRowLevel) + (oy >> sb)) * ((int64_t)1 << kRowLevel) + (ox >> sb);
+// Network output (level-7 row r, column c = j D + d) -> its place in the
+// method's near-shell rows E[oct][D] (octs row-major at level L-1), and the
+// value max(exp(y scale + shift) - floor, 0) stored there.
+struct OutE {
+    float* E;
+    int64_t row0;  // level-7 index of the batch's first row
+    int L, D;
+    float scale, shift, floor;
+};
+__device__ __forceinline__ int64_t e_index(int64_t r, int c, int L, int D) {
+    const int sb = L - 8, j = c / D, d = c - j * D;
+    const int64_t m = ((int64_t)1 << sb) - 1, m7 = ((int64_t)1 << kRowLevel) - 1;
+    const int64_t ox = ((r & m7) << sb) + (j & m);
+    const int64_t oy = (((r >> kRowLevel) & m7) << sb) + ((j >> sb) & m);
+    const int64_t oz = ((r >> (2 * kRowLevel)) << sb) + (j >> (2 * sb));
+    const int L1 = L - 1;
+    return ((((oz << L1) + oy) << L1) + ox) * D + d;
+}
+__device__ __forceinline__ void store_e(const OutE& o, int64_t row, int c, float y) {
+    o.E[e_index(o.row0 + row, c, o.L, o.D)] = fmaxf(__expf(fmaf(y, o.scale, o.shift)) - o.floor, 0.f);
 }
 
 // One thread per feature value (row, level, stencil cell): a wave writes the
@@ -128,40 +145,57 @@ constexpr int kFeatStage = 16 * (130 + 66 + 34 + 18 + 10 + 6 + 4 + 4 + 4);
 template <typename T>
 __global__ __launch_bounds__(256) void k_features_rows(const FeatArgs a, T* __restrict__ X) {
     __shared__ float stage[kFeatStage];
+    __shared__ int s_off[kFeatLevels], s_width[kFeatLevels], s_xb[kFeatLevels];
     const int64_t m = (int64_t)1 << kRowLevel;
     const int64_t r0 = a.c0 + (int64_t)blockIdx.x * kFeatBlockRows;
     const int64_t X0 = r0 & (m - 1), Y = (r0 >> kRowLevel) & (m - 1), Z = r0 >> (2 * kRowLevel);
-    int off[kFeatLevels], width[kFeatLevels];
-    int64_t xb[kFeatLevels];
-    int o = 0;
-#pragma unroll
-    for (int l = 0; l < kFeatLevels; ++l) {
-        const int sh = kRowLevel + 1 - l;  // the row's ancestor at level l - 1: X >> sh
-        xb[l] = 2 * (X0 >> sh) - 1;
-        width[l] = (int)(2 * (((X0 + kFeatBlockRows - 1) >> sh) - (X0 >> sh)) + 4);
-        off[l] = o;
-        o += 16 * width[l];
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int l = 0; l < kFeatLevels; ++l) {
+            const int sh = kRowLevel + 1 - l;  // the row's ancestor at level l - 1: X >> sh
+            s_xb[l] = (int)(2 * (X0 >> sh) - 1);
+            s_width[l] = (int)(2 * (((X0 + kFeatBlockRows - 1) >> sh) - (X0 >> sh)) + 4);
+            s_off[l] = o;
+            o += 16 * s_width[l];
+        }
     }
+    __syncthreads();
     for (int l = 0; l < kFeatLevels; ++l) {
         const int sh = kRowLevel + 1 - l;
         const int64_t nl = (int64_t)1 << l, S = nl + 2 * kHalo;
         const int64_t yb = 2 * (Y >> sh) - 1, zb = 2 * (Z >> sh) - 1;
         const float* lev = a.lev[l];
-        const int w = width[l];
+        const int w = s_width[l], xb = s_xb[l], o = s_off[l];
         for (int k = threadIdx.x; k < 16 * w; k += 256) {
             const int lx = k % w, yz = k / w;  // yz = 4 sz + sy
-            const int64_t gx = xb[l] + lx, gy = yb + (yz & 3), gz = zb + (yz >> 2);
-            stage[off[l] + k] = lev[((gz + kHalo) * S + (gy + kHalo)) * S + (gx + kHalo)];
+            const int64_t gx = xb + lx, gy = yb + (yz & 3), gz = zb + (yz >> 2);
+            stage[o + k] = lev[((gz + kHalo) * S + (gy + kHalo)) * S + (gx + kHalo)];
         }
     }
     __syncthreads();
+    // 8 consecutive features per thread and store: offsets sx = 0..3 at two
+    // consecutive sy of one (level, sz)
     T* out = X + (r0 - a.c0) * kFeat;
-    for (int k = threadIdx.x; k < kFeatBlockRows * kFeat; k += 256) {
-        const int i = k / kFeat, f = k % kFeat;
-        const int l = f >> 6, sx = f & 3, sy = (f >> 2) & 3, sz = f >> 4 & 3;
-        const int sh = kRowLevel + 1 - l;
-        const int lx = (int)(2 * ((X0 + i) >> sh) - 1 + sx - xb[l]);
-        out[k] = from_f<T>(stage[off[l] + (4 * sz + sy) * width[l] + lx]);
+    constexpr int kChunks = kFeat / 8;
+    for (int k = threadIdx.x; k < kFeatBlockRows * kChunks; k += 256) {
+        const int i = k / kChunks, f0 = 8 * (k - i * kChunks);
+        const int l = f0 >> 6, sy = (f0 >> 2) & 3, sz = (f0 >> 4) & 3;
+        const int sh = kRowLevel + 1 - l, w = s_width[l];
+        const int lx = (int)(2 * ((X0 + i) >> sh) - 1 - s_xb[l]);
+        const float* p0 = stage + s_off[l] + (4 * sz + sy) * w + lx;
+        const float* p1 = p0 + w;
+        T* dst = out + (int64_t)i * kFeat + f0;
+        if constexpr (sizeof(T) == 2) {
+            uint4 v;
+            v.x = (uint32_t)f2bf(p0[0]) | ((uint32_t)f2bf(p0[1]) << 16);
+            v.y = (uint32_t)f2bf(p0[2]) | ((uint32_t)f2bf(p0[3]) << 16);
+            v.z = (uint32_t)f2bf(p1[0]) | ((uint32_t)f2bf(p1[1]) << 16);
+            v.w = (uint32_t)f2bf(p1[2]) | ((uint32_t)f2bf(p1[3]) << 16);
+            *reinterpret_cast<uint4*>(dst) = v;
+        } else {
+            reinterpret_cast<float4*>(dst)[0] = float4{p0[0], p0[1], p0[2], p0[3]};
+            reinterpret_cast<float4*>(dst)[1] = float4{p1[0], p1[1], p1[2], p1[3]};
+        }
     }
 }
 
@@ -542,7 +576,7 @@ constexpr int kFT = 128, kFK = 32, kFP = 40;
 __global__ __launch_bounds__(256) void k_gemm_bf16_nt(const uint16_t* __restrict__ A, const uint16_t* __restrict__ Bt,
                                                       const float* __restrict__ bias, int relu, uint16_t* __restrict__ C16,
                                                       float* __restrict__ C32, int64_t ldc, int n_valid, int K,
-                                                      int ntn) {
+                                                      int ntn, const OutE oe) {
     __shared__ __attribute__((aligned(16))) uint16_t As[2][kFT][kFP];
     __shared__ __attribute__((aligned(16))) uint16_t Bs[2][kFT][kFP];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -628,8 +662,16 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_nt(const uint16_t* __restrict
                 if (relu) v = fmaxf(v, 0.f);
                 if (C16) C16[row * ldc + col] = f2bf(v);
                 if (C32) C32[row * ldc + col] = v;
+                if (oe.E) store_e(oe, row, col, v);
             }
     }
+}
+
+// network rows Y[n][Dout] of a batch -> the near-shell rows E
+__global__ void k_y_to_e(const float* __restrict__ Y, int64_t n, int dout, const OutE oe) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n * dout) return;
+    store_e(oe, idx / dout, (int)(idx % dout), Y[idx]);
 }
 
 // dst [npad][K] = src [K][N]^T, rows n >= N zero (bfloat16 weights)
@@ -640,11 +682,31 @@ __global__ void k_transpose_pad(const uint16_t* __restrict__ src, int K, int N, 
     dst[idx] = n < N ? src[(int64_t)k * N + n] : (uint16_t)0;
 }
 
-// relative chi error of each sampled leaf
-__global__ void k_sample_err(const float* __restrict__ chi_net, const int64_t* __restrict__ cells, int64_t n,
-                             const float* __restrict__ chi_ref, float* __restrict__ err) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) err[i] = fabsf(chi_net[cells[i]] - chi_ref[i]) / chi_ref[i];
+// One thread per 8^3 tile: the relative chi error of its `per` samples
+// (network chi_net at the sampled leaf against the method's sChi); a tile
+// with an error above tol (or not finite) is appended to the fail list.
+// cnt[0]: failing tiles; cnt[1]: the largest error as FP32 bits (errors are
+// >= 0, so their bit patterns order like the values; not finite -> +inf).
+__global__ void k_tile_check(const float* __restrict__ chi_net, const int64_t* __restrict__ cells,
+                             const float* __restrict__ sChi, int64_t nt, int per, float tol,
+                             int64_t* __restrict__ fail, unsigned long long* __restrict__ cnt) {
+    const int64_t tl = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (tl >= nt) return;
+    float emax = 0.f;
+    bool bad = false;
+    for (int j = 0; j < per; ++j) {
+        const int64_t i = tl * per + j;
+        const float e = fabsf(chi_net[cells[i]] - sChi[i]) / sChi[i];
+        const bool ok = e <= tol;
+        bad |= !ok;
+        emax = fmaxf(emax, isfinite(e) ? e : __builtin_inff());
+    }
+    atomicMax(reinterpret_cast<unsigned int*>(cnt + 1), __float_as_uint(emax));
+    if (bad) fail[atomicAdd(cnt, 1ull)] = tl;
+}
+
+__global__ void k_clear_u64(unsigned long long* p, int n) {
+    if ((int)threadIdx.x < n) p[threadIdx.x] = 0ull;
 }
 
 static unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -689,8 +751,13 @@ struct cd_surrogate {
     float* loss = nullptr;
     int64_t* cells = nullptr;  // [cap] scratch index list
     float* colpart = nullptr;  // [kColChunks][max(W, D)] column-sum partials
-    float* Y7 = nullptr;       // [2^21][Dout] network rows of the level-7 cells (inference)
     uint16_t* Wt = nullptr;    // transposed bfloat16 weights for the inference GEMM
+    // sampled check: sample lists, their columns, the tile list and counters;
+    // the fallback's oct lists (grown on demand, kept)
+    void* ck = nullptr;
+    size_t ck_bytes = 0;
+    void* fb = nullptr;
+    size_t fb_bytes = 0;
 };
 
 namespace cd {
@@ -744,6 +811,9 @@ int ensure_sweep_buffers(const cd_tree* t, int D);                              
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);              // sweep.hip
 bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
+int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
+bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);                            // sweep_rows.hip
 bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
 
 // The method's near shells dl = 1..3 of every oct into the tree's rows E
@@ -806,9 +876,10 @@ static void forward_rows(cd_surrogate* s, int64_t n, bool keep, hipStream_t st, 
 }
 
 // bfloat16 inference of n rows (n % 128 == 0, width % 128 == 0) on the tiled
-// GEMM, weights transposed into s->Wt first; rows into Yout [n][Dout].
+// GEMM, weights transposed into s->Wt first; outputs into Yout [n][Dout], or
+// (oe.E) straight into the near-shell rows.
 static int out_pad(const cd_surrogate* s) { return (s->Dout + kFT - 1) / kFT * kFT; }
-static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float* Yout) {
+static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float* Yout, const OutE& oe) {
     const int W = s->W, D = s->Dout, ntn3 = out_pad(s) / kFT;
     const uint16_t* X = (const uint16_t*)s->X;
     uint16_t* W1t = s->Wt;
@@ -816,12 +887,14 @@ static void forward_rows_fast(cd_surrogate* s, int64_t n, hipStream_t st, float*
     uint16_t* W3t = W2t + (int64_t)W * W;
     const int ntn = W / kFT;
     const unsigned g1 = (unsigned)(n / kFT * ntn);
-    k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat, ntn);
+    const OutE none{};
+    k_gemm_bf16_nt<<<g1, 256, 0, st>>>(X, W1t, s->P + s->off[1], 1, (uint16_t*)s->A1l, nullptr, W, W, kFeat, ntn,
+                                       none);
     k_gemm_bf16_nt<<<g1, 256, 0, st>>>((const uint16_t*)s->A1l, W2t, s->P + s->off[3], 1, (uint16_t*)s->A2l, nullptr,
-                                       W, W, W, ntn);
+                                       W, W, W, ntn, none);
     const unsigned g3 = (unsigned)(n / kFT * ntn3);
-    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, Yout, D, D, W,
-                                       ntn3);
+    k_gemm_bf16_nt<<<g3, 256, 0, st>>>((const uint16_t*)s->A2l, W3t, s->P + s->off[5], 0, nullptr, oe.E ? nullptr : Yout,
+                                       D, D, W, ntn3, oe);
 }
 
 // Loss, gradient into s->G (targets in s->Tg, activations kept).
@@ -950,8 +1023,8 @@ extern "C" void cd_surrogate_destroy(cd_surrogate* s) {
     if (!s) return;
     (void)hipDeviceSynchronize();
     free_scratch(s);
-    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Y7, (void*)s->Wt,
-                    (void*)s->lpyr})
+    for (void* p : {(void*)s->P, (void*)s->G, (void*)s->M, (void*)s->V, (void*)s->Pb, (void*)s->Wt, (void*)s->lpyr,
+                    s->ck, s->fb})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -1166,10 +1239,6 @@ extern "C" int cd_surrogate_info(const cd_surrogate* s, int32_t* info) {
     return CD_OK;
 }
 
-namespace cd {
-bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y7, float y_scale, float y_shift,
-                           float y_floor, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep_rows.hip
-}
 
 template <typename T>
 static int infer_impl(cd_surrogate* s, cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale,
@@ -1179,10 +1248,6 @@ static int infer_impl(cd_surrogate* s, cd_tree* t, const cd_weights* w, float* N
     int rc = ensure_cap(s, batch);
     if (rc == CD_OK) rc = ensure_sweep_buffers(t, w->D);
     if (rc != CD_OK) return rc;
-    if (!s->Y7 && hipMalloc((void**)&s->Y7, (size_t)rows * s->Dout * 4) != hipSuccess) {
-        set_error("hipMalloc of the network rows failed");
-        return CD_ENOMEM;
-    }
     const bool fast = sizeof(T) == 2 && s->W % kFT == 0;
     if (fast) {
         const int W = s->W, np3 = out_pad(s);
@@ -1227,18 +1292,25 @@ static int infer_impl(cd_surrogate* s, cd_tree* t, const cd_weights* w, float* N
         }
         a.logged = 1;
     }
+    // the network's near shells go straight into the method's rows E
+    // (max(exp(y out_scale + out_shift) - floor, 0) per oct and direction)
+    OutE oe{t->ext, 0, t->lmax, s->D, s->norm[3], s->norm[2], kExtFloor};
     for (int64_t c0 = 0; c0 < rows; c0 += batch) {
         a.c0 = c0;
         a.n = batch;
+        oe.row0 = c0;
         k_features_rows<T><<<(unsigned)(batch / kFeatBlockRows), 256, 0, st>>>(a, (T*)s->X);
-        if (fast) forward_rows_fast(s, batch, st, s->Y7 + c0 * s->Dout);
-        else forward_rows<T>(s, batch, false, st, s->Y7 + c0 * s->Dout);
+        if (fast) {
+            forward_rows_fast(s, batch, st, nullptr, oe);
+        } else {
+            forward_rows<T>(s, batch, false, st, s->Y);
+            k_y_to_e<<<nblk(batch * s->Dout), 256, 0, st>>>(s->Y, batch, s->Dout, oe);
+        }
     }
-    // per leaf N = N_il + Q + max(exp(y out_scale + out_shift) - floor, 0) and
-    // chi: the method's row kernel with the network rows as the shells
-    // dl = 1..3 and the method's coarse table for dl >= 4
+    // per leaf N = N_il + E + Q and chi: the method's coarse tables (dl >= 4)
+    // and row kernel, as in the plain sweep
     launch_coarse(t, w, t->lmax - 4, true, st);
-    if (!launch_surrogate_rows(t, w, s->Y7, s->norm[3], s->norm[2], kExtFloor, N, chi, chi_scale, st)) {
+    if (!launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << t->lmax, st)) {
         set_error("cd_surrogate_infer: the row kernel does not take D = %d", w->D);
         return CD_EUNSUPPORTED;
     }
@@ -1294,30 +1366,45 @@ static AmrSweepArgs uniform_oct_args(const cd_tree* t, const cd_weights* w, floa
 }
 
 // Device lists of target octs for the generic per-oct kernel: info (L, oct
-// x, y, z), the 8 child leaf indices (row-major) and each child's output row
-// (-1: not wanted).
+// x, y, z), the 8 child leaf indices (row-major), each child's output row
+// (-1: not wanted) and the oct's row of the grid's near-shell rows E.
 struct OctLists {
     int32_t* info = nullptr;
     int64_t* src = nullptr;
     int64_t* out = nullptr;
-    int64_t* erow = nullptr;  // row-major oct index (the row of the uniform grid's E), when wanted
+    int64_t* erow = nullptr;
     int64_t n = 0;
-    int alloc(int64_t count, bool with_erow = false) {
+    // bytes of the lists of `count` octs
+    static size_t bytes(int64_t count) { return (size_t)count * (16 + 64 + 64 + 8) + 4 * 256; }
+    // carve them from `base` (256-byte aligned pieces)
+    void carve(char* base, int64_t count) {
+        size_t o = 0;
+        auto take = [&](size_t b) {
+            char* p = base + o;
+            o += (b + 255) / 256 * 256;
+            return p;
+        };
         n = count;
-        if (count == 0) return CD_OK;
-        if (hipMalloc((void**)&info, count * 16) != hipSuccess || hipMalloc((void**)&src, count * 64) != hipSuccess ||
-            hipMalloc((void**)&out, count * 64) != hipSuccess ||
-            (with_erow && hipMalloc((void**)&erow, count * 8) != hipSuccess)) {
-            set_error("hipMalloc of %lld target octs failed", (long long)count);
-            return CD_ENOMEM;
-        }
-        return CD_OK;
-    }
-    ~OctLists() {
-        for (void* p : {(void*)info, (void*)src, (void*)out, (void*)erow})
-            if (p) (void)hipFree(p);
+        info = (int32_t*)take((size_t)count * 16);
+        src = (int64_t*)take((size_t)count * 64);
+        out = (int64_t*)take((size_t)count * 64);
+        erow = (int64_t*)take((size_t)count * 8);
     }
 };
+
+// a handle buffer of at least `bytes` (grown, never shrunk)
+static bool grow(void** p, size_t* have, size_t bytes) {
+    if (bytes <= *have) return true;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        *p = nullptr;
+        return false;
+    }
+    *have = bytes;
+    return true;
+}
 
 __device__ __forceinline__ uint64_t d_splitmix64(uint64_t x) {
     x += 0x9e3779b97f4a7c15ull;
@@ -1368,11 +1455,6 @@ __global__ void k_make_tile_octs(int L, int64_t tpa, const int64_t* __restrict__
     put_oct(info, src, out, erow, k, L, 4 * tx + (o & 3), 4 * ty + ((o >> 2) & 3), 4 * tz + (o >> 4), 8, 0);
 }
 
-namespace cd {
-int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
-bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
-                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);                            // sweep_rows.hip
-}
 
 // The method on listed octs; E != nullptr: the grid's external columns
 // (shells dl = 1..3) are already in E, row ol.erow[k] for oct k.
@@ -1405,94 +1487,69 @@ extern "C" int cd_surrogate_check_fallback(cd_surrogate* s, cd_tree* t, const cd
     int rc = leaf_level_ok(s, t, "cd_surrogate_check_fallback");
     if (rc == CD_OK) rc = weights_ok(s, t, w, "cd_surrogate_check_fallback");
     if (rc != CD_OK) return rc;
-
     hipStream_t st = (hipStream_t)stream;
     const float cs = (float)(gamma * av_per_nh);
-    const int L = t->lmax;
-    // coarse tables of the method (shells dl >= 4) and, where the tiled
-    // kernels take this direction set, the external columns E of every oct:
-    // the samples and the fallback then read their shells dl = 1..3 from E
-    rc = ensure_sweep_buffers(t, w->D);
+    const int L = t->lmax, D = w->D;
+    // coarse tables of the method (shells dl >= 4) and the near shells E of
+    // every oct: the samples and the fallback read their shells from them
+    rc = ensure_sweep_buffers(t, D);
     if (rc != CD_OK) return rc;
     launch_coarse(t, w, L - 4, true, st);
-    const bool tiled = tiled_supported(t, w);
-    const float* E = nullptr;
-    if (tiled) {
-        launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), st);
-        E = t->ext;
-    }
-    // samples: ceil(frac * 512) leaves per tile of 8^3
+    launch_external_tiled(t, w, t->ext, 0, 1 << (L - 5), st);
+    const float* E = t->ext;
+    // samples: ceil(frac * 512) leaves per tile of 8^3, in the handle's buffers
     const int64_t tpa = ((int64_t)1 << L) / 8, nt = tpa * tpa * tpa;
     const int per = (int)std::ceil(frac * 512.0 - 1e-9);
     const int64_t ns = nt * per;
-    OctLists sl;
-    if ((rc = sl.alloc(ns, tiled)) != CD_OK) return rc;
-    float *sN = nullptr, *sChi = nullptr, *err = nullptr;
-    int64_t* cells = nullptr;
-    struct Free {
-        std::vector<void*> p;
-        ~Free() {
-            for (void* q : p) (void)hipFree(q);
-        }
-    } guard;
-    auto dmalloc = [&guard](void** p, size_t bytes) {
-        if (hipMalloc(p, bytes) != hipSuccess) return false;
-        guard.p.push_back(*p);
-        return true;
-    };
-    if (!dmalloc((void**)&sN, (size_t)ns * w->D * 4) || !dmalloc((void**)&sChi, ns * 4) ||
-        !dmalloc((void**)&err, ns * 4) || !dmalloc((void**)&cells, ns * 8)) {
-        set_error("hipMalloc of the check samples failed");
+    const size_t lists = OctLists::bytes(ns);
+    const size_t need = lists + (size_t)ns * 8 + (size_t)ns * D * 4 + (size_t)ns * 4 + (size_t)nt * 8 + 6 * 256;
+    if (!grow(&s->ck, &s->ck_bytes, need)) {
+        set_error("hipMalloc of %zu bytes (check samples) failed", need);
         return CD_ENOMEM;
     }
+    char* base = (char*)s->ck;
+    OctLists sl;
+    sl.carve(base, ns);
+    size_t o = lists;
+    auto take = [&](size_t b) {
+        char* p = base + o;
+        o += (b + 255) / 256 * 256;
+        return p;
+    };
+    int64_t* cells = (int64_t*)take((size_t)ns * 8);
+    float* sN = (float*)take((size_t)ns * D * 4);
+    float* sChi = (float*)take((size_t)ns * 4);
+    int64_t* fail = (int64_t*)take((size_t)nt * 8);
+    unsigned long long* cnt = (unsigned long long*)take(16);
     k_make_samples<<<nblk(ns), 256, 0, st>>>(L, tpa, per, seed, ns, sl.info, sl.src, sl.out, sl.erow, cells);
     run_octs(t, w, cs, sl, sN, sChi, st, E);
-    k_sample_err<<<nblk(ns), 256, 0, st>>>(chi_dev, cells, ns, sChi, err);
-    std::vector<float> e((size_t)ns);
-    CD_HIP(hipMemcpyAsync(e.data(), err, ns * 4, hipMemcpyDeviceToHost, st));
+    k_clear_u64<<<1, 64, 0, st>>>(cnt, 2);
+    k_tile_check<<<nblk(nt), 256, 0, st>>>(chi_dev, cells, sChi, nt, per, (float)tol_chi, fail, cnt);
+    unsigned long long h[2] = {0, 0};
+    CD_HIP(hipMemcpyAsync(h, cnt, 16, hipMemcpyDeviceToHost, st));
     CD_HIP(hipStreamSynchronize(st));
-    // tiles with a failing sample: every oct recomputed by the method
-    std::vector<int64_t> fail;
-    float emax = 0.f;
-    for (int64_t tl = 0; tl < nt; ++tl) {
-        bool bad = false;
-        for (int j = 0; j < per; ++j) {
-            const float ej = e[(size_t)(tl * per + j)];
-            emax = std::max(emax, std::isfinite(ej) ? ej : INFINITY);
-            bad |= !(ej <= (float)tol_chi);
+    const int64_t nfail = (int64_t)h[0];
+    float emax;
+    const uint32_t eb = (uint32_t)h[1];
+    std::memcpy(&emax, &eb, 4);
+    if (nfail * 4 > nt) {
+        // many tiles: the method over the whole grid, straight into N and
+        // chi (the passing tiles then hold the method's values too); with E
+        // in hand only the target rows remain
+        if (!launch_target_rows(t, w, E, N_dev, chi_dev, cs, 0, (int64_t)1 << L, st)) {
+            set_error("cd_surrogate_check_fallback: the target-row kernel does not take D = %d", D);
+            return CD_EUNSUPPORTED;
         }
-        if (bad) fail.push_back(tl);
-    }
-    const int64_t nfail = (int64_t)fail.size();
-    if (nfail > 0) {
-        int64_t* dfail = nullptr;
-        if (!dmalloc((void**)&dfail, nfail * 8)) {
-            set_error("hipMalloc of the fallback tile list failed");
+    } else if (nfail > 0) {
+        // every oct (64 per tile) of the failing tiles, all 8 leaves in place
+        if (!grow(&s->fb, &s->fb_bytes, OctLists::bytes(nfail * 64))) {
+            set_error("hipMalloc of the fallback lists (%lld tiles) failed", (long long)nfail);
             return CD_ENOMEM;
         }
-        CD_HIP(hipMemcpyAsync(dfail, fail.data(), nfail * 8, hipMemcpyHostToDevice, st));
-        if (nfail * 4 > nt) {
-            // many tiles: the method over the whole grid, straight into N
-            // and chi (the passing tiles then hold the method's values too);
-            // with E in hand only the target rows remain
-            if (E) {
-                if (!launch_target_rows(t, w, E, N_dev, chi_dev, cs, 0, (int64_t)1 << L, st)) {
-                    set_error("cd_surrogate_check_fallback: the target-row kernel does not take D = %d", w->D);
-                    return CD_EUNSUPPORTED;
-                }
-            } else if ((rc = uniform_columns(t, w, N_dev, chi_dev, cs, st)) != CD_OK) {
-                return rc;
-            }
-            CD_HIP(hipGetLastError());
-            CD_HIP(hipStreamSynchronize(st));
-        } else {
-            OctLists fl;
-            if ((rc = fl.alloc(nfail * 64, tiled)) != CD_OK) return rc;
-            k_make_tile_octs<<<nblk(nfail * 64), 256, 0, st>>>(L, tpa, dfail, nfail, fl.info, fl.src, fl.out, fl.erow);
-            run_octs(t, w, cs, fl, N_dev, chi_dev, st, E);
-            CD_HIP(hipGetLastError());
-            CD_HIP(hipStreamSynchronize(st));  // lists are freed on return
-        }
+        OctLists fl;
+        fl.carve((char*)s->fb, nfail * 64);
+        k_make_tile_octs<<<nblk(nfail * 64), 256, 0, st>>>(L, tpa, fail, nfail, fl.info, fl.src, fl.out, fl.erow);
+        run_octs(t, w, cs, fl, N_dev, chi_dev, st, E);
     }
     CD_HIP(hipGetLastError());
     *n_fallback_tiles = nfail;

@@ -33,12 +33,6 @@ struct RowArgs {
     float chi_scale;
     int64_t z0;         // first target plane of this launch
     int64_t nz;         // number of target planes of this launch
-    // learned surrogate: instead of E, the shells dl = 1..3 of every target
-    // are max(exp(y s + m) - floor, 0) from the network's row of the oct's
-    // level-7 ancestor (rows x fastest; a row holds one block of D per oct
-    // inside the level-7 cell, blocks x fastest); q4 adds dl >= 4 as usual
-    const float* y7;
-    float y_scale, y_shift, y_floor;
 };
 
 #define CD_CONST __attribute__((address_space(4)))
@@ -137,17 +131,7 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
         c1[j] = p.y;
     }
     float e0[D], e1[D];
-    if (a.y7) {
-        // level L-1 oct -> its level-7 cell's row and its block in that row
-        const int sb = L - 8;
-        const int64_t oy = y >> 1, oz = z >> 1, m = ((int64_t)1 << sb) - 1;
-        const int64_t r7 = (((oz >> sb) << 7) + (oy >> sb)) * 128 + (ax >> sb);
-        const int64_t jb = (ax & m) + ((oy & m) << sb) + ((oz & m) << (2 * sb));
-        const float* yr = a.y7 + ((r7 << (3 * sb)) + jb) * D;
-#pragma unroll
-        for (int d = 0; d < D; ++d) e0[d] = fmaxf(__expf(fmaf(yr[d], a.y_scale, a.y_shift)) - a.y_floor, 0.f);
-        if (a.q4) add_coarse<D>(a, ax, Y, z >> 1, n1, e0);
-    } else if constexpr (D <= 12) {
+    if constexpr (D <= 12) {
         // short rows: each lane loads its oct's rows of E and of the coarse
         // table itself (their lines are few and the LDS is kept for staging)
         const float* er = a.E + oct * D;
@@ -291,40 +275,6 @@ static void launch_rows(const RowArgs& a, int64_t nz, hipStream_t s) {
     const int64_t seg = n1 >= 64 ? 64 : n1;
     const int64_t blocks = (nz / 2) * n1 * (n1 / seg);  // (oct row, segment) pairs
     k_target_rows<D><<<(unsigned)blocks, 256, 0, s>>>(a);
-}
-
-// The learned surrogate's rows (every target plane): shells dl = 1..3 from
-// the network rows y7 of the level-7 cells (needs 2^L >= 256; rows of
-// 8^(L-8) D values), dl >= 4 from the coarse table of level L-4 (built by
-// the coarse chain beforehand).
-bool launch_surrogate_rows(const cd_tree* t, const cd_weights* w, const float* y7, float y_scale, float y_shift,
-                           float y_floor, float* N, float* chi, float chi_scale, hipStream_t s) {
-    const int D = w->D;
-    if (t->lmax < 8) return false;
-    RowArgs a{};
-    a.leaf = t->leaf;
-    a.L = t->lmax;
-    a.q4 = t->q[t->lmax - 4];
-    a.gloc = w->gloc;
-    a.sgn = w->sgn;
-    a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));
-    a.N = N;
-    a.chi = chi;
-    a.chi_scale = chi_scale;
-    a.z0 = 0;
-    a.nz = (int64_t)1 << t->lmax;
-    a.y7 = y7;
-    a.y_scale = y_scale;
-    a.y_shift = y_shift;
-    a.y_floor = y_floor;
-    switch (D) {
-        case 6: launch_rows<6>(a, a.nz, s); return true;
-        case 12: launch_rows<12>(a, a.nz, s); return true;
-        case 24: launch_rows<24>(a, a.nz, s); return true;
-        case 40: launch_rows<40>(a, a.nz, s); return true;
-        case 48: launch_rows<48>(a, a.nz, s); return true;
-        default: return false;
-    }
 }
 
 // Target planes [z0, z0 + nz).
