@@ -189,18 +189,20 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
                                 ? (int64_t)blockIdx.x * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
                                 : ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
         const CD_CONST uint32_t* cls = (const CD_CONST uint32_t*)a.slots + (size_t)ci * D * kSlotWords;
-#pragma unroll 1
-        for (int d0 = 0; d0 < D; d0 += DG) {
-            float acc[DG];
+        // every direction of the oct first, then its whole row back to back:
+        // the row's cache lines are completed while they sit in L2 (written
+        // a piece per direction group, they were evicted half-written and
+        // written to memory several times)
+        float acc[D];
 #pragma unroll
-            for (int j = 0; j < DG; ++j)
-                acc[j] = dx1 * slot_sum(cls + (size_t)(d0 + j) * kSlotWords, lds, base, lane);
-            // the oct's row piece of external columns
-            float* row = a.E + oct * D + d0;
+        for (int d = 0; d < D; ++d) acc[d] = dx1 * slot_sum(cls + (size_t)d * kSlotWords, lds, base, lane);
+        float* row = a.E + oct * D;
+#pragma unroll
+        for (int d0 = 0; d0 < D; d0 += DG) {
             if constexpr (DG == 4)
-                *reinterpret_cast<float4*>(row) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                *reinterpret_cast<float4*>(row + d0) = make_float4(acc[d0], acc[d0 + 1], acc[d0 + 2], acc[d0 + 3]);
             else
-                *reinterpret_cast<float2*>(row) = make_float2(acc[0], acc[1]);
+                *reinterpret_cast<float2*>(row + d0) = make_float2(acc[d0], acc[d0 + 1]);
         }
     }
 }
