@@ -38,6 +38,10 @@ struct TileArgs {
     const int32_t* tile_lvl;
     const float* levs[CD_MAX_LEVEL + 1];
     double box;
+    // workgroups per tile (1, 2 or 4), each taking kRounds / split of the
+    // rounds: more workgroups for grids of few tiles (one workgroup per CU
+    // fits the LDS, and a 2^7 grid has only 64 tiles of octs)
+    int split;
 };
 
 // Read-only tables are read through the constant address space: with a
@@ -100,13 +104,14 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     using namespace tile;
     __shared__ float lds[kLdsWords];  // levels L-1, L-2, L-3 at 0, kL2, kL3 (common pitches)
 
-    const int Lw = a.tile_lvl ? __builtin_amdgcn_readfirstlane(a.tile_lvl[blockIdx.x]) : a.L;
+    const int slot = (int)blockIdx.x / a.split, part = (int)blockIdx.x - slot * a.split;
+    const int Lw = a.tile_lvl ? __builtin_amdgcn_readfirstlane(a.tile_lvl[slot]) : a.L;
     const float* lev1 = a.tile_lvl ? a.levs[Lw - 1] : a.lev1;
     const float* lev2 = a.tile_lvl ? a.levs[Lw - 2] : a.lev2;
     const float* lev3 = a.tile_lvl ? a.levs[Lw - 3] : a.lev3;
     const float dx1 = a.tile_lvl ? (float)(a.box * ldexp(1.0, 1 - Lw)) : a.dx1;
     const int tpa = a.tile_lvl ? 1 << (Lw - 5) : a.tiles_per_axis;
-    const int tile_id = a.tile_list ? a.tile_list[blockIdx.x] : (int)blockIdx.x;
+    const int tile_id = a.tile_list ? a.tile_list[slot] : slot;
     const int tx = tile_id % tpa, ty = (tile_id / tpa) % tpa,
               tz = (a.tile_list ? 0 : a.tz0) + tile_id / (tpa * tpa);
     const int X1 = tx * kOcts, Y1 = ty * kOcts, Z1 = tz * kOcts;  // tile origin, level L-1 cells
@@ -181,12 +186,13 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     constexpr int DG = D % 4 == 0 ? 4 : 2;  // directions per store
     static_assert(D % DG == 0, "direction groups must tile D");
 
-    for (int r = 0; r < kRounds; ++r) {
+    const int rpp = kRounds / a.split;  // rounds of this workgroup
+    for (int r = part * rpp; r < (part + 1) * rpp; ++r) {
         const int ci = r * 16 + wave;  // configuration class, wave-uniform
         const int cx = ci & 3, cy = (ci >> 2) & 3, cz = ci >> 4;
         const int Ax = X1 + 4 * lx + cx, Ay = Y1 + 4 * ly + cy, Az = Z1 + 4 * lz + cz;
         const int64_t oct = a.tile_list
-                                ? (int64_t)blockIdx.x * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
+                                ? (int64_t)slot * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
                                 : ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
         const CD_CONST uint32_t* cls = (const CD_CONST uint32_t*)a.slots + (size_t)ci * D * kSlotWords;
         // every direction of the oct first, then its whole row back to back:
@@ -207,10 +213,15 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
     }
 }
 
+// workgroups per tile for a launch of ntiles tiles (about two workgroups per
+// CU at least, the staging amortised over every round otherwise)
+static int split_for(int64_t ntiles) { return ntiles <= 128 ? 4 : (ntiles <= 384 ? 2 : 1); }
+
 template <int D>
-static void launch(const TileArgs& a, int nz, hipStream_t s) {
+static void launch(TileArgs a, int nz, hipStream_t s) {
     const int ntiles = a.tiles_per_axis * a.tiles_per_axis * nz;
-    k_external_tiled<D><<<ntiles, tile::kThreads, 0, s>>>(a);
+    a.split = split_for(ntiles);
+    k_external_tiled<D><<<ntiles * a.split, tile::kThreads, 0, s>>>(a);
 }
 
 // The tiled kernels handle this direction set: D in the set the row
@@ -241,7 +252,8 @@ void launch_external_tiled_list(const float* const* levs, int nlev, double box, 
     a.E = E;
     a.tile_list = tiles;
     if (ntiles <= 0) return;
-    const unsigned nb = (unsigned)ntiles;
+    a.split = split_for(ntiles);
+    const unsigned nb = (unsigned)(ntiles * a.split);
     switch (w->D) {
         case 6: k_external_tiled<6><<<nb, tile::kThreads, 0, s>>>(a); break;
         case 12: k_external_tiled<12><<<nb, tile::kThreads, 0, s>>>(a); break;
