@@ -175,7 +175,8 @@ def main():
     if sphere:
         sets = {"axes6": colden.directions(colden.CD_DIR_AXES6, 0), "mn3x4": dirs,
                 "mn5x8": colden.directions(colden.CD_DIR_PAPER_MN, 5, 8),
-                "mn7x12": colden.directions(colden.CD_DIR_PAPER_MN, 7, 12)}
+                "mn7x12": colden.directions(colden.CD_DIR_PAPER_MN, 7, 12),
+                "healpix2": colden.directions(colden.CD_DIR_HEALPIX, 2)}
     D = dirs.shape[0]
     print(f"# generated workload in {time.time() - t0:.1f}s: {tin.n_leaf} leaves, D={D}",
           file=sys.stderr, flush=True)
@@ -190,14 +191,19 @@ def main():
     rng = np.random.default_rng(0)
     check = rng.choice(tin.n_leaf, size=min(2000, tin.n_leaf), replace=False)
 
-    def measure(prec: str, mode: int = colden.CD_PRECALC73, u=None, Nout=None) -> dict:
+    def measure(prec: str, mode: int = colden.CD_PRECALC73, u=None, Nout=None, packed: bool = False) -> dict:
         u = dirs if u is None else u
         Nout = N if Nout is None else Nout
         w = colden.Weights(u, precision=PREC[prec], mode=mode)
+        if packed:  # the columns as 16-bit log codes (half the output bytes)
+            Nout = torch.empty((tin.n_leaf, u.shape[0]), dtype=torch.int16, device=dev)
 
         def step():
             tree.update(leaf)
-            colden.column_densities(tree, w, Nout, chi)
+            if packed:
+                colden.column_densities_log16(tree, w, Nout, chi)
+            else:
+                colden.column_densities(tree, w, Nout, chi)
 
         for _ in range(args.warmup):
             step()
@@ -223,9 +229,13 @@ def main():
         torch.cuda.synchronize()
         out = {"ms_per_step": ms_step, "value": tin.n_leaf * u.shape[0] / (ms_step * 1e-3),
                "stages_ms": {k: float(np.mean(v)) for k, v in stages.items()},
-               "sample": Nout[torch.from_numpy(check).to(dev)].cpu().numpy().astype(np.float64),
+               "sample": (colden.decode_log16(Nout[torch.from_numpy(check).to(dev)]) if packed else
+                          Nout[torch.from_numpy(check).to(dev)]).cpu().numpy().astype(np.float64),
                "split_steps": w.split_steps()}
         w.close()
+        if packed:
+            del Nout
+            torch.cuda.empty_cache()
         return out
 
     main_form = measure(args.precision)
@@ -260,6 +270,12 @@ def main():
                 continue
             forms[p] = measure(p)
             print(f"# form {p}: {forms[p]['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if not args.no_forms and not amr and D % 4 == 0 and L >= 5:
+        # opt-in output format: 16-bit log codes of N (|d ln N| <= 3.4e-4 by
+        # construction), FP32 and split sums
+        for p in ("fp32", "bf16x2"):
+            forms[f"{p}_log16"] = measure(p, packed=True)
+            print(f"# form {p}_log16: {forms[f'{p}_log16']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     d12 = None
     if not args.no_forms and not amr and D != 12:
         # the same field with 12 sectors (HEALPix N_side = 1)
@@ -350,7 +366,7 @@ def main():
                 e1["sets"][name] = {"D": int(u.shape[0]), "sweep_ms": ms_sweep,
                                     "cell_dir_per_s": tin.n_leaf * u.shape[0] / (ms_sweep * 1e-3),
                                     "mean_abs_dchi_vs_rays": float(d.mean()), "max_abs_dchi_vs_rays": float(d.max()),
-                                    "paper_mean_abs_dchi": paper[name],
+                                    "paper_mean_abs_dchi": paper.get(name),
                                     "max_rel_err_vs_oracle_tree": float(np.max(np.abs(gotN - ref_tree) / ref_tree))}
                 w.close()
                 del Ns, cs
@@ -371,10 +387,13 @@ def main():
              "external_ms": f["stages_ms"]["external"], "sweep_ms": f["stages_ms"]["sweep"],
              "max_rel_err_vs_oracle": rel, "max_abs_dlnN_vs_oracle": lnerr,
              "oracle_sample": f"{check.shape[0]} random leaves"}
-        if p != "fp32" and not amr and f["stages_ms"]["external"] > 0:
+        if p.endswith("_log16"):
+            o["output_format"] = ("16-bit log codes, N = 2^(40 + c/1024): 2 B per output instead of 4 "
+                                  "(an output-format change; the sums and chi are those of the unpacked form)")
+        if p not in ("fp32", "fp32_log16") and not amr and f["stages_ms"]["external"] > 0:
             flops = f["split_steps"] * 4 * 3 * (16 * 16 * 32 * 2) * n_tiles
             tf = flops / (f["stages_ms"]["external"] * 1e-3) / 1e12
-            o["mfma"] = {"kernel": f"k_external_mfma<{p}>", "flops_per_launch": flops, "achieved_tflops": tf,
+            o["mfma"] = {"kernel": f"k_external_mfma<{p.split('_')[0]}>", "flops_per_launch": flops, "achieved_tflops": tf,
                          "peak_tflops": MFMA_PEAK_TFLOPS, "frac": tf / MFMA_PEAK_TFLOPS}
         forms_out[p] = o
     if insitu is not None:

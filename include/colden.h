@@ -306,6 +306,23 @@ int cd_column_densities(cd_tree* tree, const cd_weights* w, float* N_dev, float*
                         double av_per_nh, double gamma, void* stream);
 
 /*
+ * The same sweep with the columns written in a packed 16-bit format, half
+ * the bytes of N (an output format, not part of the paper's method; the
+ * sums and chi are those of cd_column_densities, chi from the FP32 columns):
+ * Ncode_dev[n_leaf][D] (uint16, row-major, direction fastest) holds
+ *   c = round(1024 (log2 N - 40)), clamped to 0 .. 65535,
+ * so N = 2^(40 + c / 1024) to within 2^-11 in log2 (|d ln N| <= 3.4e-4)
+ * for 2^40 (1.1e12 cm^-2) <= N <= 2^104; smaller columns give c = 0.
+ * Uniform grids of 2^L >= 32 cells per axis, D in {12, 24, 40, 48}, any
+ * precision and mode of the weights.  Ncode_dev 16-byte and chi_dev 8-byte
+ * aligned.  Asynchronous on `stream`; allocates nothing.
+ * Errors: CD_EINVAL (NULL handles or output, misaligned buffers),
+ * CD_EUNSUPPORTED (adaptive tree, other D or a smaller grid), CD_EDEVICE.
+ */
+int cd_column_densities_log16(cd_tree* tree, const cd_weights* w, uint16_t* Ncode_dev, float* chi_dev,
+                              double av_per_nh, double gamma, void* stream);
+
+/*
  * Screening factor (Eq. 7): A_V = N av_per_nh, chi = (1/D) sum_d
  * exp(-gamma A_V,d).  N_dev [n_leaf][D]; writes chi_dev[n_leaf] and, if not
  * NULL, av_dev[n_leaf][D].  Asynchronous on `stream`.

@@ -24,7 +24,8 @@ GAMMA = 3.74
 EXPORTS = [
     "cd_last_error", "cd_version", "cd_directions", "cd_build_tree", "cd_tree_update",
     "cd_tree_n_leaf", "cd_tree_leaf_coords", "cd_tree_destroy", "cd_precompute_weights",
-    "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_screening_factor",
+    "cd_weights_n_dirs", "cd_weights_split_steps", "cd_weights_destroy", "cd_column_densities", "cd_column_densities_log16",
+    "cd_screening_factor",
     "cd_profile_enable", "cd_profile_read", "cd_check_densities", "cd_heating_rates", "cd_screening_heating",
     "cd_weight_lists", "cd_tree_workspace_bytes", "cd_weights_workspace_bytes", "cd_tree_set_aux_stream",
 ]
@@ -67,6 +68,7 @@ def lib():
         L.cd_weights_destroy.argtypes = [P]
         L.cd_weights_destroy.restype = None
         L.cd_column_densities.argtypes = [P, P, P, P, D, D, P]
+        L.cd_column_densities_log16.argtypes = [P, P, P, P, D, D, P]
         L.cd_screening_factor.argtypes = [P, I64, I, D, D, P, P, P]
         L.cd_profile_enable.argtypes = [P, I]
         L.cd_profile_read.argtypes = [P, P]
@@ -282,6 +284,25 @@ def column_densities(tree: Tree, w: Weights, N, chi=None, av_per_nh: float = AV_
     chip = _dev_f32(chi, "chi", numel=tree.n_leaf) if chi is not None else None
     _check(lib().cd_column_densities(tree.h, w.h, Np, chip, av_per_nh, gamma, _stream(stream)))
     return N
+
+
+def column_densities_log16(tree: Tree, w: Weights, Ncode, chi=None, av_per_nh: float = AV_PER_NH,
+                           gamma: float = GAMMA, stream=None):
+    """Ncode: int16 CUDA tensor [n_leaf, D] receiving the packed columns
+    (16-bit codes c, N = 2^(40 + c / 1024), c read as unsigned; see
+    decode_log16); chi: optional float32 [n_leaf]."""
+    import torch
+    Cp = _dev(Ncode, torch.int16, "Ncode", shape=(tree.n_leaf, w.D))
+    chip = _dev_f32(chi, "chi", numel=tree.n_leaf) if chi is not None else None
+    _check(lib().cd_column_densities_log16(tree.h, w.h, Cp, chip, av_per_nh, gamma, _stream(stream)))
+    return Ncode
+
+
+def decode_log16(Ncode):
+    """Columns (cm^-2, float64) from the packed codes of column_densities_log16."""
+    import torch
+    c = Ncode.to(torch.int32) & 0xFFFF
+    return torch.exp2(40.0 + c.to(torch.float64) / 1024.0)
 
 
 def check_densities(leaf_n, stream=None) -> int:

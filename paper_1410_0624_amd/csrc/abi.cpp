@@ -123,6 +123,30 @@ static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.slots, &w->slots, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, gf, &w->gloc, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.sgn, &w->sgn, s);
+    {
+        // the row kernel's chords per direction and parity (oy, oz) of the
+        // target row: for the pair of x targets of an oct, own-column chords
+        // Wo[j] and sibling-column chords of the low (Wsl) and high (Wsh)
+        // target, zero where the ray cannot cross into that sibling
+        const int D = w->D;
+        std::vector<float> gq((size_t)D * 4 * 12, 0.f);
+        for (int d = 0; d < D; ++d) {
+            const int sg = w->host.sgn[(size_t)d];
+            const bool fx0 = (sg & 1) == 0;  // the low-x target runs into its x sibling
+            for (int q = 0; q < 4; ++q) {
+                const int oy = q & 1, oz = q >> 1;
+                const int fyz = (oy == ((sg >> 1) & 1) ? 1 : 0) | (oz == ((sg >> 2) & 1) ? 2 : 0);
+                float* g = &gq[((size_t)d * 4 + q) * 12];
+                for (int j = 0; j < 4; ++j) {
+                    if ((j & fyz) != j) continue;
+                    g[j] = (float)w->host.gloc[(size_t)d * 8 + 2 * j];
+                    const float sib = (float)w->host.gloc[(size_t)d * 8 + 2 * j + 1];
+                    (fx0 ? g[4 + j] : g[8 + j]) = sib;
+                }
+            }
+        }
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, gq, &w->glq, s);
+    }
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.ghdr, &w->ghdr, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.gent, &w->gent, s);
     // [D][6]: the unit vector (components below 1e-14 snapped to 0) and the

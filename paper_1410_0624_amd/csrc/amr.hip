@@ -950,9 +950,9 @@ int amr_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi
     // the FP32 gather; direction counts the tiled kernels do not take are
     // gathered for every target (FP32, or on the matrix cores in bf16x2)
     const int D = w->D;
-    const bool dset = D == 6 || D == 12 || D == 24 || D == 40 || D == 48;
+    const bool dset = D == 6 || D == 12 || D == 24 || D == 40 || D == 48 || D == 84;
     if (w->precision == CD_FP16X2 && !dset) {
-        set_error("cd_column_densities: CD_FP16X2 on adaptive trees needs D in {6, 12, 24, 40, 48} "
+        set_error("cd_column_densities: CD_FP16X2 on adaptive trees needs D in {6, 12, 24, 40, 48, 84} "
                   "(binary16 needs the per-tile scale of the tiled kernel)");
         return CD_EUNSUPPORTED;
     }
@@ -1072,14 +1072,15 @@ static void launch_octs(const AmrSweepArgs& a, hipStream_t s) {
 void launch_target_octs(const AmrSweepArgs& a, hipStream_t s) {
     if (a.n_tg <= 0) return;
     if (a.E && (!a.erow || a.all_rows) && (reinterpret_cast<uintptr_t>(a.N) & 15) == 0 &&
-        (a.D == 6 || a.D == 12 || a.D == 24 || a.D == 40 || a.D == 48)) {
+        (a.D == 6 || a.D == 12 || a.D == 24 || a.D == 40 || a.D == 48 || a.D == 84)) {
         const unsigned nb = (unsigned)((a.n_tg + 31) / 32), nb2 = (unsigned)((a.n_tg + 15) / 16);
         switch (a.D) {
             case 6: k_target_leaves<6, 1><<<nb, 256, 0, s>>>(a); break;
             case 12: k_target_leaves<12, 1><<<nb, 256, 0, s>>>(a); break;
             case 24: k_target_leaves<24, 1><<<nb, 256, 0, s>>>(a); break;
             case 40: k_target_leaves<40, 2><<<nb2, 256, 0, s>>>(a); break;
-            default: k_target_leaves<48, 2><<<nb2, 256, 0, s>>>(a); break;
+            case 48: k_target_leaves<48, 2><<<nb2, 256, 0, s>>>(a); break;
+            default: k_target_leaves<84, 2><<<nb2, 256, 0, s>>>(a); break;
         }
         return;
     }

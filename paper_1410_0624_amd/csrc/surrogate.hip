@@ -811,9 +811,10 @@ int ensure_sweep_buffers(const cd_tree* t, int D);                              
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const int64_t* const* need = nullptr, const int64_t* n_need = nullptr);              // sweep.hip
 bool tiled_supported(const cd_tree* t, const cd_weights* w);                                                 // sweep_tile.hip
-int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s);  // sweep.hip
+int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s,
+                    uint16_t* Nq = nullptr);                                                                  // sweep.hip
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
-                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);                            // sweep_rows.hip
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s, uint16_t* Nq = nullptr);                            // sweep_rows.hip
 bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);  // sweep_tile.hip
 
 // The method's near shells dl = 1..3 of every oct into the tree's rows E

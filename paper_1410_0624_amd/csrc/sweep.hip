@@ -294,7 +294,7 @@ int ensure_sweep_buffers(const cd_tree* t, int D) {
 
 bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int tz0, int nz, hipStream_t s);
 bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, float* N, float* chi,
-                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s);
+                        float chi_scale, int64_t z0, int64_t nz, hipStream_t s, uint16_t* Nq = nullptr);
 
 bool tiled_supported(const cd_tree* t, const cd_weights* w);
 bool launch_external_mfma(const cd_tree* t, const cd_weights* w, float* E, hipStream_t s);
@@ -364,9 +364,15 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
     }
 }
 
-int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s) {
+int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float chi_scale, hipStream_t s,
+                    uint16_t* Nq = nullptr) {
     const int L = t->lmax;
     const int D = w->D;
+    if (Nq && !(tiled_supported(t, w) && D % 4 == 0)) {
+        set_error("cd_column_densities_log16: needs a uniform grid of 2^L >= 32 cells per axis and D in "
+                  "{12, 24, 40, 48}");
+        return CD_EUNSUPPORTED;
+    }
     if (w->len[4] != kCoarseLen) {
         set_error("internal: coarse weight lists of length %d, expected %d", w->len[4], kCoarseLen);
         return CD_EINVAL;
@@ -409,7 +415,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         launch_insitu_coarse(t, w, t->ext, true, s);
         CD_HIP(mark(CD_STAGE_COARSE, 1, s));
         CD_HIP(mark(CD_STAGE_ROWS, 0, s));
-        launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s);
+        launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s, Nq);
         CD_HIP(mark(CD_STAGE_ROWS, 1, s));
         CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
         CD_HIP(hipGetLastError());
@@ -459,7 +465,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         if (rows_on_s) {
             CD_HIP(hipStreamWaitEvent(s, t->ev[kMaxSlabs - 1], 0));
             CD_HIP(mark(CD_STAGE_ROWS, 0, s));
-            launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s);
+            launch_target_rows(t, w, t->ext, N, chi, chi_scale, 0, (int64_t)1 << L, s, Nq);
             CD_HIP(mark(CD_STAGE_ROWS, 1, s));
             CD_HIP(mark(CD_STAGE_SWEEP, 1, s));
             CD_HIP(hipGetLastError());
@@ -469,7 +475,7 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
             CD_HIP(hipStreamWaitEvent(aux, t->ev[j], 0));
             if (j == 0) CD_HIP(mark(CD_STAGE_ROWS, 0, aux));
             if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][0], aux));
-            launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, aux);
+            launch_target_rows(t, w, t->ext, N, chi, chi_scale, (int64_t)j * per * 32, (int64_t)per * 32, aux, Nq);
             if (t->prof) CD_HIP(hipEventRecord(t->pslab[1][j][1], aux));
         }
         CD_HIP(mark(CD_STAGE_ROWS, 1, aux));
@@ -506,6 +512,28 @@ extern "C" int cd_column_densities(cd_tree* t, const cd_weights* w, float* N_dev
     hipStream_t s = (hipStream_t)stream;
     if (t->uniform) return cd::uniform_columns(t, w, N_dev, chi_dev, scale, s);
     return cd::amr_columns(t, w, N_dev, chi_dev, scale, s);
+}
+
+extern "C" int cd_column_densities_log16(cd_tree* t, const cd_weights* w, uint16_t* Ncode_dev, float* chi_dev,
+                                         double av_per_nh, double gamma, void* stream) {
+    cd::clear_error();
+    if (!t || !w || !Ncode_dev) {
+        cd::set_error("cd_column_densities_log16: NULL argument");
+        return CD_EINVAL;
+    }
+    if (chi_dev && !(std::isfinite(av_per_nh) && std::isfinite(gamma))) {
+        cd::set_error("cd_column_densities_log16: non-finite screening parameters");
+        return CD_EINVAL;
+    }
+    if (!cd::is_aligned(Ncode_dev, 16) || (chi_dev && !cd::is_aligned(chi_dev, 8))) {
+        cd::set_error("cd_column_densities_log16: codes must be 16-byte aligned and chi 8-byte aligned");
+        return CD_EINVAL;
+    }
+    if (!t->uniform) {
+        cd::set_error("cd_column_densities_log16: needs a uniform grid");
+        return CD_EUNSUPPORTED;
+    }
+    return cd::uniform_columns(t, w, nullptr, chi_dev, (float)(gamma * av_per_nh), (hipStream_t)stream, Ncode_dev);
 }
 
 extern "C" int cd_screening_factor(const float* N_dev, int64_t n_leaf, int D, double av_per_nh, double gamma,

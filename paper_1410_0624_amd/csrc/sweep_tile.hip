@@ -195,20 +195,36 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
                                 ? (int64_t)slot * 4096 + (((Az - Z1) * kOcts + (Ay - Y1)) * kOcts + (Ax - X1))
                                 : ((int64_t)Az << (2 * L1)) + ((int64_t)Ay << L1) + Ax;
         const CD_CONST uint32_t* cls = (const CD_CONST uint32_t*)a.slots + (size_t)ci * D * kSlotWords;
-        // every direction of the oct first, then its whole row back to back:
-        // the row's cache lines are completed while they sit in L2 (written
-        // a piece per direction group, they were evicted half-written and
-        // written to memory several times)
-        float acc[D];
-#pragma unroll
-        for (int d = 0; d < D; ++d) acc[d] = dx1 * slot_sum(cls + (size_t)d * kSlotWords, lds, base, lane);
         float* row = a.E + oct * D;
+        if constexpr (D <= 48) {
+            // every direction of the oct first, then its whole row back to
+            // back: the row's cache lines are completed while they sit in L2
+            // (written a piece per direction group, they were evicted
+            // half-written and written to memory several times)
+            float acc[D];
 #pragma unroll
-        for (int d0 = 0; d0 < D; d0 += DG) {
-            if constexpr (DG == 4)
-                *reinterpret_cast<float4*>(row + d0) = make_float4(acc[d0], acc[d0 + 1], acc[d0 + 2], acc[d0 + 3]);
-            else
-                *reinterpret_cast<float2*>(row + d0) = make_float2(acc[d0], acc[d0 + 1]);
+            for (int d = 0; d < D; ++d) acc[d] = dx1 * slot_sum(cls + (size_t)d * kSlotWords, lds, base, lane);
+#pragma unroll
+            for (int d0 = 0; d0 < D; d0 += DG) {
+                if constexpr (DG == 4)
+                    *reinterpret_cast<float4*>(row + d0) = make_float4(acc[d0], acc[d0 + 1], acc[d0 + 2], acc[d0 + 3]);
+                else
+                    *reinterpret_cast<float2*>(row + d0) = make_float2(acc[d0], acc[d0 + 1]);
+            }
+        } else {
+            // more directions than registers for a whole row: a piece per
+            // direction group
+#pragma unroll 1
+            for (int d0 = 0; d0 < D; d0 += DG) {
+                float acc[DG];
+#pragma unroll
+                for (int j = 0; j < DG; ++j)
+                    acc[j] = dx1 * slot_sum(cls + (size_t)(d0 + j) * kSlotWords, lds, base, lane);
+                if constexpr (DG == 4)
+                    *reinterpret_cast<float4*>(row + d0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+                else
+                    *reinterpret_cast<float2*>(row + d0) = make_float2(acc[0], acc[1]);
+            }
         }
     }
 }
@@ -228,7 +244,7 @@ static void launch(TileArgs a, int nz, hipStream_t s) {
 // kernels are instantiated for, and every weight list fits its slot.
 bool tiled_weights_ok(const cd_weights* w) {
     const int D = w->D;
-    if (!(D == 6 || D == 12 || D == 24 || D == 40 || D == 48)) return false;
+    if (!(D == 6 || D == 12 || D == 24 || D == 40 || D == 48 || D == 84)) return false;
     return w->host.tile_ok;
 }
 
@@ -259,7 +275,8 @@ void launch_external_tiled_list(const float* const* levs, int nlev, double box, 
         case 12: k_external_tiled<12><<<nb, tile::kThreads, 0, s>>>(a); break;
         case 24: k_external_tiled<24><<<nb, tile::kThreads, 0, s>>>(a); break;
         case 40: k_external_tiled<40><<<nb, tile::kThreads, 0, s>>>(a); break;
-        default: k_external_tiled<48><<<nb, tile::kThreads, 0, s>>>(a); break;
+        case 48: k_external_tiled<48><<<nb, tile::kThreads, 0, s>>>(a); break;
+        default: k_external_tiled<84><<<nb, tile::kThreads, 0, s>>>(a); break;
     }
 }
 
@@ -285,7 +302,8 @@ bool launch_external_tiled(const cd_tree* t, const cd_weights* w, float* E, int 
         case 12: launch<12>(a, nz, s); break;
         case 24: launch<24>(a, nz, s); break;
         case 40: launch<40>(a, nz, s); break;
-        default: launch<48>(a, nz, s); break;
+        case 48: launch<48>(a, nz, s); break;
+        default: launch<84>(a, nz, s); break;
     }
     return true;
 }

@@ -59,8 +59,10 @@ CASES = [
     (7, 5, 30.0, 7, "healpix2"),   # base 32^3: tiled shells on the active tiles of levels 5 .. 7
     (4, 2, 8.0, 9, "healpix1"),    # finest level 4: no 16^3-oct tile anywhere, every target gathered
     (5, 1, 10.0, 10, "healpix2"),  # one tile at level 5 beside gathered targets of levels 1 .. 4
+    (7, 5, 30.0, 7, "mn7x12"),     # the paper's 7 x 12 set (84 directions) on the tiled path
 ]
-DIRS = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2), "axes6": oracle.dirs_axes6()}
+DIRS = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2), "axes6": oracle.dirs_axes6(),
+        "mn7x12": oracle.dirs_mn(7, 12)}
 
 
 @pytest.mark.parametrize("Lf,B,th,seed,dname", CASES)

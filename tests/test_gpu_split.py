@@ -43,11 +43,11 @@ PREC = {"bf16x2": 1, "fp16x2": 2}
 
 
 @pytest.mark.parametrize("pname", ["bf16x2", "fp16x2"])
-@pytest.mark.parametrize("L,dname", [(5, "healpix1"), (6, "healpix2"), (6, "axes6"), (7, "healpix1")])
+@pytest.mark.parametrize("L,dname", [(5, "healpix1"), (6, "healpix2"), (6, "axes6"), (7, "healpix1"), (6, "mn7x12")])
 def test_split_uniform_all_leaves(colden, pname, L, dname):
     tin = synth.workload_uniform(L, sigma=1.5, mean=10.0, seed=40 + L)
     dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2),
-            "axes6": oracle.dirs_axes6()}[dname]
+            "axes6": oracle.dirs_axes6(), "mn7x12": oracle.dirs_mn(7, 12)}[dname]
     N, chi = _run(colden, tin, dirs, PREC[pname])
     Nf, _ = _run(colden, tin, dirs, 0, chi=False)
     ref = oracle.Tree(tin).columns(dirs)
@@ -81,12 +81,14 @@ def test_split_c2_256_sampled(colden, pname):
     # base level >= 5
     ("bf16x2", 7, 5, 30.0, 7, "healpix2"), ("fp16x2", 7, 5, 30.0, 7, "healpix2"),
     ("fp16x2", 7, 6, 14.0, 8, "healpix1"),
+    # the paper's 7 x 12 set (84 directions) on the tiled path
+    ("bf16x2", 7, 5, 30.0, 7, "mn7x12"), ("fp16x2", 7, 5, 30.0, 7, "mn7x12"),
     # direction counts outside the tiled set: every target on the matrix cores, grouped (bf16 only)
     ("bf16x2", 6, 3, 14.0, 5, "rand7"), ("bf16x2", 7, 5, 30.0, 7, "rand13")])
 def test_split_amr_all_leaves(colden, pname, Lf, B, th, seed, dname):
     tin = synth.amr_tree(synth.lognormal_field(1 << Lf, 2.0, 10.0, seed), B, th, 10 * synth.PC_CM)
     dirs = {"healpix1": oracle.dirs_healpix(1), "healpix2": oracle.dirs_healpix(2),
-            "rand7": _rand_dirs(7, 11), "rand13": _rand_dirs(13, 12)}[dname]
+            "rand7": _rand_dirs(7, 11), "rand13": _rand_dirs(13, 12), "mn7x12": oracle.dirs_mn(7, 12)}[dname]
     N, chi = _run(colden, tin, dirs, PREC[pname])
     ref = oracle.Tree(tin).columns(dirs)
     err = _lnerr(N, ref)
