@@ -263,6 +263,23 @@ def main():
                                 "what": "|chi_prec - chi_insitu| over every leaf; |N_prec - N_insitu| / N_insitu "
                                         "over every output (p99 on 2^20 sampled outputs)"}
         del N_prec, chi_prec
+        # the Sect. 4.4 comparison's own directions: theta_1 = arccos(1 - 1/M)
+        # at phi = 0 for M = 3, 5, 7, precalculated against in situ over
+        # every leaf of the field
+        d3 = np.array([[np.sqrt(1 - (1 - 1 / M) ** 2), 0.0, 1 - 1 / M] for M in (3, 5, 7)])
+        N3 = {}
+        for mode in (colden.CD_PRECALC73, colden.CD_INSITU):
+            w3 = colden.Weights(d3, mode=mode)
+            N3[mode] = torch.empty((tin.n_leaf, 3), dtype=torch.float32, device=dev)
+            colden.column_densities(tree, w3, N3[mode])
+            w3.close()
+        rel3 = ((N3[colden.CD_PRECALC73].double() - N3[colden.CD_INSITU].double()).abs()
+                / N3[colden.CD_INSITU].double())
+        insitu["vs_precalc"]["theta1_phi0"] = {
+            f"M={M}": {"mean_rel_dN": float(rel3[:, i].mean()),
+                       "p99_rel_dN": float(torch.quantile(rel3[::max(1, tin.n_leaf // (1 << 22)), i].float(), 0.99)),
+                       "max_rel_dN": float(rel3[:, i].max())} for i, M in enumerate((3, 5, 7))}
+        del N3, rel3
         print(f"# in-situ form: {insitu['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if not args.no_forms:
         for p in PREC:
@@ -547,7 +564,7 @@ def bench_surrogate(args):
         threads = os.cpu_count() or 1
         n1 = 1 << (L - 1)
         rng = np.random.default_rng(0)
-        octs = rng.choice(n1 ** 3, size=min(args.cpu_sample_octs, n1 ** 3), replace=False)
+        octs = rng.choice(n1 ** 3, size=min(args.cpu_sample_octs or int(2e8 / (8 * D)), n1 ** 3), replace=False)
         ax, ay, az = octs % n1, (octs // n1) % n1, octs // (n1 * n1)
         n = 1 << L
         tg = np.concatenate([((2 * az + (o >> 2)) * n + 2 * ay + ((o >> 1) & 1)) * n + 2 * ax + (o & 1)

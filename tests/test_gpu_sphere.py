@@ -59,3 +59,36 @@ def test_sphere_midplane_against_exact_rays(colden, sphere, name, args, paper):
           f"mean |d chi| vs exact rays {d.mean():.4f} (max {d.max():.3f}; paper {paper})")
     assert rel.max() <= 1e-5
     assert d.mean() <= 0.10
+
+
+def test_sphere_512_effective_sampled(colden):
+    """The benchmark's sphere (128^3 base, every cell with sphere matter
+    refined to 512^3 effective, 10.9M leaves) with the 3 x 4 and 7 x 12
+    sets: sampled midplane and off-plane leaves of every level against the
+    oracle's tree method, and the midplane chi against exact rays."""
+    tin = synth.workload_sphere()
+    tr = oracle.Tree(tin)
+    dev = torch.device("cuda:0")
+    tree = colden.Tree(tin, torch.from_numpy(tin.leaf_n).to(dev))
+    lv = tin.leaf_level
+    rng = np.random.default_rng(21)
+    tg = np.concatenate([rng.choice(np.nonzero(lv == l)[0], 60, replace=False) for l in np.unique(lv)])
+    mid = synth.midplane_leaves(tin)
+    ms = np.sort(rng.choice(mid, size=120, replace=False))
+    chi_ref = oracle.screening(tr.raymarch(oracle.dirs_healpix(8), ms, nthreads=8))
+    for args, paper in (((1, 3, 4), 0.017), ((1, 7, 12), 0.018)):
+        dirs = colden.directions(*args)
+        w = colden.Weights(dirs)
+        N = torch.empty((tin.n_leaf, dirs.shape[0]), dtype=torch.float32, device=dev)
+        chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
+        colden.column_densities(tree, w, N, chi)
+        torch.cuda.synchronize()
+        allt = np.concatenate([tg, ms])
+        ref = tr.columns(dirs, allt, nthreads=8)
+        got = N[torch.from_numpy(allt).to(dev)].cpu().numpy().astype(np.float64)
+        rel = np.abs(got - ref) / ref
+        d = np.abs(chi[torch.from_numpy(ms).to(dev)].cpu().numpy().astype(np.float64) - chi_ref)
+        print(f"sphere 512^3 effective D={dirs.shape[0]}: {allt.size} leaves, max rel {rel.max():.2e}; "
+              f"midplane mean |d chi| vs exact rays {d.mean():.4f} (paper {paper})")
+        assert rel.max() <= 1e-5
+        assert d.mean() <= 0.10
