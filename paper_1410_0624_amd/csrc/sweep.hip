@@ -197,9 +197,11 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
         wt[e] = a.kt.w[row + e];
     }
     const int64_t np = n >> 1;
+    // h^3 cells of each parity, h = 2^(l-1) >= 2: a multiple of kCoarseCells,
+    // so a lane's group is whole and its cells' gathers can all be in flight
+#pragma unroll
     for (int k = 0; k < kCoarseCells; ++k) {
         const int64_t q = q0 + k;
-        if (q >= ncell) break;
         const int c[3] = {(int)(2 * (q & (h - 1)) + (par & 1)), (int)(2 * ((q >> (a.l - 1)) & (h - 1)) + ((par >> 1) & 1)),
                           (int)(2 * (q >> (2 * (a.l - 1))) + (par >> 2))};
         const float* base = a.lev + ((int64_t)(c[2] + kHalo) * S + (c[1] + kHalo)) * S + (c[0] + kHalo);
