@@ -218,6 +218,98 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
     }
 }
 
+// The same tables with the level's densities staged in LDS: a workgroup
+// takes 32 consecutive cells of one parity (whole rows or planes of the
+// parity's sub-grid, so their bounding box is the box of the first and the
+// last) and 4 state codes, a wave per code.  The window of level-l cells
+// within 5 of the box (every weight's offset) is staged once; each wave then
+// runs the direction groups with the lanes as in k_coarse_q (4 cell groups
+// of 8 cells x 16 directions), its 12 gathers per entry from LDS.  The sums
+// are those of k_coarse_q term by term.
+constexpr int kCoarseBlock = 32;                 // cells of one parity per workgroup
+constexpr int kCoarseWin = 74 * 11 * 11;         // largest window (a row of 32 cells)
+
+__global__ __launch_bounds__(256) void k_coarse_lds(const CoarseArgs a) {
+    __shared__ float win[kCoarseWin];
+    const int ncodes = a.compact ? 64 : 216;
+    const int par = blockIdx.x & 7;
+    const int code = (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t h = (int64_t)1 << (a.l - 1);
+    const int64_t ncell = h * h * h;
+    const int64_t q0 = (int64_t)blockIdx.y * kCoarseBlock;
+    const int64_t qlast = (q0 + kCoarseBlock < ncell ? q0 + kCoarseBlock : ncell) - 1;
+    const int lbits = a.l - 1;
+    auto qc = [&](int64_t q, int k) -> int64_t { return (q >> (k * lbits)) & (h - 1); };
+    int lo[3], ext[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int p = (par >> k) & 1;
+        lo[k] = (int)(2 * qc(q0, k)) + p - kHalo;                 // level-l index of the window's first cell
+        ext[k] = (int)(2 * (qc(qlast, k) - qc(q0, k))) + 1 + 2 * kHalo;
+    }
+    const int64_t n = (int64_t)1 << a.l;
+    const int64_t S = n + 2 * kHalo;
+    const int nwin = ext[0] * ext[1] * ext[2];
+    for (int i = threadIdx.x; i < nwin; i += 256) {
+        const int x = i % ext[0], y = (i / ext[0]) % ext[1], z = i / (ext[0] * ext[1]);
+        win[i] = a.lev[((int64_t)(lo[2] + z + kHalo) * S + (lo[1] + y + kHalo)) * S + (lo[0] + x + kHalo)];
+    }
+    __syncthreads();
+    if (code >= ncodes) return;  // whole wave
+    int st[3];
+    if (a.compact) {
+        st[0] = a.dl4[code & 3];
+        st[1] = a.dl4[(code >> 2) & 3];
+        st[2] = a.dl4[(code >> 4) & 3];
+    } else {
+        st[0] = code % 6;
+        st[1] = (code / 6) % 6;
+        st[2] = code / 36;
+    }
+    int combo = 0, pcode = 0, mul = 1, pmul = 1;
+    for (int k = 0; k < 3; ++k) {
+        const int p = (par >> k) & 1;
+        combo += (6 * p + st[k]) * mul;
+        pcode += a.next[st[k]][p] * pmul;
+        mul *= 12;
+        pmul *= 6;
+    }
+    const int64_t np = n >> 1;
+    const int64_t qg = q0 + (lane >> 4) * kCoarseCells;  // this lane's 8 cells
+    const bool live = qg < ncell;
+    for (int d0 = 0; d0 < a.D; d0 += 16) {
+        const int d = d0 + (lane & 15);
+        if (!live || d >= a.D) continue;
+        const int64_t row = ((int64_t)combo * a.D + d) * a.kt.len;
+        int off[kCoarseLen];
+        float wt[kCoarseLen];
+#pragma unroll
+        for (int e = 0; e < kCoarseLen; ++e) {
+            const int pk = a.kt.off[row + e];
+            off[e] = (sext8(pk >> 16) * ext[1] + sext8(pk >> 8)) * ext[0] + sext8(pk);
+            wt[e] = a.kt.w[row + e];
+        }
+#pragma unroll
+        for (int k = 0; k < kCoarseCells; ++k) {
+            const int64_t q = qg + k;
+            const int c[3] = {(int)(2 * qc(q, 0) + (par & 1)), (int)(2 * qc(q, 1) + ((par >> 1) & 1)),
+                              (int)(2 * qc(q, 2) + (par >> 2))};
+            const int wb = ((c[2] - lo[2]) * ext[1] + (c[1] - lo[1])) * ext[0] + (c[0] - lo[0]);
+            float prev = 0.f;
+            if (a.qprev) {
+                const int64_t pcell = ((int64_t)(c[2] >> 1) * np + (c[1] >> 1)) * np + (c[0] >> 1);
+                prev = a.qprev[(pcell * 216 + pcode) * a.D + d];
+            }
+            float s = 0.f;
+#pragma unroll
+            for (int e = 0; e < kCoarseLen; ++e) s = fmaf(wt[e], win[wb + off[e]], s);
+            const int64_t cell = ((int64_t)c[2] * n + c[1]) * n + c[0];
+            a.q[(cell * ncodes + code) * a.D + d] = fmaf(a.dx, s, prev);
+        }
+    }
+}
+
 // The same entries for listed keys cell * ncodes + code only (the entries
 // an adaptive tree's targets read, and those they add up from): a lane per
 // (entry, direction), 16 entries x 16 directions per workgroup.
@@ -360,8 +452,17 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
             continue;
         }
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
-        dim3 grid((c.compact ? 64 : 216) * 8 * ((D + 15) / 16),
-                  (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
+        const int ncodes = c.compact ? 64 : 216;
+        if (per_parity >= kCoarseBlock && D > 24) {
+            // every block whole: 32 cells of a parity, 4 codes per workgroup.
+            // Above 24 directions (2 or more groups of 16 per staged window):
+            // 512^3 D = 48 coarse stage 1.44 -> 1.10 ms; at 12 directions the
+            // staging outweighs the gathers it saves (0.42 -> 0.46 ms)
+            dim3 grid((unsigned)(ncodes / 4 * 8), (unsigned)(per_parity / kCoarseBlock));
+            k_coarse_lds<<<grid, 256, 0, s>>>(c);
+            continue;
+        }
+        dim3 grid(ncodes * 8 * ((D + 15) / 16), (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
         k_coarse_q<<<grid, 64, 0, s>>>(c);
     }
 }
