@@ -146,6 +146,25 @@ static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights
             }
         }
         if (rc == CD_OK) rc = cd::ws_upload(w->ws, gq, &w->glq, s);
+        // the same chords as the matrix of the row kernel's matrix-core form:
+        // row c = cx + 2 cy + 4 cz (the oct's cell), column x D + d (the x
+        // target of the pair, direction), per row parity; columns padded to
+        // a multiple of 16 with zeros
+        const int nc = 16 * ((2 * D + 15) / 16);
+        std::vector<float> gm((size_t)4 * 8 * nc, 0.f);
+        for (int q = 0; q < 4; ++q) {
+            const int oy = q & 1, oz = q >> 1;
+            for (int c = 0; c < 8; ++c) {
+                const int cx = c & 1, cy = (c >> 1) & 1, cz = c >> 2;
+                const int j = (cy ^ oy) + 2 * (cz ^ oz);
+                for (int x = 0; x < 2; ++x)
+                    for (int d = 0; d < D; ++d) {
+                        const float* g = &gq[((size_t)d * 4 + q) * 12];
+                        gm[((size_t)q * 8 + c) * nc + x * D + d] = cx == x ? g[j] : g[(x == 0 ? 4 : 8) + j];
+                    }
+            }
+        }
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, gm, &w->glm, s);
     }
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.ghdr, &w->ghdr, s);
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, w->host.gent, &w->gent, s);

@@ -176,6 +176,7 @@ struct cd_weights {
     float* gloc = nullptr;                  // device [D][8]
     int32_t* sgn = nullptr;                 // device [D]
     float* glq = nullptr;                   // device [D][4 (oy, oz)][12]: row-kernel chords Wo, Wsl, Wsh
+    float* glm = nullptr;                   // device [4 (oy, oz)][8 cells][16 ceil(2D / 16)]: the same chords by oct cell
     int32_t* ghdr = nullptr;                // device gather tables (cd::HostTables::ghdr, gent)
     int32_t* gent = nullptr;
     double* dirs = nullptr;                 // device [D][6] unit vectors (components < 1e-14 snapped to 0), reciprocals

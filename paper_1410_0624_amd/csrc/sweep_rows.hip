@@ -17,6 +17,7 @@
 // A wave's 128 targets are contiguous in N: their rows go through a small LDS
 // buffer, 32 targets at a time, and leave as fully coalesced 16-byte stores
 // (consecutive lanes, consecutive addresses); chi is written per lane pair.
+// Directions counts 24, 40 and 48 take the matrix-core form further down.
 #include <cmath>
 
 #include "cd_internal.h"
@@ -29,6 +30,7 @@ struct RowArgs {
     const float* E;     // [n_oct][D] external columns of the shells dl = 1..3
     const float* q4;    // [8^(L-4)][64][D] shells dl >= 4, or nullptr
     const float* glq;   // [D][4][12] chords by direction and row parity (oy, oz)
+    const float* glm;   // [4][8][16 ceil(2D / 16)] the same chords by oct cell (matrix-core form)
     float dxL;
     float* N;
     uint16_t* Nq;       // packed output instead of N (see log16)
@@ -294,11 +296,228 @@ __global__ __launch_bounds__(256) void k_target_rows(const RowArgs a) {
     }
 }
 
+// Sum over the 4 rows of 16 lanes of a wave (every lane gets the sum of its
+// column): v_permlane16_swap exchanges the odd rows of one operand with the
+// even rows of the other, v_permlane32_swap the upper half with the lower.
+__device__ __forceinline__ float row_sum4(float x) {
+    const uint32_t u = __float_as_uint(x);
+    const auto a = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    const float s = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+    const uint32_t v = __float_as_uint(s);
+    const auto b = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
+// The same rows with the internal + local sums on the matrix cores.  For
+// the pair of x targets of an oct in the wave's row (y, z) the sums are a
+// product of the oct's 8 densities with the chords of this row parity, as a
+// matrix W[c][x D + d] (cell c = cx + 2 cy + 4 cz of the oct, x target,
+// direction d).  Per block of 16 octs and 16 columns, two
+// v_mfma_f32_16x16x4f32 (cells cz = 0 and 1, W as the 16 x 4 operand, the
+// densities as the 4 x 16 one) accumulate onto E + Q of those columns, so a
+// lane ends with 4 consecutive directions of one target: one 16-byte LDS
+// read of E + Q, one 16-byte LDS write of N, 4 exponentials of chi.  The
+// vector ALU keeps the exponentials (the multiply-add form spends half of
+// its instructions on the 16 multiply-adds per direction and lane pair).
+// A workgroup takes K consecutive (segment, oct row) items and loads the
+// next item's E rows and densities while it computes and stores the current
+// one.  D % 4 == 0 and 16 | (octs per wave).
+template <int D, bool PK, int K>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_target_rows_mfma(const RowArgs a) {
+    constexpr int NC = 2 * D;              // columns (x target, direction)
+    constexpr int NT = (NC + 15) / 16;     // 16-column tiles, the last padded
+    constexpr int WP = 16 * NT;            // row pitch of the chord matrix
+    constexpr int DV = D / 4;              // 16-byte pieces of an E row
+    constexpr int NV = (64 * DV + 255) / 256;  // pieces of E (and Q) per thread and item
+    constexpr int EP = D + 4;              // ext row pitch: 16-byte rows, 8 consecutive octs on distinct banks
+    constexpr int RS = 2 * D + 4;          // stage pitch of a pair of rows (same)
+    const int L = a.L, L1 = L - 1;
+    const int64_t n = (int64_t)1 << L;
+    const int64_t n1 = n >> 1;
+    const int seg = n1 >= 64 ? 64 : (int)n1;
+    const int64_t segs = n1 / seg;
+    const int64_t nitems = (a.nz >> 1) * n1 * segs;  // (segment, oct row) items
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int j = lane & 15, g = lane >> 4;
+    // workgroups renumbered per XCD as in k_target_rows; K consecutive items each
+    const int64_t nbk = gridDim.x, bx = blockIdx.x % 8, kx = blockIdx.x / 8;
+    const int64_t it0 = (bx * (nbk / 8) + (bx < nbk % 8 ? bx : nbk % 8) + kx) * K;
+    if (it0 >= nitems) return;  // whole workgroup: uniform
+    // the wave's row parity (z0 is even): the same for every item
+    const int oy = w & 1, oz = w >> 1;
+
+    // W rows g (cz = 0) and 4 + g (cz = 1), column 16 t + j, scaled to cm
+    const float* gm = a.glm + (size_t)(oy + 2 * oz) * 8 * WP;
+    float wa[NT], wb[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        wa[t] = a.dxL * gm[g * WP + 16 * t + j];
+        wb[t] = a.dxL * gm[(4 + g) * WP + 16 * t + j];
+    }
+
+    // An item's inputs, loaded one item ahead: the E and Q pieces this
+    // thread stages, and the densities of oct j of each block of 16 (cell
+    // g + 4 cz) for this wave's row
+    float4 pe[NV];
+    float nb0[4], nb1[4];
+    const int64_t n4 = n1 >> 3;
+    auto fetch = [&](int64_t it) {
+        const int64_t seg_i = it % segs, orow = it / segs;
+        const int64_t Y = orow & (n1 - 1), Az = (a.z0 >> 1) + (orow >> L1), ax0 = seg_i * seg;
+        const int64_t oct0 = (Az << (2 * L1)) + (Y << L1) + ax0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int t = threadIdx.x + 256 * v, o = t / DV, c = t - o * DV;
+            if (t < seg * DV) {
+                pe[v] = reinterpret_cast<const float4*>(a.E + (oct0 + o) * D)[c];
+
+            }
+        }
+        const float* d0 = a.leaf + ((2 * Az) * n + 2 * Y + (g >> 1)) * n + 2 * ax0 + (g & 1);
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            nb0[mt] = 16 * mt < seg ? d0[2 * (16 * mt + j)] : 0.f;
+            nb1[mt] = 16 * mt < seg ? d0[n * n + 2 * (16 * mt + j)] : 0.f;
+        }
+    };
+    fetch(it0);
+
+    __shared__ float ext[64 * EP];
+    __shared__ float stage[4][16 * RS];
+    float* st = stage[w];
+    const float ncs2 = -a.chi_scale * 1.4426950408889634f;
+    for (int k = 0; k < K; ++k) {
+        const int64_t it = it0 + k;
+        if (it >= nitems) break;  // uniform
+        const int64_t seg_i = it % segs, orow = it / segs;
+        const int64_t Y = orow & (n1 - 1), Zl = orow >> L1;
+        const int64_t y = 2 * Y + oy, z = a.z0 + 2 * Zl + oz;
+        const int64_t T0 = (z * n + y) * n + 2 * seg_i * seg;  // first target of the wave
+        __syncthreads();  // the previous item's reads of ext are done
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const int t = threadIdx.x + 256 * v, o = t / DV, c = t - o * DV;
+            if (t < seg * DV) {
+                float4 e = pe[v];
+                if (a.q4) {
+                    const int64_t ax0 = seg_i * seg, Az = z >> 1;
+                    const int64_t xo = ax0 + o;
+                    const int64_t cell = ((Az >> 3) * n4 + (Y >> 3)) * n4 + (xo >> 3);
+                    const int code = (int)(((xo >> 1) & 3) + 4 * ((Y >> 1) & 3) + 16 * ((Az >> 1) & 3));
+                    const float4 q = reinterpret_cast<const float4*>(a.q4 + (cell * 64 + code) * D)[c];
+                    e.x += q.x, e.y += q.y, e.z += q.z, e.w += q.w;
+                }
+                *reinterpret_cast<float4*>(ext + o * EP + 4 * c) = e;
+            }
+        }
+        float b0[4], b1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) b0[mt] = nb0[mt], b1[mt] = nb1[mt];
+        __syncthreads();
+        if (k + 1 < K && it + 1 < nitems) fetch(it + 1);  // in flight during this item
+
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            if (16 * mt >= seg) break;
+            const float* er = ext + (16 * mt + j) * EP;
+            // the lane's columns 16 t + 4 g .. + 3: one x target (D % 4 == 0);
+            // columns past 2 D (a padded last tile) are computed and dropped
+            v4f acc[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c0 = 16 * t + 4 * g;
+                const int d = c0 < D ? c0 : (NC % 16 == 0 || c0 < NC ? c0 - D : 0);
+                acc[t] = *reinterpret_cast<const v4f*>(er + d);
+            }
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wa[t], b0[mt], acc[t], 0, 0, 0);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(wb[t], b1[mt], acc[t], 0, 0, 0);
+            float chi0 = 0.f, chi1 = 0.f;
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const int c0 = 16 * t + 4 * g;
+                const bool ok = NC % 16 == 0 || c0 < NC;
+                const float ex = ok ? __builtin_amdgcn_exp2f(ncs2 * acc[t][0]) + __builtin_amdgcn_exp2f(ncs2 * acc[t][1]) +
+                                          __builtin_amdgcn_exp2f(ncs2 * acc[t][2]) + __builtin_amdgcn_exp2f(ncs2 * acc[t][3])
+                                    : 0.f;
+                if (16 * t + 16 <= D) chi0 += ex;  // the tile's columns all of x = 0
+                else if (16 * t >= D) chi1 += ex;  // all of x = 1
+                else (c0 < D ? chi0 : chi1) += ex;
+                if (ok) {
+                    if constexpr (PK) {
+                        uint32_t* r = reinterpret_cast<uint32_t*>(st) + j * (D + 4) + (c0 >> 1);
+                        *reinterpret_cast<uint2*>(r) = uint2{log16(acc[t][0]) | (log16(acc[t][1]) << 16),
+                                                             log16(acc[t][2]) | (log16(acc[t][3]) << 16)};
+                    } else {
+                        *reinterpret_cast<v4f*>(st + j * RS + c0) = acc[t];
+                    }
+                }
+            }
+            // the 4 lane groups (rows of 16 lanes) hold the directions of oct j
+            // in 4-column pieces: summed across rows by row swaps
+            chi0 = row_sum4(chi0);
+            chi1 = row_sum4(chi1);
+            if (a.chi && g == 0)
+                __builtin_nontemporal_store(v2f{chi0 * (1.f / (float)D), chi1 * (1.f / (float)D)},
+                                            reinterpret_cast<v2f*>(a.chi + T0 + 32 * mt + 2 * j));
+            __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): the wave's LDS writes are done
+            __builtin_amdgcn_wave_barrier();
+            if constexpr (PK) {
+                // 32 rows of D codes: 16 pairs of D words at a pitch of D + 4
+                constexpr int QQ = D / 4, NQ = 16 * QQ;
+                const uint32_t* sq = reinterpret_cast<const uint32_t*>(st);
+                v4u* dst = reinterpret_cast<v4u*>(a.Nq + (T0 + 32 * mt) * D);
+                v4u v[(NQ + 63) / 64];
+#pragma unroll
+                for (int q = 0; q < (NQ + 63) / 64; ++q) {
+                    const int i = lane + 64 * q, pr = i / QQ;
+                    if (NQ % 64 == 0 || i < NQ) v[q] = *reinterpret_cast<const v4u*>(sq + pr * (D + 4) + 4 * (i - pr * QQ));
+                }
+#pragma unroll
+                for (int q = 0; q < (NQ + 63) / 64; ++q) {
+                    const int i = lane + 64 * q;
+                    if (NQ % 64 == 0 || i < NQ) __builtin_nontemporal_store(v[q], dst + i);
+                }
+            } else {
+                constexpr int Q = D / 2, NQ = 16 * Q;  // 16-byte pieces per pair of rows, per block
+                v4f* dst = reinterpret_cast<v4f*>(a.N + (T0 + 32 * mt) * D);
+#pragma unroll
+                for (int q = 0; q < (NQ + 63) / 64; ++q) {
+                    const int i = lane + 64 * q, pr = i / Q;
+                    if (NQ % 64 == 0 || i < NQ) __builtin_nontemporal_store(*reinterpret_cast<const v4f*>(st + pr * RS + 4 * (i - pr * Q)), dst + i);
+                }
+            }
+            __builtin_amdgcn_s_waitcnt(0xc07f);
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
+// (segment, oct row) items per workgroup of the matrix-core row kernel, the
+// next item's E rows and densities loaded during the current one.  512^3,
+// D = 48, per z-slab alone: FP32 rows 1.42 ms with one item (1.44, 1.50, 1.55
+// with 2, 4, 8; the multiply-add kernel 1.45), packed rows best with 8 (step
+// 6.96 -> 6.64 ms from 1 to 8 items)
+constexpr int kItemsFp32 = 1, kItemsPacked = 8;
+
 template <int D>
 static void launch_rows(const RowArgs& a, int64_t nz, hipStream_t s) {
     const int64_t n1 = (int64_t)1 << (a.L - 1);
     const int64_t seg = n1 >= 64 ? 64 : n1;
     const int64_t blocks = (nz / 2) * n1 * (n1 / seg);  // (oct row, segment) pairs
+    if constexpr (D % 4 == 0 && D >= 24 && D <= 48) {
+        if (seg % 16 == 0) {
+            if (a.Nq)
+                k_target_rows_mfma<D, true, kItemsPacked>
+                    <<<(unsigned)((blocks + kItemsPacked - 1) / kItemsPacked), 256, 0, s>>>(a);
+            else
+                k_target_rows_mfma<D, false, kItemsFp32>
+                    <<<(unsigned)((blocks + kItemsFp32 - 1) / kItemsFp32), 256, 0, s>>>(a);
+            return;
+        }
+    }
     if constexpr (D % 4 == 0) {
         if (a.Nq) {
             k_target_rows<D, true><<<(unsigned)blocks, 256, 0, s>>>(a);
@@ -321,6 +540,7 @@ bool launch_target_rows(const cd_tree* t, const cd_weights* w, const float* E, f
     // the in-situ mode has the shells dl >= 4 in E already
     a.q4 = (w->mode == CD_PRECALC73 && t->lmax - 4 >= 2) ? t->q[t->lmax - 4] : nullptr;
     a.glq = w->glq;
+    a.glm = w->glm;
     a.dxL = (float)(t->box_cm * std::ldexp(1.0, -t->lmax));
     a.N = N;
     a.chi = chi;
