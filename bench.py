@@ -75,9 +75,10 @@ MFMA_PEAK_TFLOPS = 2500.0  # dense bf16 / fp16
 
 def hbm_ceiling(torch, n_floats):
     """Plain torch copy and fill on this GPU, sized like the row kernel's
-    output (at most 2^28 floats): the rate a streaming kernel reaches here,
-    as context for roofline.frac (whose peak is the published 8 TB/s)."""
-    n = int(min(n_floats, 1 << 28))
+    output (at most 2^31 floats, well past the last-level cache): the rate a
+    streaming kernel reaches here, as context for roofline.frac (whose peak
+    is the published 8 TB/s)."""
+    n = int(min(n_floats, 1 << 31))
     a = torch.ones(n, device="cuda:0")
     b = torch.empty_like(a)
     out = {"n_bytes": n * 4}
@@ -315,7 +316,8 @@ def main():
                  "k_target_octs (per target oct, a lane per direction: external row + coarse table, internal+local, "
                  "N and chi rows)")
     else:
-        kname = f"k_target_rows<{D}> (internal+local, N and chi rows)"
+        kname = (f"k_target_rows_mfma<{D}> (internal+local on the matrix cores, N and chi rows)" if D in (24, 40, 48)
+                 else f"k_target_rows<{D}> (internal+local, N and chi rows)")
     step_bytes = alg_bytes_step(tin, D)
     achieved = step_bytes / (stage_ms["rows"] * 1e-3) / 1e9
 
