@@ -535,11 +535,15 @@ int uniform_columns(cd_tree* t, const cd_weights* w, float* N, float* chi, float
         // With one slab the rows follow the tiled kernel on s itself (no
         // hand-over between the streams before and after them)
         const int tpa = 1 << (L - 5);  // tiles per axis (16 octs each)
-        // z-slabs: the row kernel of slab j overlaps the external kernel of
-        // slab j+1 (measured +4 % at D = 48 with 4 slabs, +7 % at 512^3 and
-        // D = 12 with 2, within noise at 256^3 and D = 12, where one launch
-        // each is kept); the split kernel covers the whole grid in one launch
-        int nslab = split ? 1 : (D > 24 ? 4 : (L >= 9 ? 2 : 1));
+        // z-slabs: the row kernel of slab j beside the external kernel of
+        // slab j+1.  A tiled workgroup needs a whole CU, so beside the row
+        // kernel it mostly waits and the gain is small: at 512^3, D = 48 the
+        // FP32 rows are faster in one launch after the whole external stage
+        // (which then overlaps the coarse chain; step 8.74 -> 8.52 ms), the
+        // packed rows in 4 slabs (6.76 -> 6.66 ms); 512^3, D = 12: 2 slabs
+        // (+7 %); 256^3: one launch each.  The split kernel covers the whole
+        // grid in one launch
+        int nslab = split ? 1 : (D > 24 ? (Nq ? 4 : 1) : (L >= 9 ? 2 : 1));
         while (nslab > 1 && tpa % nslab) nslab >>= 1;
         const int per = tpa / nslab;
         auto mark = [t](int stage, int edge, hipStream_t st) -> hipError_t {

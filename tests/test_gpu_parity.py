@@ -84,8 +84,10 @@ def test_direction_families_parity(colden, name, dirs):
 
 
 def test_sweep_in_z_slabs_128(colden):
-    """D = 48 on a 128^3 grid: the sweep runs in 4 z-slabs whose row and
-    external kernels overlap; every slab boundary is checked."""
+    """D = 48 on a 128^3 grid: the FP32 rows in one launch after the
+    external stage, the packed rows (16-bit log codes) in 4 z-slabs whose
+    row and external kernels overlap; every slab boundary is checked, the
+    packed rows within their format's 2^-11 in log2 of the oracle."""
     tin = synth.workload_uniform(7, sigma=1.5, mean=10.0, seed=13)
     dirs = oracle.dirs_healpix(2)
     N, chi = _run(colden, tin, dirs)
@@ -99,6 +101,20 @@ def test_sweep_in_z_slabs_128(colden):
     assert np.isfinite(N).all()
     assert rel.max() <= REL_FP32
     assert np.abs(chi[tg] - oracle.screening(ref)).max() <= 2e-6
+
+    dev = torch.device("cuda:0")
+    leaf = torch.from_numpy(tin.leaf_n).to(dev)
+    tree = colden.Tree(tin, leaf)
+    w = colden.Weights(dirs)
+    code = torch.full((tin.n_leaf, dirs.shape[0]), -1, dtype=torch.int16, device=dev)
+    chi2 = torch.full((tin.n_leaf,), float("nan"), dtype=torch.float32, device=dev)
+    colden.column_densities_log16(tree, w, code, chi2)
+    torch.cuda.synchronize()
+    dec = colden.decode_log16(code).cpu().numpy().astype(np.float64)
+    err = np.abs(np.log(dec[tg]) - np.log(ref))
+    print(f"  packed, 4 slabs: max |d ln N| {err.max():.3e}")
+    assert err.max() <= np.log(2.0) * 2.0 ** -11 + REL_FP32
+    assert np.abs(chi2.cpu().numpy()[tg] - oracle.screening(ref)).max() <= 2e-6
 
 
 def test_c2_256_sampled_parity(colden):
