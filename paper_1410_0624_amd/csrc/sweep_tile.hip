@@ -55,8 +55,7 @@ struct TileArgs {
 // main part is straight-line code: every gather, then every multiply-add, so
 // the wave waits for the LDS once.  Lists longer than the main part (a few
 // directions of some classes) take one more block.
-__device__ __forceinline__ float slot_sum(const CD_CONST uint32_t* __restrict__ sl, const float* lds, int base,
-                                          int lane) {
+__device__ __forceinline__ float slot_sum(const CD_CONST uint32_t* __restrict__ sl, const float* lds, int base) {
     using namespace tile;
     uint32_t h[kSlotHead];
 #pragma unroll
@@ -76,9 +75,10 @@ __device__ __forceinline__ float slot_sum(const CD_CONST uint32_t* __restrict__ 
     }
 #pragma unroll
     for (int i = 0; i < kSlotMasked; ++i) {
-        // only the lanes whose parity of A >> 2 has the entry
+        // only the lanes whose parity of A >> 2 has the entry (the mask as
+        // the lane condition of one v_cndmask)
         const uint64_t lm = (uint64_t)h[kSlotMMask + 2 * i] | ((uint64_t)h[kSlotMMask + 2 * i + 1] << 32);
-        const float m = ((lm >> lane) & 1ull) ? v[kSlotMain + i] : 0.f;
+        const float m = __builtin_amdgcn_inverse_ballot_w64(lm) ? v[kSlotMain + i] : 0.f;
         a0 = fmaf(__uint_as_float(h[kSlotMW + i]), m, a0);
     }
     if (h[0] > (uint32_t)kSlotMain) {
@@ -111,7 +111,7 @@ __device__ __forceinline__ float slot_sum(const CD_CONST uint32_t* __restrict__ 
 // main part take one more block.
 template <int D>
 __device__ __forceinline__ void slot_row(const CD_CONST uint32_t* __restrict__ cls, const float* lds, int base,
-                                         int lane, float (&acc)[D]) {
+                                         float (&acc)[D]) {
     using namespace tile;
     constexpr int NO = kSlotMain + kSlotMasked;  // offsets per slot
     constexpr int NW = kSlotHead - kSlotW;       // weights, masked weights, masks
@@ -151,7 +151,7 @@ __device__ __forceinline__ void slot_row(const CD_CONST uint32_t* __restrict__ c
 #pragma unroll
         for (int i = 0; i < kSlotMasked; ++i) {
             const uint64_t lm = (uint64_t)h[kSlotMMask + 2 * i] | ((uint64_t)h[kSlotMMask + 2 * i + 1] << 32);
-            const float m = ((lm >> lane) & 1ull) ? v[kSlotMain + i] : 0.f;
+            const float m = __builtin_amdgcn_inverse_ballot_w64(lm) ? v[kSlotMain + i] : 0.f;
             a0 = fmaf(__uint_as_float(h[kSlotMW + i]), m, a0);
         }
         if (h[0] > (uint32_t)kSlotMain) {
@@ -281,7 +281,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
             // (written a piece per direction group, they were evicted
             // half-written and written to memory several times)
             float acc[D];
-            slot_row<D>(cls, lds, base, lane, acc);
+            slot_row<D>(cls, lds, base, acc);
 #pragma unroll
             for (int d0 = 0; d0 < D; d0 += DG) {
                 if constexpr (DG == 4)
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(tile::kThreads) void k_external_tiled(const TileArg
                 float acc[DG];
 #pragma unroll
                 for (int j = 0; j < DG; ++j)
-                    acc[j] = dx1 * slot_sum(cls + (size_t)(d0 + j) * kSlotWords, lds, base, lane);
+                    acc[j] = dx1 * slot_sum(cls + (size_t)(d0 + j) * kSlotWords, lds, base);
                 if constexpr (DG == 4)
                     *reinterpret_cast<float4*>(row + d0) = make_float4(acc[0], acc[1], acc[2], acc[3]);
                 else
