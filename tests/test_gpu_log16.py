@@ -67,6 +67,23 @@ def test_log16_codes_every_leaf(colden, L, nside, precision):
     assert err.max() <= LN_GATE + (0 if precision == 0 else 1e-3)
 
 
+@pytest.mark.parametrize("name,dirs", [("mn3x8", oracle.dirs_mn(3, 8)), ("mn5x8", oracle.dirs_mn(5, 8)),
+                                       ("mn7x12", oracle.dirs_mn(7, 12))])
+def test_log16_direction_families(colden, name, dirs):
+    """24 and 40 directions (the matrix-core rows, whose 16-column tiles
+    straddle the pair of x targets) and 84 (the multiply-add rows): every
+    code of a 64^3 grid against the FP32 columns' encoding and the oracle."""
+    tin = synth.workload_uniform(6, sigma=1.5, mean=10.0, seed=61)
+    _, _, N, chi, code, chi2 = _both(colden, tin, dirs)
+    c = code.cpu().numpy().astype(np.int64) & 0xFFFF
+    assert np.abs(c - _encode(N.cpu().numpy())).max() <= 1
+    assert torch.equal(chi, chi2)
+    ref = oracle.Tree(tin).columns(dirs)
+    err = np.abs(np.log(colden.decode_log16(code).cpu().numpy()) - np.log(ref))
+    print(f"{name} D={dirs.shape[0]}: decoded vs oracle max |d ln N| {err.max():.3e}")
+    assert err.max() <= LN_GATE
+
+
 def test_log16_512_sampled(colden):
     """The default benchmark's case (512^3, 48 sectors, four z-slabs):
     codes of sampled leaves in every slab and the corners against the FP64
