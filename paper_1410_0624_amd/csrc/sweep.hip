@@ -221,7 +221,7 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
 // The same tables with the level's densities staged in LDS: a workgroup
 // takes 32 consecutive cells of one parity (whole rows or planes of the
 // parity's sub-grid, so their bounding box is the box of the first and the
-// last) and 4 state codes, a wave per code.  The window of level-l cells
+// last) and CPW state codes, a wave per code.  The window of level-l cells
 // within 5 of the box (every weight's offset) is staged once; each wave then
 // runs the direction groups with the lanes as in k_coarse_q (4 cell groups
 // of 8 cells x 16 directions), its 12 gathers per entry from LDS.  The sums
@@ -229,11 +229,12 @@ __global__ __launch_bounds__(64) void k_coarse_q(const CoarseArgs a) {
 constexpr int kCoarseBlock = 32;                 // cells of one parity per workgroup
 constexpr int kCoarseWin = 74 * 11 * 11;         // largest window (a row of 32 cells)
 
-__global__ __launch_bounds__(256) void k_coarse_lds(const CoarseArgs a) {
+template <int CPW>
+__global__ __launch_bounds__(64 * CPW) void k_coarse_lds(const CoarseArgs a) {
     __shared__ float win[kCoarseWin];
     const int ncodes = a.compact ? 64 : 216;
     const int par = blockIdx.x & 7;
-    const int code = (blockIdx.x >> 3) * 4 + (threadIdx.x >> 6);
+    const int code = (blockIdx.x >> 3) * CPW + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     const int64_t h = (int64_t)1 << (a.l - 1);
     const int64_t ncell = h * h * h;
@@ -251,7 +252,7 @@ __global__ __launch_bounds__(256) void k_coarse_lds(const CoarseArgs a) {
     const int64_t n = (int64_t)1 << a.l;
     const int64_t S = n + 2 * kHalo;
     const int nwin = ext[0] * ext[1] * ext[2];
-    for (int i = threadIdx.x; i < nwin; i += 256) {
+    for (int i = threadIdx.x; i < nwin; i += 64 * CPW) {
         const int x = i % ext[0], y = (i / ext[0]) % ext[1], z = i / (ext[0] * ext[1]);
         win[i] = a.lev[((int64_t)(lo[2] + z + kHalo) * S + (lo[1] + y + kHalo)) * S + (lo[0] + x + kHalo)];
     }
@@ -454,12 +455,17 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
         const int ncodes = c.compact ? 64 : 216;
         if (per_parity >= kCoarseBlock && D > 24) {
-            // every block whole: 32 cells of a parity, 4 codes per workgroup.
-            // Above 24 directions (2 or more groups of 16 per staged window):
-            // 512^3 D = 48 coarse stage 1.44 -> 1.10 ms; at 12 directions the
-            // staging outweighs the gathers it saves (0.42 -> 0.46 ms)
-            dim3 grid((unsigned)(ncodes / 4 * 8), (unsigned)(per_parity / kCoarseBlock));
-            k_coarse_lds<<<grid, 256, 0, s>>>(c);
+            // every block whole: 32 cells of a parity; 16 codes per workgroup
+            // for the 64 of level L - 4, 8 for the 216 of the others.  Above 24
+            // directions (2 or more groups of 16 per staged window): 512^3 D =
+            // 48 coarse stage 1.44 -> 1.10 ms with 4 codes per workgroup, level
+            // L - 4 alone 501 -> 425 us with 8 (step 8.49 -> 8.39 ms), step 8.31
+            // ms with 16 at level L - 4 (fewer, larger workgroups leave the
+            // tiled kernel beside them more CUs); at 12 directions the staging
+            // outweighs the gathers it saves (0.42 -> 0.46 ms)
+            dim3 grid((unsigned)(ncodes / (c.compact ? 16 : 8) * 8), (unsigned)(per_parity / kCoarseBlock));
+            if (c.compact) k_coarse_lds<16><<<grid, 1024, 0, s>>>(c);
+            else k_coarse_lds<8><<<grid, 512, 0, s>>>(c);
             continue;
         }
         dim3 grid(ncodes * 8 * ((D + 15) / 16), (unsigned)((per_parity + 4 * kCoarseCells - 1) / (4 * kCoarseCells)));
