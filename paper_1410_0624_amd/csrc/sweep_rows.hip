@@ -356,9 +356,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
         wb[t] = a.dxL * gm[(4 + g) * WP + 16 * t + j];
     }
 
-    // An item's inputs, loaded one item ahead: the E and Q pieces this
-    // thread stages, and the densities of oct j of each block of 16 (cell
-    // g + 4 cz) for this wave's row
+    // An item's inputs, loaded one item ahead: the pieces of E this thread
+    // stages (the coarse-table rows, few and cached, are read at staging),
+    // and the densities of oct j of each block of 16 (cell g + 4 cz) for
+    // this wave's row
     float4 pe[NV];
     float nb0[4], nb1[4];
     const int64_t n4 = n1 >> 3;
@@ -371,7 +372,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
             const int t = threadIdx.x + 256 * v, o = t / DV, c = t - o * DV;
             if (t < seg * DV) {
                 pe[v] = reinterpret_cast<const float4*>(a.E + (oct0 + o) * D)[c];
-
             }
         }
         const float* d0 = a.leaf + ((2 * Az) * n + 2 * Y + (g >> 1)) * n + 2 * ax0 + (g & 1);
