@@ -349,6 +349,15 @@ def main():
         cpu = {"value": float(tg.shape[0] * D / dt), "unit": "cell*dir/s", "cores": threads,
                "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{what}, FP64 OpenMP oracle, {dt:.1f} s"}
+        # the same oracle on one thread, over 1/32 of the sample (whole octs
+        # on uniform grids)
+        tg1 = (tg[: max(tg.shape[0] // 32, 8)] if amr else
+               tg.reshape(8, -1)[:, : max(tg.shape[0] // 256, 1)].ravel())
+        t0 = time.time()
+        oracle.screening(tr.columns(dirs, tg1, nthreads=1))
+        dt1 = time.time() - t0
+        cpu["one_thread"] = {"value": float(tg1.shape[0] * D / dt1), "unit": "cell*dir/s", "cores": 1,
+                             "sample": f"{tg1.shape[0]} of those leaves, {dt1:.1f} s"}
         ref_check = tr.columns(dirs, check, nthreads=threads)
         ref_check_insitu = tr.columns(dirs, check, mode=oracle.INSITU, nthreads=threads) if insitu else None
         ref_check12 = tr.columns(colden.directions(colden.CD_DIR_HEALPIX, 1), check, nthreads=threads) if d12 else None
