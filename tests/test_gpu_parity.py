@@ -83,6 +83,20 @@ def test_direction_families_parity(colden, name, dirs):
     assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
 
 
+@pytest.mark.parametrize("name,dirs", [("mn3x8", oracle.dirs_mn(3, 8)), ("mn5x8", oracle.dirs_mn(5, 8))])
+def test_matrix_core_rows_one_block_per_wave(colden, name, dirs):
+    """32^3 grid: 16 octs per row, so each wave of the matrix-core row kernel
+    holds one 16-oct block; 24 and 40 directions (16-column tiles that
+    straddle the pair of x targets).  Every output against the oracle."""
+    tin = synth.workload_uniform(5, sigma=1.5, mean=10.0, seed=17)
+    N, chi = _run(colden, tin, dirs)
+    ref = oracle.Tree(tin).columns(dirs)
+    rel = _rel(N, ref)
+    print(f"{name} D={dirs.shape[0]} 32^3: max rel {rel.max():.3e}")
+    assert rel.max() <= REL_FP32
+    assert np.abs(chi - oracle.screening(ref)).max() <= 2e-6
+
+
 def test_sweep_in_z_slabs_128(colden):
     """D = 48 on a 128^3 grid: the FP32 rows in one launch after the
     external stage, the packed rows (16-bit log codes) in 4 z-slabs whose
