@@ -454,15 +454,15 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
         }
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
         const int ncodes = c.compact ? 64 : 216;
-        if (per_parity >= kCoarseBlock && D > 24) {
+        if (per_parity >= kCoarseBlock) {
             // every block whole: 32 cells of a parity; 16 codes per workgroup
-            // for the 64 of level L - 4, 8 for the 216 of the others.  Above 24
-            // directions (2 or more groups of 16 per staged window): 512^3 D =
-            // 48 coarse stage 1.44 -> 1.10 ms with 4 codes per workgroup, level
-            // L - 4 alone 501 -> 425 us with 8 (step 8.49 -> 8.39 ms), step 8.31
-            // ms with 16 at level L - 4 (fewer, larger workgroups leave the
-            // tiled kernel beside them more CUs); at 12 directions the staging
-            // outweighs the gathers it saves (0.42 -> 0.46 ms)
+            // for the 64 of level L - 4, 8 for the 216 of the others.  512^3, D
+            // = 48: coarse stage 1.44 -> 1.10 ms with 4 codes per workgroup,
+            // level L - 4 alone 501 -> 425 us with 8 (step 8.49 -> 8.39 ms), step
+            // 8.31 ms with 16 at level L - 4 (fewer, larger workgroups leave the
+            // tiled kernel beside them more CUs).  At 12 directions 4 codes per
+            // workgroup lost to the global gathers (0.42 -> 0.46 ms), 16 / 8
+            // gain: 512^3 step 2.70 -> 2.59 ms, 256^3 0.293 -> 0.290 ms
             dim3 grid((unsigned)(ncodes / (c.compact ? 16 : 8) * 8), (unsigned)(per_parity / kCoarseBlock));
             if (c.compact) k_coarse_lds<16><<<grid, 1024, 0, s>>>(c);
             else k_coarse_lds<8><<<grid, 512, 0, s>>>(c);
