@@ -2,6 +2,8 @@
 the FP64 oracle, through the C ABI.  Gate: max |ln N_gpu - ln N_oracle| <= 1e-3
 over every checked output; the measured error is printed per case, next to
 the FP32 sweep's."""
+import os
+
 import numpy as np
 import pytest
 
@@ -172,6 +174,37 @@ def test_c4_512_all_forms_sampled(colden, c4, nside):
         assert not torch.isnan(chi).any()
     del N, chi
     torch.cuda.empty_cache()
+
+
+def test_c4_512_fp32_million_sampled(colden, c4):
+    """The default benchmark's case (512^3, 48 sectors, FP32, the row kernel
+    in one launch over the grid) on 2^20 leaves: 131,072 random octs with all
+    8 of their leaves, every output against the oracle (Sect. 3.3, Eq. 11)
+    at 1e-5, chi at 1e-5."""
+    tin, leaf, tree, _ = c4
+    dirs = oracle.dirs_healpix(2)
+    n1 = 256
+    octs = np.random.default_rng(21).choice(n1 ** 3, size=1 << 17, replace=False)
+    ax, ay, az = octs % n1, (octs // n1) % n1, octs // (n1 * n1)
+    tg = np.concatenate([((2 * az + (o >> 2)) * 512 + 2 * ay + ((o >> 1) & 1)) * 512 + 2 * ax + (o & 1)
+                         for o in range(8)]).astype(np.int64)
+    ref = oracle.Tree(tin).columns(dirs, tg, nthreads=os.cpu_count() or 1)
+    dev = torch.device("cuda:0")
+    N = torch.empty((tin.n_leaf, 48), dtype=torch.float32, device=dev)
+    chi = torch.empty(tin.n_leaf, dtype=torch.float32, device=dev)
+    w = colden.Weights(dirs)
+    colden.column_densities(tree, w, N, chi)
+    idx = torch.from_numpy(tg).to(dev)
+    got = N[idx].cpu().numpy().astype(np.float64)
+    gchi = chi[idx].cpu().numpy().astype(np.float64)
+    w.close()
+    del N, chi
+    torch.cuda.empty_cache()
+    rel = np.abs(got - ref) / ref
+    dchi = np.abs(gchi - oracle.screening(ref)).max()
+    print(f"512^3 D=48 fp32, {tg.size} leaves: max rel {rel.max():.3e} mean {rel.mean():.3e}, max |d chi| {dchi:.2e}")
+    assert rel.max() <= 1e-5
+    assert dchi <= 1e-5
 
 
 def _rand_dirs(D, seed):
