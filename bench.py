@@ -428,7 +428,13 @@ def main():
         o = {"ms_per_step": insitu["ms_per_step"], "value": insitu["value"],
              "slowdown_vs_precalc": insitu["ms_per_step"] / main_form["ms_per_step"],
              "external_ms": insitu["stages_ms"]["external"], "insitu_coarse_ms": insitu["stages_ms"]["coarse"],
-             "rows_ms": insitu["stages_ms"]["rows"], "vs_precalc": insitu["vs_precalc"]}
+             "rows_ms": insitu["stages_ms"]["rows"], "vs_precalc": insitu["vs_precalc"],
+             # the paper's timing table (Sect. 4.4): whole RAMSES runs with
+             # screening over runs without, in situ / precalculated, on CPUs
+             "paper_context": {"t_sim_over_t0_insitu_precalc": {"12": [7.9, 1.6], "40": [15.8, 2.4],
+                                                                 "84": [26.3, 3.3]},
+                               "what": "context only: whole-simulation time ratios of the paper's CPU runs; "
+                                       "slowdown_vs_precalc here is the column sweep alone on one GPU"}}
         if ref_check_insitu is not None:
             o["max_rel_err_vs_oracle_insitu"] = float(np.max(np.abs(insitu["sample"] - ref_check_insitu)
                                                              / ref_check_insitu))
