@@ -117,6 +117,17 @@ static int weights_build(const std::vector<std::array<double, 3>>& u, cd_weights
         if (rc == CD_OK) rc = cd::ws_upload(w->ws, otf[k], &w->offT[k], s);
         if (rc == CD_OK) rc = cd::ws_upload(w->ws, wtf[k], &w->wT[k], s);
     }
+    {
+        // kind-4 offsets (x, y, z bytes) as word offsets in the coarse-table
+        // kernel's cell window (pitches kCellWinPy, kCellWinPz)
+        const std::vector<int32_t>& o4 = w->host.off[4];
+        std::vector<int32_t> ow(o4.size());
+        for (size_t i = 0; i < o4.size(); ++i) {
+            const int sx = (int8_t)(o4[i] & 0xff), sy = (int8_t)((o4[i] >> 8) & 0xff), sz = (int8_t)((o4[i] >> 16) & 0xff);
+            ow[i] = sz * cd::kCellWinPz + sy * cd::kCellWinPy + sx;
+        }
+        if (rc == CD_OK) rc = cd::ws_upload(w->ws, ow, &w->offwin4, s);
+    }
     std::vector<float> kf(w->host.kloc.begin(), w->host.kloc.end());
     std::vector<float> gf(w->host.gloc.begin(), w->host.gloc.end());
     if (rc == CD_OK) rc = cd::ws_upload(w->ws, kf, &w->kloc, s);

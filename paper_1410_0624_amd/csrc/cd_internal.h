@@ -77,6 +77,12 @@ constexpr int kHalo = 5;
 //   4: dl >= 4, reference at the centre of A_{l+2}, inner limit in one of
 //      three per-axis states
 constexpr int kKinds = 5;  // index 1..4 used
+// Window of the lane-per-cell coarse-table kernel: the level-l cells within
+// kHalo of a 4^3 block of one parity's cells, 17 per axis, staged with these
+// row and plane pitches (the lanes' cells 2 lx + 8 ly + 32 lz banks apart
+// modulo 64); the kind-4 offsets are also kept decoded for them.
+constexpr int kCellWinSide = 17, kCellWinPy = 36, kCellWinPz = 624;
+constexpr int kCellWinWords = kCellWinSide * kCellWinPz;
 constexpr int kMaxSlabs = 4;  // z-slabs overlapping the two sweep stages
 
 // Per-axis shape of a shell relative to the level-l ancestor (in level-l
@@ -171,6 +177,7 @@ struct cd_weights {
     int32_t* cnt[cd::kKinds] = {nullptr};   // device
     int32_t* offT[cd::kKinds] = {nullptr};  // device, [ncombo][len][D]: the lists with the direction fastest
     float* wT[cd::kKinds] = {nullptr};      // device, same layout
+    int32_t* offwin4 = nullptr;             // device, kind 4 [ncombo][D][len]: offsets in the cell-window layout
     float* kloc = nullptr;                  // device [8][8][D]
     uint32_t* slots = nullptr;              // device tiled-sweep tables
     float* gloc = nullptr;                  // device [D][8]

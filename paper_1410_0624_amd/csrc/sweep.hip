@@ -142,12 +142,17 @@ struct CoarseArgs {
     float* q;           // [8^l][ncodes][D]
     int compact;        // 1: level L-4, codes = 4 per axis (bits of the dl = 3, 2 ancestors)
     KindTable kt;       // kind 4
+    const int32_t* offwin;  // kind 4 offsets in the cell-window layout (kCellWinPy, kCellWinPz)
     int D;
     int8_t next[6][2];
     int8_t dl4[4];
 };
 
 constexpr int kCoarseLen = 12;
+
+// Read-only tables read through the constant address space: with a
+// wave-uniform address the loads become scalar loads.
+#define CD_CONST __attribute__((address_space(4)))
 
 // One wave per (state code, parity class, group of 16 directions, 4 groups
 // of kCoarseCells cells of that parity): the shell shape and reference point
@@ -311,6 +316,145 @@ __global__ __launch_bounds__(64 * CPW) void k_coarse_lds(const CoarseArgs a) {
     }
 }
 
+// The same tables with a lane per cell: a workgroup takes a 4^3 block of
+// the cells of one parity and CPW state codes, a wave per code, so that a
+// direction's weight list (12 offsets, decoded on the host for the window's
+// pitches, and 12 weights) is the same for the whole wave and is read with
+// scalar loads.  The window of the block's cells within kHalo (17 per axis)
+// is staged once; a lane's gathers are at its cell plus the list's offsets.
+// Each lane keeps its cell's row of D directions in registers, started from
+// the row of the parent cell's table, and writes it back to back, so the
+// row's cache lines are completed while they sit in L2.  The sums are those
+// of k_coarse_q term by term.
+template <int D, int CPW>
+__global__ __launch_bounds__(64 * CPW) void k_coarse_cells(const CoarseArgs a) {
+    static_assert(D % 4 == 0, "rows written as float4");
+    __shared__ float win[kCellWinWords];
+    const int ncodes = a.compact ? 64 : 216;
+    const int par = blockIdx.x & 7;
+    const int code = (int)(blockIdx.x >> 3) * CPW + (int)(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int bbits = a.l - 3;  // 4^3-cell blocks per axis of a parity's sub-grid: 2^(l-3)
+    const int b[3] = {(int)(blockIdx.y & ((1u << bbits) - 1)), (int)((blockIdx.y >> bbits) & ((1u << bbits) - 1)),
+                      (int)(blockIdx.y >> (2 * bbits))};
+    const int64_t n = (int64_t)1 << a.l;
+    const int64_t S = n + 2 * kHalo;
+    int lo[3];  // level-l index of the window's first cell, per axis
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lo[k] = 8 * b[k] + ((par >> k) & 1) - kHalo;
+    // every global load of a thread issued before its LDS writes
+    constexpr int nwin = kCellWinSide * kCellWinSide * kCellWinSide, nr = (nwin + 64 * CPW - 1) / (64 * CPW);
+    float wv[nr];
+#pragma unroll
+    for (int r = 0; r < nr; ++r) {
+        const int i = threadIdx.x + r * 64 * CPW;
+        if (i < nwin) {
+            const int x = i % kCellWinSide, y = (i / kCellWinSide) % kCellWinSide, z = i / (kCellWinSide * kCellWinSide);
+            wv[r] = a.lev[((int64_t)(lo[2] + z + kHalo) * S + (lo[1] + y + kHalo)) * S + (lo[0] + x + kHalo)];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < nr; ++r) {
+        const int i = threadIdx.x + r * 64 * CPW;
+        if (i < nwin) {
+            const int x = i % kCellWinSide, y = (i / kCellWinSide) % kCellWinSide, z = i / (kCellWinSide * kCellWinSide);
+            win[z * kCellWinPz + y * kCellWinPy + x] = wv[r];
+        }
+    }
+    __syncthreads();
+    if (code >= ncodes) return;  // whole wave
+    int st[3];
+    if (a.compact) {
+        st[0] = a.dl4[code & 3];
+        st[1] = a.dl4[(code >> 2) & 3];
+        st[2] = a.dl4[(code >> 4) & 3];
+    } else {
+        st[0] = code % 6;
+        st[1] = (code / 6) % 6;
+        st[2] = code / 36;
+    }
+    int combo = 0, pcode = 0, mul = 1, pmul = 1;
+    for (int k = 0; k < 3; ++k) {
+        const int p = (par >> k) & 1;
+        combo += (6 * p + st[k]) * mul;
+        pcode += a.next[st[k]][p] * pmul;
+        mul *= 12;
+        pmul *= 6;
+    }
+    combo = __builtin_amdgcn_readfirstlane(combo);
+    pcode = __builtin_amdgcn_readfirstlane(pcode);
+    const int lx = lane & 3, ly = (lane >> 2) & 3, lz = lane >> 4;
+    const int wb = (2 * lz + kHalo) * kCellWinPz + (2 * ly + kHalo) * kCellWinPy + (2 * lx + kHalo);
+    // the lane's cell: q in the parity's sub-grid (h = 2^(l-1) per axis),
+    // c = 2 q + parity at level l; its parent at level l-1 is q itself
+    const int64_t h = n >> 1;
+    const int qx = 4 * b[0] + lx, qy = 4 * b[1] + ly, qz = 4 * b[2] + lz;
+    const int64_t qi = ((int64_t)qz * h + qy) * h + qx;
+    float acc[D];
+    if (a.qprev) {
+        const float4* pr = reinterpret_cast<const float4*>(a.qprev + (qi * 216 + pcode) * D);
+#pragma unroll
+        for (int j = 0; j < D / 4; ++j) {
+            const float4 v = pr[j];
+            acc[4 * j] = v.x;
+            acc[4 * j + 1] = v.y;
+            acc[4 * j + 2] = v.z;
+            acc[4 * j + 3] = v.w;
+        }
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] = 0.f;
+    }
+    // per direction: the 12 gathers (this list already in SGPRs), the scalar
+    // loads of the next direction's list, one wait for both (scalar and LDS
+    // loads share a counter), then the multiply-adds
+    const CD_CONST uint32_t* ko = (const CD_CONST uint32_t*)a.offwin + (size_t)combo * D * kCoarseLen;
+    const CD_CONST uint32_t* kw = (const CD_CONST uint32_t*)a.kt.w + (size_t)combo * D * kCoarseLen;
+    uint32_t ho[kCoarseLen], hw[kCoarseLen];
+#pragma unroll
+    for (int e = 0; e < kCoarseLen; ++e) {
+        ho[e] = ko[e];
+        hw[e] = kw[e];
+    }
+#pragma unroll
+    for (int e = 0; e < kCoarseLen; ++e) asm volatile("" : "+s"(ho[e]), "+s"(hw[e]));
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        float v[kCoarseLen];
+#pragma unroll
+        for (int e = 0; e < kCoarseLen; ++e) v[e] = win[wb + (int)ho[e]];
+        uint32_t no[kCoarseLen], nw[kCoarseLen];
+        if (d + 1 < D) {
+#pragma unroll
+            for (int e = 0; e < kCoarseLen; ++e) {
+                no[e] = ko[(d + 1) * kCoarseLen + e];
+                nw[e] = kw[(d + 1) * kCoarseLen + e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kCoarseLen; ++e) asm volatile("" : "+v"(v[e]));
+        if (d + 1 < D) {
+#pragma unroll
+            for (int e = 0; e < kCoarseLen; ++e) asm volatile("" : "+s"(no[e]), "+s"(nw[e]));
+        }
+        float s = 0.f;
+#pragma unroll
+        for (int e = 0; e < kCoarseLen; ++e) s = fmaf(__uint_as_float(hw[e]), v[e], s);
+        acc[d] = fmaf(a.dx, s, acc[d]);
+        if (d + 1 < D) {
+#pragma unroll
+            for (int e = 0; e < kCoarseLen; ++e) {
+                ho[e] = no[e];
+                hw[e] = nw[e];
+            }
+        }
+    }
+    const int64_t cell = ((int64_t)(2 * qz + (par >> 2)) * n + (2 * qy + ((par >> 1) & 1))) * n + 2 * qx + (par & 1);
+    float4* out = reinterpret_cast<float4*>(a.q + (cell * ncodes + code) * D);
+#pragma unroll
+    for (int j = 0; j < D / 4; ++j) out[j] = make_float4(acc[4 * j], acc[4 * j + 1], acc[4 * j + 2], acc[4 * j + 3]);
+}
+
 // The same entries for listed keys cell * ncodes + code only (the entries
 // an adaptive tree's targets read, and those they add up from): a lane per
 // (entry, direction), 16 entries x 16 directions per workgroup.
@@ -430,6 +574,31 @@ static void launch_fine_path(const cd_tree* t, const cd_weights* w, const float*
     else launch_fine<48>(a, n_oct, s);
 }
 
+// k_coarse_cells for the direction counts it is instantiated for: a
+// workgroup per (4^3 cells of a parity, CPW codes); false for the others.
+// 512^3, 48 directions: level 5 alone 0.39 -> 0.22 ms and level 4 0.12 ->
+// 0.10 ms against k_coarse_lds, coarse stage beside the tiled kernel 1.38 ->
+// 0.94 ms, step 8.29 -> 8.04 ms; 12 directions 2.59 -> 2.49 ms.  Used from
+// 512 cells per parity: at 64 (216 workgroups) it takes 0.04 against 0.02 ms.
+static bool launch_coarse_cells(const CoarseArgs& c, int D, int ncodes, int64_t per_parity, hipStream_t s) {
+    const int cpw = c.compact ? 16 : 8;
+    const dim3 grid((unsigned)(ncodes / cpw * 8), (unsigned)(per_parity / 64));
+    const unsigned nt = 64u * cpw;
+#define CD_COARSE_CELLS(DD)                                                   \
+    case DD:                                                                  \
+        if (c.compact) k_coarse_cells<DD, 16><<<grid, nt, 0, s>>>(c);         \
+        else k_coarse_cells<DD, 8><<<grid, nt, 0, s>>>(c);                    \
+        return true;
+    switch (D) {
+        CD_COARSE_CELLS(12)
+        CD_COARSE_CELLS(24)
+        CD_COARSE_CELLS(40)
+        CD_COARSE_CELLS(48)
+        default: return false;
+    }
+#undef CD_COARSE_CELLS
+}
+
 void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipStream_t s,
                    const int64_t* const* need, const int64_t* n_need) {
     const int D = w->D;
@@ -454,6 +623,8 @@ void launch_coarse(cd_tree* t, const cd_weights* w, int top, bool compact, hipSt
         }
         const int64_t per_parity = (int64_t)1 << (3 * (l - 1));
         const int ncodes = c.compact ? 64 : 216;
+        c.offwin = w->offwin4;
+        if (per_parity >= 512 && w->len[4] == kCoarseLen && launch_coarse_cells(c, D, ncodes, per_parity, s)) continue;
         if (per_parity >= kCoarseBlock) {
             // every block whole: 32 cells of a parity; 16 codes per workgroup
             // for the 64 of level L - 4, 8 for the 216 of the others.  512^3, D
