@@ -176,6 +176,36 @@ def test_c4_512_all_forms_sampled(colden, c4, nside):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("m,nphi", [(3, 8), (5, 8)])
+def test_c4_512_other_direction_counts(colden, c4, m, nphi):
+    """The 512^3 workload with the paper's M x N sets of 24 and 40 directions
+    (Sect. 3.2, Eqs. 5-6), FP32: the coarse tables of levels 4 and 5 with a
+    lane per cell (216 and 64 state codes) and the matrix-core rows at these
+    direction counts, on the 20k leaves sampled across every z plane and the
+    corners, against the oracle (Sect. 3.3, Eq. 11) at 1e-5."""
+    tin, leaf, tree, tg = c4
+    dirs = oracle.dirs_mn(m, nphi)
+    D = dirs.shape[0]
+    ref = oracle.Tree(tin).columns(dirs, tg)
+    dev = torch.device("cuda:0")
+    N = torch.full((tin.n_leaf, D), float("nan"), dtype=torch.float32, device=dev)
+    chi = torch.full((tin.n_leaf,), float("nan"), dtype=torch.float32, device=dev)
+    w = colden.Weights(dirs)
+    colden.column_densities(tree, w, N, chi)
+    idx = torch.from_numpy(tg).to(dev)
+    got = N[idx].cpu().numpy().astype(np.float64)
+    gchi = chi[idx].cpu().numpy().astype(np.float64)
+    assert not torch.isnan(N).any() and not torch.isnan(chi).any()
+    w.close()
+    del N, chi
+    torch.cuda.empty_cache()
+    rel = np.abs(got - ref) / ref
+    dchi = np.abs(gchi - oracle.screening(ref)).max()
+    print(f"512^3 M x N = {m} x {nphi} (D={D}) fp32: max rel {rel.max():.3e}, max |d chi| {dchi:.2e}", flush=True)
+    assert rel.max() <= 1e-5
+    assert dchi <= 1e-5
+
+
 def test_c4_512_fp32_million_sampled(colden, c4):
     """The default benchmark's case (512^3, 48 sectors, FP32, the row kernel
     in one launch over the grid) on 2^20 leaves: 131,072 random octs with all
