@@ -256,6 +256,9 @@ struct GatherArgs {
     double box;
 };
 
+constexpr int kGB = kGatherBlock, kGM = kGatherMasked;  // gathers of one direction issued together
+static_assert(kGB <= kGatherPad && kGM <= kGatherPad, "list reads ahead stay in the padding");
+
 template <int V>
 __global__ __launch_bounds__(256) void k_external_gather(const GatherArgs a) {
     const int lane = threadIdx.x & 63;
@@ -287,37 +290,79 @@ __global__ __launch_bounds__(256) void k_external_gather(const GatherArgs a) {
     const CD_CONST int32_t* hdr = (const CD_CONST int32_t*)a.ghdr + (int64_t)ci * a.D * 4;
     const CD_CONST int32_t* ent = (const CD_CONST int32_t*)a.gent;
     float* out = a.E + (a.erow ? a.erow[t] : t) * a.D;
+    // a lane's density at an entry of kind k whose scalar word pk holds the
+    // offset (x, y, z bytes; the top byte is the parity mask of a masked
+    // dl = 3 entry)
+    auto dens = [&](int k, int32_t pk) -> float {
+        // |offset| <= 5 per axis and S < 2^13: the delta fits 32 bits
+        const int Sk = (int)S[k];
+        const int dlt = ((int)(int8_t)(pk >> 16) * Sk + (int8_t)(pk >> 8)) * Sk + (int8_t)pk;
+        return lv[k][base[k] + dlt];
+    };
     {
         float acc[V];
 #pragma unroll
         for (int j = 0; j < V; ++j) {
+            // one direction at a time (its lists held in SGPRs)
+            __builtin_amdgcn_sched_barrier(0);
             const CD_CONST int32_t* h = hdr + (d0 + j) * 4;
-            int e = h[0];
-            const int n3 = h[3];
-            const int cnt[4] = {0, h[1], h[2], n3 & 0xffff};
-            float s[4] = {0.f, 0.f, 0.f, 0.f};
+            const int e1 = h[0], c1 = h[1], c2 = h[2], n3 = h[3];
+            const int e2 = e1 + c1, e3 = e2 + c2, c3 = n3 & 0xffff, em = e3 + c3, cm = n3 >> 16;
+            // the first kGB words of each kind's list (kGM masked) read as one
+            // block of scalar loads (past the list's end into the next
+            // direction's, or into the array's zero padding), then every
+            // gather of the direction issued before the first multiply-add,
+            // so the wave waits for the memory once per direction; longer
+            // lists, which no direction set used here has, finish below
+            int32_t p1[kGB], p2[kGB], p3[kGB], pm[kGM];
+            float w1[kGB], w2[kGB], w3[kGB], wm[kGM];
 #pragma unroll
-            for (int k = 1; k <= 3; ++k) {
-                if (lv[k]) {
-#pragma unroll 4
-                    for (int i = 0; i < cnt[k]; ++i) {
-                        const int32_t pk = ent[2 * (e + i)];
-                        const int64_t dlt = ((int64_t)(int8_t)(pk >> 16) * S[k] + (int8_t)(pk >> 8)) * S[k] + (int8_t)pk;
-                        s[k] = fmaf(__int_as_float(ent[2 * (e + i) + 1]), lv[k][base[k] + dlt], s[k]);
-                    }
-                }
-                e += cnt[k];
+            for (int i = 0; i < kGB; ++i) {
+                p1[i] = ent[2 * (e1 + i)], w1[i] = __int_as_float(ent[2 * (e1 + i) + 1]);
+                p2[i] = ent[2 * (e2 + i)], w2[i] = __int_as_float(ent[2 * (e2 + i) + 1]);
+                p3[i] = ent[2 * (e3 + i)], w3[i] = __int_as_float(ent[2 * (e3 + i) + 1]);
             }
-            if (lv[3]) {
-                // entries of the dl = 3 box of some parities of A >> 2 only
-#pragma unroll 4
-                for (int i = 0, n = n3 >> 16; i < n; ++i) {
-                    const int32_t pk = ent[2 * (e + i)];
-                    const int64_t dlt = ((int64_t)(int8_t)(pk >> 16) * S[3] + (int8_t)(pk >> 8)) * S[3] + (int8_t)pk;
-                    const float v = lv[3][base[3] + dlt];
-                    s[3] = fmaf(__int_as_float(ent[2 * (e + i) + 1]), ((pk >> pbit) & 1) ? v : 0.f, s[3]);
+#pragma unroll
+            for (int i = 0; i < kGM; ++i) pm[i] = ent[2 * (em + i)], wm[i] = __int_as_float(ent[2 * (em + i) + 1]);
+            float v1[kGB], v2[kGB], v3[kGB], vm[kGM];
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[1] && i < c1) v1[i] = dens(1, p1[i]);
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[2] && i < c2) v2[i] = dens(2, p2[i]);
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[3] && i < c3) v3[i] = dens(3, p3[i]);
+#pragma unroll
+            for (int i = 0; i < kGM; ++i)
+                if (lv[3] && i < cm) vm[i] = dens(3, pm[i]);
+            float s[4] = {0.f, 0.f, 0.f, 0.f};
+            auto tail = [&](int k, int e, int c, int from) {
+                for (int i = from; i < c; ++i)
+                    s[k] = fmaf(__int_as_float(ent[2 * (e + i) + 1]), dens(k, ent[2 * (e + i)]), s[k]);
+            };
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[1] && i < c1) s[1] = fmaf(w1[i], v1[i], s[1]);
+            if (lv[1]) tail(1, e1, c1, kGB);
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[2] && i < c2) s[2] = fmaf(w2[i], v2[i], s[2]);
+            if (lv[2]) tail(2, e2, c2, kGB);
+#pragma unroll
+            for (int i = 0; i < kGB; ++i)
+                if (lv[3] && i < c3) s[3] = fmaf(w3[i], v3[i], s[3]);
+            if (lv[3]) tail(3, e3, c3, kGB);
+            // entries of the dl = 3 box of some parities of A >> 2 only
+#pragma unroll
+            for (int i = 0; i < kGM; ++i)
+                if (lv[3] && i < cm) s[3] = fmaf(wm[i], ((pm[i] >> pbit) & 1) ? vm[i] : 0.f, s[3]);
+            if (lv[3])
+                for (int i = kGM; i < cm; ++i) {
+                    const int32_t pk = ent[2 * (em + i)];
+                    s[3] = fmaf(__int_as_float(ent[2 * (em + i) + 1]), ((pk >> pbit) & 1) ? dens(3, pk) : 0.f, s[3]);
                 }
-            }
             acc[j] = fmaf(dx[1], s[1], fmaf(dx[2], s[2], fmaf(dx[3], s[3], 0.f)));
         }
         if (live) {

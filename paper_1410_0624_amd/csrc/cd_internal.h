@@ -82,6 +82,10 @@ constexpr int kKinds = 5;  // index 1..4 used
 // row and plane pitches (the lanes' cells 2 lx + 8 ly + 32 lz banks apart
 // modulo 64); the kind-4 offsets are also kept decoded for them.
 constexpr int kCellWinSide = 17, kCellWinPy = 36, kCellWinPz = 624;
+// Gather lists of the adaptive external kernel: a direction's entries are
+// read kGatherBlock per kind (kGatherMasked masked) ahead of their use, so
+// the list array ends with kGatherPad zero entries (offset 0, weight 0).
+constexpr int kGatherBlock = 8, kGatherMasked = 4, kGatherPad = 16;
 constexpr int kCellWinWords = kCellWinSide * kCellWinPz;
 constexpr int kMaxSlabs = 4;  // z-slabs overlapping the two sweep stages
 

@@ -431,6 +431,7 @@ int build_gather_tables(HostTables& t) {
             h[3] = ncommon | (nmasked << 16);
         }
     }
+    t.gent.insert(t.gent.end(), 2 * (size_t)kGatherPad, 0);  // read ahead by the gather (never used)
     return CD_OK;
 }
 
