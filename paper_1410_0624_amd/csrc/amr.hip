@@ -294,7 +294,8 @@ __global__ __launch_bounds__(256) void k_external_gather(const GatherArgs a) {
     // offset (x, y, z bytes; the top byte is the parity mask of a masked
     // dl = 3 entry)
     auto dens = [&](int k, int32_t pk) -> float {
-        // |offset| <= 5 per axis and S < 2^13: the delta fits 32 bits
+        // |offset| <= 5 per axis and S <= 2^11 + 10 (levels below CD_MAX_LEVEL):
+        // the delta fits 32 bits
         const int Sk = (int)S[k];
         const int dlt = ((int)(int8_t)(pk >> 16) * Sk + (int8_t)(pk >> 8)) * Sk + (int8_t)pk;
         return lv[k][base[k] + dlt];
@@ -312,8 +313,9 @@ __global__ __launch_bounds__(256) void k_external_gather(const GatherArgs a) {
             // block of scalar loads (past the list's end into the next
             // direction's, or into the array's zero padding), then every
             // gather of the direction issued before the first multiply-add,
-            // so the wave waits for the memory once per direction; longer
-            // lists, which no direction set used here has, finish below
+            // so the wave waits for the memory once per direction; the few
+            // longer lists (9 entries in some slots of 12 directions) finish
+            // below
             int32_t p1[kGB], p2[kGB], p3[kGB], pm[kGM];
             float w1[kGB], w2[kGB], w3[kGB], wm[kGM];
 #pragma unroll
